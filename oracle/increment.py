@@ -1,0 +1,171 @@
+"""One time increment by non-linear alternating minimisation (oracle).
+
+Algorithm 1 of the paper, small-strain form:
+    eps_0 = eps_t + d eps_bar (uniform),  phi_0 = phi_t
+    repeat  i = 1, 2, ...
+        eps_i  = momentum balance by Newton-Krylov at phi_{i-1}, from eps_{i-1}
+        phi_i  = phase-field balance at eps_i, then phi_i = max(phi_i, phi_t)
+    until  max|eps_i - eps_{i-1}| / max|eps_i - eps_t| <= tol
+      and  max|phi_i - phi_{i-1}| / max|phi_i - phi_t| <= tol   (0/0 read as 0)
+followed by the history commit of the internal variables:
+    eps_p, beta_p += sum dgamma (P_a, s_a (x) n_a)
+    g       += h_lin sum |dgamma|                 (linear hardening)
+    rho_SSD += lambda sqrt(2/3 dLp : dLp)          (SSD evolution, Sec. 2.1)
+    W_p     += sigma : d eps_p                     (plastic work, eq. tot)
+    G_s     += xi sigma : d eps_p / sqrt(rho_SSD + rho_GND)     (stored energy)
+    H        = max(H, W_e+)                        (max tensile energy, eq. crit)
+    first time G_s >= G_crit: W_crit = H + W_p     (eq. crit)
+and the lagged GND density from the committed plastic distortion.
+Readings: phi is also capped at 1; the driving state uses the threshold and the
+trigger flag of the start of the increment; rho_GND enters G_s one increment
+late.
+"""
+import numpy as np
+
+from .constitutive import GrainTables, return_map
+from .crystal import to_mandel2, from_mandel2
+from .spectral import Grid
+from .mechanics import solve_mechanics
+from .phasefield import we_plus, solve_phase_field
+from .history import nye_tensor, gnd_density
+
+T6 = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
+
+
+def tensor6(T):
+    """(M,3,3) -> (M,6) tensor components xx, yy, zz, yz, xz, xy."""
+    return np.stack([T[:, i, j] for (i, j) in T6], axis=1)
+
+
+def from_tensor6(v):
+    v = np.atleast_2d(v)
+    T = np.empty((len(v), 3, 3))
+    for a, (i, j) in enumerate(T6):
+        T[:, i, j] = v[:, a]
+        T[:, j, i] = v[:, a]
+    return T
+
+
+def _ratio(num, den):
+    if num == 0.0:
+        return 0.0
+    return num / den if den > 0.0 else np.inf
+
+
+class OracleRVE:
+    """State and increments of one periodic RVE.  ``desc`` is a flat dict of constants
+    (see ``synth.Workload.desc``); arrays are flat with x fastest."""
+
+    def __init__(self, desc, grain, quat, tau_c0=None, phi0=None):
+        self.d = dict(desc)
+        d = self.d
+        self.grid = Grid(d["n"], d["h"])
+        M = self.grid.M
+        self.gid = np.asarray(grain, dtype=np.int64)
+        quat = np.atleast_2d(np.asarray(quat, dtype=np.float64))
+        self.tab = GrainTables(quat, d["C11"], d["C12"], d["C44"])
+        G = len(quat)
+        tau = np.full(G, d["tau_c0"]) if tau_c0 is None else np.asarray(tau_c0, dtype=float)
+        self.eps = np.zeros((M, 3, 3))
+        self.epsp = np.zeros((M, 3, 3))
+        self.beta = np.zeros((M, 3, 3))
+        self.g = tau[self.gid].astype(np.float64)
+        self.phi = np.zeros(M) if phi0 is None else np.asarray(phi0, dtype=float).copy()
+        # voxels pre-set to full damage are the paper's geometric crack: a linear
+        # elastic region (no slip) whose stiffness g(1) C = k C
+        self.g[self.phi >= 1.0] = np.inf
+        self.rho_ssd = np.full(M, d["rho0"])
+        self.rho_gnd = np.zeros(M)
+        self.Wp = np.zeros(M)
+        self.Gs = np.zeros(M)
+        self.H = np.zeros(M)
+        self.Wcrit = np.zeros(M)
+        self.trig = np.zeros(M, dtype=bool)
+        self.sig = np.zeros((M, 6))         # effective stress (Mandel), last converged
+        self.sig_ws = None                  # warm start of the return map
+        self.history = []
+
+    # --- per-voxel constitutive update --------------------------------------------
+    def constit(self, epsM, dt):
+        t = self.tab
+        gid = self.gid
+        out = return_map(epsM, to_mandel2(self.epsp), self.g, dt, t.C[gid], t.S[gid],
+                         t.P[gid], self.d["gdot0"], self.d["n_exp"], sig0=self.sig_ws)
+        self.sig_ws = out[0]
+        return out
+
+    def degradation(self, phi):
+        return (1.0 - phi) ** 2 + self.d["k_res"]
+
+    # --- Algorithm 1 -------------------------------------------------------------
+    def step(self, deps6, dt):
+        d = self.d
+        grid = self.grid
+        t = self.tab
+        gid = self.gid
+        stats = {}
+        dE = from_tensor6(np.asarray(deps6, dtype=float))[0]
+        eps_t = self.eps.copy()
+        phi_t = self.phi.copy()
+        eps_prev = eps_t + dE[None]
+        phi_prev = phi_t.copy()
+        constit = lambda e: self.constit(e, dt)
+        for it in range(d["max_stag"]):
+            eps_i, sig, dgam = solve_mechanics(grid, eps_prev, eps_t, self.degradation(phi_prev),
+                                               constit, d["tol_newton"], d["tol_lin"],
+                                               d["max_newton"], d["max_krylov"], stats)
+            epsp_tr = self.epsp + from_mandel2(np.einsum("ma,mai->mi", dgam, t.P[gid]))
+            tau = np.einsum("mai,mi->ma", t.P[gid], sig)
+            wp_tr = self.Wp + (tau * dgam).sum(1)
+            we = we_plus(eps_i - epsp_tr, t.C4[gid])
+            S = np.where(self.trig, d["ell"] / d["Gc"] * np.maximum(0.0, we + wp_tr - self.Wcrit),
+                         0.0)
+            phi_sol = solve_phase_field(grid, S, d["ell"], x0=phi_prev, rtol=d["tol_lin"],
+                                        max_iter=d["max_krylov"], stats=stats)
+            phi_i = np.minimum(1.0, np.maximum(phi_t, phi_sol))
+            r_e = _ratio(np.abs(tensor6(eps_i - eps_prev)).max(),
+                         np.abs(tensor6(eps_i - eps_t)).max())
+            r_p = _ratio(np.abs(phi_i - phi_prev).max(), np.abs(phi_i - phi_t).max())
+            eps_prev, phi_prev = eps_i, phi_i
+            stats["stag"] = it + 1
+            if r_e <= d["tol_stag"] and r_p <= d["tol_stag"]:
+                break
+        else:
+            raise RuntimeError("alternating minimisation did not converge")
+        # --- commit (all in float64) ---
+        self.eps = eps_prev
+        self.phi = phi_prev
+        self.sig = sig
+        dbeta = np.einsum("ma,maij->mij", dgam, t.SN[gid])
+        self.epsp = epsp_tr
+        self.beta = self.beta + dbeta
+        self.g = self.g + d["h_lin"] * np.abs(dgam).sum(1)
+        self.rho_ssd = self.rho_ssd + d["lambda_ssd"] * np.sqrt(
+            2.0 / 3.0 * np.einsum("mij,mij->m", dbeta, dbeta))
+        dw = (tau * dgam).sum(1)
+        self.Wp = self.Wp + dw
+        self.Gs = self.Gs + d["xi_store"] * dw / np.sqrt(self.rho_ssd + self.rho_gnd)
+        self.H = np.maximum(self.H, we)
+        newly = (~self.trig) & (self.Gs >= d["G_crit"])
+        self.Wcrit = np.where(newly, self.H + self.Wp, self.Wcrit)
+        self.trig = self.trig | newly
+        lam = nye_tensor(grid, self.beta, d["ell_fp"])
+        self.rho_gnd = gnd_density(lam, t.R[gid], d["burgers"])
+        gphi = self.degradation(self.phi)
+        stats["macro_stress"] = tensor6((gphi[:, None, None] * from_mandel2(sig)).mean(0,
+                                        keepdims=True))[0]
+        stats["macro_strain"] = tensor6(self.eps.mean(0, keepdims=True))[0]
+        stats["max_phi"] = float(self.phi.max())
+        stats["n_trig"] = int(self.trig.sum())
+        self.history.append(stats)
+        return stats
+
+    # --- fields in the exchange layout ----------------------------------------------
+    def fields(self):
+        gphi = self.degradation(self.phi)
+        sig_t = from_mandel2(self.sig)
+        return dict(strain=tensor6(self.eps), stress=tensor6(gphi[:, None, None] * sig_t),
+                    stress_eff=tensor6(sig_t), damage=self.phi.copy(), gs=self.Gs.copy(),
+                    rho_ssd=self.rho_ssd.copy(), rho_gnd=self.rho_gnd.copy(), wp=self.Wp.copy(),
+                    h=self.H.copy(), wcrit=self.Wcrit.copy(), trig=self.trig.astype(float),
+                    eps_p=tensor6(self.epsp), g=self.g.copy())

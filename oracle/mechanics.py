@@ -1,0 +1,90 @@
+"""Momentum balance at fixed damage: Newton + Krylov in Fourier space (oracle).
+
+Sec. 3.1, eqs. momentum, fdef, newton, precf, avstiff (small strain):
+find the displacement fluctuation u such that, with
+    eps = eps_bar + F^-1{ sym(i xi~ (x) u^) },
+the degraded stress g(phi) sigma(eps) is divergence free on every frequency
+with xi~ != 0.  Each Newton step solves the linearised balance
+    - i xi~ . F{ g K : F^-1{ sym(i xi~ (x) du^) } } = i xi~ . F{ g sigma }
+preconditioned by M = [xi~ . Kbar . xi~]^-1, Kbar = mean(g K) (eq. precf).
+
+Readings:
+* With the strength frozen over the step the tangent K is symmetric positive
+  definite, so the linearised operator is symmetric positive definite and the
+  Krylov solver is preconditioned conjugate gradients (the paper names GMRES;
+  both converge to the same Newton correction).
+* The unknown here is the real displacement correction field (the paper's
+  real-FFT reduction is a change of basis of the same real vector space).
+* Newton is globalised by backtracking on the convex incremental energy
+  Pi(u) = mean(g w(eps(u))), whose gradient is the residual; the converged
+  state is the same equilibrium, and full steps are taken near it.
+* Newton stops when max|sym grad du| <= tol * max|eps_i - eps_t| (the paper's
+  criterion, with the applied step).
+"""
+import numpy as np
+from scipy.sparse.linalg import LinearOperator, cg
+
+from .crystal import to_mandel2, from_mandel2, from_mandel4
+
+
+def solve_mechanics(grid, eps0, eps_t, gphi, constit, tol_newton, tol_lin, max_newton,
+                    max_krylov, stats=None):
+    """Equilibrated strain (M,3,3) starting from ``eps0``.
+
+    constit(eps_mandel) -> (sig_mandel, dgam, K_mandel, w) is the per-voxel update.
+    gphi: (M,) degradation g(phi).  Returns (eps, sig_mandel, dgam) at the solution.
+    """
+    n = grid.n
+    gphi = np.asarray(gphi, dtype=np.float64)
+    eps = np.array(eps0, dtype=np.float64, copy=True)
+    sigM, dgam, KM, w = constit(to_mandel2(eps))
+    Pi = np.mean(gphi * w)
+    for it in range(max_newton):
+        gK = gphi[:, None, None] * KM
+        Ainv = grid.acoustic_inverse(from_mandel4(gK.mean(0)))
+        gK_g = grid.to_grid(gK)
+        gsig = grid.to_grid(gphi[:, None, None] * from_mandel2(sigM))
+        rhs = grid.ifft(grid.div_hat(grid.fft(gsig))).ravel()
+        count = [0]
+
+        def matvec(x):
+            count[0] += 1
+            u = x.reshape(n + (3,))
+            de = grid.ifft(grid.sym_grad_hat(grid.fft(u)))
+            ds = from_mandel2(np.einsum("...ij,...j->...i", gK_g, to_mandel2(de)))
+            return -grid.ifft(grid.div_hat(grid.fft(ds))).ravel()
+
+        def prec(x):
+            y = np.einsum("...ik,...k->...i", Ainv, grid.fft(x.reshape(n + (3,))))
+            return grid.ifft(y).ravel()
+
+        N = rhs.size
+        A = LinearOperator((N, N), matvec=matvec, dtype=np.float64)
+        P = LinearOperator((N, N), matvec=prec, dtype=np.float64)
+        du, info = cg(A, rhs, rtol=tol_lin, atol=0.0, maxiter=max_krylov, M=P)
+        if info != 0:
+            raise RuntimeError(f"Krylov solve did not converge (info={info})")
+        de = grid.to_flat(grid.ifft(grid.sym_grad_hat(grid.fft(du.reshape(n + (3,))))))
+        # backtracking on the incremental energy along de
+        slope = np.mean(gphi * np.einsum("mi,mi->m", sigM, to_mandel2(de)))
+        t = 1.0
+        for _ls in range(40):
+            trial = eps + t * de
+            s_t, dg_t, K_t, w_t = constit(to_mandel2(trial))
+            Pi_t = np.mean(gphi * w_t)
+            if Pi_t - Pi <= 1e-4 * t * slope + 1e-13 * abs(Pi):
+                break
+            t *= 0.5
+        else:
+            raise RuntimeError("Newton line search failed")
+        eps = trial
+        sigM, dgam, KM, Pi = s_t, dg_t, K_t, Pi_t
+        if stats is not None:
+            stats["matvecs"] = stats.get("matvecs", 0) + count[0]
+            stats["newton"] = stats.get("newton", 0) + 1
+            stats["ls_cuts"] = stats.get("ls_cuts", 0) + _ls
+        num = t * np.abs(de).max()
+        den = np.abs(eps - eps_t).max()
+        if num <= tol_newton * den or num == 0.0:
+            return eps, sigM, dgam
+    raise RuntimeError("Newton did not converge")
