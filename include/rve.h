@@ -1,0 +1,184 @@
+/* rve.h -- C ABI of the MI355X (gfx950) solver for one load increment of the
+ * FFT-based crystal-plasticity phase-field fatigue model of Lucarini, Dunne and
+ * Martinez-Paneda (2023), in its small-strain form.
+ *
+ * Problem (Sec. 3.1): a periodic box of N1 x N2 x N3 cubic voxels of edge h, fields
+ * at voxel centres, strain control through the macroscopic strain.  One increment
+ * (Algorithm 1) takes the state at time t, a macroscopic strain increment and a time
+ * step, and returns the state at t + dt: the momentum balance div[g(phi) sigma] = 0
+ * (eqs. str1, momentum, newton) is solved by Newton's method with a Krylov solver
+ * preconditioned by the acoustic tensor of the volume-averaged tangent (eqs. precf,
+ * avstiff); the phase field solves (phi - l^2 lap phi) - 2 (1 - phi) S = 0 (eqs. strpf,
+ * phase, str2) with the stored-energy driving state S (eqs. crit, decMiehe, zeta);
+ * the two alternate until both relative corrections fall below tol_stag, with the
+ * pointwise irreversibility phi >= phi_t.  The history (SSD density, plastic work,
+ * stored energy density G_s, W_crit) and the regularised Nye-tensor GND density
+ * (eq. nye1 and the Fourier curl of Sec. 3.1) are committed at the end.
+ *
+ * Conventions.
+ *  - Every voxel array is structure-of-arrays, x fastest: voxel (i, j, k) is element
+ *    i + N1*(j + N2*k) of each component.
+ *  - Symmetric tensors have 6 components in the order xx, yy, zz, yz, xz, xy
+ *    (tensor shear components, not engineering strains).
+ *  - Units: SI (m, s, Pa, J/m^2).
+ *  - Every function returns an int status (RVE_OK = 0, negative on error) and never
+ *    throws; rve_last_error() gives a message for the calling thread.
+ *  - Handles are not thread safe; one handle per thread.
+ */
+#ifndef RVE_H
+#define RVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  RVE_OK = 0,
+  RVE_E_ARG = -1,     /* invalid argument: sizes not 2^a 3^b, non-finite input, bad ids */
+  RVE_E_NOMEM = -2,   /* the arena is smaller than rve_footprint_bytes()                */
+  RVE_E_DEVICE = -3,  /* a HIP call failed                                              */
+  RVE_E_NOCONV = -4,  /* a solver did not converge; the state is left at time t         */
+  RVE_E_STATE = -5    /* call out of order (e.g. a step before the microstructure)      */
+};
+
+enum { RVE_FP64 = 0, RVE_MIXED = 1 };
+
+/* Field selection bits for rve_fields(); fields are written in increasing bit order. */
+enum {
+  RVE_F_STRAIN = 1u << 0,     /* 6: total strain eps                                   */
+  RVE_F_STRESS = 1u << 1,     /* 6: degraded stress g(phi) sigma (the equilibrated one) */
+  RVE_F_STRESS_EFF = 1u << 2, /* 6: effective (undegraded) stress sigma                 */
+  RVE_F_DAMAGE = 1u << 3,     /* 1: phase field phi                                     */
+  RVE_F_GS = 1u << 4,         /* 1: stored energy density G_s [J/m^2]                   */
+  RVE_F_RHO_SSD = 1u << 5,    /* 1: SSD density [1/m^2]                                 */
+  RVE_F_RHO_GND = 1u << 6,    /* 1: GND density [1/m^2] (lagged one increment)          */
+  RVE_F_WP = 1u << 7,         /* 1: plastic work W_p [J/m^3]                            */
+  RVE_F_H = 1u << 8,          /* 1: max over time of the tensile elastic energy          */
+  RVE_F_WCRIT = 1u << 9,      /* 1: threshold W_crit (0 until triggered)                 */
+  RVE_F_TRIG = 1u << 10,      /* 1: 1.0 where G_s has reached G_crit                     */
+  RVE_F_EPS_P = 1u << 11,     /* 6: plastic strain                                       */
+  RVE_F_SLIP_RES = 1u << 12,  /* 1: slip resistance g (inf in pre-cracked voxels)        */
+  RVE_F_BETA_P = 1u << 13     /* 9: plastic distortion, row-major 3x3                    */
+};
+
+/* Problem description.  n[a] must be of the form 2^p 3^q with 1 <= n[a] <= 512. */
+typedef struct rve_desc {
+  int32_t n[3];
+  int32_t precision;        /* RVE_FP64: everything FP64.  RVE_MIXED: FFTs, spectral
+                               operators, the tangent field and Krylov vectors in FP32;
+                               return mapping, Krylov dot products, norms, the phase-field
+                               solve and the history in FP64.                          */
+  double h;                 /* voxel edge [m]                                         */
+  double C11, C12, C44;     /* cubic elastic constants, crystal frame [Pa]            */
+  double gdot0, n_exp;      /* power-law flow: reference slip rate [1/s], exponent     */
+  double tau_c0, h_lin;     /* default initial slip resistance, linear hardening [Pa]  */
+  double lambda_ssd, rho0;  /* SSD evolution coefficient [1/m^2], initial SSD [1/m^2]  */
+  double burgers;           /* Burgers vector length [m]                               */
+  double xi_store;          /* stored fraction of plastic work in G_s [-]              */
+  double ell, Gc, G_crit;   /* phase-field length [m], toughness [J/m^2], G_s threshold */
+  double k_res;             /* residual stiffness in g(phi) = (1-phi)^2 + k_res        */
+  double ell_fp;            /* regularisation length of the plastic distortion [m]     */
+  double tol_stag;          /* alternating-minimisation tolerance (paper: 5e-3)        */
+  double tol_newton;        /* Newton tolerance on max|sym grad du| / max|eps - eps_t|  */
+  double tol_lin;           /* relative Krylov tolerance (paper: 1e-5)                  */
+  int32_t max_stag, max_newton, max_krylov;
+  int32_t max_grains;       /* capacity of the per-grain tables (>= n_grains)           */
+} rve_desc;
+
+/* Per-increment report, filled by rve_step_increment (also on RVE_E_NOCONV). */
+typedef struct rve_stats {
+  int32_t stag_iters;       /* alternating-minimisation passes                        */
+  int32_t newton_iters;     /* Newton iterations, all passes                          */
+  int32_t krylov_iters;     /* momentum Krylov iterations = operator applications     */
+  int32_t pf_iters;         /* phase-field Krylov iterations                          */
+  int32_t ls_cuts;          /* Newton step halvings                                   */
+  int32_t rm_failures;      /* voxels whose return mapping did not converge           */
+  double macro_stress[6];   /* volume average of g(phi) sigma [Pa]                     */
+  double macro_strain[6];   /* volume average of eps                                  */
+  double max_phi;           /* max of phi                                             */
+  double max_phi_slip;      /* max of phi over voxels that can slip (not pre-cracked)   */
+  double n_triggered;       /* voxels with G_s >= G_crit                               */
+  double ms_total, ms_constitutive, ms_mech_krylov, ms_phase_field, ms_commit;
+} rve_stats;
+
+/* Device bytes a handle with this description needs in its arena (0 if invalid). */
+size_t rve_footprint_bytes(const rve_desc* d);
+
+/* Create a handle.  dev_arena: device memory of arena_bytes bytes, owned by the caller
+ * and kept alive until rve_destroy (the library allocates no device memory itself).
+ * hip_stream: the hipStream_t all work of this handle is ordered on (NULL = default).
+ * Errors: RVE_E_ARG (bad description), RVE_E_NOMEM (arena too small), RVE_E_DEVICE. */
+int rve_create(const rve_desc* d, void* dev_arena, size_t arena_bytes, void* hip_stream,
+               struct rve_s** out);
+
+/* Set the microstructure and the initial state (all host arrays, copied).
+ * grain_of_voxel: N ints in [0, n_grains), x fastest.
+ * quat_wxyz: 4*n_grains unit quaternions (w,x,y,z) rotating crystal vectors into the
+ *            sample frame (normalised here; |q| must be within 1e-6 of 1).
+ * tau_c0_per_grain: n_grains initial slip resistances [Pa], or NULL for d->tau_c0.
+ * phi0: N initial damage values in [0, 1], or NULL for 0.  Voxels with phi0 = 1 are
+ *       a pre-cracked region: linear elastic (no slip), stiffness g(1) C = k_res C, as
+ *       the paper models geometric cracks.
+ * Resets the state to t = 0: zero strain and stress, SSD = rho0, every other internal
+ * variable 0.  Errors: RVE_E_ARG. */
+int rve_set_microstructure(struct rve_s* h, const int32_t* grain_of_voxel, int32_t n_grains,
+                           const double* quat_wxyz, const double* tau_c0_per_grain,
+                           const double* phi0);
+
+/* One load increment (Algorithm 1) under the macroscopic strain increment deps_macro
+ * (6 components) over the time step dt > 0.  Synchronous on the handle's stream.
+ * Transactional: on RVE_E_NOCONV the state stays at time t (the caller may retry with
+ * a smaller increment).  st may be NULL.  Errors: RVE_E_ARG (non-finite input),
+ * RVE_E_STATE (no microstructure), RVE_E_NOCONV, RVE_E_DEVICE. */
+int rve_step_increment(struct rve_s* h, const double deps_macro[6], double dt, rve_stats* st);
+
+/* Copy the fields selected by field_mask to host_out (n_doubles capacity), each as
+ * SoA components of N values in increasing bit order.  Errors: RVE_E_ARG if the
+ * buffer is too small, RVE_E_STATE before rve_set_microstructure. */
+int rve_fields(struct rve_s* h, uint32_t field_mask, double* host_out, size_t n_doubles);
+
+/* Release the handle (the arena stays owned by the caller). */
+int rve_destroy(struct rve_s* h);
+
+/* Message of the last error on this thread ("" if none). */
+const char* rve_last_error(void);
+
+/* Number of doubles rve_fields writes for field_mask (0 for an unknown bit). */
+size_t rve_fields_count(const struct rve_s* h, uint32_t field_mask);
+
+/* ---- diagnostics: single building blocks on the handle's grid and precision ------ */
+
+/* Forward real FFT (unnormalised, exp(-i xi.x)) of ncomp real fields (host, N each,
+ * ncomp <= 9) to their half spectra (host, 2*N1h*N2*N3 doubles each, re/im
+ * interleaved, bin kx + N1h*(ky + N2*kz), N1h = N1/2 + 1).  Uses the handle's scratch
+ * buffers; the physical state is not touched. */
+int rve_diag_rfft(struct rve_s* h, int32_t ncomp, const double* real_in, double* spec_out);
+
+/* Inverse of rve_diag_rfft, normalised (returns the real fields). */
+int rve_diag_irfft(struct rve_s* h, int32_t ncomp, const double* spec_in, double* real_out);
+
+/* Constitutive update of every voxel at the given total strain eps6 (host, 6*N) with
+ * the current internal variables and time step dt: writes the effective stress
+ * (6*N) and g(phi) K as 21 Mandel upper-triangle entries (21*N, row-major over
+ * (0,0),(0,1)..(0,5),(1,1)..(5,5)).  Either output may be NULL.  The stored stress
+ * of the state is restored afterwards. */
+int rve_diag_constitutive(struct rve_s* h, const double* eps6, double dt, double* sig6_out,
+                          double* gk21_out);
+
+/* Apply the preconditioned linearised equilibrium operator of the current tangent
+ * field to a displacement field: given real displacements u (host, 3*N), return
+ * v = F^-1{ M . (-i xi~) . F{ gK : F^-1{ sym(i xi~ (x) F{u}) } } } (host, 3*N), with M
+ * the acoustic-tensor preconditioner of the mean tangent.  Requires a preceding
+ * rve_diag_constitutive (which sets the tangent field). */
+int rve_diag_operator(struct rve_s* h, const double* u3, double* v3);
+
+typedef struct rve_s* rve_t;
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RVE_H */

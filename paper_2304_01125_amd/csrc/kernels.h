@@ -1,0 +1,148 @@
+// Kernel launchers of the HIP library (host-callable, all on an explicit stream).
+#pragma once
+#include "common.h"
+
+namespace rvefft {
+
+// FFT plans of one grid: axis lengths, radix schedules and device twiddle tables.
+struct Plans {
+  Grid g;
+  AxisPlan ax[3];
+  const void* tw64[3];     // cplx<double>[n_a], exp(-2 pi i k / n_a)
+  const void* tw32[3];     // cplx<float>[n_a]
+  const void* tw_ptr(int axis, bool f64) const { return f64 ? tw64[axis] : tw32[axis]; }
+};
+
+// Radix schedule of a length 2^a 3^b; returns false for other lengths.
+bool make_axis_plan(int n, AxisPlan* out);
+
+// Block-level deterministic sum: wave shuffles, then the waves in order; thread 0
+// writes partial[blockIdx.x].  `red` is LDS of blockDim.x/64 doubles.
+__device__ inline void block_partial_sum(double v, double* partial, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+    partial[blockIdx.x] = s;
+  }
+}
+
+// --- spectral passes (spectral.hip) ------------------------------------------------
+template <typename R>
+void launch_x_r2c(const Plans& p, const void* in, bool in_f64, long long in_cs, const double* phi,
+                  double kres, cplx<R>* out, long long out_cs, int ncomp, hipStream_t st);
+template <typename R>
+void launch_x_c2r(const Plans& p, const cplx<R>* in, long long in_cs, void* out, bool out_f64,
+                  long long out_cs, int ncomp, double scale, int accumulate, hipStream_t st);
+template <typename R>
+void launch_x_tangent(const Plans& p, cplx<R>* data, long long cs, const R* gK, double scale,
+                      hipStream_t st);
+template <typename R>
+void launch_fft_yz(const Plans& p, cplx<R>* data, long long cs, int ncomp, int axis, bool inv,
+                   hipStream_t st);
+template <typename R>
+void launch_sym_grad(const Plans& p, const cplx<R>* u, long long ucs, cplx<R>* e, long long ecs,
+                     hipStream_t st);
+template <typename R>
+void launch_div(const Plans& p, const cplx<R>* s, long long scs, cplx<R>* out, long long ocs,
+                double sign, hipStream_t st);
+template <typename R>
+int launch_precond(const Plans& p, const cplx<R>* r, cplx<R>* z, long long cs, const double* kbar21,
+                   double* partial, hipStream_t st);
+template <typename R>
+void launch_pf_scale(const Plans& p, cplx<R>* d, double ell, double scale, hipStream_t st);
+template <typename R>
+void launch_curl_reg(const Plans& p, cplx<R>* b9, long long cs, double ell_fp, double scale,
+                     hipStream_t st);
+
+// --- voxel kernels (voxel.hip) -------------------------------------------------------
+// Per-grain table: GT_STRIDE doubles per grain.
+enum {
+  GT_C = 0,        // Mandel stiffness, 36 (sample frame)
+  GT_S = 36,       // Mandel compliance, 36
+  GT_P = 72,       // Mandel Schmid tensors sym(s (x) n), 12 x 6
+  GT_SN = 144,     // s (x) n, 12 x 9 row-major
+  GT_R = 252,      // rotation crystal -> sample, 9 row-major
+  GT_STRIDE = 261
+};
+
+struct Material {
+  double dt, gdot0, nexp, kres, h_lin, lambda_ssd, xi_store, G_crit, ell, Gc, burgers;
+};
+
+// number of reduction values written by each voxel kernel per block
+enum { RED_CONST = 28,  // 21 sum gK, 1 sum g*w, 6 sum g*sigma
+       RED_SOURCE = 2,  // sum S, sum S^2
+       RED_COMMIT = 15, // 6 sum g*sigma, 6 sum eps, max phi, n_trig, max phi outside pre-set
+       RED_MAX4 = 4 };
+
+int voxel_grid(long long n);
+
+template <typename R>
+void launch_constitutive(long long N, const double* eps, const double* deps, double t,
+                         const double* epsp, const double* gslip, const int* grain,
+                         const double* gtab, double* sig, const double* phi, R* gK,
+                         const Material& m, double* partial, int* fail, hipStream_t st);
+void launch_source(long long N, const double* eps, const double* sig, const double* epsp,
+                   const double* gslip, const int* grain, const double* gtab, const double* wp,
+                   const double* trig, const double* wcrit, double* S, double* wep,
+                   const Material& m, double* partial, hipStream_t st);
+void launch_commit(long long N, const double* sig, double* gslip, double* epsp, double* beta,
+                   double* rho_ssd, const double* rho_gnd, double* wp, double* gs, double* H,
+                   double* wcrit, double* trig, const double* wep, const double* phi,
+                   const double* eps, const int* grain, const double* gtab, const Material& m,
+                   double* partial, hipStream_t st);
+void launch_gnd(long long N, const double* lam9, const int* grain, const double* gtab,
+                const double* Q81, double burgers, double* rho_gnd, hipStream_t st);
+// eps += t * deps; partial maxima of |t deps| and |eps - eps_t| (2 values)
+void launch_eps_update(long long N, double* eps, const double* deps, double t, const double* eps_t,
+                       double* partial, hipStream_t st);
+// partial sum of g(phi) sigma : deps (tensor double contraction)
+void launch_slope(long long N, const double* sig, const double* deps, const double* phi,
+                  double kres, double* partial, hipStream_t st);
+// staggered-loop maxima: |eps-eps_prev|, |eps-eps_t|, |phi-phi_prev|, |phi-phi_t|
+void launch_stag_norms(long long N, const double* eps, const double* eps_prev, const double* eps_t,
+                       const double* phi, const double* phi_prev, const double* phi_t,
+                       double* partial, hipStream_t st);
+// eps[c] += de[c] for the 6 components (uniform macroscopic increment)
+void launch_add_uniform(long long N, double* eps, const double de[6], hipStream_t st);
+// phi = min(1, max(phi_t, x))
+void launch_clamp(long long N, const double* x, const double* phi_t, double* phi, hipStream_t st);
+
+// --- reductions and vector kernels (vector.hip) ---------------------------------------
+// out[c] = sum (or max) over b < nblk of partial[c*nblk + b], fixed order.
+void launch_reduce(const double* partial, int nblk, int ncomp, int op_max, double* out,
+                   hipStream_t st);
+// Parseval-weighted <a,b> over ncomp half-spectrum components; returns #blocks.
+template <typename R>
+int launch_sdot(const Plans& p, const cplx<R>* a, const cplx<R>* b, long long cs, int ncomp,
+                double* partial, hipStream_t st);
+// CG updates on half-spectrum vectors (3 comps), scalars read from device `sc`:
+// x += a p ; r -= a q ; partial <r,r>   with a = sc[ia] / sc[ib]
+template <typename R>
+int launch_cg_xr(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, const cplx<R>* q,
+                 long long cs, const double* sc, int ia, int ib, double* partial, hipStream_t st);
+// p = z + b p with b = sc[ia] / sc[ib]
+template <typename R>
+void launch_cg_p(const Plans& p, cplx<R>* pv, const cplx<R>* z, long long cs, const double* sc,
+                 int ia, int ib, hipStream_t st);
+// real-vector kernels (phase field)
+int launch_rdot(long long n, const double* a, const double* b, double* partial, hipStream_t st);
+// pq = <p, w + 2 S p>
+int launch_pf_pq(long long n, const double* p, const double* w, const double* S, double* partial,
+                 hipStream_t st);
+// x += a p ; r -= a (w + 2 S p) ; partial <r,r>
+int launch_pf_xr(long long n, double* x, double* r, const double* p, const double* w,
+                 const double* S, const double* sc, int ia, int ib, double* partial, hipStream_t st);
+// p = z + b p ; w = r + b w
+void launch_pf_pw(long long n, double* p, double* w, const double* z, const double* r,
+                  const double* sc, int ia, int ib, hipStream_t st);
+// y = a * x (real)
+void launch_rscale(long long n, const double* x, double a, double* y, hipStream_t st);
+// zero a complex/real buffer of `bytes` bytes with a fill kernel
+void launch_zero(void* ptr, size_t bytes, hipStream_t st);
+
+}  // namespace rvefft

@@ -1,0 +1,918 @@
+// Host driver and C ABI: arena layout, crystal tables, Algorithm 1 with the Newton /
+// Krylov momentum solver, the phase-field solver, the history commit and the GND
+// update.  Every kernel runs on the handle's stream; the host only reads scalars.
+#include "../../include/rve.h"
+#include "kernels.h"
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace rvefft;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(RVE_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+bool smooth23(int n) {
+  if (n < 1 || n > kMaxN) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ---- crystal tables (host, FP64) ---------------------------------------------------
+// The 12 FCC slip systems: plane normals {111} with three <110> directions each.
+const double kSlipN[12][3] = {{1, 1, 1},  {1, 1, 1},  {1, 1, 1},  {-1, 1, 1}, {-1, 1, 1}, {-1, 1, 1},
+                              {1, -1, 1}, {1, -1, 1}, {1, -1, 1}, {1, 1, -1}, {1, 1, -1}, {1, 1, -1}};
+const double kSlipS[12][3] = {{0, 1, -1}, {1, 0, -1}, {1, -1, 0}, {0, 1, -1}, {1, 0, 1}, {1, 1, 0},
+                              {0, 1, 1},  {1, 0, -1}, {1, 1, 0},  {0, 1, 1},  {1, 0, 1}, {1, -1, 0}};
+// The 6 <110> screw line directions.
+const double kScrew[6][3] = {{1, 1, 0}, {1, -1, 0}, {1, 0, 1}, {1, 0, -1}, {0, 1, 1}, {0, 1, -1}};
+
+const int kPairs[6][2] = {{0, 0}, {1, 1}, {2, 2}, {1, 2}, {0, 2}, {0, 1}};
+
+void normalize3(double v[3]) {
+  const double s = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  for (int i = 0; i < 3; ++i) v[i] /= s;
+}
+
+void quat_rot(const double* q, double R[3][3]) {
+  double w = q[0], x = q[1], y = q[2], z = q[3];
+  const double s = std::sqrt(w * w + x * x + y * y + z * z);
+  w /= s; x /= s; y /= s; z /= s;
+  R[0][0] = 1 - 2 * (y * y + z * z); R[0][1] = 2 * (x * y - w * z); R[0][2] = 2 * (x * z + w * y);
+  R[1][0] = 2 * (x * y + w * z); R[1][1] = 1 - 2 * (x * x + z * z); R[1][2] = 2 * (y * z - w * x);
+  R[2][0] = 2 * (x * z - w * y); R[2][1] = 2 * (y * z + w * x); R[2][2] = 1 - 2 * (x * x + y * y);
+}
+
+// Gauss-Jordan inverse with partial pivoting of an n x n row-major matrix.
+bool invert(std::vector<double>& A, int n) {
+  std::vector<double> I(n * n, 0.0);
+  for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+    if (A[piv * n + c] == 0.0) return false;
+    for (int k = 0; k < n; ++k) {
+      std::swap(A[c * n + k], A[piv * n + k]);
+      std::swap(I[c * n + k], I[piv * n + k]);
+    }
+    const double d = A[c * n + c];
+    for (int k = 0; k < n; ++k) { A[c * n + k] /= d; I[c * n + k] /= d; }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = A[r * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) { A[r * n + k] -= f * A[c * n + k]; I[r * n + k] -= f * I[c * n + k]; }
+    }
+  }
+  A = I;
+  return true;
+}
+
+// One grain's table: rotated Mandel stiffness and compliance, Mandel Schmid tensors,
+// s (x) n and the rotation.
+bool grain_table(const double* q, double C11, double C12, double C44, double* out) {
+  double R[3][3];
+  quat_rot(q, R);
+  double c0[3][3][3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) {
+          double v = C12 * (i == j) * (k == l) + C44 * ((i == k) * (j == l) + (i == l) * (j == k));
+          if (i == j && j == k && k == l) v += C11 - C12 - 2.0 * C44;
+          c0[i][j][k][l] = v;
+        }
+  // rotate each index: C'_ijkl = R_ia R_jb R_kc R_ld C_abcd, in four contractions
+  double t1[3][3][3][3], t2[3][3][3][3];
+  auto contract = [&](double (&src)[3][3][3][3], double (&dst)[3][3][3][3], int slot) {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k)
+          for (int l = 0; l < 3; ++l) {
+            double s = 0.0;
+            for (int a = 0; a < 3; ++a) {
+              const int idx[4] = {i, j, k, l};
+              int src_idx[4] = {i, j, k, l};
+              src_idx[slot] = a;
+              s += R[idx[slot]][a] * src[src_idx[0]][src_idx[1]][src_idx[2]][src_idx[3]];
+            }
+            dst[i][j][k][l] = s;
+          }
+  };
+  contract(c0, t1, 0);
+  contract(t1, t2, 1);
+  contract(t2, t1, 2);
+  contract(t1, t2, 3);
+  const double w[6] = {1, 1, 1, std::sqrt(2.0), std::sqrt(2.0), std::sqrt(2.0)};
+  std::vector<double> Cm(36);
+  for (int a = 0; a < 6; ++a)
+    for (int b = 0; b < 6; ++b)
+      Cm[a * 6 + b] = w[a] * w[b] * t2[kPairs[a][0]][kPairs[a][1]][kPairs[b][0]][kPairs[b][1]];
+  std::vector<double> Sm = Cm;
+  if (!invert(Sm, 6)) return false;
+  for (int i = 0; i < 36; ++i) { out[GT_C + i] = Cm[i]; out[GT_S + i] = Sm[i]; }
+  for (int a = 0; a < 12; ++a) {
+    double s0[3] = {kSlipS[a][0], kSlipS[a][1], kSlipS[a][2]};
+    double n0[3] = {kSlipN[a][0], kSlipN[a][1], kSlipN[a][2]};
+    normalize3(s0);
+    normalize3(n0);
+    double s[3], n[3];
+    for (int i = 0; i < 3; ++i) {
+      s[i] = R[i][0] * s0[0] + R[i][1] * s0[1] + R[i][2] * s0[2];
+      n[i] = R[i][0] * n0[0] + R[i][1] * n0[1] + R[i][2] * n0[2];
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) out[GT_SN + a * 9 + i * 3 + j] = s[i] * n[j];
+    for (int b = 0; b < 6; ++b) {
+      const int i = kPairs[b][0], j = kPairs[b][1];
+      out[GT_P + a * 6 + b] = w[b] * 0.5 * (s[i] * n[j] + s[j] * n[i]);
+    }
+  }
+  for (int i = 0; i < 9; ++i) out[GT_R + i] = R[i / 3][i % 3];
+  return true;
+}
+
+// Q = (A A^T)^-1 for the 9 x 18 crystal-frame GND basis (12 edge: s (x) (s x n),
+// 6 screw: d (x) d), row-major vec.
+bool gnd_q(double* Q) {
+  std::vector<double> A(9 * 18, 0.0);
+  for (int a = 0; a < 12; ++a) {
+    double s[3] = {kSlipS[a][0], kSlipS[a][1], kSlipS[a][2]};
+    double n[3] = {kSlipN[a][0], kSlipN[a][1], kSlipN[a][2]};
+    normalize3(s);
+    normalize3(n);
+    const double t[3] = {s[1] * n[2] - s[2] * n[1], s[2] * n[0] - s[0] * n[2], s[0] * n[1] - s[1] * n[0]};
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) A[(i * 3 + j) * 18 + a] = s[i] * t[j];
+  }
+  for (int b = 0; b < 6; ++b) {
+    double d[3] = {kScrew[b][0], kScrew[b][1], kScrew[b][2]};
+    normalize3(d);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) A[(i * 3 + j) * 18 + 12 + b] = d[i] * d[j];
+  }
+  std::vector<double> M(81, 0.0);
+  for (int i = 0; i < 9; ++i)
+    for (int j = 0; j < 9; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 18; ++k) s += A[i * 18 + k] * A[j * 18 + k];
+      M[i * 9 + j] = s;
+    }
+  if (!invert(M, 9)) return false;
+  for (int i = 0; i < 81; ++i) Q[i] = M[i];
+  return true;
+}
+
+}  // namespace
+
+// ---- handle ------------------------------------------------------------------------
+struct rve_s {
+  rve_desc d;
+  Grid g;
+  Plans pl;
+  hipStream_t st;
+  bool f64;               // spectral precision
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  // state (FP64)
+  double *eps, *eps_t, *eps_prev, *deps, *sig, *sig_t, *epsp, *beta, *gslip, *rho_ssd, *rho_gnd,
+      *wp, *gs, *H, *wcrit, *trig, *phi, *phi_t, *phi_prev, *S, *wep;
+  int* grain;
+  double* gtab;
+  double* Q81;
+  void* gK;               // 21 N reals (R)
+  void* spec;             // 9 NH complex (R): operator work and GND scratch
+  void* cg[6];            // x, r, z, p, q, b : 3 NH complex each
+  double* rbuf;           // 9 N doubles: phase-field vectors / Nye tensor
+  double* partial;        // reduction partials
+  double* scal;           // device scalars
+  int* failc;
+  double* hs = nullptr;   // pinned host scalars
+  bool micro = false;
+  int n_grains = 0;
+};
+
+namespace {
+
+enum { SC_K = 0,        // 28 constitutive sums (21 gK, g w, 6 g sigma)
+       SC_KBAR = 32,    // 21 mean tangent
+       SC_RZ0 = 56, SC_RZ1 = 57, SC_PQ = 58, SC_RR = 59, SC_BB = 60,
+       SC_MISC = 64,    // generic reduce outputs (16)
+       SC_N = 96 };
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Bump allocation of every buffer; with h->base == nullptr only the size is summed.
+void layout(rve_s* h) {
+  const long long N = h->g.nvox, NH = h->g.nspec;
+  const size_t csz = h->f64 ? 16 : 8, rsz = h->f64 ? 8 : 4;
+  h->used = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = h->base ? (void*)(h->base + h->used) : nullptr;
+    h->used += align_up(bytes);
+    return p;
+  };
+  auto fd = [&](long long cnt) { return (double*)take((size_t)cnt * 8); };
+  h->eps = fd(6 * N); h->eps_t = fd(6 * N); h->eps_prev = fd(6 * N); h->deps = fd(6 * N);
+  h->sig = fd(6 * N); h->sig_t = fd(6 * N); h->epsp = fd(6 * N); h->beta = fd(9 * N);
+  h->gslip = fd(N); h->rho_ssd = fd(N); h->rho_gnd = fd(N); h->wp = fd(N); h->gs = fd(N);
+  h->H = fd(N); h->wcrit = fd(N); h->trig = fd(N); h->phi = fd(N); h->phi_t = fd(N);
+  h->phi_prev = fd(N); h->S = fd(N); h->wep = fd(N);
+  h->grain = (int*)take((size_t)N * 4);
+  h->gtab = fd((long long)h->d.max_grains * GT_STRIDE);
+  h->Q81 = fd(81);
+  h->gK = take((size_t)21 * N * rsz);
+  h->spec = take((size_t)9 * NH * csz);
+  for (int i = 0; i < 6; ++i) h->cg[i] = take((size_t)3 * NH * csz);
+  h->rbuf = fd(9 * N);
+  h->partial = fd((long long)kMaxRedBlocks * 32);
+  h->scal = fd(SC_N);
+  h->failc = (int*)take(256);
+  for (int a = 0; a < 3; ++a) {
+    h->pl.tw64[a] = take((size_t)h->pl.ax[a].n * 16);
+    h->pl.tw32[a] = take((size_t)h->pl.ax[a].n * 8);
+  }
+}
+
+int validate(const rve_desc* d) {
+  if (!d) return fail(RVE_E_ARG, "null description");
+  for (int a = 0; a < 3; ++a)
+    if (!smooth23(d->n[a])) return fail(RVE_E_ARG, "grid sizes must be 2^p 3^q in [1, 512]");
+  if (d->precision != RVE_FP64 && d->precision != RVE_MIXED)
+    return fail(RVE_E_ARG, "precision must be RVE_FP64 or RVE_MIXED");
+  const double pos[] = {d->h, d->C44, d->gdot0, d->n_exp, d->tau_c0, d->rho0, d->burgers, d->ell,
+                        d->Gc, d->k_res, d->tol_stag, d->tol_newton, d->tol_lin};
+  for (double v : pos)
+    if (!(v > 0.0) || !std::isfinite(v)) return fail(RVE_E_ARG, "non-positive or non-finite constant");
+  const double nonneg[] = {d->h_lin, d->lambda_ssd, d->xi_store, d->G_crit, d->ell_fp};
+  for (double v : nonneg)
+    if (!(v >= 0.0) || !std::isfinite(v)) return fail(RVE_E_ARG, "negative or non-finite constant");
+  if (!(d->C11 > d->C12) || !(d->C11 + 2 * d->C12 > 0))
+    return fail(RVE_E_ARG, "elastic constants are not positive definite");
+  if (d->max_stag < 1 || d->max_newton < 1 || d->max_krylov < 1 || d->max_grains < 1)
+    return fail(RVE_E_ARG, "iteration limits and max_grains must be >= 1");
+  return RVE_OK;
+}
+
+void init_grid(rve_s* h) {
+  Grid& g = h->g;
+  g.n1 = h->d.n[0]; g.n2 = h->d.n[1]; g.n3 = h->d.n[2];
+  g.n1h = g.n1 / 2 + 1;
+  g.nvox = (long long)g.n1 * g.n2 * g.n3;
+  g.nspec = (long long)g.n1h * g.n2 * g.n3;
+  g.h = h->d.h;
+  g.L1 = g.n1 * g.h; g.L2 = g.n2 * g.h; g.L3 = g.n3 * g.h;
+  h->pl.g = g;
+  for (int a = 0; a < 3; ++a) make_axis_plan(h->d.n[a], &h->pl.ax[a]);
+  h->f64 = (h->d.precision == RVE_FP64);
+}
+
+// ---- small helpers on the handle ---------------------------------------------------
+struct Ctx {
+  rve_s* h;
+  hipStream_t st;
+  long long N, NH;
+};
+
+int sync_read(rve_s* h, int first, int count) {
+  HIPCHK(hipMemcpyAsync(h->hs + first, h->scal + first, count * sizeof(double),
+                        hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  HIPCHK(hipGetLastError());
+  return RVE_OK;
+}
+
+template <typename R>
+struct Ops {
+  typedef cplx<R> C;
+  rve_s* h;
+  hipStream_t st;
+  long long N, NH;
+  C* W;            // 6-component operator work (first 6 comps of spec)
+  C* v(int i) { return (C*)h->cg[i]; }
+  R* gK() { return (R*)h->gK; }
+
+  explicit Ops(rve_s* hh) : h(hh), st(hh->st), N(hh->g.nvox), NH(hh->g.nspec) { W = (C*)h->spec; }
+
+  // forward 3-D real FFT of ncomp real comps (stride in_cs) into spec comps
+  void fwd(const void* in, bool in64, long long in_cs, int ncomp, C* out, const double* phi = nullptr) {
+    launch_x_r2c<R>(h->pl, in, in64, in_cs, phi, h->d.k_res, out, NH, ncomp, st);
+    launch_fft_yz<R>(h->pl, out, NH, ncomp, 1, false, st);
+    launch_fft_yz<R>(h->pl, out, NH, ncomp, 2, false, st);
+  }
+  // inverse 3-D FFT (in place on spec comps, then rows to real out)
+  void inv(C* in, int ncomp, void* out, bool out64, long long out_cs, double scale, int acc) {
+    launch_fft_yz<R>(h->pl, in, NH, ncomp, 2, true, st);
+    launch_fft_yz<R>(h->pl, in, NH, ncomp, 1, true, st);
+    launch_x_c2r<R>(h->pl, in, NH, out, out64, out_cs, ncomp, scale, acc, st);
+  }
+  // q = B p = - i xi~ . F{ gK : F^-1{ sym(i xi~ (x) p) } }
+  void matvec(const C* p, C* q) {
+    launch_sym_grad<R>(h->pl, p, NH, W, NH, st);
+    launch_fft_yz<R>(h->pl, W, NH, 6, 2, true, st);
+    launch_fft_yz<R>(h->pl, W, NH, 6, 1, true, st);
+    launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st);
+    launch_fft_yz<R>(h->pl, W, NH, 6, 1, false, st);
+    launch_fft_yz<R>(h->pl, W, NH, 6, 2, false, st);
+    launch_div<R>(h->pl, W, NH, q, NH, -1.0, st);
+  }
+  // mean tangent from the constitutive sums
+  void kbar() { launch_rscale(21, h->scal + SC_K, 1.0 / (double)N, h->scal + SC_KBAR, st); }
+
+  int constitutive(const double* deps, double t, const double* phi) {
+    Material m = mat(0.0);
+    m.dt = cur_dt;
+    launch_constitutive<R>(N, h->eps, deps, t, h->epsp, h->gslip, h->grain, h->gtab, h->sig, phi,
+                           gK(), m, h->partial, h->failc, st);
+    launch_reduce(h->partial, voxel_grid(N), RED_CONST, 0, h->scal + SC_K, st);
+    return RVE_OK;
+  }
+  double cur_dt = 0.0;
+  Material mat(double dt) const {
+    Material m;
+    m.dt = dt; m.gdot0 = h->d.gdot0; m.nexp = h->d.n_exp; m.kres = h->d.k_res;
+    m.h_lin = h->d.h_lin; m.lambda_ssd = h->d.lambda_ssd; m.xi_store = h->d.xi_store;
+    m.G_crit = h->d.G_crit; m.ell = h->d.ell; m.Gc = h->d.Gc; m.burgers = h->d.burgers;
+    return m;
+  }
+
+  // Preconditioned CG on B du = c (c in cg[5]); solution in cg[0].
+  int pcg(int& iters) {
+    C *x = v(0), *r = v(1), *z = v(2), *p = v(3), *q = v(4), *b = v(5);
+    const size_t bytes = (size_t)3 * NH * sizeof(C);
+    launch_zero(x, bytes, st);
+    HIPCHK(hipMemcpyAsync(r, b, bytes, hipMemcpyDeviceToDevice, st));
+    int nb = launch_sdot<R>(h->pl, b, b, NH, 3, h->partial, st);
+    launch_reduce(h->partial, nb, 1, 0, h->scal + SC_BB, st);
+    nb = launch_precond<R>(h->pl, r, z, NH, h->scal + SC_KBAR, h->partial, st);
+    launch_reduce(h->partial, nb, 1, 0, h->scal + SC_RZ0, st);
+    HIPCHK(hipMemcpyAsync(p, z, bytes, hipMemcpyDeviceToDevice, st));
+    int rc = sync_read(h, SC_BB, 1);
+    if (rc) return rc;
+    const double bb = h->hs[SC_BB];
+    iters = 0;
+    if (!(bb > 0.0)) return std::isfinite(bb) ? RVE_OK : fail(RVE_E_NOCONV, "non-finite residual");
+    const double tol2 = h->d.tol_lin * h->d.tol_lin * bb;
+    int cur = SC_RZ0, nxt = SC_RZ1;
+    for (int k = 0; k < h->d.max_krylov; ++k) {
+      matvec(p, q);
+      nb = launch_sdot<R>(h->pl, p, q, NH, 3, h->partial, st);
+      launch_reduce(h->partial, nb, 1, 0, h->scal + SC_PQ, st);
+      nb = launch_cg_xr<R>(h->pl, x, r, p, q, NH, h->scal, cur, SC_PQ, h->partial, st);
+      launch_reduce(h->partial, nb, 1, 0, h->scal + SC_RR, st);
+      rc = sync_read(h, SC_PQ, 2);
+      if (rc) return rc;
+      iters = k + 1;
+      const double pq = h->hs[SC_PQ], rr = h->hs[SC_RR];
+      if (!(pq > 0.0) || !std::isfinite(rr)) return fail(RVE_E_NOCONV, "momentum CG breakdown");
+      if (rr <= tol2) return RVE_OK;
+      nb = launch_precond<R>(h->pl, r, z, NH, h->scal + SC_KBAR, h->partial, st);
+      launch_reduce(h->partial, nb, 1, 0, h->scal + nxt, st);
+      launch_cg_p<R>(h->pl, p, z, NH, h->scal, nxt, cur, st);
+      std::swap(cur, nxt);
+    }
+    return fail(RVE_E_NOCONV, "momentum Krylov solver reached max_krylov");
+  }
+};
+
+template <typename R>
+int run_increment(rve_s* h, const double de[6], double dt, rve_stats* out) {
+  Ops<R> o(h);
+  o.cur_dt = dt;
+  hipStream_t st = h->st;
+  const long long N = h->g.nvox;
+  const double invN = 1.0 / (double)N;
+  rve_stats s;
+  std::memset(&s, 0, sizeof(s));
+  const double t0 = now_ms();
+  int rc;
+  // transactional copies of the state at time t
+  HIPCHK(hipMemcpyAsync(h->eps_t, h->eps, 6 * N * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->sig_t, h->sig, 6 * N * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->phi_t, h->phi, N * 8, hipMemcpyDeviceToDevice, st));
+  launch_zero(h->failc, sizeof(int), st);
+  // eps_0 = eps_t + d eps_bar (uniform)
+  launch_add_uniform(N, h->eps, de, st);
+  HIPCHK(hipMemcpyAsync(h->eps_prev, h->eps, 6 * N * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->phi_prev, h->phi_t, N * 8, hipMemcpyDeviceToDevice, st));
+
+  bool converged = false;
+  for (int it = 0; it < h->d.max_stag && !converged; ++it) {
+    s.stag_iters = it + 1;
+    // ---- momentum balance at phi_prev (Newton + PCG, line search on the energy) ----
+    double tc = now_ms();
+    o.constitutive(nullptr, 0.0, h->phi_prev);
+    if ((rc = sync_read(h, SC_K, 28))) return rc;
+    s.ms_constitutive += now_ms() - tc;
+    double Pi = h->hs[SC_K + 21] * invN;
+    bool newton_ok = false;
+    for (int nit = 0; nit < h->d.max_newton; ++nit) {
+      s.newton_iters++;
+      double tk = now_ms();
+      o.kbar();
+      // c = i xi~ . F{ g sigma }
+      o.fwd(h->sig, true, N, 6, o.W, h->phi_prev);
+      launch_div<R>(h->pl, o.W, o.NH, o.v(5), o.NH, 1.0, st);
+      int kit = 0;
+      rc = o.pcg(kit);
+      s.krylov_iters += kit;
+      if (rc) { s.ms_mech_krylov += now_ms() - tk; goto fail_out; }
+      // deps = F^-1{ sym(i xi~ (x) du) }
+      launch_sym_grad<R>(h->pl, o.v(0), o.NH, o.W, o.NH, st);
+      o.inv(o.W, 6, h->deps, true, N, invN, 0);
+      launch_slope(N, h->sig, h->deps, h->phi_prev, h->d.k_res, h->partial, st);
+      launch_reduce(h->partial, voxel_grid(N), 1, 0, h->scal + SC_MISC, st);
+      if ((rc = sync_read(h, SC_MISC, 1))) return rc;
+      const double slope = h->hs[SC_MISC] * invN;
+      s.ms_mech_krylov += now_ms() - tk;
+      // backtracking on the incremental energy
+      tc = now_ms();
+      double t = 1.0, Pit = 0.0;
+      bool acc = false;
+      for (int ls = 0; ls < 40; ++ls) {
+        o.constitutive(h->deps, t, h->phi_prev);
+        if ((rc = sync_read(h, SC_K, 28))) return rc;
+        Pit = h->hs[SC_K + 21] * invN;
+        if (Pit - Pi <= 1e-4 * t * slope + 1e-13 * std::fabs(Pi)) { acc = true; break; }
+        t *= 0.5;
+        s.ls_cuts++;
+      }
+      s.ms_constitutive += now_ms() - tc;
+      if (!acc) { rc = fail(RVE_E_NOCONV, "Newton line search failed"); goto fail_out; }
+      Pi = Pit;
+      launch_eps_update(N, h->eps, h->deps, t, h->eps_t, h->partial, st);
+      launch_reduce(h->partial, voxel_grid(N), 2, 1, h->scal + SC_MISC, st);
+      if ((rc = sync_read(h, SC_MISC, 2))) return rc;
+      const double num = h->hs[SC_MISC], den = h->hs[SC_MISC + 1];
+      if (num <= h->d.tol_newton * den || num == 0.0) { newton_ok = true; break; }
+    }
+    if (!newton_ok) { rc = fail(RVE_E_NOCONV, "Newton reached max_newton"); goto fail_out; }
+    // ---- phase field at eps_i ----
+    {
+      double tp = now_ms();
+      Material m = o.mat(dt);
+      launch_source(N, h->eps, h->sig, h->epsp, h->gslip, h->grain, h->gtab, h->wp, h->trig,
+                    h->wcrit, h->S, h->wep, m, h->partial, st);
+      launch_reduce(h->partial, voxel_grid(N), RED_SOURCE, 0, h->scal + SC_MISC, st);
+      if ((rc = sync_read(h, SC_MISC, 2))) return rc;
+      const double sumS = h->hs[SC_MISC], sumS2 = h->hs[SC_MISC + 1];
+      double* X = h->rbuf;
+      double *Rr = h->rbuf + N, *Z = h->rbuf + 2 * N, *P = h->rbuf + 3 * N, *Wv = h->rbuf + 4 * N;
+      launch_zero(X, N * 8, st);
+      if (sumS > 0.0) {
+        typedef cplx<R> C;
+        C* W1 = (C*)h->spec;
+        const double bb = 4.0 * sumS2;
+        const double tol2 = h->d.tol_lin * h->d.tol_lin * bb;
+        launch_rscale(N, h->S, 2.0, Rr, st);
+        auto prec = [&](const double* in, double* outp) {
+          launch_x_r2c<R>(h->pl, in, true, N, nullptr, 0.0, W1, o.NH, 1, st);
+          launch_fft_yz<R>(h->pl, W1, o.NH, 1, 1, false, st);
+          launch_fft_yz<R>(h->pl, W1, o.NH, 1, 2, false, st);
+          launch_pf_scale<R>(h->pl, W1, h->d.ell, invN, st);
+          launch_fft_yz<R>(h->pl, W1, o.NH, 1, 2, true, st);
+          launch_fft_yz<R>(h->pl, W1, o.NH, 1, 1, true, st);
+          launch_x_c2r<R>(h->pl, W1, o.NH, outp, true, N, 1, 1.0, 0, st);
+        };
+        prec(Rr, Z);
+        int nb = launch_rdot(N, Rr, Z, h->partial, st);
+        launch_reduce(h->partial, nb, 1, 0, h->scal + SC_RZ0, st);
+        HIPCHK(hipMemcpyAsync(P, Z, N * 8, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(Wv, Rr, N * 8, hipMemcpyDeviceToDevice, st));
+        int cur = SC_RZ0, nxt = SC_RZ1;
+        bool ok = false;
+        for (int k = 0; k < h->d.max_krylov; ++k) {
+          nb = launch_pf_pq(N, P, Wv, h->S, h->partial, st);
+          launch_reduce(h->partial, nb, 1, 0, h->scal + SC_PQ, st);
+          nb = launch_pf_xr(N, X, Rr, P, Wv, h->S, h->scal, cur, SC_PQ, h->partial, st);
+          launch_reduce(h->partial, nb, 1, 0, h->scal + SC_RR, st);
+          if ((rc = sync_read(h, SC_PQ, 2))) return rc;
+          s.pf_iters++;
+          if (!(h->hs[SC_PQ] > 0.0) || !std::isfinite(h->hs[SC_RR])) break;
+          if (h->hs[SC_RR] <= tol2) { ok = true; break; }
+          prec(Rr, Z);
+          nb = launch_rdot(N, Rr, Z, h->partial, st);
+          launch_reduce(h->partial, nb, 1, 0, h->scal + nxt, st);
+          launch_pf_pw(N, P, Wv, Z, Rr, h->scal, nxt, cur, st);
+          std::swap(cur, nxt);
+        }
+        if (!ok) {
+          s.ms_phase_field += now_ms() - tp;
+          rc = fail(RVE_E_NOCONV, "phase-field Krylov solver did not converge");
+          goto fail_out;
+        }
+      }
+      launch_clamp(N, X, h->phi_t, h->phi, st);
+      launch_stag_norms(N, h->eps, h->eps_prev, h->eps_t, h->phi, h->phi_prev, h->phi_t,
+                        h->partial, st);
+      launch_reduce(h->partial, voxel_grid(N), 4, 1, h->scal + SC_MISC, st);
+      if ((rc = sync_read(h, SC_MISC, 4))) return rc;
+      auto ratio = [](double a, double b) { return a == 0.0 ? 0.0 : (b > 0.0 ? a / b : INFINITY); };
+      const double re = ratio(h->hs[SC_MISC], h->hs[SC_MISC + 1]);
+      const double rp = ratio(h->hs[SC_MISC + 2], h->hs[SC_MISC + 3]);
+      HIPCHK(hipMemcpyAsync(h->eps_prev, h->eps, 6 * N * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(h->phi_prev, h->phi, N * 8, hipMemcpyDeviceToDevice, st));
+      s.ms_phase_field += now_ms() - tp;
+      if (re <= h->d.tol_stag && rp <= h->d.tol_stag) converged = true;
+    }
+  }
+  if (!converged) { rc = fail(RVE_E_NOCONV, "alternating minimisation reached max_stag"); goto fail_out; }
+  {
+    int nfail = 0;
+    HIPCHK(hipMemcpyAsync(&nfail, h->failc, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    s.rm_failures = nfail;
+    if (nfail > 0) { rc = fail(RVE_E_NOCONV, "return mapping did not converge"); goto fail_out; }
+  }
+  {
+    // ---- commit ----
+    double tcm = now_ms();
+    Material m = o.mat(dt);
+    launch_commit(N, h->sig, h->gslip, h->epsp, h->beta, h->rho_ssd, h->rho_gnd, h->wp, h->gs, h->H,
+                  h->wcrit, h->trig, h->wep, h->phi, h->eps, h->grain, h->gtab, m, h->partial, st);
+    const int nb = voxel_grid(N);
+    launch_reduce(h->partial, nb, 13, 0, h->scal + SC_MISC, st);
+    launch_reduce(h->partial + 13LL * nb, nb, 2, 1, h->scal + SC_MISC + 13, st);
+    // GND density from the committed plastic distortion (used by the next increment)
+    typedef cplx<R> C;
+    C* B9 = (C*)h->spec;
+    o.fwd(h->beta, true, N, 9, B9);
+    launch_curl_reg<R>(h->pl, B9, o.NH, h->d.ell_fp, invN, st);
+    o.inv(B9, 9, h->rbuf, true, N, 1.0, 0);
+    launch_gnd(N, h->rbuf, h->grain, h->gtab, h->Q81, h->d.burgers, h->rho_gnd, st);
+    if ((rc = sync_read(h, SC_MISC, 15))) return rc;
+    for (int c = 0; c < 6; ++c) {
+      s.macro_stress[c] = h->hs[SC_MISC + c] * invN;
+      s.macro_strain[c] = h->hs[SC_MISC + 6 + c] * invN;
+    }
+    s.n_triggered = h->hs[SC_MISC + 12];
+    s.max_phi = h->hs[SC_MISC + 13];
+    s.max_phi_slip = h->hs[SC_MISC + 14];
+    s.ms_commit = now_ms() - tcm;
+  }
+  s.ms_total = now_ms() - t0;
+  if (out) *out = s;
+  return RVE_OK;
+
+fail_out:
+  // roll back to time t
+  {
+    std::string msg = g_err;
+    (void)hipMemcpyAsync(h->eps, h->eps_t, 6 * N * 8, hipMemcpyDeviceToDevice, st);
+    (void)hipMemcpyAsync(h->sig, h->sig_t, 6 * N * 8, hipMemcpyDeviceToDevice, st);
+    (void)hipMemcpyAsync(h->phi, h->phi_t, N * 8, hipMemcpyDeviceToDevice, st);
+    (void)hipStreamSynchronize(st);
+    s.ms_total = now_ms() - t0;
+    if (out) *out = s;
+    g_err = msg;
+  }
+  return rc;
+}
+
+}  // namespace
+
+// ---- C ABI -------------------------------------------------------------------------
+extern "C" {
+
+const char* rve_last_error(void) { return g_err.c_str(); }
+
+size_t rve_footprint_bytes(const rve_desc* d) {
+  if (validate(d) != RVE_OK) return 0;
+  rve_s tmp;
+  tmp.d = *d;
+  init_grid(&tmp);
+  tmp.base = nullptr;
+  layout(&tmp);
+  return tmp.used;
+}
+
+int rve_create(const rve_desc* d, void* dev_arena, size_t arena_bytes, void* hip_stream,
+               rve_s** out) {
+  if (!out) return fail(RVE_E_ARG, "null output handle");
+  *out = nullptr;
+  int rc = validate(d);
+  if (rc) return rc;
+  rve_s* h = new rve_s();
+  h->d = *d;
+  init_grid(h);
+  h->base = nullptr;
+  layout(h);
+  if (!dev_arena) { delete h; return fail(RVE_E_ARG, "null arena"); }
+  if (arena_bytes < h->used) {
+    delete h;
+    return fail(RVE_E_NOMEM, "arena smaller than rve_footprint_bytes");
+  }
+  h->base = (char*)dev_arena;
+  h->cap = arena_bytes;
+  layout(h);
+  h->st = (hipStream_t)hip_stream;
+  if (hipHostMalloc((void**)&h->hs, SC_N * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    delete h;
+    return fail(RVE_E_DEVICE, "hipHostMalloc failed");
+  }
+  // twiddle tables, exp(-2 pi i k / n), computed in FP64
+  for (int a = 0; a < 3; ++a) {
+    const int n = h->pl.ax[a].n;
+    std::vector<double> t64(2 * n);
+    std::vector<float> t32(2 * n);
+    for (int k = 0; k < n; ++k) {
+      // reduce the angle to the first octant-friendly form k/n in [0, 1)
+      const double ang = -2.0 * M_PI * (double)k / (double)n;
+      t64[2 * k] = std::cos(ang);
+      t64[2 * k + 1] = std::sin(ang);
+      t32[2 * k] = (float)t64[2 * k];
+      t32[2 * k + 1] = (float)t64[2 * k + 1];
+    }
+    if (hipMemcpyAsync((void*)h->pl.tw64[a], t64.data(), n * 16, hipMemcpyHostToDevice, h->st) !=
+            hipSuccess ||
+        hipMemcpyAsync((void*)h->pl.tw32[a], t32.data(), n * 8, hipMemcpyHostToDevice, h->st) !=
+            hipSuccess) {
+      (void)hipHostFree(h->hs);
+      delete h;
+      return fail(RVE_E_DEVICE, "twiddle upload failed");
+    }
+  }
+  double Q[81];
+  gnd_q(Q);
+  if (hipMemcpyAsync(h->Q81, Q, 81 * 8, hipMemcpyHostToDevice, h->st) != hipSuccess ||
+      hipStreamSynchronize(h->st) != hipSuccess) {
+    (void)hipHostFree(h->hs);
+    delete h;
+    return fail(RVE_E_DEVICE, "table upload failed");
+  }
+  *out = h;
+  return RVE_OK;
+}
+
+int rve_set_microstructure(rve_s* h, const int32_t* grain, int32_t n_grains, const double* quat,
+                           const double* tau0, const double* phi0) {
+  if (!h || !grain || !quat) return fail(RVE_E_ARG, "null argument");
+  if (n_grains < 1 || n_grains > h->d.max_grains) return fail(RVE_E_ARG, "n_grains out of range");
+  const long long N = h->g.nvox;
+  for (long long v = 0; v < N; ++v)
+    if (grain[v] < 0 || grain[v] >= n_grains) return fail(RVE_E_ARG, "grain id out of range");
+  std::vector<double> tab((size_t)n_grains * GT_STRIDE);
+  for (int gi = 0; gi < n_grains; ++gi) {
+    const double* q = quat + 4 * gi;
+    const double nq = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    if (!std::isfinite(nq) || std::fabs(nq - 1.0) > 1e-6) return fail(RVE_E_ARG, "quaternion not unit");
+    if (tau0 && !(tau0[gi] > 0.0 && std::isfinite(tau0[gi]))) return fail(RVE_E_ARG, "bad tau_c0");
+    if (!grain_table(q, h->d.C11, h->d.C12, h->d.C44, tab.data() + (size_t)gi * GT_STRIDE))
+      return fail(RVE_E_ARG, "singular stiffness");
+  }
+  std::vector<double> g((size_t)N), ph((size_t)N, 0.0), rho((size_t)N, h->d.rho0);
+  for (long long v = 0; v < N; ++v) {
+    if (phi0) {
+      if (!(phi0[v] >= 0.0 && phi0[v] <= 1.0)) return fail(RVE_E_ARG, "phi0 outside [0,1]");
+      ph[v] = phi0[v];
+    }
+    g[v] = (ph[v] >= 1.0) ? INFINITY : (tau0 ? tau0[grain[v]] : h->d.tau_c0);
+  }
+  hipStream_t st = h->st;
+  HIPCHK(hipMemcpyAsync(h->gtab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->grain, grain, N * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->gslip, g.data(), N * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->phi, ph.data(), N * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->rho_ssd, rho.data(), N * 8, hipMemcpyHostToDevice, st));
+  double* zero6[] = {h->eps, h->sig, h->epsp};
+  for (double* p : zero6) launch_zero(p, 6 * N * 8, st);
+  launch_zero(h->beta, 9 * N * 8, st);
+  double* zero1[] = {h->rho_gnd, h->wp, h->gs, h->H, h->wcrit, h->trig, h->S, h->wep};
+  for (double* p : zero1) launch_zero(p, N * 8, st);
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  h->micro = true;
+  h->n_grains = n_grains;
+  return RVE_OK;
+}
+
+int rve_step_increment(rve_s* h, const double deps[6], double dt, rve_stats* st) {
+  if (!h || !deps) return fail(RVE_E_ARG, "null argument");
+  if (!h->micro) return fail(RVE_E_STATE, "microstructure not set");
+  for (int c = 0; c < 6; ++c)
+    if (!std::isfinite(deps[c])) return fail(RVE_E_ARG, "non-finite strain increment");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RVE_E_ARG, "dt must be positive and finite");
+  g_err.clear();
+  return h->f64 ? run_increment<double>(h, deps, dt, st) : run_increment<float>(h, deps, dt, st);
+}
+
+size_t rve_fields_count(const rve_s* h, uint32_t mask) {
+  if (!h) return 0;
+  const uint32_t six = RVE_F_STRAIN | RVE_F_STRESS | RVE_F_STRESS_EFF | RVE_F_EPS_P;
+  size_t c = 0;
+  for (int b = 0; b < 14; ++b) {
+    const uint32_t bit = 1u << b;
+    if (!(mask & bit)) continue;
+    c += (bit & six) ? 6 : (bit == RVE_F_BETA_P ? 9 : 1);
+  }
+  if (mask >> 14) return 0;
+  return c * (size_t)h->g.nvox;
+}
+
+int rve_fields(rve_s* h, uint32_t mask, double* out, size_t n) {
+  if (!h || !out) return fail(RVE_E_ARG, "null argument");
+  if (!h->micro) return fail(RVE_E_STATE, "microstructure not set");
+  if (mask >> 14) return fail(RVE_E_ARG, "unknown field bit");
+  const size_t need = rve_fields_count(h, mask);
+  if (n < need) return fail(RVE_E_ARG, "output buffer too small");
+  const long long N = h->g.nvox;
+  hipStream_t st = h->st;
+  double* o = out;
+  auto cp = [&](const double* src, int nc) -> int {
+    HIPCHK(hipMemcpyAsync(o, src, (size_t)nc * N * 8, hipMemcpyDeviceToHost, st));
+    o += (size_t)nc * N;
+    return RVE_OK;
+  };
+  int rc = RVE_OK;
+  std::vector<double> phi;
+  for (int b = 0; b < 14 && rc == RVE_OK; ++b) {
+    const uint32_t bit = 1u << b;
+    if (!(mask & bit)) continue;
+    switch (bit) {
+      case RVE_F_STRAIN: rc = cp(h->eps, 6); break;
+      case RVE_F_STRESS: {
+        double* dst = o;
+        rc = cp(h->sig, 6);
+        if (rc) break;
+        phi.resize((size_t)N);
+        HIPCHK(hipMemcpyAsync(phi.data(), h->phi, N * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int c = 0; c < 6; ++c)
+          for (long long v = 0; v < N; ++v) {
+            const double q = 1.0 - phi[v];
+            dst[c * N + v] *= q * q + h->d.k_res;
+          }
+        break;
+      }
+      case RVE_F_STRESS_EFF: rc = cp(h->sig, 6); break;
+      case RVE_F_DAMAGE: rc = cp(h->phi, 1); break;
+      case RVE_F_GS: rc = cp(h->gs, 1); break;
+      case RVE_F_RHO_SSD: rc = cp(h->rho_ssd, 1); break;
+      case RVE_F_RHO_GND: rc = cp(h->rho_gnd, 1); break;
+      case RVE_F_WP: rc = cp(h->wp, 1); break;
+      case RVE_F_H: rc = cp(h->H, 1); break;
+      case RVE_F_WCRIT: rc = cp(h->wcrit, 1); break;
+      case RVE_F_TRIG: rc = cp(h->trig, 1); break;
+      case RVE_F_EPS_P: rc = cp(h->epsp, 6); break;
+      case RVE_F_SLIP_RES: rc = cp(h->gslip, 1); break;
+      case RVE_F_BETA_P: rc = cp(h->beta, 9); break;
+    }
+  }
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(st));
+  return RVE_OK;
+}
+
+int rve_destroy(rve_s* h) {
+  if (!h) return RVE_OK;
+  if (h->st) (void)hipStreamSynchronize(h->st);
+  else (void)hipDeviceSynchronize();
+  if (h->hs) (void)hipHostFree(h->hs);
+  delete h;
+  return RVE_OK;
+}
+
+}  // extern "C"
+
+// ---- diagnostics -------------------------------------------------------------------
+template <typename R>
+static int diag_fft(rve_s* h, int ncomp, const double* in, double* out, bool forward) {
+  typedef cplx<R> C;
+  Ops<R> o(h);
+  const long long N = h->g.nvox, NH = h->g.nspec;
+  C* W = (C*)h->spec;
+  hipStream_t st = h->st;
+  if (forward) {
+    HIPCHK(hipMemcpyAsync(h->rbuf, in, (size_t)ncomp * N * 8, hipMemcpyHostToDevice, st));
+    o.fwd(h->rbuf, true, N, ncomp, W);
+    std::vector<C> tmp((size_t)ncomp * NH);
+    HIPCHK(hipMemcpyAsync(tmp.data(), W, tmp.size() * sizeof(C), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (size_t i = 0; i < tmp.size(); ++i) { out[2 * i] = tmp[i].x; out[2 * i + 1] = tmp[i].y; }
+  } else {
+    std::vector<C> tmp((size_t)ncomp * NH);
+    for (size_t i = 0; i < tmp.size(); ++i) { tmp[i].x = (R)in[2 * i]; tmp[i].y = (R)in[2 * i + 1]; }
+    HIPCHK(hipMemcpyAsync(W, tmp.data(), tmp.size() * sizeof(C), hipMemcpyHostToDevice, st));
+    o.inv(W, ncomp, h->rbuf, true, N, 1.0 / (double)N, 0);
+    HIPCHK(hipMemcpyAsync(out, h->rbuf, (size_t)ncomp * N * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  HIPCHK(hipGetLastError());
+  return RVE_OK;
+}
+
+template <typename R>
+static int diag_const(rve_s* h, const double* eps6, double dt, double* sig_out, double* gk_out) {
+  Ops<R> o(h);
+  o.cur_dt = dt;
+  const long long N = h->g.nvox;
+  hipStream_t st = h->st;
+  // keep the state: eps -> eps_prev, sig -> sig_t (restored below)
+  HIPCHK(hipMemcpyAsync(h->eps_prev, h->eps, 6 * N * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->sig_t, h->sig, 6 * N * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->eps, eps6, 6 * N * 8, hipMemcpyHostToDevice, st));
+  launch_zero(h->failc, sizeof(int), st);
+  o.constitutive(nullptr, 0.0, h->phi);
+  o.kbar();
+  if (sig_out) HIPCHK(hipMemcpyAsync(sig_out, h->sig, 6 * N * 8, hipMemcpyDeviceToHost, st));
+  if (gk_out) {
+    std::vector<R> tmp((size_t)21 * N);
+    HIPCHK(hipMemcpyAsync(tmp.data(), h->gK, tmp.size() * sizeof(R), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (size_t i = 0; i < tmp.size(); ++i) gk_out[i] = (double)tmp[i];
+  }
+  int nfail = 0;
+  HIPCHK(hipMemcpyAsync(&nfail, h->failc, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(h->eps, h->eps_prev, 6 * N * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->sig, h->sig_t, 6 * N * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  if (nfail) return fail(RVE_E_NOCONV, "return mapping did not converge");
+  return RVE_OK;
+}
+
+template <typename R>
+static int diag_op(rve_s* h, const double* u3, double* v3) {
+  typedef cplx<R> C;
+  Ops<R> o(h);
+  const long long N = h->g.nvox, NH = h->g.nspec;
+  hipStream_t st = h->st;
+  HIPCHK(hipMemcpyAsync(h->rbuf, u3, 3 * N * 8, hipMemcpyHostToDevice, st));
+  o.fwd(h->rbuf, true, N, 3, o.v(3));
+  o.matvec(o.v(3), o.v(4));
+  launch_precond<R>(h->pl, o.v(4), o.v(2), NH, h->scal + SC_KBAR, h->partial, st);
+  HIPCHK(hipMemcpyAsync(o.W, o.v(2), 3 * NH * sizeof(C), hipMemcpyDeviceToDevice, st));
+  o.inv(o.W, 3, h->rbuf, true, N, 1.0 / (double)N, 0);
+  HIPCHK(hipMemcpyAsync(v3, h->rbuf, 3 * N * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  return RVE_OK;
+}
+
+extern "C" {
+
+int rve_diag_rfft(rve_s* h, int32_t ncomp, const double* in, double* out) {
+  if (!h || !in || !out || ncomp < 1 || ncomp > 9) return fail(RVE_E_ARG, "bad argument");
+  return h->f64 ? diag_fft<double>(h, ncomp, in, out, true) : diag_fft<float>(h, ncomp, in, out, true);
+}
+
+int rve_diag_irfft(rve_s* h, int32_t ncomp, const double* in, double* out) {
+  if (!h || !in || !out || ncomp < 1 || ncomp > 9) return fail(RVE_E_ARG, "bad argument");
+  return h->f64 ? diag_fft<double>(h, ncomp, in, out, false)
+                : diag_fft<float>(h, ncomp, in, out, false);
+}
+
+int rve_diag_constitutive(rve_s* h, const double* eps6, double dt, double* sig6, double* gk21) {
+  if (!h || !eps6 || !(dt > 0.0)) return fail(RVE_E_ARG, "bad argument");
+  if (!h->micro) return fail(RVE_E_STATE, "microstructure not set");
+  return h->f64 ? diag_const<double>(h, eps6, dt, sig6, gk21)
+                : diag_const<float>(h, eps6, dt, sig6, gk21);
+}
+
+int rve_diag_operator(rve_s* h, const double* u3, double* v3) {
+  if (!h || !u3 || !v3) return fail(RVE_E_ARG, "bad argument");
+  if (!h->micro) return fail(RVE_E_STATE, "microstructure not set");
+  return h->f64 ? diag_op<double>(h, u3, v3) : diag_op<float>(h, u3, v3);
+}
+
+}  // extern "C"
+
+// ---- radix schedule ------------------------------------------------------------------
+namespace rvefft {
+bool make_axis_plan(int n, AxisPlan* out) {
+  AxisPlan p;
+  p.n = n;
+  p.nst = 0;
+  int m = n;
+  while (m % 4 == 0 && p.nst < kMaxStages) { p.radix[p.nst++] = 4; m /= 4; }
+  while (m % 2 == 0 && p.nst < kMaxStages) { p.radix[p.nst++] = 2; m /= 2; }
+  while (m % 3 == 0 && p.nst < kMaxStages) { p.radix[p.nst++] = 3; m /= 3; }
+  for (int i = p.nst; i < kMaxStages; ++i) p.radix[i] = 1;
+  *out = p;
+  return m == 1;
+}
+}  // namespace rvefft

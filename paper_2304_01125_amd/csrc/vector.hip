@@ -1,0 +1,243 @@
+// Krylov vector kernels and deterministic reductions.
+//
+// The momentum Krylov space is the real vector space of half-spectrum displacement
+// corrections; its inner product weights every bin by its multiplicity in the full
+// spectrum (1 on the x-bins 0 and N1/2, 2 elsewhere), i.e. Parseval's identity for
+// the real fields they represent.  All dot products accumulate in FP64; every
+// reduction is a fixed tree (per-block partials, then one block in index order), so
+// results are bitwise reproducible run to run.
+#include "kernels.h"
+
+namespace rvefft {
+
+static int vgrid(long long n) {
+  long long b = (n + 255) / 256;
+  return (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
+}
+
+__global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ partial, int nblk, int op_max,
+                         double* __restrict__ out) {
+  __shared__ double sh[256];
+  const int c = blockIdx.x;
+  double s = op_max ? -INFINITY : 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    const double x = partial[(long long)c * nblk + b];
+    s = op_max ? fmax(s, x) : s + x;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double y = sh[threadIdx.x + w];
+      sh[threadIdx.x] = op_max ? fmax(sh[threadIdx.x], y) : sh[threadIdx.x] + y;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = sh[0];
+}
+
+void launch_reduce(const double* partial, int nblk, int ncomp, int op_max, double* out,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(ncomp), dim3(256), 0, st, partial, nblk, op_max, out);
+}
+
+__device__ __forceinline__ double pw_weight(long long b, const Grid& g) {
+  const int kx = (int)(b % g.n1h);
+  return (kx == 0 || (g.n1 % 2 == 0 && kx == g.n1 / 2)) ? 1.0 : 2.0;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_sdot(const cplx<R>* __restrict__ a, const cplx<R>* __restrict__ bv, long long cs,
+                       int ncomp, Grid g, double* __restrict__ partial) {
+  __shared__ double red[16];
+  double acc = 0.0;
+  for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < g.nspec;
+       b += (long long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < ncomp; ++c) {
+      const cplx<R> x = a[c * cs + b], y = bv[c * cs + b];
+      s += (double)x.x * (double)y.x + (double)x.y * (double)y.y;
+    }
+    acc += pw_weight(b, g) * s;
+  }
+  block_partial_sum(acc, partial, red);
+}
+
+template <typename R>
+int launch_sdot(const Plans& p, const cplx<R>* a, const cplx<R>* b, long long cs, int ncomp,
+                double* partial, hipStream_t st) {
+  const int nb = vgrid(p.g.nspec);
+  hipLaunchKernelGGL((k_sdot<R>), dim3(nb), dim3(256), 0, st, a, b, cs, ncomp, p.g, partial);
+  return nb;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_cg_xr(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r,
+                        const cplx<R>* __restrict__ pv, const cplx<R>* __restrict__ q, long long cs,
+                        const double* __restrict__ sc, int ia, int ib, Grid g,
+                        double* __restrict__ partial) {
+  __shared__ double red[16];
+  const double al = sc[ia] / sc[ib];
+  double acc = 0.0;
+  for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < g.nspec;
+       b += (long long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const long long i = c * cs + b;
+      const cplx<R> pp = pv[i], qq = q[i];
+      cplx<R> xx = x[i], rr = r[i];
+      xx.x = (R)((double)xx.x + al * (double)pp.x);
+      xx.y = (R)((double)xx.y + al * (double)pp.y);
+      rr.x = (R)((double)rr.x - al * (double)qq.x);
+      rr.y = (R)((double)rr.y - al * (double)qq.y);
+      x[i] = xx;
+      r[i] = rr;
+      s += (double)rr.x * (double)rr.x + (double)rr.y * (double)rr.y;
+    }
+    acc += pw_weight(b, g) * s;
+  }
+  block_partial_sum(acc, partial, red);
+}
+
+template <typename R>
+int launch_cg_xr(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, const cplx<R>* q,
+                 long long cs, const double* sc, int ia, int ib, double* partial, hipStream_t st) {
+  const int nb = vgrid(p.g.nspec);
+  hipLaunchKernelGGL((k_cg_xr<R>), dim3(nb), dim3(256), 0, st, x, r, pv, q, cs, sc, ia, ib, p.g,
+                     partial);
+  return nb;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_cg_p(cplx<R>* __restrict__ pv, const cplx<R>* __restrict__ z, long long cs,
+                       const double* __restrict__ sc, int ia, int ib, long long nspec) {
+  const double be = sc[ia] / sc[ib];
+  for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < nspec;
+       b += (long long)gridDim.x * blockDim.x) {
+    for (int c = 0; c < 3; ++c) {
+      const long long i = c * cs + b;
+      const cplx<R> zz = z[i], pp = pv[i];
+      pv[i] = cplx<R>{(R)((double)zz.x + be * (double)pp.x), (R)((double)zz.y + be * (double)pp.y)};
+    }
+  }
+}
+
+template <typename R>
+void launch_cg_p(const Plans& p, cplx<R>* pv, const cplx<R>* z, long long cs, const double* sc,
+                 int ia, int ib, hipStream_t st) {
+  hipLaunchKernelGGL((k_cg_p<R>), dim3(vgrid(p.g.nspec)), dim3(256), 0, st, pv, z, cs, sc, ia, ib,
+                     p.g.nspec);
+}
+
+template int launch_sdot<double>(const Plans&, const cplx<double>*, const cplx<double>*, long long,
+                                 int, double*, hipStream_t);
+template int launch_sdot<float>(const Plans&, const cplx<float>*, const cplx<float>*, long long,
+                                int, double*, hipStream_t);
+template int launch_cg_xr<double>(const Plans&, cplx<double>*, cplx<double>*, const cplx<double>*,
+                                  const cplx<double>*, long long, const double*, int, int, double*,
+                                  hipStream_t);
+template int launch_cg_xr<float>(const Plans&, cplx<float>*, cplx<float>*, const cplx<float>*,
+                                 const cplx<float>*, long long, const double*, int, int, double*,
+                                 hipStream_t);
+template void launch_cg_p<double>(const Plans&, cplx<double>*, const cplx<double>*, long long,
+                                  const double*, int, int, hipStream_t);
+template void launch_cg_p<float>(const Plans&, cplx<float>*, const cplx<float>*, long long,
+                                 const double*, int, int, hipStream_t);
+
+// ---- real vectors (phase field) -------------------------------------------------------
+__global__ void __launch_bounds__(256) k_rdot(long long n, const double* __restrict__ a, const double* __restrict__ b,
+                       double* __restrict__ partial) {
+  __shared__ double red[16];
+  double acc = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    acc += a[i] * b[i];
+  block_partial_sum(acc, partial, red);
+}
+
+int launch_rdot(long long n, const double* a, const double* b, double* partial, hipStream_t st) {
+  const int nb = vgrid(n);
+  hipLaunchKernelGGL(k_rdot, dim3(nb), dim3(256), 0, st, n, a, b, partial);
+  return nb;
+}
+
+__global__ void __launch_bounds__(256) k_pf_pq(long long n, const double* __restrict__ p, const double* __restrict__ w,
+                        const double* __restrict__ S, double* __restrict__ partial) {
+  __shared__ double red[16];
+  double acc = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    acc += p[i] * (w[i] + 2.0 * S[i] * p[i]);
+  block_partial_sum(acc, partial, red);
+}
+
+int launch_pf_pq(long long n, const double* p, const double* w, const double* S, double* partial,
+                 hipStream_t st) {
+  const int nb = vgrid(n);
+  hipLaunchKernelGGL(k_pf_pq, dim3(nb), dim3(256), 0, st, n, p, w, S, partial);
+  return nb;
+}
+
+__global__ void __launch_bounds__(256) k_pf_xr(long long n, double* __restrict__ x, double* __restrict__ r,
+                        const double* __restrict__ p, const double* __restrict__ w,
+                        const double* __restrict__ S, const double* __restrict__ sc, int ia, int ib,
+                        double* __restrict__ partial) {
+  __shared__ double red[16];
+  const double al = sc[ia] / sc[ib];
+  double acc = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double pp = p[i];
+    x[i] += al * pp;
+    const double rr = r[i] - al * (w[i] + 2.0 * S[i] * pp);
+    r[i] = rr;
+    acc += rr * rr;
+  }
+  block_partial_sum(acc, partial, red);
+}
+
+int launch_pf_xr(long long n, double* x, double* r, const double* p, const double* w,
+                 const double* S, const double* sc, int ia, int ib, double* partial, hipStream_t st) {
+  const int nb = vgrid(n);
+  hipLaunchKernelGGL(k_pf_xr, dim3(nb), dim3(256), 0, st, n, x, r, p, w, S, sc, ia, ib, partial);
+  return nb;
+}
+
+__global__ void __launch_bounds__(256) k_pf_pw(long long n, double* __restrict__ p, double* __restrict__ w,
+                        const double* __restrict__ z, const double* __restrict__ r,
+                        const double* __restrict__ sc, int ia, int ib) {
+  const double be = sc[ia] / sc[ib];
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    p[i] = z[i] + be * p[i];
+    w[i] = r[i] + be * w[i];
+  }
+}
+
+void launch_pf_pw(long long n, double* p, double* w, const double* z, const double* r,
+                  const double* sc, int ia, int ib, hipStream_t st) {
+  hipLaunchKernelGGL(k_pf_pw, dim3(vgrid(n)), dim3(256), 0, st, n, p, w, z, r, sc, ia, ib);
+}
+
+__global__ void __launch_bounds__(256) k_rscale(long long n, const double* __restrict__ x, double a, double* __restrict__ y) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = a * x[i];
+}
+
+void launch_rscale(long long n, const double* x, double a, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_rscale, dim3(vgrid(n)), dim3(256), 0, st, n, x, a, y);
+}
+
+__global__ void __launch_bounds__(256) k_zero(uint32_t* __restrict__ p, long long nw) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nw;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+void launch_zero(void* ptr, size_t bytes, hipStream_t st) {
+  const long long nw = (long long)(bytes / 4);
+  hipLaunchKernelGGL(k_zero, dim3(vgrid(nw)), dim3(256), 0, st, (uint32_t*)ptr, nw);
+}
+
+}  // namespace rvefft

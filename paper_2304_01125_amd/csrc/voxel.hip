@@ -1,0 +1,710 @@
+// Per-voxel kernels: crystal-plasticity update with consistent tangent, the
+// phase-field driving state, the history commit and the GND density (Sec. 2).
+//
+// Constitutive model (small-strain form of Sec. 2.1 with a power-law flow rule):
+//   dgamma_a = dt gdot0 sign(tau_a) |tau_a / g|^n,  tau_a = P_a : sigma,
+//   P_a = sym(s_a (x) n_a); backward Euler on sigma with g frozen over the step:
+//   R(sigma) = C^-1 (sigma - sigma_tr) + sum_a dgamma_a P_a = 0,
+//   sigma_tr = C (eps - eps_p).
+// R is the gradient of a strictly convex potential Phi; the root is found by a
+// Newton iteration with backtracking on Phi (FP64 in every precision mode), and
+// the consistent tangent is K = (C^-1 + sum_a d dgamma_a / d tau_a P_a P_a^T)^-1.
+// All 6x6 algebra is in the Mandel basis.
+#include "kernels.h"
+
+namespace rvefft {
+
+static constexpr double kSqrt2 = 1.41421356237309504880;
+static constexpr double kInvSqrt2 = 0.70710678118654752440;
+
+int voxel_grid(long long n) {
+  long long b = (n + 255) / 256;
+  return (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
+}
+
+// Deterministic block sums of NC values: shuffles within each wave, then the
+// waves in index order.  Thread c < NC writes partial[c * gridDim.x + blockIdx.x].
+template <int NC, bool MAX>
+__device__ void block_partials(double (&v)[NC], double* partial) {
+  __shared__ double red[NC][16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    double x = v[c];
+    for (int off = 32; off > 0; off >>= 1) {
+      const double y = __shfl_down(x, off, 64);
+      x = MAX ? fmax(x, y) : x + y;
+    }
+    if (lane == 0) red[c][wid] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < NC) {
+    double s = red[threadIdx.x][0];
+    for (int w = 1; w < nw; ++w) s = MAX ? fmax(s, red[threadIdx.x][w]) : s + red[threadIdx.x][w];
+    partial[(long long)threadIdx.x * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+__device__ __forceinline__ void to_mandel(const double t[6], double m[6]) {
+  m[0] = t[0]; m[1] = t[1]; m[2] = t[2];
+  m[3] = kSqrt2 * t[3]; m[4] = kSqrt2 * t[4]; m[5] = kSqrt2 * t[5];
+}
+__device__ __forceinline__ void from_mandel(const double m[6], double t[6]) {
+  t[0] = m[0]; t[1] = m[1]; t[2] = m[2];
+  t[3] = kInvSqrt2 * m[3]; t[4] = kInvSqrt2 * m[4]; t[5] = kInvSqrt2 * m[5];
+}
+
+// Slip increments at stress sig (Mandel): tau, dgamma, d dgamma / d tau.
+__device__ __forceinline__ void slip(const double* __restrict__ P, const double sig[6], double g,
+                                     double dtg0, double nexp, double tau[12], double dg[12],
+                                     double ddg[12], double axn[12]) {
+#pragma unroll
+  for (int a = 0; a < 12; ++a) {
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) s += P[a * 6 + b] * sig[b];
+    tau[a] = s;
+    const double x = s / g;
+    const double ax = fabs(x);
+    const double pw = pow(ax, nexp - 1.0);       // |x|^(n-1)
+    axn[a] = ax * pw;                              // |x|^n
+    dg[a] = dtg0 * copysign(axn[a], x);
+    ddg[a] = dtg0 * nexp / g * pw;
+  }
+}
+
+// Phi(sig) = 1/2 (sig-sig_tr) S (sig-sig_tr) + dt gdot0/(n+1) sum |tau| |tau/g|^n
+__device__ __forceinline__ double potential(const double* __restrict__ S, const double* __restrict__ P,
+                                            const double sig[6], const double str[6], double g,
+                                            double dtg0, double nexp) {
+  double d[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) d[i] = sig[i] - str[i];
+  double el = 0.0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) s += S[i * 6 + j] * d[j];
+    el += d[i] * s;
+  }
+  double pl = 0.0;
+#pragma unroll
+  for (int a = 0; a < 12; ++a) {
+    double t = 0.0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) t += P[a * 6 + b] * sig[b];
+    const double ax = fabs(t / g);
+    pl += fabs(t) * ax * pow(ax, nexp - 1.0);
+  }
+  return 0.5 * el + dtg0 / (nexp + 1.0) * pl;
+}
+
+// Residual and Jacobian (full 6x6) at sig.
+__device__ __forceinline__ void resjac(const double* __restrict__ S, const double* __restrict__ P,
+                                       const double sig[6], const double str[6], double g,
+                                       double dtg0, double nexp, double Rv[6], double J[6][6],
+                                       double tau[12], double dg[12]) {
+  double ddg[12], axn[12];
+  slip(P, sig, g, dtg0, nexp, tau, dg, ddg, axn);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      s += S[i * 6 + j] * (sig[j] - str[j]);
+      J[i][j] = S[i * 6 + j];
+    }
+    Rv[i] = s;
+  }
+#pragma unroll
+  for (int a = 0; a < 12; ++a) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      const double pi = P[a * 6 + i];
+      Rv[i] += dg[a] * pi;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) J[i][j] += ddg[a] * pi * P[a * 6 + j];
+    }
+  }
+}
+
+// In-place Cholesky factor (lower) of an SPD 6x6; returns false if not SPD.
+__device__ __forceinline__ bool chol6(double A[6][6]) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    double s = A[j][j];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (k < j) s -= A[j][k] * A[j][k];
+    if (!(s > 0.0)) return false;
+    const double d = sqrt(s);
+    A[j][j] = d;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      if (i > j) {
+        double t = A[i][j];
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+          if (k < j) t -= A[i][k] * A[j][k];
+        A[i][j] = t / d;
+      }
+    }
+  }
+  return true;
+}
+
+__device__ __forceinline__ void chol6_solve(const double L[6][6], const double b[6], double x[6]) {
+  double y[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double s = b[i];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (k < i) s -= L[i][k] * y[k];
+    y[i] = s / L[i][i];
+  }
+#pragma unroll
+  for (int i = 5; i >= 0; --i) {
+    double s = y[i];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (k > i) s -= L[k][i] * x[k];
+    x[i] = s / L[i][i];
+  }
+}
+
+// Solve the return map from the warm start in sig (Mandel, in/out).  Returns the
+// number of Newton iterations, or -1 if it did not converge.
+__device__ int return_map(const double* __restrict__ S, const double* __restrict__ P,
+                          const double str[6], double g, double dtg0, double nexp, double sig[6]) {
+  double scale = 0.0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) scale = fmax(scale, fabs(str[i]));
+  scale += g;
+  int it;
+  bool conv = false;
+  for (it = 0; it < 400; ++it) {
+    double Rv[6], J[6][6], tau[12], dg[12], d[6];
+    resjac(S, P, sig, str, g, dtg0, nexp, Rv, J, tau, dg);
+    if (!chol6(J)) return -1;
+    double mR[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) mR[i] = -Rv[i];
+    chol6_solve(J, mR, d);
+    const double phi0 = potential(S, P, sig, str, g, dtg0, nexp);
+    double slope = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) slope += Rv[i] * d[i];
+    double t = 1.0;
+    for (int ls = 0; ls < 60; ++ls) {
+      double c[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) c[i] = sig[i] + t * d[i];
+      const double phi1 = potential(S, P, c, str, g, dtg0, nexp);
+      if (phi1 <= phi0 + 1e-4 * t * slope + 1e-13 * fabs(phi0)) break;
+      t *= 0.5;
+    }
+    double smax = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      const double st = t * d[i];
+      sig[i] += st;
+      smax = fmax(smax, fabs(st));
+    }
+    if (smax <= 1e-13 * scale) { conv = true; break; }
+  }
+  if (!conv) return -1;
+  // one polishing Newton step at the root
+  {
+    double Rv[6], J[6][6], tau[12], dg[12], d[6];
+    resjac(S, P, sig, str, g, dtg0, nexp, Rv, J, tau, dg);
+    if (!chol6(J)) return -1;
+    chol6_solve(J, Rv, d);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) sig[i] -= d[i];
+  }
+  return it + 1;
+}
+
+// K = J^-1 from the Cholesky factor L of J (packed 21 upper, row-major).
+__device__ __forceinline__ void chol6_inverse21(const double L[6][6], double K21[21]) {
+  double Li[6][6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (k < i && k >= c) s -= L[i][k] * Li[k][c];
+      Li[i][c] = (i >= c) ? s / L[i][i] : 0.0;
+    }
+  }
+  int idx = 0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i; j < 6; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (k >= j) s += Li[k][i] * Li[k][j];
+      K21[idx++] = s;
+    }
+}
+
+__device__ __forceinline__ void load6(const double* __restrict__ f, long long N, long long v, double o[6]) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) o[c] = f[c * N + v];
+}
+
+// ---------------------------------------------------------------------------
+// Constitutive update at eps + t*deps.  Writes sigma (tensor comps), g(phi) K
+// (21 Mandel entries) and the block partials of sum gK (21), sum g w and
+// sum g sigma (6), with w = 1/2 sig_tr S sig_tr - Phi(sig) the incremental energy.
+template <typename R>
+__global__ void __launch_bounds__(256) k_constitutive(long long N, const double* __restrict__ eps,
+                               const double* __restrict__ deps, double t,
+                               const double* __restrict__ epsp, const double* __restrict__ gslip,
+                               const int* __restrict__ grain, const double* __restrict__ gtab,
+                               double* __restrict__ sig_io, const double* __restrict__ phi,
+                               R* __restrict__ gK, Material m, double* __restrict__ partial,
+                               int* __restrict__ fail) {
+  double acc[RED_CONST];
+#pragma unroll
+  for (int c = 0; c < RED_CONST; ++c) acc[c] = 0.0;
+  const double dtg0 = m.dt * m.gdot0;
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x) {
+    const double* gt = gtab + (long long)grain[v] * GT_STRIDE;
+    const double* C = gt + GT_C;
+    const double* S = gt + GT_S;
+    const double* P = gt + GT_P;
+    double e[6], ep[6], s0[6], em[6], epm[6], str[6], sig[6];
+    load6(eps, N, v, e);
+    if (deps) {
+      double de[6];
+      load6(deps, N, v, de);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) e[c] += t * de[c];
+    }
+    load6(epsp, N, v, ep);
+    load6(sig_io, N, v, s0);
+    to_mandel(e, em);
+    to_mandel(ep, epm);
+    to_mandel(s0, sig);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) s += C[i * 6 + j] * (em[j] - epm[j]);
+      str[i] = s;
+    }
+    const double g = gslip[v];
+    const int its = return_map(S, P, str, g, dtg0, m.nexp, sig);
+    if (its < 0) atomicAdd(fail, 1);
+    // tangent at the root
+    double Rv[6], J[6][6], tau[12], dg[12];
+    resjac(S, P, sig, str, g, dtg0, m.nexp, Rv, J, tau, dg);
+    double K21[21];
+    if (chol6(J)) chol6_inverse21(J, K21);
+    else {
+      atomicAdd(fail, 1);
+#pragma unroll
+      for (int c = 0; c < 21; ++c) K21[c] = 0.0;
+    }
+    const double q = 1.0 - phi[v];
+    const double gphi = q * q + m.kres;
+#pragma unroll
+    for (int c = 0; c < 21; ++c) {
+      const double kk = gphi * K21[c];
+      gK[(long long)c * N + v] = (R)kk;
+      acc[c] += kk;
+    }
+    double el = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) s += S[i * 6 + j] * str[j];
+      el += str[i] * s;
+    }
+    const double w = 0.5 * el - potential(S, P, sig, str, g, dtg0, m.nexp);
+    acc[21] += gphi * w;
+    double st[6];
+    from_mandel(sig, st);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      sig_io[c * N + v] = st[c];
+      acc[22 + c] += gphi * st[c];
+    }
+  }
+  block_partials<RED_CONST, false>(acc, partial);
+}
+
+template <typename R>
+void launch_constitutive(long long N, const double* eps, const double* deps, double t,
+                         const double* epsp, const double* gslip, const int* grain,
+                         const double* gtab, double* sig, const double* phi, R* gK,
+                         const Material& m, double* partial, int* fail, hipStream_t st) {
+  hipLaunchKernelGGL((k_constitutive<R>), dim3(voxel_grid(N)), dim3(256), 0, st, N, eps, deps, t,
+                     epsp, gslip, grain, gtab, sig, phi, gK, m, partial, fail);
+}
+template void launch_constitutive<double>(long long, const double*, const double*, double,
+                                          const double*, const double*, const int*, const double*,
+                                          double*, const double*, double*, const Material&,
+                                          double*, int*, hipStream_t);
+template void launch_constitutive<float>(long long, const double*, const double*, double,
+                                         const double*, const double*, const int*, const double*,
+                                         double*, const double*, float*, const Material&, double*,
+                                         int*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Cyclic Jacobi eigen-decomposition of a symmetric 3x3 (columns of V = vectors).
+__device__ void jacobi3(double a[3][3], double d[3], double V[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+    const double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+    if (off <= 1e-36 * dia || off == 0.0) break;
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = (pq == 2) ? 1 : 0;
+      const int qq = (pq == 0) ? 1 : 2;
+      const double apq = a[p][qq];
+      if (apq == 0.0) continue;
+      const double theta = (a[qq][qq] - a[p][p]) / (2.0 * apq);
+      const double tt = copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
+      const double c = 1.0 / sqrt(tt * tt + 1.0);
+      const double s = tt * c;
+      for (int k = 0; k < 3; ++k) {
+        const double akp = a[k][p], akq = a[k][qq];
+        a[k][p] = c * akp - s * akq;
+        a[k][qq] = s * akp + c * akq;
+      }
+      for (int k = 0; k < 3; ++k) {
+        const double apk = a[p][k], aqk = a[qq][k];
+        a[p][k] = c * apk - s * aqk;
+        a[qq][k] = s * apk + c * aqk;
+      }
+      for (int k = 0; k < 3; ++k) {
+        const double vkp = V[k][p], vkq = V[k][qq];
+        V[k][p] = c * vkp - s * vkq;
+        V[k][qq] = s * vkp + c * vkq;
+      }
+    }
+  }
+  d[0] = a[0][0]; d[1] = a[1][1]; d[2] = a[2][2];
+}
+
+// 1/2 eps+ : C : eps+ with eps+ the positive spectral part of the elastic strain
+// (tensor comps), C Mandel (eq. decMiehe, small-strain reading).
+__device__ double tensile_energy(const double ee[6], const double* __restrict__ C) {
+  double a[3][3] = {{ee[0], ee[5], ee[4]}, {ee[5], ee[1], ee[3]}, {ee[4], ee[3], ee[2]}};
+  double d[3], V[3][3];
+  jacobi3(a, d, V);
+  double P[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += fmax(d[k], 0.0) * V[i][k] * V[j][k];
+      P[i][j] = s;
+    }
+  const double pt[6] = {P[0][0], P[1][1], P[2][2], P[1][2], P[0][2], P[0][1]};
+  double pm[6];
+  to_mandel(pt, pm);
+  double e = 0.0;
+  for (int i = 0; i < 6; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < 6; ++j) s += C[i * 6 + j] * pm[j];
+    e += pm[i] * s;
+  }
+  return 0.5 * e;
+}
+
+// Driving state of the phase field (eq. zeta, read as S = (l/Gc) <W - W_crit> after
+// the stored-energy threshold is reached) from the converged effective stress:
+// trial slip, trial plastic work and the tensile elastic energy.
+__global__ void __launch_bounds__(256) k_source(long long N, const double* __restrict__ eps, const double* __restrict__ sig,
+                         const double* __restrict__ epsp, const double* __restrict__ gslip,
+                         const int* __restrict__ grain, const double* __restrict__ gtab,
+                         const double* __restrict__ wp, const double* __restrict__ trig,
+                         const double* __restrict__ wcrit, double* __restrict__ S_out,
+                         double* __restrict__ wep_out, Material m, double* __restrict__ partial) {
+  double acc[RED_SOURCE] = {0.0, 0.0};
+  const double dtg0 = m.dt * m.gdot0;
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x) {
+    const double* gt = gtab + (long long)grain[v] * GT_STRIDE;
+    const double* P = gt + GT_P;
+    double st[6], sm[6], e[6], ep[6];
+    load6(sig, N, v, st);
+    load6(eps, N, v, e);
+    load6(epsp, N, v, ep);
+    to_mandel(st, sm);
+    double tau[12], dg[12], ddg[12], axn[12];
+    slip(P, sm, gslip[v], dtg0, m.nexp, tau, dg, ddg, axn);
+    double dpm[6] = {0, 0, 0, 0, 0, 0};
+    double dw = 0.0;
+#pragma unroll
+    for (int a = 0; a < 12; ++a) {
+      dw += tau[a] * dg[a];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) dpm[i] += dg[a] * P[a * 6 + i];
+    }
+    double dpt[6];
+    from_mandel(dpm, dpt);
+    double ee[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) ee[i] = e[i] - (ep[i] + dpt[i]);
+    const double we = tensile_energy(ee, gt + GT_C);
+    const double W = we + wp[v] + dw;
+    const double S = (trig[v] != 0.0) ? m.ell / m.Gc * fmax(0.0, W - wcrit[v]) : 0.0;
+    S_out[v] = S;
+    wep_out[v] = we;
+    acc[0] += S;
+    acc[1] += S * S;
+  }
+  block_partials<RED_SOURCE, false>(acc, partial);
+}
+
+void launch_source(long long N, const double* eps, const double* sig, const double* epsp,
+                   const double* gslip, const int* grain, const double* gtab, const double* wp,
+                   const double* trig, const double* wcrit, double* S, double* wep,
+                   const Material& m, double* partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_source, dim3(voxel_grid(N)), dim3(256), 0, st, N, eps, sig, epsp, gslip,
+                     grain, gtab, wp, trig, wcrit, S, wep, m, partial);
+}
+
+// History commit of one converged increment (FP64), Sec. 2.1-2.3:
+// eps_p, beta_p, g (linear hardening), rho_SSD, W_p, G_s, H = max W_e+, W_crit.
+// Partials: sums of g(phi) sigma (6), eps (6) and the trigger flag; maxima of phi
+// and of phi over voxels that can slip.
+__global__ void __launch_bounds__(256) k_commit(long long N, const double* __restrict__ sig, double* __restrict__ gslip,
+                         double* __restrict__ epsp, double* __restrict__ beta,
+                         double* __restrict__ rho_ssd, const double* __restrict__ rho_gnd,
+                         double* __restrict__ wp, double* __restrict__ gs, double* __restrict__ H,
+                         double* __restrict__ wcrit, double* __restrict__ trig,
+                         const double* __restrict__ wep, const double* __restrict__ phi,
+                         const double* __restrict__ eps, const int* __restrict__ grain,
+                         const double* __restrict__ gtab, Material m,
+                         double* __restrict__ partial) {
+  double acc[13];
+  double mx[2] = {0.0, 0.0};
+#pragma unroll
+  for (int c = 0; c < 13; ++c) acc[c] = 0.0;
+  const double dtg0 = m.dt * m.gdot0;
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x) {
+    const double* gt = gtab + (long long)grain[v] * GT_STRIDE;
+    const double* P = gt + GT_P;
+    const double* SN = gt + GT_SN;
+    double st[6], sm[6];
+    load6(sig, N, v, st);
+    to_mandel(st, sm);
+    const double g = gslip[v];
+    double tau[12], dg[12], ddg[12], axn[12];
+    slip(P, sm, g, dtg0, m.nexp, tau, dg, ddg, axn);
+    double dpm[6] = {0, 0, 0, 0, 0, 0};
+    double db[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double dw = 0.0, sabs = 0.0;
+#pragma unroll
+    for (int a = 0; a < 12; ++a) {
+      dw += tau[a] * dg[a];
+      sabs += fabs(dg[a]);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) dpm[i] += dg[a] * P[a * 6 + i];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) db[i] += dg[a] * SN[a * 9 + i];
+    }
+    double dpt[6];
+    from_mandel(dpm, dpt);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) epsp[i * N + v] += dpt[i];
+    double db2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      beta[i * N + v] += db[i];
+      db2 += db[i] * db[i];
+    }
+    gslip[v] = g + m.h_lin * sabs;
+    const double rs = rho_ssd[v] + m.lambda_ssd * sqrt(2.0 / 3.0 * db2);
+    rho_ssd[v] = rs;
+    const double wpn = wp[v] + dw;
+    wp[v] = wpn;
+    const double gsn = gs[v] + m.xi_store * dw / sqrt(rs + rho_gnd[v]);
+    gs[v] = gsn;
+    const double hn = fmax(H[v], wep[v]);
+    H[v] = hn;
+    double tr = trig[v];
+    if (tr == 0.0 && gsn >= m.G_crit) {
+      wcrit[v] = hn + wpn;
+      tr = 1.0;
+      trig[v] = 1.0;
+    }
+    const double q = 1.0 - phi[v];
+    const double gphi = q * q + m.kres;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      acc[c] += gphi * st[c];
+      acc[6 + c] += eps[c * N + v];
+    }
+    acc[12] += tr;
+    mx[0] = fmax(mx[0], phi[v]);
+    if (isfinite(g)) mx[1] = fmax(mx[1], phi[v]);
+  }
+  block_partials<13, false>(acc, partial);
+  __syncthreads();
+  block_partials<2, true>(mx, partial + 13LL * gridDim.x);
+}
+
+void launch_commit(long long N, const double* sig, double* gslip, double* epsp, double* beta,
+                   double* rho_ssd, const double* rho_gnd, double* wp, double* gs, double* H,
+                   double* wcrit, double* trig, const double* wep, const double* phi,
+                   const double* eps, const int* grain, const double* gtab, const Material& m,
+                   double* partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_commit, dim3(voxel_grid(N)), dim3(256), 0, st, N, sig, gslip, epsp, beta,
+                     rho_ssd, rho_gnd, wp, gs, H, wcrit, trig, wep, phi, eps, grain, gtab, m,
+                     partial);
+}
+
+// rho_GND = sqrt(vec(Lc)^T Q vec(Lc)) / b with Lc = R^T Lambda R (crystal frame) and
+// Q = (A A^T)^-1, the squared norm of the minimum-norm split into 12 edge and 6
+// screw densities (eq. nye1 and the L2-norm scheme).
+__global__ void __launch_bounds__(256) k_gnd(long long N, const double* __restrict__ lam9, const int* __restrict__ grain,
+                      const double* __restrict__ gtab, const double* __restrict__ Q81,
+                      double burgers, double* __restrict__ rho) {
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x) {
+    const double* Rm = gtab + (long long)grain[v] * GT_STRIDE + GT_R;
+    double L[3][3], T[3][3], Lc[9];
+    for (int i = 0; i < 9; ++i) L[i / 3][i % 3] = lam9[i * N + v];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) s += L[i][k] * Rm[k * 3 + j];
+        T[i][j] = s;                  // Lambda R
+      }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) s += Rm[k * 3 + i] * T[k][j];
+        Lc[i * 3 + j] = s;            // R^T Lambda R
+      }
+    double q = 0.0;
+    for (int i = 0; i < 9; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < 9; ++j) s += Q81[i * 9 + j] * Lc[j];
+      q += Lc[i] * s;
+    }
+    rho[v] = sqrt(fmax(q, 0.0)) / burgers;
+  }
+}
+
+void launch_gnd(long long N, const double* lam9, const int* grain, const double* gtab,
+                const double* Q81, double burgers, double* rho_gnd, hipStream_t st) {
+  hipLaunchKernelGGL(k_gnd, dim3(voxel_grid(N)), dim3(256), 0, st, N, lam9, grain, gtab, Q81,
+                     burgers, rho_gnd);
+}
+
+__global__ void __launch_bounds__(256) k_eps_update(long long N, double* __restrict__ eps, const double* __restrict__ deps,
+                             double t, const double* __restrict__ eps_t, double* __restrict__ partial) {
+  double mx[2] = {0.0, 0.0};
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double d = t * deps[c * N + v];
+      const double e = eps[c * N + v] + d;
+      eps[c * N + v] = e;
+      mx[0] = fmax(mx[0], fabs(d));
+      mx[1] = fmax(mx[1], fabs(e - eps_t[c * N + v]));
+    }
+  }
+  block_partials<2, true>(mx, partial);
+}
+
+void launch_eps_update(long long N, double* eps, const double* deps, double t, const double* eps_t,
+                       double* partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_eps_update, dim3(voxel_grid(N)), dim3(256), 0, st, N, eps, deps, t, eps_t,
+                     partial);
+}
+
+__global__ void __launch_bounds__(256) k_slope(long long N, const double* __restrict__ sig, const double* __restrict__ deps,
+                        const double* __restrict__ phi, double kres, double* __restrict__ partial) {
+  double acc[1] = {0.0};
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) s += (c < 3 ? 1.0 : 2.0) * sig[c * N + v] * deps[c * N + v];
+    const double q = 1.0 - phi[v];
+    acc[0] += (q * q + kres) * s;
+  }
+  block_partials<1, false>(acc, partial);
+}
+
+void launch_slope(long long N, const double* sig, const double* deps, const double* phi,
+                  double kres, double* partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_slope, dim3(voxel_grid(N)), dim3(256), 0, st, N, sig, deps, phi, kres,
+                     partial);
+}
+
+__global__ void __launch_bounds__(256) k_stag_norms(long long N, const double* __restrict__ eps,
+                             const double* __restrict__ eps_prev, const double* __restrict__ eps_t,
+                             const double* __restrict__ phi, const double* __restrict__ phi_prev,
+                             const double* __restrict__ phi_t, double* __restrict__ partial) {
+  double mx[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double e = eps[c * N + v];
+      mx[0] = fmax(mx[0], fabs(e - eps_prev[c * N + v]));
+      mx[1] = fmax(mx[1], fabs(e - eps_t[c * N + v]));
+    }
+    mx[2] = fmax(mx[2], fabs(phi[v] - phi_prev[v]));
+    mx[3] = fmax(mx[3], fabs(phi[v] - phi_t[v]));
+  }
+  block_partials<4, true>(mx, partial);
+}
+
+void launch_stag_norms(long long N, const double* eps, const double* eps_prev, const double* eps_t,
+                       const double* phi, const double* phi_prev, const double* phi_t,
+                       double* partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_stag_norms, dim3(voxel_grid(N)), dim3(256), 0, st, N, eps, eps_prev, eps_t,
+                     phi, phi_prev, phi_t, partial);
+}
+
+struct Six {
+  double v[6];
+};
+
+__global__ void __launch_bounds__(256) k_add_uniform(long long N, double* __restrict__ eps, Six de) {
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) eps[c * N + v] += de.v[c];
+}
+
+void launch_add_uniform(long long N, double* eps, const double de[6], hipStream_t st) {
+  Six s;
+  for (int c = 0; c < 6; ++c) s.v[c] = de[c];
+  hipLaunchKernelGGL(k_add_uniform, dim3(voxel_grid(N)), dim3(256), 0, st, N, eps, s);
+}
+
+__global__ void __launch_bounds__(256) k_clamp(long long N, const double* __restrict__ x, const double* __restrict__ phi_t,
+                        double* __restrict__ phi) {
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x)
+    phi[v] = fmin(1.0, fmax(phi_t[v], x[v]));
+}
+
+void launch_clamp(long long N, const double* x, const double* phi_t, double* phi, hipStream_t st) {
+  hipLaunchKernelGGL(k_clamp, dim3(voxel_grid(N)), dim3(256), 0, st, N, x, phi_t, phi);
+}
+
+}  // namespace rvefft

@@ -1,0 +1,262 @@
+"""Thin ctypes binding of the C ABI declared in include/rve.h.
+
+Only argument marshalling lives here: every step of the increment runs in the HIP
+library ``librve.so``.  PyTorch provides the device arena (a uint8 tensor) and
+the stream.  The binding refuses to run without the compiled library.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librve.so")
+
+RVE_OK, RVE_E_ARG, RVE_E_NOMEM, RVE_E_DEVICE, RVE_E_NOCONV, RVE_E_STATE = 0, -1, -2, -3, -4, -5
+RVE_FP64, RVE_MIXED = 0, 1
+
+FIELDS = [  # (name, bit, components) in the order rve_fields writes them
+    ("strain", 1 << 0, 6), ("stress", 1 << 1, 6), ("stress_eff", 1 << 2, 6),
+    ("damage", 1 << 3, 1), ("gs", 1 << 4, 1), ("rho_ssd", 1 << 5, 1), ("rho_gnd", 1 << 6, 1),
+    ("wp", 1 << 7, 1), ("h", 1 << 8, 1), ("wcrit", 1 << 9, 1), ("trig", 1 << 10, 1),
+    ("eps_p", 1 << 11, 6), ("g", 1 << 12, 1), ("beta_p", 1 << 13, 9),
+]
+FIELD_BITS = {n: (b, c) for n, b, c in FIELDS}
+
+
+class RveDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("precision", ctypes.c_int32), ("h", ctypes.c_double),
+                ("C11", ctypes.c_double), ("C12", ctypes.c_double), ("C44", ctypes.c_double),
+                ("gdot0", ctypes.c_double), ("n_exp", ctypes.c_double),
+                ("tau_c0", ctypes.c_double), ("h_lin", ctypes.c_double),
+                ("lambda_ssd", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("burgers", ctypes.c_double), ("xi_store", ctypes.c_double),
+                ("ell", ctypes.c_double), ("Gc", ctypes.c_double), ("G_crit", ctypes.c_double),
+                ("k_res", ctypes.c_double), ("ell_fp", ctypes.c_double),
+                ("tol_stag", ctypes.c_double), ("tol_newton", ctypes.c_double),
+                ("tol_lin", ctypes.c_double), ("max_stag", ctypes.c_int32),
+                ("max_newton", ctypes.c_int32), ("max_krylov", ctypes.c_int32),
+                ("max_grains", ctypes.c_int32)]
+
+
+class RveStats(ctypes.Structure):
+    _fields_ = [("stag_iters", ctypes.c_int32), ("newton_iters", ctypes.c_int32),
+                ("krylov_iters", ctypes.c_int32), ("pf_iters", ctypes.c_int32),
+                ("ls_cuts", ctypes.c_int32), ("rm_failures", ctypes.c_int32),
+                ("macro_stress", ctypes.c_double * 6), ("macro_strain", ctypes.c_double * 6),
+                ("max_phi", ctypes.c_double), ("max_phi_slip", ctypes.c_double),
+                ("n_triggered", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("ms_constitutive", ctypes.c_double), ("ms_mech_krylov", ctypes.c_double),
+                ("ms_phase_field", ctypes.c_double), ("ms_commit", ctypes.c_double)]
+
+    def as_dict(self):
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if isinstance(v, ctypes.Array) else v
+        return out
+
+
+_lib = None
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def load():
+    """Load librve.so (after torch, so that both use the same HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (the HIP runtime must be torch's)
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.rve_footprint_bytes.restype = ctypes.c_size_t
+    lib.rve_footprint_bytes.argtypes = [ctypes.POINTER(RveDesc)]
+    lib.rve_create.restype = ctypes.c_int
+    lib.rve_create.argtypes = [ctypes.POINTER(RveDesc), _P, ctypes.c_size_t, _P,
+                               ctypes.POINTER(_P)]
+    lib.rve_set_microstructure.restype = ctypes.c_int
+    lib.rve_set_microstructure.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                           _D, _D, _D]
+    lib.rve_step_increment.restype = ctypes.c_int
+    lib.rve_step_increment.argtypes = [_P, _D, ctypes.c_double, ctypes.POINTER(RveStats)]
+    lib.rve_fields.restype = ctypes.c_int
+    lib.rve_fields.argtypes = [_P, ctypes.c_uint32, _D, ctypes.c_size_t]
+    lib.rve_fields_count.restype = ctypes.c_size_t
+    lib.rve_fields_count.argtypes = [_P, ctypes.c_uint32]
+    lib.rve_destroy.restype = ctypes.c_int
+    lib.rve_destroy.argtypes = [_P]
+    lib.rve_last_error.restype = ctypes.c_char_p
+    lib.rve_last_error.argtypes = []
+    for name in ("rve_diag_rfft", "rve_diag_irfft"):
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [_P, ctypes.c_int32, _D, _D]
+    lib.rve_diag_constitutive.restype = ctypes.c_int
+    lib.rve_diag_constitutive.argtypes = [_P, _D, ctypes.c_double, _D, _D]
+    lib.rve_diag_operator.restype = ctypes.c_int
+    lib.rve_diag_operator.argtypes = [_P, _D, _D]
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    """Names of the C ABI entry points (as declared in include/rve.h)."""
+    return ["rve_footprint_bytes", "rve_create", "rve_set_microstructure", "rve_step_increment",
+            "rve_fields", "rve_fields_count", "rve_destroy", "rve_last_error", "rve_diag_rfft",
+            "rve_diag_irfft", "rve_diag_constitutive", "rve_diag_operator"]
+
+
+class RveError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rve error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != RVE_OK:
+        raise RveError(rc, load().rve_last_error().decode())
+    return rc
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_D) if a is not None else None
+
+
+def make_desc(desc, precision=RVE_FP64, max_grains=4096):
+    d = RveDesc()
+    for a in range(3):
+        d.n[a] = int(desc["n"][a])
+    d.precision = int(precision)
+    for k in ("h", "C11", "C12", "C44", "gdot0", "n_exp", "tau_c0", "h_lin", "lambda_ssd", "rho0",
+              "burgers", "xi_store", "ell", "Gc", "G_crit", "k_res", "ell_fp", "tol_stag",
+              "tol_newton", "tol_lin"):
+        setattr(d, k, float(desc[k]))
+    d.max_stag = int(desc["max_stag"])
+    d.max_newton = int(desc["max_newton"])
+    d.max_krylov = int(desc["max_krylov"])
+    d.max_grains = int(max_grains)
+    return d
+
+
+def rve_footprint_bytes(d):
+    return load().rve_footprint_bytes(ctypes.byref(d))
+
+
+def rve_create(d, arena_ptr, arena_bytes, stream_ptr):
+    h = _P()
+    _check(load().rve_create(ctypes.byref(d), _P(arena_ptr), arena_bytes, _P(stream_ptr),
+                             ctypes.byref(h)))
+    return h
+
+
+def rve_set_microstructure(h, grain, quat, tau_c0=None, phi0=None):
+    g = np.ascontiguousarray(grain, dtype=np.int32)
+    q = np.ascontiguousarray(quat, dtype=np.float64).reshape(-1, 4)
+    t = None if tau_c0 is None else np.ascontiguousarray(tau_c0, dtype=np.float64)
+    p = None if phi0 is None else np.ascontiguousarray(phi0, dtype=np.float64)
+    _check(load().rve_set_microstructure(h, g.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                         len(q), _dptr(q), _dptr(t), _dptr(p)))
+
+
+def rve_step_increment(h, deps6, dt):
+    de = np.ascontiguousarray(deps6, dtype=np.float64)
+    st = RveStats()
+    rc = load().rve_step_increment(h, _dptr(de), float(dt), ctypes.byref(st))
+    return rc, st.as_dict()
+
+
+def rve_fields(h, mask, nvox):
+    n = load().rve_fields_count(h, mask)
+    out = np.empty(n, dtype=np.float64)
+    _check(load().rve_fields(h, mask, _dptr(out), n))
+    return out
+
+
+def rve_destroy(h):
+    return load().rve_destroy(h)
+
+
+class RVE:
+    """One periodic RVE solved on the GPU.  ``desc`` is the flat dict of
+    ``synth.Workload.desc()``; precision is RVE_FP64 or RVE_MIXED."""
+
+    def __init__(self, desc, precision=RVE_FP64, device=0, stream=None, max_grains=4096):
+        import torch
+        lib = load()
+        self.desc = dict(desc)
+        self.n = tuple(int(v) for v in desc["n"])
+        self.nvox = int(np.prod(self.n))
+        self._d = make_desc(desc, precision, max_grains)
+        nbytes = lib.rve_footprint_bytes(ctypes.byref(self._d))
+        if nbytes == 0:
+            raise RveError(RVE_E_ARG, lib.rve_last_error().decode())
+        self.device = torch.device("cuda", device)
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        torch.cuda.synchronize(self.device)
+        self.h = rve_create(self._d, self.arena.data_ptr(), nbytes, self.stream.cuda_stream)
+        self.footprint = nbytes
+
+    def set_microstructure(self, grain, quat, tau_c0=None, phi0=None):
+        rve_set_microstructure(self.h, grain, quat, tau_c0, phi0)
+
+    def step(self, deps6, dt, check=True):
+        rc, st = rve_step_increment(self.h, deps6, dt)
+        st["status"] = rc
+        if check:
+            _check(rc)
+        return st
+
+    def fields(self, names=("strain", "stress", "damage")):
+        mask = 0
+        for nm in names:
+            mask |= FIELD_BITS[nm][0]
+        flat = rve_fields(self.h, mask, self.nvox)
+        out, off = {}, 0
+        for nm, bit, nc in FIELDS:
+            if mask & bit:
+                blk = flat[off:off + nc * self.nvox]
+                out[nm] = blk.reshape(nc, self.nvox).T.copy() if nc > 1 else blk.copy()
+                off += nc * self.nvox
+        return out
+
+    # diagnostics ---------------------------------------------------------------------
+    def rfft(self, real, ncomp):
+        nh = (self.n[0] // 2 + 1) * self.n[1] * self.n[2]
+        a = np.ascontiguousarray(real, dtype=np.float64).ravel()
+        out = np.empty(2 * nh * ncomp)
+        _check(load().rve_diag_rfft(self.h, ncomp, _dptr(a), _dptr(out)))
+        return out.view(np.complex128).reshape(ncomp, nh)
+
+    def irfft(self, spec, ncomp):
+        s = np.ascontiguousarray(spec, dtype=np.complex128).ravel().view(np.float64)
+        out = np.empty(ncomp * self.nvox)
+        _check(load().rve_diag_irfft(self.h, ncomp, _dptr(s), _dptr(out)))
+        return out.reshape(ncomp, self.nvox)
+
+    def constitutive(self, eps6, dt):
+        e = np.ascontiguousarray(np.asarray(eps6, dtype=np.float64).T).ravel()
+        sig = np.empty(6 * self.nvox)
+        gk = np.empty(21 * self.nvox)
+        _check(load().rve_diag_constitutive(self.h, _dptr(e), float(dt), _dptr(sig), _dptr(gk)))
+        return sig.reshape(6, self.nvox).T, gk.reshape(21, self.nvox).T
+
+    def operator(self, u3):
+        u = np.ascontiguousarray(np.asarray(u3, dtype=np.float64).T).ravel()
+        v = np.empty(3 * self.nvox)
+        _check(load().rve_diag_operator(self.h, _dptr(u), _dptr(v)))
+        return v.reshape(3, self.nvox).T
+
+    def close(self):
+        if getattr(self, "h", None):
+            rve_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,99 @@
+"""Host-side checks of the C ABI: every symbol declared in include/rve.h is exported,
+argument validation and the footprint are correct.  No GPU call is made."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rve.h")
+LIB = os.path.join(ROOT, "paper_2304_01125_amd", "librve.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="librve.so not built")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(rve_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    import paper_2304_01125_amd as p
+    lib = p.load()
+    names = declared_symbols()
+    assert "rve_create" in names and "rve_step_increment" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(p.exported_symbols()) == names
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes mirrors of rve_desc / rve_stats agree with the C compiler's layout."""
+    import shutil
+    import subprocess
+    from paper_2304_01125_amd.rve import RveDesc, RveStats
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = {"rve_desc": RveDesc, "rve_stats": RveStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rve.h"', "int main(void){"]
+    for cname, py in fields.items():
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    want = []
+    for py in fields.values():
+        want.append(ctypes.sizeof(py))
+        want.extend(getattr(py, f).offset for f, _ in py._fields_)
+    assert got == want
+
+
+def test_footprint_and_validation():
+    import paper_2304_01125_amd as p
+    from synth import workload
+    w = workload("notched-crystal-16")
+    d = p.make_desc(w.desc())
+    fp = p.rve_footprint_bytes(d)
+    n = 16 ** 3
+    assert fp > 65 * n * 8                      # at least the FP64 state
+    dm = p.make_desc(w.desc(), p.RVE_MIXED)
+    assert p.rve_footprint_bytes(dm) < fp       # FP32 spectral buffers are smaller
+    bad = p.make_desc(w.desc())
+    bad.n[0] = 10                               # 10 = 2 * 5 is not 2^p 3^q
+    assert p.rve_footprint_bytes(bad) == 0
+    assert "2^p 3^q" in p.load().rve_last_error().decode()
+    bad = p.make_desc(w.desc())
+    bad.tol_lin = float("nan")
+    assert p.rve_footprint_bytes(bad) == 0
+
+
+def test_create_rejects_small_or_null_arena():
+    import paper_2304_01125_amd as p
+    from synth import workload
+    lib = p.load()
+    d = p.make_desc(workload("notched-crystal-16").desc())
+    h = ctypes.c_void_p()
+    rc = lib.rve_create(ctypes.byref(d), None, 0, None, ctypes.byref(h))
+    assert rc == p.RVE_E_ARG and not h.value
+    fp = p.rve_footprint_bytes(d)
+    rc = lib.rve_create(ctypes.byref(d), ctypes.c_void_p(4096), fp - 1, None, ctypes.byref(h))
+    assert rc == p.RVE_E_NOMEM
+
+
+def test_null_handle_calls_fail_cleanly():
+    import paper_2304_01125_amd as p
+    lib = p.load()
+    de = np.zeros(6)
+    st = p.rve.RveStats()
+    assert lib.rve_step_increment(None, de.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1.0,
+                                  ctypes.byref(st)) == p.RVE_E_ARG
+    assert lib.rve_destroy(None) == p.RVE_OK

@@ -1,0 +1,101 @@
+"""Whole-increment parity of the GPU path with the CPU oracle (Algorithm 1), plus the
+transactional error paths, on small grids the oracle finishes in seconds."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import OracleRVE
+from synth import small_polycrystal, single_crystal, make_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def run_pair(w, n_inc, precision=0):
+    from paper_2304_01125_amd import RVE
+    inp = make_inputs(w)
+    desc = w.desc()
+    gpu = RVE(desc, precision)
+    gpu.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+    ora = OracleRVE(desc, inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+    out = []
+    for k in range(n_inc):
+        de = [0, inp["deps"][k], 0, 0, 0, 0]
+        sg = gpu.step(de, inp["dt"][k])
+        so = ora.step(de, inp["dt"][k])
+        print(f"  inc {k}: gpu newton {sg['newton_iters']} krylov {sg['krylov_iters']} "
+              f"stag {sg['stag_iters']} | oracle newton {so['newton']} stag {so['stag']}",
+              flush=True)
+        out.append((sg, so))
+    return gpu, ora, out
+
+
+def compare(gpu, ora, tol_field=1e-9, tol_phi=1e-8):
+    f = gpu.fields(("strain", "stress", "damage", "gs", "wp", "eps_p", "rho_ssd", "rho_gnd"))
+    o = ora.fields()
+    errs = {k: rel_l2(f[k], o[k]) for k in ("strain", "stress", "gs", "wp", "eps_p", "rho_ssd")}
+    errs["damage_max"] = np.abs(f["damage"] - o["damage"]).max()
+    errs["rho_gnd"] = rel_l2(f["rho_gnd"], o["rho_gnd"]) if np.linalg.norm(o["rho_gnd"]) > 0 else \
+        np.abs(f["rho_gnd"]).max()
+    print("  errors:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert errs["strain"] <= tol_field and errs["stress"] <= tol_field
+    assert errs["damage_max"] <= tol_phi
+    for k in ("gs", "wp", "eps_p", "rho_ssd", "rho_gnd"):
+        assert errs[k] <= 1e-8, (k, errs[k])
+    return errs
+
+
+def test_polycrystal_increments_match_oracle():
+    print("polycrystal 12x8x6, 4 grains, 4 increments", flush=True)
+    w = small_polycrystal(n=(12, 8, 6), n_grains=4, seed=7).parity()
+    gpu, ora, _ = run_pair(w, 4)
+    compare(gpu, ora)
+    gpu.close()
+
+
+def test_damage_increments_match_oracle():
+    print("polycrystal 8x8x8, 3 grains, low G_crit: damage active", flush=True)
+    w = dataclasses.replace(small_polycrystal(n=(8, 8, 8), n_grains=3, seed=5), G_crit=0.02,
+                            amplitude=0.006).parity()
+    gpu, ora, out = run_pair(w, 7)
+    assert out[-1][1]["n_trig"] > 0 and ora.phi.max() > 0
+    compare(gpu, ora)
+    gpu.close()
+
+
+def test_noconv_leaves_state_unchanged_and_bad_input_is_rejected():
+    from paper_2304_01125_amd import RVE, RVE_E_NOCONV, RVE_E_ARG, RveError
+    w = small_polycrystal(n=(8, 6, 4), n_grains=3, seed=2)
+    inp = make_inputs(w)
+    r = RVE(dataclasses.replace(w, max_krylov=1).desc())
+    r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+    before = r.fields(("strain", "stress_eff", "damage"))
+    st = r.step([0, 2e-3, 0, 0, 0, 0], 1.0, check=False)
+    assert st["status"] == RVE_E_NOCONV
+    after = r.fields(("strain", "stress_eff", "damage"))
+    for k in before:
+        assert np.array_equal(before[k], after[k])
+    with pytest.raises(RveError) as e:
+        r.step([0, float("nan"), 0, 0, 0, 0], 1.0)
+    assert e.value.code == RVE_E_ARG
+    r.close()
+
+
+def test_repeatable_bitwise():
+    from paper_2304_01125_amd import RVE
+    w = small_polycrystal(n=(8, 8, 4), n_grains=3, seed=9)
+    inp = make_inputs(w)
+    res = []
+    for _ in range(2):
+        r = RVE(w.desc())
+        r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+        for k in range(3):
+            r.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k])
+        res.append(r.fields(("strain", "stress", "gs")))
+        r.close()
+    for k in res[0]:
+        assert np.array_equal(res[0][k], res[1][k]), k
