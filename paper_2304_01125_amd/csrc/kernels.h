@@ -52,6 +52,9 @@ void launch_div(const Plans& p, const cplx<R>* s, long long scs, cplx<R>* out, l
 template <typename R>
 int launch_precond(const Plans& p, const cplx<R>* r, cplx<R>* z, long long cs, const double* kbar21,
                    double* partial, hipStream_t st);
+// Hermitian projection of the self-conjugate x-planes (spectra of real fields)
+template <typename R>
+void launch_herm_proj(const Plans& p, cplx<R>* v, long long cs, int ncomp, hipStream_t st);
 template <typename R>
 void launch_pf_scale(const Plans& p, cplx<R>* d, double ell, double scale, hipStream_t st);
 template <typename R>

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -16,6 +17,7 @@ using namespace rvefft;
 namespace {
 
 thread_local std::string g_err;
+const bool g_debug = std::getenv("RVE_DEBUG") != nullptr;
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -388,6 +390,7 @@ struct Ops {
       if (rc) return rc;
       iters = k + 1;
       const double pq = h->hs[SC_PQ], rr = h->hs[SC_RR];
+      if (g_debug) std::fprintf(stderr, "  pcg %d pq %.6e rr/bb %.6e\n", k, pq, std::sqrt(rr / bb));
       if (!(pq > 0.0) || !std::isfinite(rr)) return fail(RVE_E_NOCONV, "momentum CG breakdown");
       if (rr <= tol2) return RVE_OK;
       nb = launch_precond<R>(h->pl, r, z, NH, h->scal + SC_KBAR, h->partial, st);
@@ -437,6 +440,7 @@ int run_increment(rve_s* h, const double de[6], double dt, rve_stats* out) {
       // c = i xi~ . F{ g sigma }
       o.fwd(h->sig, true, N, 6, o.W, h->phi_prev);
       launch_div<R>(h->pl, o.W, o.NH, o.v(5), o.NH, 1.0, st);
+      launch_herm_proj<R>(h->pl, o.v(5), o.NH, 3, st);
       int kit = 0;
       rc = o.pcg(kit);
       s.krylov_iters += kit;

@@ -329,6 +329,50 @@ __global__ void __launch_bounds__(256) k_div(const cplx<R>* __restrict__ s, long
   }
 }
 
+// Bin of -k on a self-conjugate x-plane (same kx, negated ky and kz).
+__device__ __forceinline__ long long partner_bin(const Bin& q, const Grid& g) {
+  const int ky = (g.n2 - q.ky) % g.n2, kz = (g.n3 - q.kz) % g.n3;
+  return (long long)q.kx + (long long)g.n1h * (ky + (long long)g.n2 * kz);
+}
+
+// In-place projection of ncomp half-spectrum components onto spectra of real fields:
+// on the x-planes kx = 0 and kx = N1/2 each pair (k, -k) is replaced by its Hermitian
+// part.  One thread per bin of those planes; the thread of the smaller index of a
+// pair writes both entries.
+template <typename R>
+__global__ void __launch_bounds__(256) k_herm_proj(cplx<R>* __restrict__ v, long long cs, int ncomp,
+                                                   Grid g) {
+  const int nplanes = (g.n1 % 2 == 0 && g.n1 > 1) ? 2 : 1;
+  const long long per = (long long)g.n2 * g.n3;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < per * nplanes;
+       t += (long long)gridDim.x * blockDim.x) {
+    Bin q;
+    q.kx = (t < per) ? 0 : g.n1 / 2;
+    const long long rem = t % per;
+    q.ky = (int)(rem % g.n2);
+    q.kz = (int)(rem / g.n2);
+    const long long b = (long long)q.kx + (long long)g.n1h * rem;
+    const long long bp = partner_bin(q, g);
+    if (bp < b) continue;
+    for (int c = 0; c < ncomp; ++c) {
+      const cplx<R> a = v[c * cs + b], o = v[c * cs + bp];
+      const cplx<R> h = {R(0.5) * (a.x + o.x), R(0.5) * (a.y - o.y)};
+      v[c * cs + b] = h;
+      v[c * cs + bp] = cplx<R>{h.x, -h.y};
+    }
+  }
+}
+
+template <typename R>
+void launch_herm_proj(const Plans& p, cplx<R>* v, long long cs, int ncomp, hipStream_t st) {
+  const long long n = (long long)p.g.n2 * p.g.n3 * 2;
+  long long nb = (n + 255) / 256;
+  hipLaunchKernelGGL((k_herm_proj<R>), dim3((int)(nb < 1 ? 1 : nb)), dim3(256), 0, st, v, cs,
+                     ncomp, p.g);
+}
+template void launch_herm_proj<double>(const Plans&, cplx<double>*, long long, int, hipStream_t);
+template void launch_herm_proj<float>(const Plans&, cplx<float>*, long long, int, hipStream_t);
+
 // Mandel index of the symmetric pair (i, j) and its weight.
 __device__ __forceinline__ int mandel_index(int i, int j) {
   if (i == j) return i;
@@ -367,6 +411,14 @@ __global__ void __launch_bounds__(256) k_precond(const cplx<R>* __restrict__ r, 
     const double t[3] = {freq(q.kx, g.n1, g.L1, true), freq(q.ky, g.n2, g.L2, true),
                          freq(q.kz, g.n3, g.L3, true)};
     cplx<R> ri[3] = {r[b], r[cs + b], r[2 * cs + b]};
+    if (q.kx == 0 || (g.n1 % 2 == 0 && q.kx == g.n1 / 2)) {
+      // self-conjugate x-planes: keep the Hermitian part r(k) = conj r(-k) only
+      const long long bp = partner_bin(q, g);
+      for (int c = 0; c < 3; ++c) {
+        const cplx<R> o = r[c * cs + bp];
+        ri[c] = cplx<R>{R(0.5) * (ri[c].x + o.x), R(0.5) * (ri[c].y - o.y)};
+      }
+    }
     cplx<R> zo[3] = {{0, 0}, {0, 0}, {0, 0}};
     if (t[0] != 0.0 || t[1] != 0.0 || t[2] != 0.0) {
       double A[3][3];
