@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Benchmark: voxel-iterations per second of the FFT crystal-plasticity phase-field
+increment on one GPU.
+
+A step is one load increment (Algorithm 1: constitutive updates, Newton-Krylov
+momentum solve with the Green-operator preconditioner, phase-field solve, history
+commit, GND update) of the 128^3 polycrystal with 512 log-normal Laguerre grains,
+fully reversed strain cycling at +-0.5 %, at the paper's production tolerances.
+A voxel-iteration is one application of the momentum operator to one voxel; the
+rate counts every operator application of the timed increments over their whole
+wall time (constitutive work, phase field, commit and host synchronisation
+included).  Inputs are resident on the GPU before timing starts.
+
+Printed: one JSON line with the FP64 rate, the mixed-precision rate and its macro
+stress error against the FP64 run, the roofline of the dominant operator kernel
+(HIP events on the library's stream) and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel-iters/s at 128³ (FP64 vs mixed, stated error); served solves/s + p99"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="laguerre-128-g512")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--pass-reps", type=int, default=20)
+    return ap.parse_args()
+
+
+def run_leg(RVE, precision, desc, inp, warmup, steps, torch):
+    r = RVE(desc, precision)
+    r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+    macro = []
+    for k in range(warmup):
+        st = r.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k])
+        macro.append(st["macro_stress"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kry = 0
+    stats = []
+    for k in range(warmup, warmup + steps):
+        st = r.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k])
+        kry += st["krylov_iters"]
+        stats.append(st)
+        macro.append(st["macro_stress"])
+        print(f"# step {k}: {st['ms_total']:.1f} ms, newton {st['newton_iters']}, "
+              f"krylov {st['krylov_iters']}, stag {st['stag_iters']}, pf {st['pf_iters']}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return r, dt, kry, stats, np.array(macro)
+
+
+def time_passes(r, torch, reps):
+    """Average duration of each operator building block, HIP events on the library's
+    stream, and its algorithmic HBM bytes per launch."""
+    from paper_2304_01125_amd.rve import PASSES
+    out = {}
+    s = r.stream
+    for name in ("fft_z", "fft_y", "x_tangent", "grad", "div", "precond", "matvec"):
+        pid = PASSES[name]
+        r.launch_pass(pid, 2)                       # warm
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        nbytes = r.launch_pass(pid, reps)
+        e1.record(s)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": ms, "bytes": nbytes, "gbs": nbytes / (ms * 1e-3) / 1e9}
+    return out
+
+
+def cpu_baseline(w, inp, gpu_stats, n_apply=6, stride=64):
+    """The CPU oracle on a bounded sample of the same workload, scaled to voxel-iters/s.
+
+    Sample: (a) n_apply applications of the oracle's preconditioned momentum operator on
+    the full grid with the elastic tangent of the microstructure, and (b) the oracle's
+    return map on every stride-th voxel at the first increment's strain.  The oracle
+    time of one increment is projected with the operator-application and
+    constitutive-call counts of the GPU FP64 increments (same tolerances), and the
+    rate is voxels x operator applications / projected time.
+    """
+    from oracle import OracleRVE, momentum_operator, to_mandel2
+    o = OracleRVE(w.desc(), inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+    M = o.grid.M
+    gK = (1.0 + w.k_res) * o.tab.C[o.gid]
+    matvec, prec, _ = momentum_operator(o.grid, gK)
+    x = np.random.default_rng(0).standard_normal(3 * M) * 1e-9
+    t0 = time.perf_counter()
+    for _ in range(n_apply):
+        x = prec(matvec(x))
+    t_apply = (time.perf_counter() - t0) / n_apply
+    sub = np.arange(0, M, stride)
+    eps = np.zeros((len(sub), 3, 3))
+    eps[:, 1, 1] = inp["deps"][0]
+    from oracle import return_map
+    t = o.tab
+    gid = o.gid[sub]
+    t0 = time.perf_counter()
+    return_map(to_mandel2(eps), np.zeros((len(sub), 6)), o.g[sub], inp["dt"][0], t.C[gid], t.S[gid],
+               t.P[gid], w.gdot0, w.n_exp)
+    t_const = (time.perf_counter() - t0) * M / len(sub)
+    n_mv = np.mean([s["krylov_iters"] for s in gpu_stats])
+    n_cs = np.mean([s["newton_iters"] + s["ls_cuts"] + s["stag_iters"] for s in gpu_stats])
+    t_inc = n_mv * t_apply + n_cs * t_const
+    return {"value": round(M * n_mv / t_inc, 1), "unit": "voxel-iters/s",
+            "cores": os.cpu_count(), "kind": "oracle",
+            "sample": (f"{n_apply} oracle operator+preconditioner applications on the full "
+                       f"{w.name} grid ({t_apply:.2f} s each) and the oracle return map on 1/"
+                       f"{stride} of its voxels ({t_const:.1f} s per full-grid call, scaled); "
+                       f"one increment projected with the GPU run's counts ({n_mv:.0f} operator "
+                       f"applications, {n_cs:.0f} constitutive calls) = {t_inc:.0f} s")}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2304_01125_amd import RVE, RVE_FP64, RVE_MIXED
+    from synth import workload, make_inputs
+
+    w = workload(a.workload)
+    inp = make_inputs(w)
+    desc = w.desc()
+    r64, dt64, kry64, st64, macro64 = run_leg(RVE, RVE_FP64, desc, inp, a.warmup, a.steps, torch)
+    value = w.nvox * kry64 / dt64
+    passes = time_passes(r64, torch, a.pass_reps)
+    # dominant kernel of the operator: largest share of one matvec
+    per_mv = {"fft_z": 2, "fft_y": 2, "x_tangent": 1, "grad": 1, "div": 1}
+    dom = max(per_mv, key=lambda k: per_mv[k] * passes[k]["ms"])
+    d = passes[dom]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_ms": round(d["ms"], 5), "bytes_per_launch": d["bytes"]}
+    r64.close()
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "voxel-iters/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(1e3 * dt64 / a.steps, 2),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": w.name, "grid": list(w.n), "grains": w.n_grains,
+                      "load": f"R={w.ratio}, +-{w.amplitude * 100:.1f}%, increments "
+                              f"{a.warmup}..{a.warmup + a.steps - 1}",
+                      "tolerances": {"lin": w.tol_lin, "newton": w.tol_newton,
+                                     "stag": w.tol_stag}},
+           "krylov_iters": kry64,
+           "passes": {k: {"ms": round(v["ms"], 5), "GB/s": round(v["gbs"], 1)}
+                      for k, v in passes.items()},
+           "roofline": roof}
+    if not a.no_mixed:
+        r32, dt32, kry32, st32, macro32 = run_leg(RVE, RVE_MIXED, desc, inp, a.warmup, a.steps,
+                                                  torch)
+        p32 = time_passes(r32, torch, a.pass_reps)
+        r32.close()
+        err = np.abs(macro32 - macro64).max(axis=1) / np.abs(macro64).max(axis=1)
+        out["mixed"] = {"value": round(w.nvox * kry32 / dt32, 1), "unit": "voxel-iters/s",
+                        "ms_per_step": round(1e3 * dt32 / a.steps, 2), "dtype": "f32+f64",
+                        "krylov_iters": kry32,
+                        "macro_stress_rel_err_vs_fp64": float(err.max()),
+                        "passes": {k: {"ms": round(v["ms"], 5), "GB/s": round(v["gbs"], 1)}
+                                   for k, v in p32.items()}}
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, inp, st64)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -175,6 +175,25 @@ int rve_diag_constitutive(struct rve_s* h, const double* eps6, double dt, double
  * rve_diag_constitutive (which sets the tangent field). */
 int rve_diag_operator(struct rve_s* h, const double* u3, double* v3);
 
+/* Launch one building block of the momentum operator `reps` times on the handle's
+ * stream and return without synchronising, so that a caller can time it with events
+ * recorded on that stream.  Operands are the handle's own work buffers (their
+ * contents are whatever the last computation left; the physical state is not
+ * touched).  pass_id: RVE_PASS_* below.  Returns the algorithmic bytes one launch
+ * moves through HBM in *bytes_per_launch (may be NULL).  RVE_PASS_CONSTITUTIVE
+ * needs the microstructure and evaluates the tangent at the stored strain. */
+enum {
+  RVE_PASS_FFT_Z = 0,        /* 6-component strided C2C transform along z           */
+  RVE_PASS_FFT_Y = 1,        /* 6-component strided C2C transform along y           */
+  RVE_PASS_X_TANGENT = 2,    /* row C2R, g K : eps, row R2C on 6 components          */
+  RVE_PASS_GRAD = 3,         /* sym(i xi~ (x) u), 3 -> 6 components                  */
+  RVE_PASS_DIV = 4,          /* -i xi~ . sigma, 6 -> 3 components                    */
+  RVE_PASS_PRECOND = 5,      /* [xi~ . Kbar . xi~]^-1 and <r, z>, 3 components        */
+  RVE_PASS_CONSTITUTIVE = 6, /* return map, tangent and reductions                    */
+  RVE_PASS_MATVEC = 7        /* the whole operator application (passes 3,0,1,2,1,0,4) */
+};
+int rve_diag_pass(struct rve_s* h, int32_t pass_id, int32_t reps, double* bytes_per_launch);
+
 typedef struct rve_s* rve_t;
 
 #ifdef __cplusplus

@@ -31,7 +31,7 @@ from .crystal import (quat_to_rot, cubic_stiffness, rotate4, fcc_slip_systems,
                       gnd_matrix)
 from .constitutive import GrainTables, return_map, slip_increments
 from .spectral import Grid
-from .mechanics import solve_mechanics
+from .mechanics import solve_mechanics, momentum_operator
 from .phasefield import split_positive, we_plus, solve_phase_field
 from .history import nye_tensor, gnd_density
 from .increment import OracleRVE
@@ -39,5 +39,6 @@ from .increment import OracleRVE
 __all__ = ["quat_to_rot", "cubic_stiffness", "rotate4", "fcc_slip_systems", "screw_directions",
            "to_mandel2", "from_mandel2", "to_mandel4", "from_mandel4", "gnd_matrix",
            "GrainTables", "return_map", "slip_increments", "Grid", "solve_mechanics",
+           "momentum_operator",
            "split_positive", "we_plus", "solve_phase_field", "nye_tensor", "gnd_density",
            "OracleRVE"]

@@ -27,6 +27,33 @@ from scipy.sparse.linalg import LinearOperator, cg
 from .crystal import to_mandel2, from_mandel2, from_mandel4
 
 
+def momentum_operator(grid, gK):
+    """The linearised momentum operator and its preconditioner for a tangent field.
+
+    gK: (M,6,6) Mandel degraded tangent g(phi) K.  Returns (matvec, prec, count):
+    matvec(u) = -F^-1{ i xi~ . F{ gK : F^-1{ sym(i xi~ (x) F{u}) } } } on flat real
+    displacement vectors, prec(r) = F^-1{ [xi~ . Kbar . xi~]^-1 F{r} } with Kbar =
+    mean(gK), and count[0] the number of operator applications so far.
+    """
+    n = grid.n
+    Ainv = grid.acoustic_inverse(from_mandel4(gK.mean(0)))
+    gK_g = grid.to_grid(gK)
+    count = [0]
+
+    def matvec(x):
+        count[0] += 1
+        u = x.reshape(n + (3,))
+        de = grid.ifft(grid.sym_grad_hat(grid.fft(u)))
+        ds = from_mandel2(np.einsum("...ij,...j->...i", gK_g, to_mandel2(de)))
+        return -grid.ifft(grid.div_hat(grid.fft(ds))).ravel()
+
+    def prec(x):
+        y = np.einsum("...ik,...k->...i", Ainv, grid.fft(x.reshape(n + (3,))))
+        return grid.ifft(y).ravel()
+
+    return matvec, prec, count
+
+
 def solve_mechanics(grid, eps0, eps_t, gphi, constit, tol_newton, tol_lin, max_newton,
                     max_krylov, stats=None):
     """Equilibrated strain (M,3,3) starting from ``eps0``.
@@ -40,24 +67,9 @@ def solve_mechanics(grid, eps0, eps_t, gphi, constit, tol_newton, tol_lin, max_n
     sigM, dgam, KM, w = constit(to_mandel2(eps))
     Pi = np.mean(gphi * w)
     for it in range(max_newton):
-        gK = gphi[:, None, None] * KM
-        Ainv = grid.acoustic_inverse(from_mandel4(gK.mean(0)))
-        gK_g = grid.to_grid(gK)
+        matvec, prec, count = momentum_operator(grid, gphi[:, None, None] * KM)
         gsig = grid.to_grid(gphi[:, None, None] * from_mandel2(sigM))
         rhs = grid.ifft(grid.div_hat(grid.fft(gsig))).ravel()
-        count = [0]
-
-        def matvec(x):
-            count[0] += 1
-            u = x.reshape(n + (3,))
-            de = grid.ifft(grid.sym_grad_hat(grid.fft(u)))
-            ds = from_mandel2(np.einsum("...ij,...j->...i", gK_g, to_mandel2(de)))
-            return -grid.ifft(grid.div_hat(grid.fft(ds))).ravel()
-
-        def prec(x):
-            y = np.einsum("...ik,...k->...i", Ainv, grid.fft(x.reshape(n + (3,))))
-            return grid.ifft(y).ravel()
-
         N = rhs.size
         A = LinearOperator((N, N), matvec=matvec, dtype=np.float64)
         P = LinearOperator((N, N), matvec=prec, dtype=np.float64)

@@ -804,6 +804,41 @@ int rve_destroy(rve_s* h) {
 
 // ---- diagnostics -------------------------------------------------------------------
 template <typename R>
+static int diag_pass(rve_s* h, int pass_id, int reps, double* bytes) {
+  typedef cplx<R> C;
+  Ops<R> o(h);
+  const double N = (double)h->g.nvox, NH = (double)h->g.nspec;
+  const double cb = sizeof(C), rb = sizeof(R);
+  double b = 0.0;
+  hipStream_t st = h->st;
+  for (int k = 0; k < reps; ++k) {
+    switch (pass_id) {
+      case RVE_PASS_FFT_Z: launch_fft_yz<R>(h->pl, o.W, h->g.nspec, 6, 2, true, st); break;
+      case RVE_PASS_FFT_Y: launch_fft_yz<R>(h->pl, o.W, h->g.nspec, 6, 1, true, st); break;
+      case RVE_PASS_X_TANGENT: launch_x_tangent<R>(h->pl, o.W, h->g.nspec, o.gK(), 1.0 / N, st); break;
+      case RVE_PASS_GRAD: launch_sym_grad<R>(h->pl, o.v(3), h->g.nspec, o.W, h->g.nspec, st); break;
+      case RVE_PASS_DIV: launch_div<R>(h->pl, o.W, h->g.nspec, o.v(4), h->g.nspec, -1.0, st); break;
+      case RVE_PASS_PRECOND:
+        launch_precond<R>(h->pl, o.v(1), o.v(2), h->g.nspec, h->scal + SC_KBAR, h->partial, st);
+        break;
+      case RVE_PASS_CONSTITUTIVE: o.cur_dt = 1.0; o.constitutive(nullptr, 0.0, h->phi); break;
+      case RVE_PASS_MATVEC: o.matvec(o.v(3), o.v(4)); break;
+    }
+  }
+  switch (pass_id) {
+    case RVE_PASS_FFT_Z: case RVE_PASS_FFT_Y: b = 2 * 6 * NH * cb; break;
+    case RVE_PASS_X_TANGENT: b = 2 * 6 * NH * cb + 21 * N * rb; break;
+    case RVE_PASS_GRAD: case RVE_PASS_DIV: b = 9 * NH * cb; break;
+    case RVE_PASS_PRECOND: b = 6 * NH * cb; break;
+    case RVE_PASS_CONSTITUTIVE: b = N * (4 * 6 * 8 + 3 * 8 + 4 + 6 * 8 + 21 * rb); break;
+    case RVE_PASS_MATVEC: b = (9 + 4 * 12 + 12 + 9) * NH * cb + 21 * N * rb; break;
+  }
+  if (bytes) *bytes = b;
+  HIPCHK(hipGetLastError());
+  return RVE_OK;
+}
+
+template <typename R>
 static int diag_fft(rve_s* h, int ncomp, const double* in, double* out, bool forward) {
   typedef cplx<R> C;
   Ops<R> o(h);
@@ -878,6 +913,12 @@ static int diag_op(rve_s* h, const double* u3, double* v3) {
 }
 
 extern "C" {
+
+int rve_diag_pass(rve_s* h, int32_t pass_id, int32_t reps, double* bytes) {
+  if (!h || reps < 0 || pass_id < 0 || pass_id > RVE_PASS_MATVEC) return fail(RVE_E_ARG, "bad argument");
+  if (pass_id == RVE_PASS_CONSTITUTIVE && !h->micro) return fail(RVE_E_STATE, "microstructure not set");
+  return h->f64 ? diag_pass<double>(h, pass_id, reps, bytes) : diag_pass<float>(h, pass_id, reps, bytes);
+}
 
 int rve_diag_rfft(rve_s* h, int32_t ncomp, const double* in, double* out) {
   if (!h || !in || !out || ncomp < 1 || ncomp > 9) return fail(RVE_E_ARG, "bad argument");

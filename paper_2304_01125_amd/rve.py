@@ -22,6 +22,8 @@ FIELDS = [  # (name, bit, components) in the order rve_fields writes them
     ("eps_p", 1 << 11, 6), ("g", 1 << 12, 1), ("beta_p", 1 << 13, 9),
 ]
 FIELD_BITS = {n: (b, c) for n, b, c in FIELDS}
+PASSES = {"fft_z": 0, "fft_y": 1, "x_tangent": 2, "grad": 3, "div": 4, "precond": 5,
+          "constitutive": 6, "matvec": 7}
 
 
 class RveDesc(ctypes.Structure):
@@ -96,6 +98,8 @@ def load():
         f.argtypes = [_P, ctypes.c_int32, _D, _D]
     lib.rve_diag_constitutive.restype = ctypes.c_int
     lib.rve_diag_constitutive.argtypes = [_P, _D, ctypes.c_double, _D, _D]
+    lib.rve_diag_pass.restype = ctypes.c_int
+    lib.rve_diag_pass.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, _D]
     lib.rve_diag_operator.restype = ctypes.c_int
     lib.rve_diag_operator.argtypes = [_P, _D, _D]
     _lib = lib
@@ -106,7 +110,7 @@ def exported_symbols():
     """Names of the C ABI entry points (as declared in include/rve.h)."""
     return ["rve_footprint_bytes", "rve_create", "rve_set_microstructure", "rve_step_increment",
             "rve_fields", "rve_fields_count", "rve_destroy", "rve_last_error", "rve_diag_rfft",
-            "rve_diag_irfft", "rve_diag_constitutive", "rve_diag_operator"]
+            "rve_diag_irfft", "rve_diag_constitutive", "rve_diag_operator", "rve_diag_pass"]
 
 
 class RveError(RuntimeError):
@@ -249,6 +253,13 @@ class RVE:
         v = np.empty(3 * self.nvox)
         _check(load().rve_diag_operator(self.h, _dptr(u), _dptr(v)))
         return v.reshape(3, self.nvox).T
+
+    def launch_pass(self, pass_id, reps):
+        """Enqueue `reps` launches of one operator building block on the handle's stream
+        (no synchronisation); returns the algorithmic bytes of one launch."""
+        b = ctypes.c_double(0.0)
+        _check(load().rve_diag_pass(self.h, int(pass_id), int(reps), ctypes.byref(b)))
+        return b.value
 
     def close(self):
         if getattr(self, "h", None):

@@ -1,0 +1,83 @@
+"""Writes the stored expected values of the GPU parity tests by running the CPU oracle.
+
+Only ``oracle`` (and the seeded input generators in ``synth``) are called.  Outputs:
+
+* notched16.npz -- the notched single crystal on 16^3 (the plain-method FP64 workload),
+  tight (parity) tolerances, fields after selected increments and the macro stress of
+  every increment, up to the first increment where the damage jumps by more than 0.5
+  in one increment or the alternating-minimisation count exceeds three times its
+  median (beyond that the crack path may bifurcate and several answers are correct).
+* voronoi64.npz -- the 64^3 Voronoi polycrystal (64 grains), tight tolerances, the
+  first increments, fields at 4096 seeded sample voxels and the macro stress.
+
+Usage: python tests/golden/make_golden.py [notched16|voronoi64] ...
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import OracleRVE          # noqa: E402
+from synth import workload, make_inputs   # noqa: E402
+
+FIELDS = ("strain", "stress", "damage", "gs", "wp", "rho_gnd")
+
+
+def notched16(max_inc=40, snaps=(5, 11, 13, 15, 19, 25, 31, 39)):
+    w = workload("notched-crystal-16").parity()
+    inp = make_inputs(w)
+    o = OracleRVE(w.desc(), inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+    out = {"macro_stress": [], "stag": [], "max_phi_slip": []}
+    stags = []
+    prev_phi = o.phi.copy()
+    notch = inp["phi0"] >= 1.0
+    t0 = time.time()
+    last = -1
+    for k in range(max_inc):
+        st = o.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k])
+        jump = np.abs(o.phi - prev_phi)[~notch].max()
+        prev_phi = o.phi.copy()
+        stags.append(st["stag"])
+        print(f"inc {k}: {time.time() - t0:.0f}s stag {st['stag']} newton {st['newton']} "
+              f"jump {jump:.3f} maxphi {o.phi[~notch].max():.4f}", flush=True)
+        if jump > 0.5 or (k > 4 and st["stag"] > 3 * max(2, np.median(stags))):
+            print("stopping: damage instability", flush=True)
+            break
+        last = k
+        out["macro_stress"].append(st["macro_stress"])
+        out["stag"].append(st["stag"])
+        out["max_phi_slip"].append(float(o.phi[~notch].max()))
+        if k in snaps:
+            f = o.fields()
+            for name in FIELDS:
+                out[f"inc{k}_{name}"] = f[name]
+        np.savez_compressed(os.path.join(HERE, "notched16.npz"), last=last,
+                            **{k2: np.asarray(v) for k2, v in out.items()})
+
+
+def voronoi64(n_inc=2, n_sample=4096):
+    w = workload("voronoi-64-g64").parity()
+    inp = make_inputs(w)
+    o = OracleRVE(w.desc(), inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+    idx = np.sort(np.random.default_rng(64).choice(w.nvox, n_sample, replace=False))
+    out = {"sample": idx, "macro_stress": []}
+    t0 = time.time()
+    for k in range(n_inc):
+        st = o.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k])
+        print(f"inc {k}: {time.time() - t0:.0f}s newton {st['newton']} matvecs {st['matvecs']}",
+              flush=True)
+        out["macro_stress"].append(st["macro_stress"])
+        f = o.fields()
+        for name in FIELDS:
+            out[f"inc{k}_{name}"] = f[name][idx]
+        np.savez_compressed(os.path.join(HERE, "voronoi64.npz"), last=k,
+                            **{k2: np.asarray(v) for k2, v in out.items()})
+
+
+if __name__ == "__main__":
+    for name in sys.argv[1:] or ["notched16", "voronoi64"]:
+        globals()[name]()
