@@ -3,8 +3,9 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["csrc/rve.hip", "csrc/spectral.hip", "csrc/voxel.hip", "csrc/vector.hip"]
-FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+SOURCES = ["csrc/rve.hip", "csrc/passes.hip", "csrc/spectral.hip", "csrc/voxel.hip",
+           "csrc/vector.hip"]
+FLAGS = ["-O3", "-std=c++20", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 

@@ -94,4 +94,143 @@ __device__ cplx<R>* fft_pencils(cplx<R>* a, cplx<R>* b, const cplx<R>* tw, const
   return a;
 }
 
+// ---- compile-time lengths ---------------------------------------------------------
+// Radix of stage s of the schedule used for length n (4s first, then 2, then 3s) and
+// the number of stages; identical to make_axis_plan.
+constexpr int ct_radix(int n, int s) {
+  int m = n, k = 0;
+  while (m % 4 == 0) { if (k == s) return 4; m /= 4; ++k; }
+  while (m % 2 == 0) { if (k == s) return 2; m /= 2; ++k; }
+  while (m % 3 == 0) { if (k == s) return 3; m /= 3; ++k; }
+  return 1;
+}
+constexpr int ct_nstages(int n) {
+  int m = n, k = 0;
+  while (m % 4 == 0) { m /= 4; ++k; }
+  while (m % 2 == 0) { m /= 2; ++k; }
+  while (m % 3 == 0) { m /= 3; ++k; }
+  return k;
+}
+
+// One Stockham stage with every size known at compile time.  Layout: element (n, p)
+// at n*SN + p*SP.  P pencils; PFAST as in fft_pencils.  P may be 0 for "runtime P"
+// (only with PFAST = false, where no division by P is needed).
+template <typename R, int N, int S, int NS, int SN, int SP, int PCT, bool PFAST>
+__device__ __forceinline__ void ct_stage(const cplx<R>* __restrict__ a, cplx<R>* __restrict__ b,
+                                         const cplx<R>* __restrict__ tw, int P, bool inv) {
+  constexpr int r = ct_radix(N, S);
+  constexpr int nb = N / r;
+  constexpr int tstride = N / (NS * r);
+  const int Pn = PCT ? PCT : P;
+  const int sp = SP ? SP : 0;
+  for (int t = threadIdx.x; t < nb * Pn; t += blockDim.x) {
+    int p, j;
+    if constexpr (PFAST) { p = t % PCT; j = t / PCT; } else { j = t % nb; p = t / nb; }
+    const int k = j % NS;
+    cplx<R> v[4];
+#pragma unroll
+    for (int q = 0; q < r; ++q) v[q] = a[(j + q * nb) * SN + p * sp];
+#pragma unroll
+    for (int q = 1; q < r; ++q) {
+      cplx<R> w = tw[q * k * tstride];
+      if (inv) w.y = -w.y;
+      v[q] = cmul(v[q], w);
+    }
+    small_dft(v, r, inv);
+    const int idxD = (j / NS) * NS * r + k;
+#pragma unroll
+    for (int q = 0; q < r; ++q) b[(idxD + q * NS) * SN + p * sp] = v[q];
+  }
+}
+
+template <typename R, int N, int S, int NS, int SN, int SP, int PCT, bool PFAST>
+__device__ __forceinline__ cplx<R>* ct_run(cplx<R>* a, cplx<R>* b, const cplx<R>* tw, int P,
+                                           bool inv) {
+  if constexpr (S == ct_nstages(N)) {
+    return a;
+  } else {
+    ct_stage<R, N, S, NS, SN, SP, PCT, PFAST>(a, b, tw, P, inv);
+    __syncthreads();
+    return ct_run<R, N, S + 1, NS * ct_radix(N, S), SN, SP, PCT, PFAST>(b, a, tw, P, inv);
+  }
+}
+
+// TX pencils of length N in layout [n][TX] (pencil fastest): strided passes.
+template <typename R, int N, int TX>
+__device__ __forceinline__ cplx<R>* fft_tiles_ct(cplx<R>* a, cplx<R>* b, const cplx<R>* tw,
+                                                 bool inv) {
+  return ct_run<R, N, 0, 1, TX, 1, TX, true>(a, b, tw, TX, inv);
+}
+
+// P pencils of length N in layout [p][N+1] (row fastest): x passes.
+template <typename R, int N>
+__device__ __forceinline__ cplx<R>* fft_rows_ct(cplx<R>* a, cplx<R>* b, const cplx<R>* tw, int P,
+                                                bool inv) {
+  return ct_run<R, N, 0, 1, 1, N + 1, 0, false>(a, b, tw, P, inv);
+}
+
+// ---- in-place (single LDS buffer) stages ------------------------------------------
+// Each thread first reads the inputs of all its butterflies into registers, the block
+// synchronises, then every thread writes its outputs over the same buffer: half the
+// LDS of a ping-pong pair, hence twice the resident blocks.  NT = block size.
+template <typename R, int N, int S, int NS, int SN, int SP, int P, bool PFAST, int NT>
+__device__ __forceinline__ void ct_stage_ip(cplx<R>* __restrict__ a, const cplx<R>* __restrict__ tw,
+                                            bool inv) {
+  constexpr int r = ct_radix(N, S);
+  constexpr int nb = N / r;
+  constexpr int tstride = N / (NS * r);
+  constexpr int total = nb * P;
+  constexpr int per = (total + NT - 1) / NT;
+  cplx<R> v[per][4];
+#pragma unroll
+  for (int u = 0; u < per; ++u) {
+    const int t = threadIdx.x + u * NT;
+    if (t < total) {
+      int p, j;
+      if constexpr (PFAST) { p = t % P; j = t / P; } else { j = t % nb; p = t / nb; }
+#pragma unroll
+      for (int q = 0; q < r; ++q) v[u][q] = a[(j + q * nb) * SN + p * SP];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < per; ++u) {
+    const int t = threadIdx.x + u * NT;
+    if (t < total) {
+      int p, j;
+      if constexpr (PFAST) { p = t % P; j = t / P; } else { j = t % nb; p = t / nb; }
+      const int k = j % NS;
+#pragma unroll
+      for (int q = 1; q < r; ++q) {
+        cplx<R> w = tw[q * k * tstride];
+        if (inv) w.y = -w.y;
+        v[u][q] = cmul(v[u][q], w);
+      }
+      small_dft(v[u], r, inv);
+      const int idxD = (j / NS) * NS * r + k;
+#pragma unroll
+      for (int q = 0; q < r; ++q) a[(idxD + q * NS) * SN + p * SP] = v[u][q];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename R, int N, int S, int NS, int SN, int SP, int P, bool PFAST, int NT>
+__device__ __forceinline__ void ct_run_ip(cplx<R>* a, const cplx<R>* tw, bool inv) {
+  if constexpr (S < ct_nstages(N)) {
+    ct_stage_ip<R, N, S, NS, SN, SP, P, PFAST, NT>(a, tw, inv);
+    ct_run_ip<R, N, S + 1, NS * ct_radix(N, S), SN, SP, P, PFAST, NT>(a, tw, inv);
+  }
+}
+
+// In-place transforms: TX pencils in [n][TX] layout, or P rows in [p][N+1] layout.
+template <typename R, int N, int TX, int NT>
+__device__ __forceinline__ void fft_tiles_ip(cplx<R>* a, const cplx<R>* tw, bool inv) {
+  ct_run_ip<R, N, 0, 1, TX, 1, TX, true, NT>(a, tw, inv);
+}
+template <typename R, int N, int P, int NT>
+__device__ __forceinline__ void fft_rows_ip(cplx<R>* a, const cplx<R>* tw, bool inv) {
+  ct_run_ip<R, N, 0, 1, 1, N + 1, P, false, NT>(a, tw, inv);
+}
+
 }  // namespace rvefft

@@ -13,6 +13,9 @@ struct Plans {
   const void* tw_ptr(int axis, bool f64) const { return f64 ? tw64[axis] : tw32[axis]; }
 };
 
+// Upload the constant twiddle tables of the register DFTs (current device).
+void upload_reg_twiddles(hipStream_t st);
+
 // Radix schedule of a length 2^a 3^b; returns false for other lengths.
 bool make_axis_plan(int n, AxisPlan* out);
 
@@ -39,19 +42,19 @@ void launch_x_c2r(const Plans& p, const cplx<R>* in, long long in_cs, void* out,
                   long long out_cs, int ncomp, double scale, int accumulate, hipStream_t st);
 template <typename R>
 void launch_x_tangent(const Plans& p, cplx<R>* data, long long cs, const R* gK, double scale,
-                      hipStream_t st);
+                      hipStream_t st, const double* stop = nullptr);
 template <typename R>
 void launch_fft_yz(const Plans& p, cplx<R>* data, long long cs, int ncomp, int axis, bool inv,
-                   hipStream_t st);
+                   hipStream_t st, const double* stop = nullptr);
 template <typename R>
 void launch_sym_grad(const Plans& p, const cplx<R>* u, long long ucs, cplx<R>* e, long long ecs,
-                     hipStream_t st);
+                     hipStream_t st, const double* stop = nullptr);
 template <typename R>
 void launch_div(const Plans& p, const cplx<R>* s, long long scs, cplx<R>* out, long long ocs,
-                double sign, hipStream_t st);
+                double sign, hipStream_t st, const double* stop = nullptr);
 template <typename R>
 int launch_precond(const Plans& p, const cplx<R>* r, cplx<R>* z, long long cs, const double* kbar21,
-                   double* partial, hipStream_t st);
+                   double* partial, hipStream_t st, const double* stop = nullptr);
 // Hermitian projection of the self-conjugate x-planes (spectra of real fields)
 template <typename R>
 void launch_herm_proj(const Plans& p, cplx<R>* v, long long cs, int ncomp, hipStream_t st);
@@ -74,6 +77,7 @@ enum {
 
 struct Material {
   double dt, gdot0, nexp, kres, h_lin, lambda_ssd, xi_store, G_crit, ell, Gc, burgers;
+  int nexp_int;   // nexp when it is an integer in [1, 64], else 0 (then pow is used)
 };
 
 // number of reduction values written by each voxel kernel per block
@@ -87,7 +91,7 @@ int voxel_grid(long long n);
 template <typename R>
 void launch_constitutive(long long N, const double* eps, const double* deps, double t,
                          const double* epsp, const double* gslip, const int* grain,
-                         const double* gtab, double* sig, const double* phi, R* gK,
+                         const double* gtab, double* sig, const double* phi, R* gK, double* gw,
                          const Material& m, double* partial, int* fail, hipStream_t st);
 void launch_source(long long N, const double* eps, const double* sig, const double* epsp,
                    const double* gslip, const int* grain, const double* gtab, const double* wp,
@@ -118,20 +122,23 @@ void launch_clamp(long long N, const double* x, const double* phi_t, double* phi
 // --- reductions and vector kernels (vector.hip) ---------------------------------------
 // out[c] = sum (or max) over b < nblk of partial[c*nblk + b], fixed order.
 void launch_reduce(const double* partial, int nblk, int ncomp, int op_max, double* out,
-                   hipStream_t st);
+                   hipStream_t st, const double* stop = nullptr);
 // Parseval-weighted <a,b> over ncomp half-spectrum components; returns #blocks.
 template <typename R>
 int launch_sdot(const Plans& p, const cplx<R>* a, const cplx<R>* b, long long cs, int ncomp,
-                double* partial, hipStream_t st);
+                double* partial, hipStream_t st, const double* stop = nullptr);
 // CG updates on half-spectrum vectors (3 comps), scalars read from device `sc`:
 // x += a p ; r -= a q ; partial <r,r>   with a = sc[ia] / sc[ib]
 template <typename R>
 int launch_cg_xr(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, const cplx<R>* q,
-                 long long cs, const double* sc, int ia, int ib, double* partial, hipStream_t st);
+                 long long cs, const double* sc, int ia, int ib, double* partial, hipStream_t st,
+                 const double* stop = nullptr);
 // p = z + b p with b = sc[ia] / sc[ib]
 template <typename R>
 void launch_cg_p(const Plans& p, cplx<R>* pv, const cplx<R>* z, long long cs, const double* sc,
-                 int ia, int ib, hipStream_t st);
+                 int ia, int ib, hipStream_t st, const double* stop = nullptr);
+// device-side CG convergence test (see vector.hip)
+void launch_cg_check(double* sc, int flag, int iter, int rr, int tol2, int pq, hipStream_t st);
 // real-vector kernels (phase field)
 int launch_rdot(long long n, const double* a, const double* b, double* partial, hipStream_t st);
 // pq = <p, w + 2 S p>

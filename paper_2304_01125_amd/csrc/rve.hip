@@ -202,7 +202,7 @@ struct rve_s {
   size_t cap = 0, used = 0;
   // state (FP64)
   double *eps, *eps_t, *eps_prev, *deps, *sig, *sig_t, *epsp, *beta, *gslip, *rho_ssd, *rho_gnd,
-      *wp, *gs, *H, *wcrit, *trig, *phi, *phi_t, *phi_prev, *S, *wep;
+      *wp, *gs, *H, *wcrit, *trig, *phi, *phi_t, *phi_prev, *S, *wep, *gw;
   int* grain;
   double* gtab;
   double* Q81;
@@ -223,6 +223,7 @@ namespace {
 enum { SC_K = 0,        // 28 constitutive sums (21 gK, g w, 6 g sigma)
        SC_KBAR = 32,    // 21 mean tangent
        SC_RZ0 = 56, SC_RZ1 = 57, SC_PQ = 58, SC_RR = 59, SC_BB = 60,
+       SC_FLAG = 61, SC_ITER = 62, SC_TOL2 = 63,
        SC_MISC = 64,    // generic reduce outputs (16)
        SC_N = 96 };
 
@@ -243,7 +244,7 @@ void layout(rve_s* h) {
   h->sig = fd(6 * N); h->sig_t = fd(6 * N); h->epsp = fd(6 * N); h->beta = fd(9 * N);
   h->gslip = fd(N); h->rho_ssd = fd(N); h->rho_gnd = fd(N); h->wp = fd(N); h->gs = fd(N);
   h->H = fd(N); h->wcrit = fd(N); h->trig = fd(N); h->phi = fd(N); h->phi_t = fd(N);
-  h->phi_prev = fd(N); h->S = fd(N); h->wep = fd(N);
+  h->phi_prev = fd(N); h->S = fd(N); h->wep = fd(N); h->gw = fd(N);
   h->grain = (int*)take((size_t)N * 4);
   h->gtab = fd((long long)h->d.max_grains * GT_STRIDE);
   h->Q81 = fd(81);
@@ -332,15 +333,16 @@ struct Ops {
     launch_fft_yz<R>(h->pl, in, NH, ncomp, 1, true, st);
     launch_x_c2r<R>(h->pl, in, NH, out, out64, out_cs, ncomp, scale, acc, st);
   }
-  // q = B p = - i xi~ . F{ gK : F^-1{ sym(i xi~ (x) p) } }
-  void matvec(const C* p, C* q) {
-    launch_sym_grad<R>(h->pl, p, NH, W, NH, st);
-    launch_fft_yz<R>(h->pl, W, NH, 6, 2, true, st);
-    launch_fft_yz<R>(h->pl, W, NH, 6, 1, true, st);
-    launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st);
-    launch_fft_yz<R>(h->pl, W, NH, 6, 1, false, st);
-    launch_fft_yz<R>(h->pl, W, NH, 6, 2, false, st);
-    launch_div<R>(h->pl, W, NH, q, NH, -1.0, st);
+  // q = B p = - i xi~ . F{ gK : F^-1{ sym(i xi~ (x) p) } }; every launch is skipped
+  // once *stop is non-zero (device-side Krylov termination).
+  void matvec(const C* p, C* q, const double* stop = nullptr) {
+    launch_sym_grad<R>(h->pl, p, NH, W, NH, st, stop);
+    launch_fft_yz<R>(h->pl, W, NH, 6, 2, true, st, stop);
+    launch_fft_yz<R>(h->pl, W, NH, 6, 1, true, st, stop);
+    launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
+    launch_fft_yz<R>(h->pl, W, NH, 6, 1, false, st, stop);
+    launch_fft_yz<R>(h->pl, W, NH, 6, 2, false, st, stop);
+    launch_div<R>(h->pl, W, NH, q, NH, -1.0, st, stop);
   }
   // mean tangent from the constitutive sums
   void kbar() { launch_rscale(21, h->scal + SC_K, 1.0 / (double)N, h->scal + SC_KBAR, st); }
@@ -349,7 +351,7 @@ struct Ops {
     Material m = mat(0.0);
     m.dt = cur_dt;
     launch_constitutive<R>(N, h->eps, deps, t, h->epsp, h->gslip, h->grain, h->gtab, h->sig, phi,
-                           gK(), m, h->partial, h->failc, st);
+                           gK(), h->gw, m, h->partial, h->failc, st);
     launch_reduce(h->partial, voxel_grid(N), RED_CONST, 0, h->scal + SC_K, st);
     return RVE_OK;
   }
@@ -359,44 +361,59 @@ struct Ops {
     m.dt = dt; m.gdot0 = h->d.gdot0; m.nexp = h->d.n_exp; m.kres = h->d.k_res;
     m.h_lin = h->d.h_lin; m.lambda_ssd = h->d.lambda_ssd; m.xi_store = h->d.xi_store;
     m.G_crit = h->d.G_crit; m.ell = h->d.ell; m.Gc = h->d.Gc; m.burgers = h->d.burgers;
+    const double ne = h->d.n_exp;
+    m.nexp_int = (ne == std::floor(ne) && ne >= 1.0 && ne <= 64.0) ? (int)ne : 0;
     return m;
   }
 
-  // Preconditioned CG on B du = c (c in cg[5]); solution in cg[0].
+  // Preconditioned CG on B du = c (c in cg[5]); solution in cg[0].  Iterations are
+  // enqueued in batches; the convergence test runs on the device and turns the rest of
+  // a batch into no-ops, so the host synchronises once per batch.
   int pcg(int& iters) {
     C *x = v(0), *r = v(1), *z = v(2), *p = v(3), *q = v(4), *b = v(5);
     const size_t bytes = (size_t)3 * NH * sizeof(C);
+    double* sc = h->scal;
     launch_zero(x, bytes, st);
     HIPCHK(hipMemcpyAsync(r, b, bytes, hipMemcpyDeviceToDevice, st));
     int nb = launch_sdot<R>(h->pl, b, b, NH, 3, h->partial, st);
-    launch_reduce(h->partial, nb, 1, 0, h->scal + SC_BB, st);
-    nb = launch_precond<R>(h->pl, r, z, NH, h->scal + SC_KBAR, h->partial, st);
-    launch_reduce(h->partial, nb, 1, 0, h->scal + SC_RZ0, st);
+    launch_reduce(h->partial, nb, 1, 0, sc + SC_BB, st);
+    nb = launch_precond<R>(h->pl, r, z, NH, sc + SC_KBAR, h->partial, st);
+    launch_reduce(h->partial, nb, 1, 0, sc + SC_RZ0, st);
     HIPCHK(hipMemcpyAsync(p, z, bytes, hipMemcpyDeviceToDevice, st));
     int rc = sync_read(h, SC_BB, 1);
     if (rc) return rc;
     const double bb = h->hs[SC_BB];
     iters = 0;
     if (!(bb > 0.0)) return std::isfinite(bb) ? RVE_OK : fail(RVE_E_NOCONV, "non-finite residual");
-    const double tol2 = h->d.tol_lin * h->d.tol_lin * bb;
+    h->hs[SC_FLAG] = 0.0;
+    h->hs[SC_ITER] = 0.0;
+    h->hs[SC_TOL2] = h->d.tol_lin * h->d.tol_lin * bb;
+    HIPCHK(hipMemcpyAsync(sc + SC_FLAG, h->hs + SC_FLAG, 3 * sizeof(double), hipMemcpyHostToDevice, st));
+    const double* stop = sc + SC_FLAG;
     int cur = SC_RZ0, nxt = SC_RZ1;
-    for (int k = 0; k < h->d.max_krylov; ++k) {
-      matvec(p, q);
-      nb = launch_sdot<R>(h->pl, p, q, NH, 3, h->partial, st);
-      launch_reduce(h->partial, nb, 1, 0, h->scal + SC_PQ, st);
-      nb = launch_cg_xr<R>(h->pl, x, r, p, q, NH, h->scal, cur, SC_PQ, h->partial, st);
-      launch_reduce(h->partial, nb, 1, 0, h->scal + SC_RR, st);
-      rc = sync_read(h, SC_PQ, 2);
+    int queued = 0, batch = 4;
+    while (queued < h->d.max_krylov) {
+      const int nq = std::min(batch, h->d.max_krylov - queued);
+      for (int k = 0; k < nq; ++k) {
+        matvec(p, q, stop);
+        nb = launch_sdot<R>(h->pl, p, q, NH, 3, h->partial, st, stop);
+        launch_reduce(h->partial, nb, 1, 0, sc + SC_PQ, st, stop);
+        nb = launch_cg_xr<R>(h->pl, x, r, p, q, NH, sc, cur, SC_PQ, h->partial, st, stop);
+        launch_reduce(h->partial, nb, 1, 0, sc + SC_RR, st, stop);
+        launch_cg_check(sc, SC_FLAG, SC_ITER, SC_RR, SC_TOL2, SC_PQ, st);
+        nb = launch_precond<R>(h->pl, r, z, NH, sc + SC_KBAR, h->partial, st, stop);
+        launch_reduce(h->partial, nb, 1, 0, sc + nxt, st, stop);
+        launch_cg_p<R>(h->pl, p, z, NH, sc, nxt, cur, st, stop);
+        std::swap(cur, nxt);
+      }
+      queued += nq;
+      rc = sync_read(h, SC_FLAG, 2);
       if (rc) return rc;
-      iters = k + 1;
-      const double pq = h->hs[SC_PQ], rr = h->hs[SC_RR];
-      if (g_debug) std::fprintf(stderr, "  pcg %d pq %.6e rr/bb %.6e\n", k, pq, std::sqrt(rr / bb));
-      if (!(pq > 0.0) || !std::isfinite(rr)) return fail(RVE_E_NOCONV, "momentum CG breakdown");
-      if (rr <= tol2) return RVE_OK;
-      nb = launch_precond<R>(h->pl, r, z, NH, h->scal + SC_KBAR, h->partial, st);
-      launch_reduce(h->partial, nb, 1, 0, h->scal + nxt, st);
-      launch_cg_p<R>(h->pl, p, z, NH, h->scal, nxt, cur, st);
-      std::swap(cur, nxt);
+      iters = (int)h->hs[SC_ITER];
+      if (g_debug) std::fprintf(stderr, "  pcg queued %d ran %d flag %g\n", queued, iters, h->hs[SC_FLAG]);
+      if (h->hs[SC_FLAG] == 1.0) return RVE_OK;
+      if (h->hs[SC_FLAG] == 2.0) return fail(RVE_E_NOCONV, "momentum CG breakdown");
+      batch = std::min(2 * batch, 16);
     }
     return fail(RVE_E_NOCONV, "momentum Krylov solver reached max_krylov");
   }
@@ -660,6 +677,7 @@ int rve_create(const rve_desc* d, void* dev_arena, size_t arena_bytes, void* hip
       return fail(RVE_E_DEVICE, "twiddle upload failed");
     }
   }
+  upload_reg_twiddles(h->st);
   double Q[81];
   gnd_q(Q);
   if (hipMemcpyAsync(h->Q81, Q, 81 * 8, hipMemcpyHostToDevice, h->st) != hipSuccess ||

@@ -16,7 +16,8 @@ static int vgrid(long long n) {
 }
 
 __global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ partial, int nblk, int op_max,
-                         double* __restrict__ out) {
+                         double* __restrict__ out, const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
   __shared__ double sh[256];
   const int c = blockIdx.x;
   double s = op_max ? -INFINITY : 0.0;
@@ -37,8 +38,8 @@ __global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ parti
 }
 
 void launch_reduce(const double* partial, int nblk, int ncomp, int op_max, double* out,
-                   hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce, dim3(ncomp), dim3(256), 0, st, partial, nblk, op_max, out);
+                   hipStream_t st, const double* stop) {
+  hipLaunchKernelGGL(k_reduce, dim3(ncomp), dim3(256), 0, st, partial, nblk, op_max, out, stop);
 }
 
 __device__ __forceinline__ double pw_weight(long long b, const Grid& g) {
@@ -48,7 +49,9 @@ __device__ __forceinline__ double pw_weight(long long b, const Grid& g) {
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_sdot(const cplx<R>* __restrict__ a, const cplx<R>* __restrict__ bv, long long cs,
-                       int ncomp, Grid g, double* __restrict__ partial) {
+                       int ncomp, Grid g, double* __restrict__ partial,
+                       const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
   __shared__ double red[16];
   double acc = 0.0;
   for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < g.nspec;
@@ -65,9 +68,9 @@ __global__ void __launch_bounds__(256) k_sdot(const cplx<R>* __restrict__ a, con
 
 template <typename R>
 int launch_sdot(const Plans& p, const cplx<R>* a, const cplx<R>* b, long long cs, int ncomp,
-                double* partial, hipStream_t st) {
+                double* partial, hipStream_t st, const double* stop) {
   const int nb = vgrid(p.g.nspec);
-  hipLaunchKernelGGL((k_sdot<R>), dim3(nb), dim3(256), 0, st, a, b, cs, ncomp, p.g, partial);
+  hipLaunchKernelGGL((k_sdot<R>), dim3(nb), dim3(256), 0, st, a, b, cs, ncomp, p.g, partial, stop);
   return nb;
 }
 
@@ -75,7 +78,8 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_cg_xr(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r,
                         const cplx<R>* __restrict__ pv, const cplx<R>* __restrict__ q, long long cs,
                         const double* __restrict__ sc, int ia, int ib, Grid g,
-                        double* __restrict__ partial) {
+                        double* __restrict__ partial, const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
   __shared__ double red[16];
   const double al = sc[ia] / sc[ib];
   double acc = 0.0;
@@ -101,16 +105,19 @@ __global__ void __launch_bounds__(256) k_cg_xr(cplx<R>* __restrict__ x, cplx<R>*
 
 template <typename R>
 int launch_cg_xr(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, const cplx<R>* q,
-                 long long cs, const double* sc, int ia, int ib, double* partial, hipStream_t st) {
+                 long long cs, const double* sc, int ia, int ib, double* partial, hipStream_t st,
+                 const double* stop) {
   const int nb = vgrid(p.g.nspec);
   hipLaunchKernelGGL((k_cg_xr<R>), dim3(nb), dim3(256), 0, st, x, r, pv, q, cs, sc, ia, ib, p.g,
-                     partial);
+                     partial, stop);
   return nb;
 }
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_cg_p(cplx<R>* __restrict__ pv, const cplx<R>* __restrict__ z, long long cs,
-                       const double* __restrict__ sc, int ia, int ib, long long nspec) {
+                       const double* __restrict__ sc, int ia, int ib, long long nspec,
+                       const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
   const double be = sc[ia] / sc[ib];
   for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < nspec;
        b += (long long)gridDim.x * blockDim.x) {
@@ -124,25 +131,40 @@ __global__ void __launch_bounds__(256) k_cg_p(cplx<R>* __restrict__ pv, const cp
 
 template <typename R>
 void launch_cg_p(const Plans& p, cplx<R>* pv, const cplx<R>* z, long long cs, const double* sc,
-                 int ia, int ib, hipStream_t st) {
+                 int ia, int ib, hipStream_t st, const double* stop) {
   hipLaunchKernelGGL((k_cg_p<R>), dim3(vgrid(p.g.nspec)), dim3(256), 0, st, pv, z, cs, sc, ia, ib,
-                     p.g.nspec);
+                     p.g.nspec, stop);
+}
+
+// Convergence test of one CG iteration on the device.  sc[flag] = 0 while running,
+// 1 when converged (sc[rr] <= sc[tol2]), 2 on breakdown (non-positive curvature or a
+// non-finite residual); sc[iter] counts the iterations that ran.
+__global__ void k_cg_check(double* __restrict__ sc, int flag, int iter, int rr, int tol2, int pq) {
+  if (threadIdx.x != 0 || sc[flag] != 0.0) return;
+  sc[iter] += 1.0;
+  const double r = sc[rr];
+  if (!(sc[pq] > 0.0) || !isfinite(r)) sc[flag] = 2.0;
+  else if (r <= sc[tol2]) sc[flag] = 1.0;
+}
+
+void launch_cg_check(double* sc, int flag, int iter, int rr, int tol2, int pq, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(64), 0, st, sc, flag, iter, rr, tol2, pq);
 }
 
 template int launch_sdot<double>(const Plans&, const cplx<double>*, const cplx<double>*, long long,
-                                 int, double*, hipStream_t);
+                                 int, double*, hipStream_t, const double*);
 template int launch_sdot<float>(const Plans&, const cplx<float>*, const cplx<float>*, long long,
-                                int, double*, hipStream_t);
+                                int, double*, hipStream_t, const double*);
 template int launch_cg_xr<double>(const Plans&, cplx<double>*, cplx<double>*, const cplx<double>*,
                                   const cplx<double>*, long long, const double*, int, int, double*,
-                                  hipStream_t);
+                                  hipStream_t, const double*);
 template int launch_cg_xr<float>(const Plans&, cplx<float>*, cplx<float>*, const cplx<float>*,
                                  const cplx<float>*, long long, const double*, int, int, double*,
-                                 hipStream_t);
+                                 hipStream_t, const double*);
 template void launch_cg_p<double>(const Plans&, cplx<double>*, const cplx<double>*, long long,
-                                  const double*, int, int, hipStream_t);
+                                  const double*, int, int, hipStream_t, const double*);
 template void launch_cg_p<float>(const Plans&, cplx<float>*, const cplx<float>*, long long,
-                                 const double*, int, int, hipStream_t);
+                                 const double*, int, int, hipStream_t, const double*);
 
 // ---- real vectors (phase field) -------------------------------------------------------
 __global__ void __launch_bounds__(256) k_rdot(long long n, const double* __restrict__ a, const double* __restrict__ b,

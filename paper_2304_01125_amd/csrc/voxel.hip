@@ -54,10 +54,24 @@ __device__ __forceinline__ void from_mandel(const double m[6], double t[6]) {
   t[3] = kInvSqrt2 * m[3]; t[4] = kInvSqrt2 * m[4]; t[5] = kInvSqrt2 * m[5];
 }
 
+// x^e for x >= 0: binary powering when the exponent is a small integer (ei >= 0),
+// the library pow otherwise.
+__device__ __forceinline__ double pow_e(double x, double e, int ei) {
+  if (ei >= 0) {
+    double r = 1.0, b = x;
+    for (int k = ei; k; k >>= 1) {
+      if (k & 1) r *= b;
+      b *= b;
+    }
+    return r;
+  }
+  return pow(x, e);
+}
+
 // Slip increments at stress sig (Mandel): tau, dgamma, d dgamma / d tau.
 __device__ __forceinline__ void slip(const double* __restrict__ P, const double sig[6], double g,
-                                     double dtg0, double nexp, double tau[12], double dg[12],
-                                     double ddg[12], double axn[12]) {
+                                     double dtg0, double nexp, int nm1, double tau[12],
+                                     double dg[12], double ddg[12], double axn[12]) {
 #pragma unroll
   for (int a = 0; a < 12; ++a) {
     double s = 0.0;
@@ -66,7 +80,7 @@ __device__ __forceinline__ void slip(const double* __restrict__ P, const double 
     tau[a] = s;
     const double x = s / g;
     const double ax = fabs(x);
-    const double pw = pow(ax, nexp - 1.0);       // |x|^(n-1)
+    const double pw = pow_e(ax, nexp - 1.0, nm1);   // |x|^(n-1)
     axn[a] = ax * pw;                              // |x|^n
     dg[a] = dtg0 * copysign(axn[a], x);
     ddg[a] = dtg0 * nexp / g * pw;
@@ -76,7 +90,7 @@ __device__ __forceinline__ void slip(const double* __restrict__ P, const double 
 // Phi(sig) = 1/2 (sig-sig_tr) S (sig-sig_tr) + dt gdot0/(n+1) sum |tau| |tau/g|^n
 __device__ __forceinline__ double potential(const double* __restrict__ S, const double* __restrict__ P,
                                             const double sig[6], const double str[6], double g,
-                                            double dtg0, double nexp) {
+                                            double dtg0, double nexp, int nm1) {
   double d[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) d[i] = sig[i] - str[i];
@@ -95,7 +109,7 @@ __device__ __forceinline__ double potential(const double* __restrict__ S, const 
 #pragma unroll
     for (int b = 0; b < 6; ++b) t += P[a * 6 + b] * sig[b];
     const double ax = fabs(t / g);
-    pl += fabs(t) * ax * pow(ax, nexp - 1.0);
+    pl += fabs(t) * ax * pow_e(ax, nexp - 1.0, nm1);
   }
   return 0.5 * el + dtg0 / (nexp + 1.0) * pl;
 }
@@ -103,10 +117,10 @@ __device__ __forceinline__ double potential(const double* __restrict__ S, const 
 // Residual and Jacobian (full 6x6) at sig.
 __device__ __forceinline__ void resjac(const double* __restrict__ S, const double* __restrict__ P,
                                        const double sig[6], const double str[6], double g,
-                                       double dtg0, double nexp, double Rv[6], double J[6][6],
-                                       double tau[12], double dg[12]) {
+                                       double dtg0, double nexp, int nm1, double Rv[6],
+                                       double J[6][6], double tau[12], double dg[12]) {
   double ddg[12], axn[12];
-  slip(P, sig, g, dtg0, nexp, tau, dg, ddg, axn);
+  slip(P, sig, g, dtg0, nexp, nm1, tau, dg, ddg, axn);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     double s = 0.0;
@@ -177,7 +191,8 @@ __device__ __forceinline__ void chol6_solve(const double L[6][6], const double b
 // Solve the return map from the warm start in sig (Mandel, in/out).  Returns the
 // number of Newton iterations, or -1 if it did not converge.
 __device__ int return_map(const double* __restrict__ S, const double* __restrict__ P,
-                          const double str[6], double g, double dtg0, double nexp, double sig[6]) {
+                          const double str[6], double g, double dtg0, double nexp, int nm1,
+                          double sig[6]) {
   double scale = 0.0;
 #pragma unroll
   for (int i = 0; i < 6; ++i) scale = fmax(scale, fabs(str[i]));
@@ -186,13 +201,13 @@ __device__ int return_map(const double* __restrict__ S, const double* __restrict
   bool conv = false;
   for (it = 0; it < 400; ++it) {
     double Rv[6], J[6][6], tau[12], dg[12], d[6];
-    resjac(S, P, sig, str, g, dtg0, nexp, Rv, J, tau, dg);
+    resjac(S, P, sig, str, g, dtg0, nexp, nm1, Rv, J, tau, dg);
     if (!chol6(J)) return -1;
     double mR[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) mR[i] = -Rv[i];
     chol6_solve(J, mR, d);
-    const double phi0 = potential(S, P, sig, str, g, dtg0, nexp);
+    const double phi0 = potential(S, P, sig, str, g, dtg0, nexp, nm1);
     double slope = 0.0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) slope += Rv[i] * d[i];
@@ -201,7 +216,7 @@ __device__ int return_map(const double* __restrict__ S, const double* __restrict
       double c[6];
 #pragma unroll
       for (int i = 0; i < 6; ++i) c[i] = sig[i] + t * d[i];
-      const double phi1 = potential(S, P, c, str, g, dtg0, nexp);
+      const double phi1 = potential(S, P, c, str, g, dtg0, nexp, nm1);
       if (phi1 <= phi0 + 1e-4 * t * slope + 1e-13 * fabs(phi0)) break;
       t *= 0.5;
     }
@@ -218,7 +233,7 @@ __device__ int return_map(const double* __restrict__ S, const double* __restrict
   // one polishing Newton step at the root
   {
     double Rv[6], J[6][6], tau[12], dg[12], d[6];
-    resjac(S, P, sig, str, g, dtg0, nexp, Rv, J, tau, dg);
+    resjac(S, P, sig, str, g, dtg0, nexp, nm1, Rv, J, tau, dg);
     if (!chol6(J)) return -1;
     chol6_solve(J, Rv, d);
 #pragma unroll
@@ -260,21 +275,18 @@ __device__ __forceinline__ void load6(const double* __restrict__ f, long long N,
 }
 
 // ---------------------------------------------------------------------------
-// Constitutive update at eps + t*deps.  Writes sigma (tensor comps), g(phi) K
-// (21 Mandel entries) and the block partials of sum gK (21), sum g w and
-// sum g sigma (6), with w = 1/2 sig_tr S sig_tr - Phi(sig) the incremental energy.
+// Constitutive update at eps + t*deps.  Writes sigma (tensor comps), g(phi) K (21
+// Mandel entries) and g(phi) w per voxel, with w = 1/2 sig_tr S sig_tr - Phi(sig) the
+// incremental energy.
 template <typename R>
-__global__ void __launch_bounds__(256) k_constitutive(long long N, const double* __restrict__ eps,
-                               const double* __restrict__ deps, double t,
-                               const double* __restrict__ epsp, const double* __restrict__ gslip,
-                               const int* __restrict__ grain, const double* __restrict__ gtab,
-                               double* __restrict__ sig_io, const double* __restrict__ phi,
-                               R* __restrict__ gK, Material m, double* __restrict__ partial,
-                               int* __restrict__ fail) {
-  double acc[RED_CONST];
-#pragma unroll
-  for (int c = 0; c < RED_CONST; ++c) acc[c] = 0.0;
+__global__ void __launch_bounds__(256)
+k_constitutive(long long N, const double* __restrict__ eps, const double* __restrict__ deps,
+               double t, const double* __restrict__ epsp, const double* __restrict__ gslip,
+               const int* __restrict__ grain, const double* __restrict__ gtab,
+               double* __restrict__ sig_io, const double* __restrict__ phi, R* __restrict__ gK,
+               double* __restrict__ gw, Material m, int* __restrict__ fail) {
   const double dtg0 = m.dt * m.gdot0;
+  const int nm1 = m.nexp_int > 0 ? m.nexp_int - 1 : -1;
   for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
        v += (long long)gridDim.x * blockDim.x) {
     const double* gt = gtab + (long long)grain[v] * GT_STRIDE;
@@ -302,11 +314,11 @@ __global__ void __launch_bounds__(256) k_constitutive(long long N, const double*
       str[i] = s;
     }
     const double g = gslip[v];
-    const int its = return_map(S, P, str, g, dtg0, m.nexp, sig);
+    const int its = return_map(S, P, str, g, dtg0, m.nexp, nm1, sig);
     if (its < 0) atomicAdd(fail, 1);
     // tangent at the root
     double Rv[6], J[6][6], tau[12], dg[12];
-    resjac(S, P, sig, str, g, dtg0, m.nexp, Rv, J, tau, dg);
+    resjac(S, P, sig, str, g, dtg0, m.nexp, nm1, Rv, J, tau, dg);
     double K21[21];
     if (chol6(J)) chol6_inverse21(J, K21);
     else {
@@ -317,11 +329,7 @@ __global__ void __launch_bounds__(256) k_constitutive(long long N, const double*
     const double q = 1.0 - phi[v];
     const double gphi = q * q + m.kres;
 #pragma unroll
-    for (int c = 0; c < 21; ++c) {
-      const double kk = gphi * K21[c];
-      gK[(long long)c * N + v] = (R)kk;
-      acc[c] += kk;
-    }
+    for (int c = 0; c < 21; ++c) gK[(long long)c * N + v] = (R)(gphi * K21[c]);
     double el = 0.0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
@@ -330,15 +338,32 @@ __global__ void __launch_bounds__(256) k_constitutive(long long N, const double*
       for (int j = 0; j < 6; ++j) s += S[i * 6 + j] * str[j];
       el += str[i] * s;
     }
-    const double w = 0.5 * el - potential(S, P, sig, str, g, dtg0, m.nexp);
-    acc[21] += gphi * w;
+    gw[v] = gphi * (0.5 * el - potential(S, P, sig, str, g, dtg0, m.nexp, nm1));
     double st[6];
     from_mandel(sig, st);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      sig_io[c * N + v] = st[c];
-      acc[22 + c] += gphi * st[c];
-    }
+    for (int c = 0; c < 6; ++c) sig_io[c * N + v] = st[c];
+  }
+}
+
+// Block partials of the constitutive sums: sum gK (21), sum g w, sum g(phi) sigma (6).
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_const_sums(long long N, const R* __restrict__ gK, const double* __restrict__ gw,
+             const double* __restrict__ sig, const double* __restrict__ phi, double kres,
+             double* __restrict__ partial) {
+  double acc[RED_CONST];
+#pragma unroll
+  for (int c = 0; c < RED_CONST; ++c) acc[c] = 0.0;
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < 21; ++c) acc[c] += (double)gK[(long long)c * N + v];
+    acc[21] += gw[v];
+    const double q = 1.0 - phi[v];
+    const double gphi = q * q + kres;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[22 + c] += gphi * sig[c * N + v];
   }
   block_partials<RED_CONST, false>(acc, partial);
 }
@@ -346,19 +371,22 @@ __global__ void __launch_bounds__(256) k_constitutive(long long N, const double*
 template <typename R>
 void launch_constitutive(long long N, const double* eps, const double* deps, double t,
                          const double* epsp, const double* gslip, const int* grain,
-                         const double* gtab, double* sig, const double* phi, R* gK,
+                         const double* gtab, double* sig, const double* phi, R* gK, double* gw,
                          const Material& m, double* partial, int* fail, hipStream_t st) {
-  hipLaunchKernelGGL((k_constitutive<R>), dim3(voxel_grid(N)), dim3(256), 0, st, N, eps, deps, t,
-                     epsp, gslip, grain, gtab, sig, phi, gK, m, partial, fail);
+  const long long nb = (N + 255) / 256;
+  hipLaunchKernelGGL((k_constitutive<R>), dim3((int)(nb < 1 ? 1 : nb)), dim3(256), 0, st, N, eps,
+                     deps, t, epsp, gslip, grain, gtab, sig, phi, gK, gw, m, fail);
+  hipLaunchKernelGGL((k_const_sums<R>), dim3(voxel_grid(N)), dim3(256), 0, st, N, gK, gw, sig,
+                     phi, m.kres, partial);
 }
 template void launch_constitutive<double>(long long, const double*, const double*, double,
                                           const double*, const double*, const int*, const double*,
-                                          double*, const double*, double*, const Material&,
-                                          double*, int*, hipStream_t);
+                                          double*, const double*, double*, double*,
+                                          const Material&, double*, int*, hipStream_t);
 template void launch_constitutive<float>(long long, const double*, const double*, double,
                                          const double*, const double*, const int*, const double*,
-                                         double*, const double*, float*, const Material&, double*,
-                                         int*, hipStream_t);
+                                         double*, const double*, float*, double*, const Material&,
+                                         double*, int*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Cyclic Jacobi eigen-decomposition of a symmetric 3x3 (columns of V = vectors).
@@ -446,7 +474,7 @@ __global__ void __launch_bounds__(256) k_source(long long N, const double* __res
     load6(epsp, N, v, ep);
     to_mandel(st, sm);
     double tau[12], dg[12], ddg[12], axn[12];
-    slip(P, sm, gslip[v], dtg0, m.nexp, tau, dg, ddg, axn);
+    slip(P, sm, gslip[v], dtg0, m.nexp, m.nexp_int > 0 ? m.nexp_int - 1 : -1, tau, dg, ddg, axn);
     double dpm[6] = {0, 0, 0, 0, 0, 0};
     double dw = 0.0;
 #pragma unroll
@@ -507,7 +535,7 @@ __global__ void __launch_bounds__(256) k_commit(long long N, const double* __res
     to_mandel(st, sm);
     const double g = gslip[v];
     double tau[12], dg[12], ddg[12], axn[12];
-    slip(P, sm, g, dtg0, m.nexp, tau, dg, ddg, axn);
+    slip(P, sm, g, dtg0, m.nexp, m.nexp_int > 0 ? m.nexp_int - 1 : -1, tau, dg, ddg, axn);
     double dpm[6] = {0, 0, 0, 0, 0, 0};
     double db[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     double dw = 0.0, sabs = 0.0;

@@ -45,7 +45,15 @@ def notched16(max_inc=40, snaps=(5, 11, 13, 15, 19, 25, 31, 39)):
         print(f"inc {k}: {time.time() - t0:.0f}s stag {st['stag']} newton {st['newton']} "
               f"jump {jump:.3f} maxphi {o.phi[~notch].max():.4f}", flush=True)
         if jump > 0.5 or (k > 4 and st["stag"] > 3 * max(2, np.median(stags))):
+            # keep the increment of the jump itself as a separate record, then stop
             print("stopping: damage instability", flush=True)
+            f = o.fields()
+            for name in FIELDS:
+                out[f"jump_{name}"] = f[name]
+            out["jump_inc"] = k
+            out["jump_macro_stress"] = st["macro_stress"]
+            np.savez_compressed(os.path.join(HERE, "notched16.npz"), last=last,
+                                **{k2: np.asarray(v) for k2, v in out.items()})
             break
         last = k
         out["macro_stress"].append(st["macro_stress"])

@@ -11,7 +11,8 @@ from synth import small_polycrystal, make_inputs
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [(4, 4, 4), (3, 3, 3), (6, 4, 3), (16, 16, 16), (48, 32, 12), (12, 18, 9), (64, 8, 4)]
+SIZES = [(4, 4, 4), (3, 3, 3), (6, 4, 3), (16, 16, 16), (48, 32, 12), (12, 18, 9), (64, 8, 4),
+         (128, 128, 4), (32, 8, 128), (96, 48, 96), (256, 256, 2), (18, 64, 64)]
 
 
 def _rve(n, precision=0, n_grains=4, seed=3):
