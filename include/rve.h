@@ -194,6 +194,19 @@ enum {
 };
 int rve_diag_pass(struct rve_s* h, int32_t pass_id, int32_t reps, double* bytes_per_launch);
 
+/* ---- serving: many independent solves at once -------------------------------------
+ * Advance n independent handles by one load increment each, concurrently: one host
+ * thread drives each handle (every handle was created on its own stream), so the
+ * kernels of the n increments overlap on the device.  This is the tick of a
+ * continuous-batching server: a caller admits new handles and retires finished ones
+ * between ticks.  deps: n x 6 macroscopic strain increments; dt: n time steps;
+ * status: n per-handle return codes (as rve_step_increment); stats: n reports or NULL.
+ * Each handle's results are bitwise those of stepping it alone.  Returns RVE_OK when
+ * every handle succeeded, otherwise the first failing handle's code.  The handles must
+ * be distinct; the call returns after all increments have finished. */
+int rve_pool_step(struct rve_s* const* handles, int32_t n, const double* deps, const double* dt,
+                  int32_t* status, rve_stats* stats);
+
 typedef struct rve_s* rve_t;
 
 #ifdef __cplusplus

@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace rvefft;
@@ -216,6 +217,7 @@ struct rve_s {
   double* hs = nullptr;   // pinned host scalars
   bool micro = false;
   int n_grains = 0;
+  int device = 0;         // device current at creation
 };
 
 namespace {
@@ -651,6 +653,7 @@ int rve_create(const rve_desc* d, void* dev_arena, size_t arena_bytes, void* hip
   h->cap = arena_bytes;
   layout(h);
   h->st = (hipStream_t)hip_stream;
+  (void)hipGetDevice(&h->device);
   if (hipHostMalloc((void**)&h->hs, SC_N * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     delete h;
     return fail(RVE_E_DEVICE, "hipHostMalloc failed");
@@ -739,7 +742,33 @@ int rve_step_increment(rve_s* h, const double deps[6], double dt, rve_stats* st)
     if (!std::isfinite(deps[c])) return fail(RVE_E_ARG, "non-finite strain increment");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RVE_E_ARG, "dt must be positive and finite");
   g_err.clear();
+  int cur = -1;
+  if (hipGetDevice(&cur) == hipSuccess && cur != h->device) HIPCHK(hipSetDevice(h->device));
   return h->f64 ? run_increment<double>(h, deps, dt, st) : run_increment<float>(h, deps, dt, st);
+}
+
+int rve_pool_step(rve_s* const* hs, int32_t n, const double* deps, const double* dt,
+                  int32_t* status, rve_stats* stats) {
+  if (n < 0 || (n > 0 && (!hs || !deps || !dt || !status))) return fail(RVE_E_ARG, "bad argument");
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j)
+      if (hs[i] == hs[j]) return fail(RVE_E_ARG, "handles must be distinct");
+  std::vector<std::string> errs((size_t)n);
+  auto one = [&](int i) {
+    status[i] = rve_step_increment(hs[i], deps + 6 * i, dt[i], stats ? stats + i : nullptr);
+    if (status[i] != RVE_OK) errs[i] = g_err;
+  };
+  if (n == 1) {
+    one(0);
+  } else {
+    std::vector<std::thread> th;
+    th.reserve((size_t)n);
+    for (int i = 0; i < n; ++i) th.emplace_back(one, i);
+    for (auto& t : th) t.join();
+  }
+  for (int i = 0; i < n; ++i)
+    if (status[i] != RVE_OK) return fail(status[i], "handle " + std::to_string(i) + ": " + errs[i]);
+  return RVE_OK;
 }
 
 size_t rve_fields_count(const rve_s* h, uint32_t mask) {

@@ -100,6 +100,9 @@ def load():
     lib.rve_diag_constitutive.argtypes = [_P, _D, ctypes.c_double, _D, _D]
     lib.rve_diag_pass.restype = ctypes.c_int
     lib.rve_diag_pass.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, _D]
+    lib.rve_pool_step.restype = ctypes.c_int
+    lib.rve_pool_step.argtypes = [ctypes.POINTER(_P), ctypes.c_int32, _D, _D,
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(RveStats)]
     lib.rve_diag_operator.restype = ctypes.c_int
     lib.rve_diag_operator.argtypes = [_P, _D, _D]
     _lib = lib
@@ -110,7 +113,8 @@ def exported_symbols():
     """Names of the C ABI entry points (as declared in include/rve.h)."""
     return ["rve_footprint_bytes", "rve_create", "rve_set_microstructure", "rve_step_increment",
             "rve_fields", "rve_fields_count", "rve_destroy", "rve_last_error", "rve_diag_rfft",
-            "rve_diag_irfft", "rve_diag_constitutive", "rve_diag_operator", "rve_diag_pass"]
+            "rve_diag_irfft", "rve_diag_constitutive", "rve_diag_operator", "rve_diag_pass",
+            "rve_pool_step"]
 
 
 class RveError(RuntimeError):
@@ -183,6 +187,18 @@ def rve_destroy(h):
     return load().rve_destroy(h)
 
 
+def rve_pool_step(handles, deps, dt):
+    """One concurrent increment of several handles; returns (rc, status list, stats list)."""
+    n = len(handles)
+    arr = (_P * n)(*[h.value if isinstance(h, _P) else h for h in handles])
+    de = np.ascontiguousarray(np.asarray(deps, dtype=np.float64).reshape(n, 6))
+    d = np.ascontiguousarray(np.asarray(dt, dtype=np.float64).reshape(n))
+    status = (ctypes.c_int32 * n)()
+    stats = (RveStats * n)()
+    rc = load().rve_pool_step(arr, n, _dptr(de), _dptr(d), status, stats)
+    return rc, list(status), [s.as_dict() for s in stats]
+
+
 class RVE:
     """One periodic RVE solved on the GPU.  ``desc`` is the flat dict of
     ``synth.Workload.desc()``; precision is RVE_FP64 or RVE_MIXED."""
@@ -200,7 +216,6 @@ class RVE:
         self.device = torch.device("cuda", device)
         self.arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        torch.cuda.synchronize(self.device)
         self.h = rve_create(self._d, self.arena.data_ptr(), nbytes, self.stream.cuda_stream)
         self.footprint = nbytes
 

@@ -1,0 +1,261 @@
+"""Continuous-batching server of independent RVE solves on one GPU.
+
+Requests (a microstructure, a grid size and a load history each) arrive over time.
+The server keeps up to `max_slots` solves resident in HBM, admits a waiting request as
+soon as a slot is free and its arena footprint fits the memory budget, and advances
+all resident solves by one load increment per tick with ``rve_pool_step`` (one HIP
+stream per slot, so their kernels overlap on the device).  A request that finishes its
+last increment releases its slot and memory at once; newcomers join at the next tick,
+without waiting for the others to finish.  Reported: solves/s, p50/p99 latency
+(arrival to completion) and the same for serial solves.
+
+    python -m paper_2304_01125_amd.serve --requests 400 [--slots 8] [--json out.json]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+
+def prepare(reqs, workers=None):
+    """Client-side inputs of every request (microstructure and load history)."""
+    from synth import request_workload, make_inputs
+    items = []
+    if workers and workers > 1:
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            inps = list(ex.map(_make, reqs))
+    else:
+        inps = [_make(r) for r in reqs]
+    for r, inp in zip(reqs, inps):
+        items.append((request_workload(r), inp))
+    return items
+
+
+def _make(req):
+    from synth import request_workload, make_inputs
+    return make_inputs(request_workload(req))
+
+
+class Server:
+    def __init__(self, precision, max_slots=8, budget_bytes=32 << 30, device=0):
+        import torch
+        from . import load
+        load()
+        self.torch = torch
+        self.precision = precision
+        self.max_slots = max_slots
+        self.budget = budget_bytes
+        self.device = torch.device("cuda", device)
+        self.streams = [torch.cuda.Stream(self.device) for _ in range(max_slots)]
+
+    def run(self, items, arrivals, keep_fields=False, log=None):
+        """items: [(workload, inputs)], arrivals: seconds after start (non-decreasing).
+        Returns per-request dicts (latency, status, ...) and the wall time."""
+        from .rve import RVE, rve_pool_step
+        from . import make_desc, rve_footprint_bytes
+        torch = self.torch
+        n = len(items)
+        order = list(np.argsort(arrivals, kind="stable"))
+        out = [None] * n
+        waiting, active = [], []          # active: dicts with slot, handle, k
+        free_slots = list(range(self.max_slots))
+        used = 0
+        t0 = time.perf_counter()
+        nxt = 0
+        ticks = 0
+        while nxt < n or waiting or active:
+            now = time.perf_counter() - t0
+            while nxt < n and arrivals[order[nxt]] <= now:
+                waiting.append(order[nxt])
+                nxt += 1
+            # admission: free slot and memory
+            while waiting and free_slots:
+                i = waiting[0]
+                w, inp = items[i]
+                need = rve_footprint_bytes(make_desc(w.desc(), self.precision))
+                if used + need > self.budget and active:
+                    break
+                waiting.pop(0)
+                slot = free_slots.pop(0)
+                r = RVE(w.desc(), self.precision, stream=self.streams[slot])
+                r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+                used += r.footprint
+                active.append(dict(i=i, slot=slot, rve=r, k=0, t_admit=now, iters=0))
+            if not active:
+                if nxt < n:
+                    time.sleep(max(0.0, min(0.01, arrivals[order[nxt]] - now)))
+                continue
+            deps = np.zeros((len(active), 6))
+            dts = np.zeros(len(active))
+            for a_i, a in enumerate(active):
+                w, inp = items[a["i"]]
+                deps[a_i, 1] = inp["deps"][a["k"]]
+                dts[a_i] = inp["dt"][a["k"]]
+            rc, status, stats = rve_pool_step([a["rve"].h for a in active], deps, dts)
+            ticks += 1
+            done_now = time.perf_counter() - t0
+            still = []
+            for a, s, st in zip(active, status, stats):
+                a["k"] += 1
+                a["iters"] += st["krylov_iters"]
+                w, inp = items[a["i"]]
+                if s != 0 or a["k"] == len(inp["deps"]):
+                    rec = dict(id=a["i"], n=w.n[0], status=s, latency=done_now - arrivals[a["i"]],
+                               queued=a["t_admit"] - arrivals[a["i"]], krylov_iters=a["iters"],
+                               macro_stress=st["macro_stress"])
+                    if keep_fields:
+                        rec["fields"] = a["rve"].fields(("strain", "stress", "damage"))
+                    out[a["i"]] = rec
+                    used -= a["rve"].footprint
+                    a["rve"].close()
+                    free_slots.append(a["slot"])
+                    if log:
+                        log(f"request {a['i']} ({w.n[0]}^3) done: status {s}, "
+                            f"latency {rec['latency']:.3f} s")
+                else:
+                    still.append(a)
+            active = still
+        wall = time.perf_counter() - t0
+        return out, wall, ticks
+
+
+    def run_async(self, items, arrivals, keep_fields=False, log=None):
+        """Slot-per-thread variant: each slot's host thread takes the oldest arrived
+        request that fits the memory budget, runs its increments on the slot's stream,
+        releases its memory and takes the next one; slots never wait for each other."""
+        import threading
+        from .rve import RVE
+        n = len(items)
+        order = list(np.argsort(arrivals, kind="stable"))
+        out = [None] * n
+        lock = threading.Lock()
+        state = {"next": 0, "used": 0}
+        from . import make_desc, rve_footprint_bytes
+        need = [rve_footprint_bytes(make_desc(w.desc(), self.precision)) for w, _ in items]
+        t0 = time.perf_counter()
+
+        def worker(slot):
+            torch = self.torch
+            torch.cuda.set_device(self.device)
+            while True:
+                with lock:
+                    if state["next"] >= n:
+                        return
+                    i = order[state["next"]]
+                    wait = arrivals[i] - (time.perf_counter() - t0)
+                    if wait > 0 or state["used"] + need[i] > self.budget:
+                        i = None
+                    else:
+                        state["next"] += 1
+                        state["used"] += need[i]
+                if i is None:
+                    time.sleep(0.002)
+                    continue
+                w, inp = items[i]
+                t_admit = time.perf_counter() - t0
+                r = RVE(w.desc(), self.precision, stream=self.streams[slot])
+                r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+                it, st = 0, {"status": 0, "macro_stress": None}
+                for k in range(len(inp["deps"])):
+                    st = r.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k], check=False)
+                    it += st["krylov_iters"]
+                    if st["status"] != 0:
+                        break
+                done = time.perf_counter() - t0
+                rec = dict(id=i, n=w.n[0], status=st["status"], latency=done - arrivals[i],
+                           queued=t_admit - arrivals[i], krylov_iters=it,
+                           macro_stress=st["macro_stress"])
+                if keep_fields:
+                    rec["fields"] = r.fields(("strain", "stress", "damage"))
+                r.close()
+                del r
+                out[i] = rec
+                with lock:
+                    state["used"] -= need[i]
+                if log:
+                    log(f"request {i} ({w.n[0]}^3) done on slot {slot}: status {rec['status']}, "
+                        f"latency {rec['latency']:.3f} s")
+
+        threads = [threading.Thread(target=worker, args=(s_,)) for s_ in range(self.max_slots)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        return out, time.perf_counter() - t0
+
+
+def run_serial(items, precision, keep_fields=False):
+    """Each request alone, back to back (no queueing): per-request solve times."""
+    import torch
+    from .rve import RVE
+    out = []
+    t0 = time.perf_counter()
+    for i, (w, inp) in enumerate(items):
+        t1 = time.perf_counter()
+        r = RVE(w.desc(), precision)
+        r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+        it = 0
+        for k in range(len(inp["deps"])):
+            st = r.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k], check=False)
+            it += st["krylov_iters"]
+            if st["status"] != 0:
+                break
+        torch.cuda.synchronize()
+        rec = dict(id=i, n=w.n[0], status=st["status"], latency=time.perf_counter() - t1,
+                   krylov_iters=it, macro_stress=st["macro_stress"])
+        if keep_fields:
+            rec["fields"] = r.fields(("strain", "stress", "damage"))
+        out.append(rec)
+        r.close()
+    return out, time.perf_counter() - t0
+
+
+def summary(recs, wall):
+    lat = np.array([r["latency"] for r in recs])
+    return {"solves_per_s": round(len(recs) / wall, 3), "p50_ms": round(1e3 * np.percentile(lat, 50), 1),
+            "p99_ms": round(1e3 * np.percentile(lat, 99), 1), "n": len(recs),
+            "wall_s": round(wall, 2)}
+
+
+def serve_benchmark(n_req=400, slots=8, seed=4, workers=8, log=None):
+    """Serial plain-FP64 baseline, then the mixed-precision server on a Poisson stream at
+    rate factor x the serial capacity.  Returns a JSON-able dict."""
+    from synth import serving_requests
+    from . import RVE_FP64, RVE_MIXED
+    factor, gaps, reqs = serving_requests(n_req, seed)
+    items = prepare(reqs, workers)
+    serial, wall_s = run_serial(items, RVE_FP64)
+    cap = len(serial) / wall_s
+    lam = factor * cap
+    arrivals = np.cumsum(gaps) / lam
+    srv = Server(RVE_MIXED, max_slots=slots)
+    res, wall = srv.run_async(items, arrivals, log=log)
+    ok = sum(1 for r in res if r["status"] == 0)
+    ok_s = sum(1 for r in serial if r["status"] == 0)
+    return {"requests": n_req, "slots": slots, "rate_factor": round(factor, 3),
+            "arrival_rate_per_s": round(lam, 3), "completed": ok, "completed_serial": ok_s,
+            "server_mixed": summary(res, wall), "serial_fp64": summary(serial, wall_s)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=400)
+    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--json", default=None)
+    a = ap.parse_args()
+    res = serve_benchmark(a.requests, a.slots, a.seed, a.workers,
+                          log=lambda m: print(m, file=sys.stderr, flush=True))
+    print(json.dumps(res), flush=True)
+    if a.json:
+        with open(a.json, "w") as f:
+            json.dump(res, f)
+
+
+if __name__ == "__main__":
+    main()

@@ -12,7 +12,9 @@ from .microstructure import (periodic_voronoi, periodic_laguerre, shoemake_quate
 from .loading import triangular_waveform
 from .workloads import (Workload, workload, WORKLOADS, make_inputs, small_polycrystal,
                         single_crystal)
+from .serving import serving_requests, request_workload
 
 __all__ = ["periodic_voronoi", "periodic_laguerre", "shoemake_quaternions",
            "lognormal_laguerre_weights", "notch_mask", "triangular_waveform", "Workload",
-           "workload", "WORKLOADS", "make_inputs", "small_polycrystal", "single_crystal"]
+           "workload", "WORKLOADS", "make_inputs", "small_polycrystal", "single_crystal",
+           "serving_requests", "request_workload"]

@@ -56,7 +56,7 @@ class Workload:
     tol_newton: float = 5e-3
     tol_lin: float = 1e-5
     max_stag: int = 50
-    max_newton: int = 30
+    max_newton: int = 100
     max_krylov: int = 500
     gmres_restart: int = 30
 
@@ -64,7 +64,7 @@ class Workload:
         """Copy with the tight tolerances under which the discrete solution is unique
         to well below the parity bar."""
         return dataclasses.replace(self, tol_stag=1e-11, tol_newton=1e-11, tol_lin=1e-12,
-                                   max_stag=200, max_newton=50, max_krylov=4000)
+                                   max_stag=200, max_newton=100, max_krylov=4000)
 
     @property
     def nvox(self):
