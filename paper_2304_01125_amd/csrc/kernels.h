@@ -55,9 +55,24 @@ void launch_div(const Plans& p, const cplx<R>* s, long long scs, cplx<R>* out, l
 template <typename R>
 int launch_precond(const Plans& p, const cplx<R>* r, cplx<R>* z, long long cs, const double* kbar21,
                    double* partial, hipStream_t st, const double* stop = nullptr);
+// Fused conjugate-gradient kernels (spectral.hip):
+// p = z + (sc[ia]/sc[ib]) p, then e = sym(i xi~ (x) p)
+template <typename R>
+void launch_grad_cgp(const Plans& p, cplx<R>* pv, const cplx<R>* z, long long cs, const double* sc,
+                     int ia, int ib, cplx<R>* e, hipStream_t st, const double* stop = nullptr);
+// q = -i xi~ . s and block partials of <p, q>; returns #blocks
+template <typename R>
+int launch_div_dot(const Plans& p, const cplx<R>* s, cplx<R>* q, const cplx<R>* pv, long long cs,
+                   double* partial, hipStream_t st, const double* stop = nullptr);
+// x += a p, r -= a q (a = sc[ia]/sc[ib]), z = M r, partials <r,r>, <r,z>; returns #blocks
+template <typename R>
+int launch_cg_update(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, const cplx<R>* q,
+                     cplx<R>* z, long long cs, const double* kbar21, const double* sc, int ia,
+                     int ib, double* partial, hipStream_t st, const double* stop = nullptr);
 // Hermitian projection of the self-conjugate x-planes (spectra of real fields)
 template <typename R>
-void launch_herm_proj(const Plans& p, cplx<R>* v, long long cs, int ncomp, hipStream_t st);
+void launch_herm_proj(const Plans& p, cplx<R>* v, long long cs, int ncomp, hipStream_t st,
+                      const double* stop = nullptr);
 template <typename R>
 void launch_pf_scale(const Plans& p, cplx<R>* d, double ell, double scale, hipStream_t st);
 template <typename R>
@@ -139,6 +154,9 @@ void launch_cg_p(const Plans& p, cplx<R>* pv, const cplx<R>* z, long long cs, co
                  int ia, int ib, hipStream_t st, const double* stop = nullptr);
 // device-side CG convergence test (see vector.hip)
 void launch_cg_check(double* sc, int flag, int iter, int rr, int tol2, int pq, hipStream_t st);
+// as launch_cg_check, and while running copies sc[rzn] to sc[nxt]
+void launch_cg_check2(double* sc, int flag, int iter, int rr, int tol2, int pq, int rzn, int nxt,
+                      hipStream_t st);
 // real-vector kernels (phase field)
 int launch_rdot(long long n, const double* a, const double* b, double* partial, hipStream_t st);
 // pq = <p, w + 2 S p>

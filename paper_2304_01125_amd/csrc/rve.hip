@@ -226,6 +226,7 @@ enum { SC_K = 0,        // 28 constitutive sums (21 gK, g w, 6 g sigma)
        SC_KBAR = 32,    // 21 mean tangent
        SC_RZ0 = 56, SC_RZ1 = 57, SC_PQ = 58, SC_RR = 59, SC_BB = 60,
        SC_FLAG = 61, SC_ITER = 62, SC_TOL2 = 63,
+       SC_ZERO = 80, SC_ONE = 81, SC_RRN = 82, SC_RZN = 83,
        SC_MISC = 64,    // generic reduce outputs (16)
        SC_N = 96 };
 
@@ -376,12 +377,12 @@ struct Ops {
     const size_t bytes = (size_t)3 * NH * sizeof(C);
     double* sc = h->scal;
     launch_zero(x, bytes, st);
+    launch_zero(p, bytes, st);      // the first iteration forms p = z + 0 * p
     HIPCHK(hipMemcpyAsync(r, b, bytes, hipMemcpyDeviceToDevice, st));
     int nb = launch_sdot<R>(h->pl, b, b, NH, 3, h->partial, st);
     launch_reduce(h->partial, nb, 1, 0, sc + SC_BB, st);
     nb = launch_precond<R>(h->pl, r, z, NH, sc + SC_KBAR, h->partial, st);
     launch_reduce(h->partial, nb, 1, 0, sc + SC_RZ0, st);
-    HIPCHK(hipMemcpyAsync(p, z, bytes, hipMemcpyDeviceToDevice, st));
     int rc = sync_read(h, SC_BB, 1);
     if (rc) return rc;
     const double bb = h->hs[SC_BB];
@@ -390,23 +391,32 @@ struct Ops {
     h->hs[SC_FLAG] = 0.0;
     h->hs[SC_ITER] = 0.0;
     h->hs[SC_TOL2] = h->d.tol_lin * h->d.tol_lin * bb;
+    h->hs[SC_ZERO] = 0.0;
+    h->hs[SC_ONE] = 1.0;
     HIPCHK(hipMemcpyAsync(sc + SC_FLAG, h->hs + SC_FLAG, 3 * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(sc + SC_ZERO, h->hs + SC_ZERO, 2 * sizeof(double), hipMemcpyHostToDevice, st));
     const double* stop = sc + SC_FLAG;
-    int cur = SC_RZ0, nxt = SC_RZ1;
     int queued = 0, batch = 4;
     while (queued < h->d.max_krylov) {
       const int nq = std::min(batch, h->d.max_krylov - queued);
-      for (int k = 0; k < nq; ++k) {
-        matvec(p, q, stop);
-        nb = launch_sdot<R>(h->pl, p, q, NH, 3, h->partial, st, stop);
+      for (int kk = 0; kk < nq; ++kk) {
+        const int k = queued + kk;
+        const int cur = SC_RZ0 + (k & 1), prv = SC_RZ0 + ((k + 1) & 1);
+        // p = z + beta p (beta = rz_k / rz_{k-1}, 0 on the first iteration), gradient
+        if (k == 0) launch_grad_cgp<R>(h->pl, p, z, NH, sc, SC_ZERO, SC_ONE, W, st, stop);
+        else launch_grad_cgp<R>(h->pl, p, z, NH, sc, cur, prv, W, st, stop);
+        launch_fft_yz<R>(h->pl, W, NH, 6, 2, true, st, stop);
+        launch_fft_yz<R>(h->pl, W, NH, 6, 1, true, st, stop);
+        launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
+        launch_fft_yz<R>(h->pl, W, NH, 6, 1, false, st, stop);
+        launch_fft_yz<R>(h->pl, W, NH, 6, 2, false, st, stop);
+        nb = launch_div_dot<R>(h->pl, W, q, p, NH, h->partial, st, stop);
         launch_reduce(h->partial, nb, 1, 0, sc + SC_PQ, st, stop);
-        nb = launch_cg_xr<R>(h->pl, x, r, p, q, NH, sc, cur, SC_PQ, h->partial, st, stop);
-        launch_reduce(h->partial, nb, 1, 0, sc + SC_RR, st, stop);
-        launch_cg_check(sc, SC_FLAG, SC_ITER, SC_RR, SC_TOL2, SC_PQ, st);
-        nb = launch_precond<R>(h->pl, r, z, NH, sc + SC_KBAR, h->partial, st, stop);
-        launch_reduce(h->partial, nb, 1, 0, sc + nxt, st, stop);
-        launch_cg_p<R>(h->pl, p, z, NH, sc, nxt, cur, st, stop);
-        std::swap(cur, nxt);
+        launch_herm_proj<R>(h->pl, q, NH, 3, st, stop);
+        nb = launch_cg_update<R>(h->pl, x, r, p, q, z, NH, sc + SC_KBAR, sc, cur, SC_PQ,
+                                 h->partial, st, stop);
+        launch_reduce(h->partial, nb, 2, 0, sc + SC_RRN, st, stop);
+        launch_cg_check2(sc, SC_FLAG, SC_ITER, SC_RRN, SC_TOL2, SC_PQ, SC_RZN, prv, st);
       }
       queued += nq;
       rc = sync_read(h, SC_FLAG, 2);

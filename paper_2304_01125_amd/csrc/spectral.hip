@@ -17,6 +17,8 @@ __device__ __forceinline__ double freq(int k, int N, double L, bool tilde) {
   return kTwoPi * (double)m / L;
 }
 
+static int grid_for(long long n);
+
 // ---------------------------------------------------------------------------
 // Pointwise operators.  Thread per half-spectrum bin.
 struct Bin {
@@ -93,7 +95,8 @@ __device__ __forceinline__ long long partner_bin(const Bin& q, const Grid& g) {
 // pair writes both entries.
 template <typename R>
 __global__ void __launch_bounds__(256) k_herm_proj(cplx<R>* __restrict__ v, long long cs, int ncomp,
-                                                   Grid g) {
+                                                   Grid g, const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
   const int nplanes = (g.n1 % 2 == 0 && g.n1 > 1) ? 2 : 1;
   const long long per = (long long)g.n2 * g.n3;
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < per * nplanes;
@@ -116,14 +119,17 @@ __global__ void __launch_bounds__(256) k_herm_proj(cplx<R>* __restrict__ v, long
 }
 
 template <typename R>
-void launch_herm_proj(const Plans& p, cplx<R>* v, long long cs, int ncomp, hipStream_t st) {
+void launch_herm_proj(const Plans& p, cplx<R>* v, long long cs, int ncomp, hipStream_t st,
+                      const double* stop) {
   const long long n = (long long)p.g.n2 * p.g.n3 * 2;
   long long nb = (n + 255) / 256;
   hipLaunchKernelGGL((k_herm_proj<R>), dim3((int)(nb < 1 ? 1 : nb)), dim3(256), 0, st, v, cs,
-                     ncomp, p.g);
+                     ncomp, p.g, stop);
 }
-template void launch_herm_proj<double>(const Plans&, cplx<double>*, long long, int, hipStream_t);
-template void launch_herm_proj<float>(const Plans&, cplx<float>*, long long, int, hipStream_t);
+template void launch_herm_proj<double>(const Plans&, cplx<double>*, long long, int, hipStream_t,
+                                       const double*);
+template void launch_herm_proj<float>(const Plans&, cplx<float>*, long long, int, hipStream_t,
+                                      const double*);
 
 // Mandel index of the symmetric pair (i, j) and its weight.
 __device__ __forceinline__ int mandel_index(int i, int j) {
@@ -136,6 +142,213 @@ __device__ __forceinline__ int mandel_index(int i, int j) {
 __device__ __forceinline__ double parseval_w(int kx, int n1) {
   return (kx == 0 || (n1 % 2 == 0 && kx == n1 / 2)) ? 1.0 : 2.0;
 }
+
+// Fourth-order mean tangent from its 21 Mandel entries into LDS (81 values).
+__device__ __forceinline__ void load_kbar4(double* K4, const double* __restrict__ kbar21) {
+  if (threadIdx.x < 81) {
+    const int i = threadIdx.x / 27, j = (threadIdx.x / 9) % 3, k = (threadIdx.x / 3) % 3,
+              l = threadIdx.x % 3;
+    const int a = mandel_index(i, j), b = mandel_index(k, l);
+    const int lo = min(a, b), hi = max(a, b);
+    const int idx = lo * 6 - lo * (lo - 1) / 2 + (hi - lo);
+    const double wa = (a < 3) ? 1.0 : 1.41421356237309504880;
+    const double wb = (b < 3) ? 1.0 : 1.41421356237309504880;
+    K4[threadIdx.x] = kbar21[idx] / (wa * wb);
+  }
+}
+
+// zo = [t . K . t]^-1 ri (zero where t = 0), t = xi~ of the bin.
+template <typename R>
+__device__ __forceinline__ void apply_M(const double t[3], const double* K4, const cplx<R> ri[3],
+                                        cplx<R> zo[3]) {
+  zo[0] = zo[1] = zo[2] = cplx<R>{0, 0};
+  if (t[0] == 0.0 && t[1] == 0.0 && t[2] == 0.0) return;
+  double A[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int k = i; k < 3; ++k) {
+      double s = 0.0;
+      for (int j = 0; j < 3; ++j)
+        for (int l = 0; l < 3; ++l) s += t[j] * K4[((i * 3 + j) * 3 + k) * 3 + l] * t[l];
+      A[i][k] = s;
+      A[k][i] = s;
+    }
+  const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+  const double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+  const double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+  const double id = 1.0 / (A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02);
+  double Mi[3][3];
+  Mi[0][0] = c00 * id;
+  Mi[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * id;
+  Mi[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * id;
+  Mi[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * id;
+  Mi[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * id;
+  Mi[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * id;
+  Mi[1][0] = Mi[0][1];
+  Mi[2][0] = Mi[0][2];
+  Mi[2][1] = Mi[1][2];
+  for (int i = 0; i < 3; ++i) {
+    double zx = 0, zy = 0;
+    for (int k = 0; k < 3; ++k) { zx += Mi[i][k] * (double)ri[k].x; zy += Mi[i][k] * (double)ri[k].y; }
+    zo[i] = cplx<R>{(R)zx, (R)zy};
+  }
+}
+
+// ---- fused conjugate-gradient kernels ---------------------------------------------
+// p = z + beta p (beta = sc[ia] / sc[ib]), then e = sym(i xi~ (x) p)  (3 -> 6 comps).
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_grad_cgp(cplx<R>* __restrict__ pv, const cplx<R>* __restrict__ z, long long cs,
+           const double* __restrict__ sc, int ia, int ib, cplx<R>* __restrict__ e, long long ecs,
+           Grid g, const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
+  const double be = sc[ia] / sc[ib];
+  for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < g.nspec;
+       b += (long long)gridDim.x * blockDim.x) {
+    const Bin q = bin_of(b, g);
+    const R t1 = (R)freq(q.kx, g.n1, g.L1, true);
+    const R t2 = (R)freq(q.ky, g.n2, g.L2, true);
+    const R t3 = (R)freq(q.kz, g.n3, g.L3, true);
+    cplx<R> u[3];
+    for (int c = 0; c < 3; ++c) {
+      const cplx<R> zz = z[c * cs + b], pp = pv[c * cs + b];
+      u[c] = cplx<R>{(R)((double)zz.x + be * (double)pp.x), (R)((double)zz.y + be * (double)pp.y)};
+      pv[c * cs + b] = u[c];
+    }
+    auto ic = [](R s, cplx<R> a) { return cplx<R>{-s * a.y, s * a.x}; };
+    const R h = R(0.5);
+    e[b] = ic(t1, u[0]);
+    e[ecs + b] = ic(t2, u[1]);
+    e[2 * ecs + b] = ic(t3, u[2]);
+    e[3 * ecs + b] = cscale(cadd(ic(t2, u[2]), ic(t3, u[1])), h);
+    e[4 * ecs + b] = cscale(cadd(ic(t1, u[2]), ic(t3, u[0])), h);
+    e[5 * ecs + b] = cscale(cadd(ic(t1, u[1]), ic(t2, u[0])), h);
+  }
+}
+
+// q = -i xi~ . s  (6 -> 3 comps) and the block partial of the Parseval-weighted <p, q>.
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_div_dot(const cplx<R>* __restrict__ s, long long scs, cplx<R>* __restrict__ out, long long ocs,
+          const cplx<R>* __restrict__ pv, Grid g, double* __restrict__ partial,
+          const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
+  __shared__ double red[16];
+  double acc = 0.0;
+  for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < g.nspec;
+       b += (long long)gridDim.x * blockDim.x) {
+    const Bin q = bin_of(b, g);
+    const R t1 = (R)freq(q.kx, g.n1, g.L1, true);
+    const R t2 = (R)freq(q.ky, g.n2, g.L2, true);
+    const R t3 = (R)freq(q.kz, g.n3, g.L3, true);
+    const cplx<R> xx = s[b], yy = s[scs + b], zz = s[2 * scs + b];
+    const cplx<R> yz = s[3 * scs + b], xz = s[4 * scs + b], xy = s[5 * scs + b];
+    const cplx<R> d[3] = {
+        {t1 * xx.x + t2 * xy.x + t3 * xz.x, t1 * xx.y + t2 * xy.y + t3 * xz.y},
+        {t1 * xy.x + t2 * yy.x + t3 * yz.x, t1 * xy.y + t2 * yy.y + t3 * yz.y},
+        {t1 * xz.x + t2 * yz.x + t3 * zz.x, t1 * xz.y + t2 * yz.y + t3 * zz.y}};
+    double dot = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const cplx<R> qq = {d[c].y, -d[c].x};        // -i d
+      out[c * ocs + b] = qq;
+      const cplx<R> pp = pv[c * ocs + b];
+      dot += (double)pp.x * (double)qq.x + (double)pp.y * (double)qq.y;
+    }
+    acc += parseval_w(q.kx, g.n1) * dot;
+  }
+  block_partial_sum(acc, partial, red);
+}
+
+// alpha = sc[ia] / sc[ib]; x += alpha p; r -= alpha q; z = M r; block partials of
+// <r, r> and <r, z> (Parseval weights) at partial[0][blk], partial[1][blk].
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_cg_update(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __restrict__ pv,
+            const cplx<R>* __restrict__ qv, cplx<R>* __restrict__ z, long long cs,
+            const double* __restrict__ kbar21, const double* __restrict__ sc, int ia, int ib,
+            Grid g, double* __restrict__ partial, const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
+  __shared__ double K4[81];
+  __shared__ double red[2][16];
+  load_kbar4(K4, kbar21);
+  __syncthreads();
+  const double al = sc[ia] / sc[ib];
+  double rr = 0.0, rz = 0.0;
+  for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < g.nspec;
+       b += (long long)gridDim.x * blockDim.x) {
+    const Bin q = bin_of(b, g);
+    const double t[3] = {freq(q.kx, g.n1, g.L1, true), freq(q.ky, g.n2, g.L2, true),
+                         freq(q.kz, g.n3, g.L3, true)};
+    cplx<R> rv[3], zo[3];
+    for (int c = 0; c < 3; ++c) {
+      const long long i = c * cs + b;
+      const cplx<R> pp = pv[i], qq = qv[i];
+      cplx<R> xx = x[i], rr_ = r[i];
+      xx.x = (R)((double)xx.x + al * (double)pp.x);
+      xx.y = (R)((double)xx.y + al * (double)pp.y);
+      rr_.x = (R)((double)rr_.x - al * (double)qq.x);
+      rr_.y = (R)((double)rr_.y - al * (double)qq.y);
+      x[i] = xx;
+      r[i] = rr_;
+      rv[c] = rr_;
+    }
+    apply_M(t, K4, rv, zo);
+    double a = 0.0, bz = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      z[c * cs + b] = zo[c];
+      a += (double)rv[c].x * (double)rv[c].x + (double)rv[c].y * (double)rv[c].y;
+      bz += (double)rv[c].x * (double)zo[c].x + (double)rv[c].y * (double)zo[c].y;
+    }
+    const double w = parseval_w(q.kx, g.n1);
+    rr += w * a;
+    rz += w * bz;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    rr += __shfl_down(rr, off, 64);
+    rz += __shfl_down(rz, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) { red[0][wid] = rr; red[1][wid] = rz; }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double sum = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += red[threadIdx.x][w];
+    partial[(long long)threadIdx.x * gridDim.x + blockIdx.x] = sum;
+  }
+}
+
+template <typename R>
+void launch_grad_cgp(const Plans& p, cplx<R>* pv, const cplx<R>* z, long long cs, const double* sc,
+                     int ia, int ib, cplx<R>* e, hipStream_t st, const double* stop) {
+  hipLaunchKernelGGL((k_grad_cgp<R>), dim3(grid_for(p.g.nspec)), dim3(256), 0, st, pv, z, cs, sc,
+                     ia, ib, e, cs, p.g, stop);
+}
+template <typename R>
+int launch_div_dot(const Plans& p, const cplx<R>* s, cplx<R>* q, const cplx<R>* pv, long long cs,
+                   double* partial, hipStream_t st, const double* stop) {
+  const int nb = grid_for(p.g.nspec);
+  hipLaunchKernelGGL((k_div_dot<R>), dim3(nb), dim3(256), 0, st, s, cs, q, cs, pv, p.g, partial,
+                     stop);
+  return nb;
+}
+template <typename R>
+int launch_cg_update(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, const cplx<R>* q,
+                     cplx<R>* z, long long cs, const double* kbar21, const double* sc, int ia,
+                     int ib, double* partial, hipStream_t st, const double* stop) {
+  const int nb = grid_for(p.g.nspec);
+  hipLaunchKernelGGL((k_cg_update<R>), dim3(nb), dim3(256), 0, st, x, r, pv, q, z, cs, kbar21, sc,
+                     ia, ib, p.g, partial, stop);
+  return nb;
+}
+#define RVE_CG_INST(R)                                                                           \
+  template void launch_grad_cgp<R>(const Plans&, cplx<R>*, const cplx<R>*, long long,             \
+                                   const double*, int, int, cplx<R>*, hipStream_t, const double*); \
+  template int launch_div_dot<R>(const Plans&, const cplx<R>*, cplx<R>*, const cplx<R>*,          \
+                                 long long, double*, hipStream_t, const double*);                \
+  template int launch_cg_update<R>(const Plans&, cplx<R>*, cplx<R>*, const cplx<R>*,              \
+                                   const cplx<R>*, cplx<R>*, long long, const double*,           \
+                                   const double*, int, int, double*, hipStream_t, const double*);
+RVE_CG_INST(double)
+RVE_CG_INST(float)
 
 // z = M r with M = [xi~ . Kbar . xi~]^-1 (zero where xi~ = 0), and the block
 // partial of the Parseval-weighted <r, z>.  kbar21 is the 21-entry Mandel mean

@@ -151,6 +151,21 @@ void launch_cg_check(double* sc, int flag, int iter, int rr, int tol2, int pq, h
   hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(64), 0, st, sc, flag, iter, rr, tol2, pq);
 }
 
+__global__ void k_cg_check2(double* __restrict__ sc, int flag, int iter, int rr, int tol2, int pq,
+                            int rzn, int nxt) {
+  if (threadIdx.x != 0 || sc[flag] != 0.0) return;
+  sc[iter] += 1.0;
+  sc[nxt] = sc[rzn];
+  const double r = sc[rr];
+  if (!(sc[pq] > 0.0) || !isfinite(r)) sc[flag] = 2.0;
+  else if (r <= sc[tol2]) sc[flag] = 1.0;
+}
+
+void launch_cg_check2(double* sc, int flag, int iter, int rr, int tol2, int pq, int rzn, int nxt,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_check2, dim3(1), dim3(64), 0, st, sc, flag, iter, rr, tol2, pq, rzn, nxt);
+}
+
 template int launch_sdot<double>(const Plans&, const cplx<double>*, const cplx<double>*, long long,
                                  int, double*, hipStream_t, const double*);
 template int launch_sdot<float>(const Plans&, const cplx<float>*, const cplx<float>*, long long,
