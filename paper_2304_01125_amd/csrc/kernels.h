@@ -87,7 +87,15 @@ enum {
   GT_P = 72,       // Mandel Schmid tensors sym(s (x) n), 12 x 6
   GT_SN = 144,     // s (x) n, 12 x 9 row-major
   GT_R = 252,      // rotation crystal -> sample, 9 row-major
-  GT_STRIDE = 261
+  GT_Q = 261,      // the same rotation acting on Mandel vectors, 6 x 6 row-major
+  GT_STRIDE = 297
+};
+
+// Grain-independent crystal-frame constants (Mandel): Schmid tensors of the 12 slip
+// systems, cubic stiffness (c11, c12 normal block, c66 = 2 C44 shear) and its inverse.
+struct CrystalFrame {
+  double P[72];
+  double c11, c12, c66, s11, s12, s66;
 };
 
 struct Material {
@@ -107,7 +115,8 @@ template <typename R>
 void launch_constitutive(long long N, const double* eps, const double* deps, double t,
                          const double* epsp, const double* gslip, const int* grain,
                          const double* gtab, double* sig, const double* phi, R* gK, double* gw,
-                         const Material& m, double* partial, int* fail, hipStream_t st);
+                         const CrystalFrame& cf, const Material& m, double* partial, int* fail,
+                         hipStream_t st);
 void launch_source(long long N, const double* eps, const double* sig, const double* epsp,
                    const double* gslip, const int* grain, const double* gtab, const double* wp,
                    const double* trig, const double* wcrit, double* S, double* wep,

@@ -156,7 +156,43 @@ bool grain_table(const double* q, double C11, double C12, double C44, double* ou
     }
   }
   for (int i = 0; i < 9; ++i) out[GT_R + i] = R[i / 3][i % 3];
+  // Mandel form of T -> R T R^T: column b is the image of the b-th Mandel basis tensor
+  for (int b = 0; b < 6; ++b) {
+    double T[3][3] = {};
+    const int k = kPairs[b][0], l = kPairs[b][1];
+    T[k][l] += 1.0 / w[b];
+    if (k != l) T[l][k] += 1.0 / w[b];
+    for (int a = 0; a < 6; ++a) {
+      const int i = kPairs[a][0], j = kPairs[a][1];
+      double v = 0.0;
+      for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) v += R[i][p] * T[p][q] * R[j][q];
+      out[GT_Q + a * 6 + b] = w[a] * v;
+    }
+  }
   return true;
+}
+
+// Crystal-frame constants shared by all grains.
+void crystal_frame(double C11, double C12, double C44, CrystalFrame* cf) {
+  const double w[6] = {1, 1, 1, std::sqrt(2.0), std::sqrt(2.0), std::sqrt(2.0)};
+  for (int a = 0; a < 12; ++a) {
+    double s[3] = {kSlipS[a][0], kSlipS[a][1], kSlipS[a][2]};
+    double n[3] = {kSlipN[a][0], kSlipN[a][1], kSlipN[a][2]};
+    normalize3(s);
+    normalize3(n);
+    for (int b = 0; b < 6; ++b) {
+      const int i = kPairs[b][0], j = kPairs[b][1];
+      cf->P[a * 6 + b] = w[b] * 0.5 * (s[i] * n[j] + s[j] * n[i]);
+    }
+  }
+  cf->c11 = C11;
+  cf->c12 = C12;
+  cf->c66 = 2.0 * C44;
+  const double det = (C11 - C12) * (C11 + 2.0 * C12);
+  cf->s11 = (C11 + C12) / det;
+  cf->s12 = -C12 / det;
+  cf->s66 = 1.0 / (2.0 * C44);
 }
 
 // Q = (A A^T)^-1 for the 9 x 18 crystal-frame GND basis (12 edge: s (x) (s x n),
@@ -206,6 +242,7 @@ struct rve_s {
       *wp, *gs, *H, *wcrit, *trig, *phi, *phi_t, *phi_prev, *S, *wep, *gw;
   int* grain;
   double* gtab;
+  CrystalFrame cf;        // crystal-frame slip and elasticity constants
   double* Q81;
   void* gK;               // 21 N reals (R)
   void* spec;             // 9 NH complex (R): operator work and GND scratch
@@ -354,7 +391,7 @@ struct Ops {
     Material m = mat(0.0);
     m.dt = cur_dt;
     launch_constitutive<R>(N, h->eps, deps, t, h->epsp, h->gslip, h->grain, h->gtab, h->sig, phi,
-                           gK(), h->gw, m, h->partial, h->failc, st);
+                           gK(), h->gw, h->cf, m, h->partial, h->failc, st);
     launch_reduce(h->partial, voxel_grid(N), RED_CONST, 0, h->scal + SC_K, st);
     return RVE_OK;
   }
@@ -664,6 +701,7 @@ int rve_create(const rve_desc* d, void* dev_arena, size_t arena_bytes, void* hip
   layout(h);
   h->st = (hipStream_t)hip_stream;
   (void)hipGetDevice(&h->device);
+  crystal_frame(h->d.C11, h->d.C12, h->d.C44, &h->cf);
   if (hipHostMalloc((void**)&h->hs, SC_N * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     delete h;
     return fail(RVE_E_DEVICE, "hipHostMalloc failed");

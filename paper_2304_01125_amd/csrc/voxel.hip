@@ -87,112 +87,157 @@ __device__ __forceinline__ void slip(const double* __restrict__ P, const double 
   }
 }
 
+// Packed upper triangle of a symmetric 6x6, row-major: (0,0),(0,1)..(0,5),(1,1)..(5,5).
+__device__ __forceinline__ constexpr int pk(int i, int j) {
+  return (i <= j) ? i * 6 - i * (i - 1) / 2 + (j - i) : j * 6 - j * (j - 1) / 2 + (i - j);
+}
+
+// The return map runs in the crystal frame: there the Schmid tensors and the cubic
+// stiffness are the same for every grain (kernel-argument constants, read through the
+// scalar unit), so only the stress state of a voxel occupies vector registers.  The
+// potential, residual and tangent are invariant under the (orthogonal) Mandel rotation.
+
+// y = S x for the cubic Mandel matrix with normal block (a on, b off the diagonal) and
+// shear diagonal c.
+__device__ __forceinline__ void cubic_mul(double a, double b, double c, const double x[6],
+                                          double y[6]) {
+  y[0] = a * x[0] + b * (x[1] + x[2]);
+  y[1] = a * x[1] + b * (x[0] + x[2]);
+  y[2] = a * x[2] + b * (x[0] + x[1]);
+  y[3] = c * x[3];
+  y[4] = c * x[4];
+  y[5] = c * x[5];
+}
+
 // Phi(sig) = 1/2 (sig-sig_tr) S (sig-sig_tr) + dt gdot0/(n+1) sum |tau| |tau/g|^n
-__device__ __forceinline__ double potential(const double* __restrict__ S, const double* __restrict__ P,
-                                            const double sig[6], const double str[6], double g,
-                                            double dtg0, double nexp, int nm1) {
-  double d[6];
+__device__ __forceinline__ double potential(const CrystalFrame& cf, const double sig[6],
+                                            const double str[6], double ig, double dtg0,
+                                            double nexp, int nm1) {
+  double d[6], Sd[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) d[i] = sig[i] - str[i];
+  cubic_mul(cf.s11, cf.s12, cf.s66, d, Sd);
   double el = 0.0;
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) s += S[i * 6 + j] * d[j];
-    el += d[i] * s;
-  }
+  for (int i = 0; i < 6; ++i) el += d[i] * Sd[i];
   double pl = 0.0;
-#pragma unroll
+#pragma unroll 1
   for (int a = 0; a < 12; ++a) {
     double t = 0.0;
 #pragma unroll
-    for (int b = 0; b < 6; ++b) t += P[a * 6 + b] * sig[b];
-    const double ax = fabs(t / g);
+    for (int b = 0; b < 6; ++b) t += cf.P[a * 6 + b] * sig[b];
+    const double ax = fabs(t * ig);
     pl += fabs(t) * ax * pow_e(ax, nexp - 1.0, nm1);
   }
   return 0.5 * el + dtg0 / (nexp + 1.0) * pl;
 }
 
-// Residual and Jacobian (full 6x6) at sig.
-__device__ __forceinline__ void resjac(const double* __restrict__ S, const double* __restrict__ P,
-                                       const double sig[6], const double str[6], double g,
-                                       double dtg0, double nexp, int nm1, double Rv[6],
-                                       double J[6][6], double tau[12], double dg[12]) {
-  double ddg[12], axn[12];
-  slip(P, sig, g, dtg0, nexp, nm1, tau, dg, ddg, axn);
+// Residual R = S (sig - sig_tr) + sum dgamma P and packed Jacobian J (21), accumulated
+// slip system by slip system.
+__device__ __forceinline__ void resjac(const CrystalFrame& cf, const double sig[6],
+                                       const double str[6], double ig, double dtg0, double nexp,
+                                       int nm1, double Rv[6], double J[21]) {
+  double d[6];
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    double s = 0.0;
+  for (int i = 0; i < 6; ++i) d[i] = sig[i] - str[i];
+  cubic_mul(cf.s11, cf.s12, cf.s66, d, Rv);
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      s += S[i * 6 + j] * (sig[j] - str[j]);
-      J[i][j] = S[i * 6 + j];
-    }
-    Rv[i] = s;
-  }
+  for (int i = 0; i < 6; ++i)
 #pragma unroll
+    for (int j = i; j < 6; ++j)
+      J[pk(i, j)] = (i == j) ? (i < 3 ? cf.s11 : cf.s66) : ((j < 3) ? cf.s12 : 0.0);
+#pragma unroll 1
   for (int a = 0; a < 12; ++a) {
+    double t = 0.0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) t += cf.P[a * 6 + b] * sig[b];
+    const double x = t * ig;
+    const double ax = fabs(x);
+    const double pw = pow_e(ax, nexp - 1.0, nm1);       // |x|^(n-1)
+    const double dg = dtg0 * copysign(ax * pw, x);
+    const double ddg = dtg0 * nexp * ig * pw;
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      const double pi = P[a * 6 + i];
-      Rv[i] += dg[a] * pi;
+      Rv[i] += dg * cf.P[a * 6 + i];
+      const double di = ddg * cf.P[a * 6 + i];
 #pragma unroll
-      for (int j = 0; j < 6; ++j) J[i][j] += ddg[a] * pi * P[a * 6 + j];
+      for (int j = i; j < 6; ++j) J[pk(i, j)] += di * cf.P[a * 6 + j];
     }
   }
 }
 
-// In-place Cholesky factor (lower) of an SPD 6x6; returns false if not SPD.
-__device__ __forceinline__ bool chol6(double A[6][6]) {
+// In-place upper Cholesky J = U^T U on the packed triangle; false if not SPD.
+__device__ __forceinline__ bool chol6p(double J[21]) {
 #pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    double s = A[j][j];
+  for (int i = 0; i < 6; ++i) {
+    double s = J[pk(i, i)];
 #pragma unroll
-    for (int k = 0; k < 6; ++k)
-      if (k < j) s -= A[j][k] * A[j][k];
+    for (int k = 0; k < i; ++k) s -= J[pk(k, i)] * J[pk(k, i)];
     if (!(s > 0.0)) return false;
     const double d = sqrt(s);
-    A[j][j] = d;
+    J[pk(i, i)] = d;
+    const double id = 1.0 / d;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      if (i > j) {
-        double t = A[i][j];
+    for (int j = i + 1; j < 6; ++j) {
+      double t = J[pk(i, j)];
 #pragma unroll
-        for (int k = 0; k < 6; ++k)
-          if (k < j) t -= A[i][k] * A[j][k];
-        A[i][j] = t / d;
-      }
+      for (int k = 0; k < i; ++k) t -= J[pk(k, i)] * J[pk(k, j)];
+      J[pk(i, j)] = t * id;
     }
   }
   return true;
 }
 
-__device__ __forceinline__ void chol6_solve(const double L[6][6], const double b[6], double x[6]) {
+// Solve U^T U x = b with the packed upper factor U.
+__device__ __forceinline__ void chol6p_solve(const double U[21], const double b[6], double x[6]) {
   double y[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     double s = b[i];
 #pragma unroll
-    for (int k = 0; k < 6; ++k)
-      if (k < i) s -= L[i][k] * y[k];
-    y[i] = s / L[i][i];
+    for (int k = 0; k < i; ++k) s -= U[pk(k, i)] * y[k];
+    y[i] = s / U[pk(i, i)];
   }
 #pragma unroll
   for (int i = 5; i >= 0; --i) {
     double s = y[i];
 #pragma unroll
-    for (int k = 0; k < 6; ++k)
-      if (k > i) s -= L[k][i] * x[k];
-    x[i] = s / L[i][i];
+    for (int k = i + 1; k < 6; ++k) s -= U[pk(i, k)] * x[k];
+    x[i] = s / U[pk(i, i)];
   }
 }
 
-// Solve the return map from the warm start in sig (Mandel, in/out).  Returns the
-// number of Newton iterations, or -1 if it did not converge.
-__device__ int return_map(const double* __restrict__ S, const double* __restrict__ P,
-                          const double str[6], double g, double dtg0, double nexp, int nm1,
-                          double sig[6]) {
+// K = J^-1 = U^-1 U^-T (packed 21) from the packed upper factor U.
+__device__ __forceinline__ void chol6p_inverse(const double U[21], double K[21]) {
+  double W[21];            // W = U^-1, upper triangular, packed
+#pragma unroll
+  for (int j = 5; j >= 0; --j) {
+    W[pk(j, j)] = 1.0 / U[pk(j, j)];
+#pragma unroll
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = i + 1; k <= j; ++k) s += U[pk(i, k)] * W[pk(k, j)];
+      W[pk(i, j)] = -s / U[pk(i, i)];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i; j < 6; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = j; k < 6; ++k) s += W[pk(i, k)] * W[pk(j, k)];
+      K[pk(i, j)] = s;
+    }
+}
+
+// Solve the return map from the warm start in sig (crystal-frame Mandel, in/out) with
+// Newton steps and a backtracking line search on Phi.  Returns the number of Newton
+// iterations, or -1 if it did not converge.
+__device__ int return_map(const CrystalFrame& cf, const double str[6], double g, double dtg0,
+                          double nexp, int nm1, double sig[6]) {
+  const double ig = 1.0 / g;
   double scale = 0.0;
 #pragma unroll
   for (int i = 0; i < 6; ++i) scale = fmax(scale, fabs(str[i]));
@@ -200,14 +245,13 @@ __device__ int return_map(const double* __restrict__ S, const double* __restrict
   int it;
   bool conv = false;
   for (it = 0; it < 400; ++it) {
-    double Rv[6], J[6][6], tau[12], dg[12], d[6];
-    resjac(S, P, sig, str, g, dtg0, nexp, nm1, Rv, J, tau, dg);
-    if (!chol6(J)) return -1;
-    double mR[6];
+    double Rv[6], J[21], d[6], mR[6];
+    resjac(cf, sig, str, ig, dtg0, nexp, nm1, Rv, J);
+    if (!chol6p(J)) return -1;
 #pragma unroll
     for (int i = 0; i < 6; ++i) mR[i] = -Rv[i];
-    chol6_solve(J, mR, d);
-    const double phi0 = potential(S, P, sig, str, g, dtg0, nexp, nm1);
+    chol6p_solve(J, mR, d);
+    const double phi0 = potential(cf, sig, str, ig, dtg0, nexp, nm1);
     double slope = 0.0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) slope += Rv[i] * d[i];
@@ -216,7 +260,7 @@ __device__ int return_map(const double* __restrict__ S, const double* __restrict
       double c[6];
 #pragma unroll
       for (int i = 0; i < 6; ++i) c[i] = sig[i] + t * d[i];
-      const double phi1 = potential(S, P, c, str, g, dtg0, nexp, nm1);
+      const double phi1 = potential(cf, c, str, ig, dtg0, nexp, nm1);
       if (phi1 <= phi0 + 1e-4 * t * slope + 1e-13 * fabs(phi0)) break;
       t *= 0.5;
     }
@@ -232,46 +276,36 @@ __device__ int return_map(const double* __restrict__ S, const double* __restrict
   if (!conv) return -1;
   // one polishing Newton step at the root
   {
-    double Rv[6], J[6][6], tau[12], dg[12], d[6];
-    resjac(S, P, sig, str, g, dtg0, nexp, nm1, Rv, J, tau, dg);
-    if (!chol6(J)) return -1;
-    chol6_solve(J, Rv, d);
+    double Rv[6], J[21], d[6];
+    resjac(cf, sig, str, ig, dtg0, nexp, nm1, Rv, J);
+    if (!chol6p(J)) return -1;
+    chol6p_solve(J, Rv, d);
 #pragma unroll
     for (int i = 0; i < 6; ++i) sig[i] -= d[i];
   }
   return it + 1;
 }
 
-// K = J^-1 from the Cholesky factor L of J (packed 21 upper, row-major).
-__device__ __forceinline__ void chol6_inverse21(const double L[6][6], double K21[21]) {
-  double Li[6][6];
-#pragma unroll
-  for (int c = 0; c < 6; ++c) {
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-#pragma unroll
-      for (int k = 0; k < 6; ++k)
-        if (k < i && k >= c) s -= L[i][k] * Li[k][c];
-      Li[i][c] = (i >= c) ? s / L[i][i] : 0.0;
-    }
-  }
-  int idx = 0;
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
-    for (int j = i; j < 6; ++j) {
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k < 6; ++k)
-        if (k >= j) s += Li[k][i] * Li[k][j];
-      K21[idx++] = s;
-    }
-}
-
 __device__ __forceinline__ void load6(const double* __restrict__ f, long long N, long long v, double o[6]) {
 #pragma unroll
   for (int c = 0; c < 6; ++c) o[c] = f[c * N + v];
+}
+
+// Component c of a component-major field at byte offset boff (< 4 GiB): the component
+// base is uniform (scalar registers) and the lane offset 32 bits, so a voxel's many
+// component accesses share one offset register instead of a 64-bit address each.
+template <typename T>
+__device__ __forceinline__ T& comp(T* f, long long N, int c, unsigned boff) {
+  return *(T*)((char*)(f + c * N) + boff);
+}
+template <typename T>
+__device__ __forceinline__ const T& comp(const T* f, long long N, int c, unsigned boff) {
+  return *(const T*)((const char*)(f + c * N) + boff);
+}
+__device__ __forceinline__ void load6o(const double* __restrict__ f, long long N, unsigned boff,
+                                       double o[6]) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) o[c] = comp(f, N, c, boff);
 }
 
 // ---------------------------------------------------------------------------
@@ -284,65 +318,97 @@ k_constitutive(long long N, const double* __restrict__ eps, const double* __rest
                double t, const double* __restrict__ epsp, const double* __restrict__ gslip,
                const int* __restrict__ grain, const double* __restrict__ gtab,
                double* __restrict__ sig_io, const double* __restrict__ phi, R* __restrict__ gK,
-               double* __restrict__ gw, Material m, int* __restrict__ fail) {
+               double* __restrict__ gw, CrystalFrame cf, Material m, int* __restrict__ fail) {
   const double dtg0 = m.dt * m.gdot0;
   const int nm1 = m.nexp_int > 0 ? m.nexp_int - 1 : -1;
-  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
-       v += (long long)gridDim.x * blockDim.x) {
-    const double* gt = gtab + (long long)grain[v] * GT_STRIDE;
-    const double* C = gt + GT_C;
-    const double* S = gt + GT_S;
-    const double* P = gt + GT_P;
-    double e[6], ep[6], s0[6], em[6], epm[6], str[6], sig[6];
-    load6(eps, N, v, e);
+  // one voxel per thread (N < 2^29, so byte offsets fit 32 bits)
+  const unsigned v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < N) {
+    const unsigned b8 = v * 8u, bR = v * (unsigned)sizeof(R);
+    // Q: Mandel rotation crystal -> sample (orthogonal, so Q^T maps back)
+    const double* Q = gtab + (long long)comp(grain, N, 0, v * 4u) * GT_STRIDE + GT_Q;
+    double e[6], ep[6], s0[6], de[6], em[6], sm[6], ec[6], str[6], sig[6];
+    load6o(eps, N, b8, e);
     if (deps) {
-      double de[6];
-      load6(deps, N, v, de);
+      load6o(deps, N, b8, de);
 #pragma unroll
       for (int c = 0; c < 6; ++c) e[c] += t * de[c];
     }
-    load6(epsp, N, v, ep);
-    load6(sig_io, N, v, s0);
+    load6o(epsp, N, b8, ep);
+    load6o(sig_io, N, b8, s0);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) e[c] -= ep[c];
     to_mandel(e, em);
-    to_mandel(ep, epm);
-    to_mandel(s0, sig);
+    to_mandel(s0, sm);
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      double s = 0.0;
+    for (int j = 0; j < 6; ++j) {
+      double a = 0.0, b = 0.0;
 #pragma unroll
-      for (int j = 0; j < 6; ++j) s += C[i * 6 + j] * (em[j] - epm[j]);
-      str[i] = s;
+      for (int i = 0; i < 6; ++i) {
+        a += Q[i * 6 + j] * em[i];
+        b += Q[i * 6 + j] * sm[i];
+      }
+      ec[j] = a;
+      sig[j] = b;
     }
-    const double g = gslip[v];
-    const int its = return_map(S, P, str, g, dtg0, m.nexp, nm1, sig);
+    cubic_mul(cf.c11, cf.c12, cf.c66, ec, str);
+    const double g = comp(gslip, N, 0, b8);
+    const int its = return_map(cf, str, g, dtg0, m.nexp, nm1, sig);
     if (its < 0) atomicAdd(fail, 1);
-    // tangent at the root
-    double Rv[6], J[6][6], tau[12], dg[12];
-    resjac(S, P, sig, str, g, dtg0, m.nexp, nm1, Rv, J, tau, dg);
-    double K21[21];
-    if (chol6(J)) chol6_inverse21(J, K21);
+    const double ig = 1.0 / g;
+    // tangent at the root, crystal frame
+    double Rv[6], J[21];
+    resjac(cf, sig, str, ig, dtg0, m.nexp, nm1, Rv, J);
+    double K[21];
+    if (chol6p(J)) chol6p_inverse(J, K);
     else {
       atomicAdd(fail, 1);
 #pragma unroll
-      for (int c = 0; c < 21; ++c) K21[c] = 0.0;
+      for (int c = 0; c < 21; ++c) K[c] = 0.0;
     }
-    const double q = 1.0 - phi[v];
+    const double q = 1.0 - comp(phi, N, 0, b8);
     const double gphi = q * q + m.kres;
+    // incremental energy (frame invariant)
+    {
+      double Ss[6];
+      cubic_mul(cf.s11, cf.s12, cf.s66, str, Ss);
+      double el = 0.0;
 #pragma unroll
-    for (int c = 0; c < 21; ++c) gK[(long long)c * N + v] = (R)(gphi * K21[c]);
-    double el = 0.0;
+      for (int i = 0; i < 6; ++i) el += str[i] * Ss[i];
+      comp(gw, N, 0, b8) = gphi * (0.5 * el - potential(cf, sig, str, ig, dtg0, m.nexp, nm1));
+    }
+    // back to the sample frame: sigma = Q sig, gK = g(phi) Q K Q^T
+    {
+      double ss[6], st[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) a += Q[i * 6 + k] * sig[k];
+        ss[i] = a;
+      }
+      from_mandel(ss, st);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) comp(sig_io, N, c, b8) = st[c];
+    }
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      double s = 0.0;
+      double u[6];                 // row i of Q K
 #pragma unroll
-      for (int j = 0; j < 6; ++j) s += S[i * 6 + j] * str[j];
-      el += str[i] * s;
+      for (int l = 0; l < 6; ++l) {
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) a += Q[i * 6 + k] * K[pk(k, l)];
+        u[l] = a;
+      }
+#pragma unroll
+      for (int j = i; j < 6; ++j) {
+        double a = 0.0;
+#pragma unroll
+        for (int l = 0; l < 6; ++l) a += u[l] * Q[j * 6 + l];
+        comp(gK, N, pk(i, j), bR) = (R)(gphi * a);
+      }
     }
-    gw[v] = gphi * (0.5 * el - potential(S, P, sig, str, g, dtg0, m.nexp, nm1));
-    double st[6];
-    from_mandel(sig, st);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) sig_io[c * N + v] = st[c];
   }
 }
 
@@ -372,21 +438,24 @@ template <typename R>
 void launch_constitutive(long long N, const double* eps, const double* deps, double t,
                          const double* epsp, const double* gslip, const int* grain,
                          const double* gtab, double* sig, const double* phi, R* gK, double* gw,
-                         const Material& m, double* partial, int* fail, hipStream_t st) {
+                         const CrystalFrame& cf, const Material& m, double* partial, int* fail,
+                         hipStream_t st) {
   const long long nb = (N + 255) / 256;
   hipLaunchKernelGGL((k_constitutive<R>), dim3((int)(nb < 1 ? 1 : nb)), dim3(256), 0, st, N, eps,
-                     deps, t, epsp, gslip, grain, gtab, sig, phi, gK, gw, m, fail);
+                     deps, t, epsp, gslip, grain, gtab, sig, phi, gK, gw, cf, m, fail);
   hipLaunchKernelGGL((k_const_sums<R>), dim3(voxel_grid(N)), dim3(256), 0, st, N, gK, gw, sig,
                      phi, m.kres, partial);
 }
 template void launch_constitutive<double>(long long, const double*, const double*, double,
                                           const double*, const double*, const int*, const double*,
                                           double*, const double*, double*, double*,
-                                          const Material&, double*, int*, hipStream_t);
+                                          const CrystalFrame&, const Material&, double*, int*,
+                                          hipStream_t);
 template void launch_constitutive<float>(long long, const double*, const double*, double,
                                          const double*, const double*, const int*, const double*,
-                                         double*, const double*, float*, double*, const Material&,
-                                         double*, int*, hipStream_t);
+                                         double*, const double*, float*, double*,
+                                         const CrystalFrame&, const Material&, double*, int*,
+                                         hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Cyclic Jacobi eigen-decomposition of a symmetric 3x3 (columns of V = vectors).
