@@ -190,7 +190,13 @@ enum {
   RVE_PASS_DIV = 4,          /* -i xi~ . sigma, 6 -> 3 components                    */
   RVE_PASS_PRECOND = 5,      /* [xi~ . Kbar . xi~]^-1 and <r, z>, 3 components        */
   RVE_PASS_CONSTITUTIVE = 6, /* return map, tangent and reductions                    */
-  RVE_PASS_MATVEC = 7        /* the whole operator application (passes 3,0,1,2,1,0,4) */
+  RVE_PASS_MATVEC = 7,       /* the whole operator application, as the solver runs it:
+                                passes 8,1,2,1,9 where available, else 3,0,1,2,1,0,4   */
+  RVE_PASS_ZGRAD = 8,        /* CG direction update p = z + beta p, sym(i xi~ (x) p) and
+                                the inverse z transform in one pass (even N1 and N3 in
+                                16,32,48,64,96,128,256; RVE_E_ARG otherwise)            */
+  RVE_PASS_ZDIV = 9          /* forward z transform, -i xi~ . sigma and block partials
+                                of <p, q> in one pass (same grids as RVE_PASS_ZGRAD)    */
 };
 int rve_diag_pass(struct rve_s* h, int32_t pass_id, int32_t reps, double* bytes_per_launch);
 

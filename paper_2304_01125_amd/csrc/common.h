@@ -49,6 +49,20 @@ struct Grid {
   double L1, L2, L3;        // box lengths [m]
 };
 
+// Angular frequency of index k on an axis of N points and length L (signed, numpy
+// ordering).  With tilde the Nyquist index of an even axis maps to zero: the
+// derivative of a real field has no Nyquist component.
+__device__ __forceinline__ double freq(int k, int N, double L, bool tilde) {
+  if (tilde && (N % 2 == 0) && k == N / 2) return 0.0;
+  const int m = (k <= (N - 1) / 2) ? k : k - N;
+  return 6.283185307179586476925286766559 * (double)m / L;
+}
+
+// Parseval weight of a half-spectrum bin (x-bins 0 and N1/2 stand for themselves).
+__device__ __forceinline__ double parseval_w(int kx, int n1) {
+  return (kx == 0 || (n1 % 2 == 0 && kx == n1 / 2)) ? 1.0 : 2.0;
+}
+
 // Reduction width: one partial per block, summed in a fixed order by one block.
 constexpr int kRedBlock = 256;
 constexpr int kMaxRedBlocks = 2048;

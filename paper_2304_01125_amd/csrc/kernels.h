@@ -64,11 +64,27 @@ void launch_grad_cgp(const Plans& p, cplx<R>* pv, const cplx<R>* z, long long cs
 template <typename R>
 int launch_div_dot(const Plans& p, const cplx<R>* s, cplx<R>* q, const cplx<R>* pv, long long cs,
                    double* partial, hipStream_t st, const double* stop = nullptr);
-// x += a p, r -= a q (a = sc[ia]/sc[ib]), z = M r, partials <r,r>, <r,z>; returns #blocks
+// z passes fused with the operator's end points (passes.hip); available for even n1 and
+// n3 in the register-DFT set.  zgrad_inv: p_new = z + (sc[ia]/sc[ib]) p_old (stored),
+// e = F_z^-1{sym(i xi~ (x) p_new)}.  zdiv_fwd: q = -i xi~ . F_z{s} and block partials of
+// <p, q>; returns #blocks.
 template <typename R>
-int launch_cg_update(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, const cplx<R>* q,
-                     cplx<R>* z, long long cs, const double* kbar21, const double* sc, int ia,
-                     int ib, double* partial, hipStream_t st, const double* stop = nullptr);
+bool fused_z_available(const Plans& p);
+template <typename R>
+void launch_zgrad_inv(const Plans& p, const cplx<R>* z, const cplx<R>* pold, cplx<R>* pnew,
+                      long long cs, const double* sc, int ia, int ib, cplx<R>* e, hipStream_t st,
+                      const double* stop = nullptr);
+template <typename R>
+int launch_zdiv_fwd(const Plans& p, const cplx<R>* s, cplx<R>* q, const cplx<R>* pv, long long cs,
+                    double* partial, hipStream_t st, const double* stop = nullptr);
+// One CG step after the operator: alpha = sc[cur] / sc[ipq]; x += alpha p;
+// r -= alpha h(q), with h the Hermitian projection of the self-conjugate x-planes
+// applied on the fly; z = M r; block partials of <r, r> and <r, z> at partial[0][blk],
+// partial[1][blk].  Returns #blocks.
+template <typename R>
+int launch_cg_step(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, const cplx<R>* q,
+                   cplx<R>* z, long long cs, const double* kbar21, const double* sc, int cur,
+                   int ipq, double* partial, hipStream_t st, const double* stop);
 // Hermitian projection of the self-conjugate x-planes (spectra of real fields)
 template <typename R>
 void launch_herm_proj(const Plans& p, cplx<R>* v, long long cs, int ncomp, hipStream_t st,
@@ -145,27 +161,21 @@ void launch_clamp(long long N, const double* x, const double* phi_t, double* phi
 
 // --- reductions and vector kernels (vector.hip) ---------------------------------------
 // out[c] = sum (or max) over b < nblk of partial[c*nblk + b], fixed order.
+// CG reductions with the device-side control: reduce_pq sums the partials of <p, q>
+// into sc[ipq] and sets sc[iflag] = 2 unless it is positive and finite; reduce_check
+// sums <r, r> and <r, z>, counts the iteration in sc[iiter], stores <r, z> in sc[nxt]
+// and sets sc[iflag] to 1 when <r, r> <= sc[itol2] or 2 when it is not finite.  Both are
+// no-ops once sc[iflag] is non-zero.
+void launch_reduce_pq(const double* partial, int nblk, double* sc, int ipq, int iflag,
+                      hipStream_t st);
+void launch_reduce_check(const double* partial, int nblk, double* sc, int iiter, int nxt,
+                         int iflag, int itol2, hipStream_t st);
 void launch_reduce(const double* partial, int nblk, int ncomp, int op_max, double* out,
                    hipStream_t st, const double* stop = nullptr);
 // Parseval-weighted <a,b> over ncomp half-spectrum components; returns #blocks.
 template <typename R>
 int launch_sdot(const Plans& p, const cplx<R>* a, const cplx<R>* b, long long cs, int ncomp,
                 double* partial, hipStream_t st, const double* stop = nullptr);
-// CG updates on half-spectrum vectors (3 comps), scalars read from device `sc`:
-// x += a p ; r -= a q ; partial <r,r>   with a = sc[ia] / sc[ib]
-template <typename R>
-int launch_cg_xr(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, const cplx<R>* q,
-                 long long cs, const double* sc, int ia, int ib, double* partial, hipStream_t st,
-                 const double* stop = nullptr);
-// p = z + b p with b = sc[ia] / sc[ib]
-template <typename R>
-void launch_cg_p(const Plans& p, cplx<R>* pv, const cplx<R>* z, long long cs, const double* sc,
-                 int ia, int ib, hipStream_t st, const double* stop = nullptr);
-// device-side CG convergence test (see vector.hip)
-void launch_cg_check(double* sc, int flag, int iter, int rr, int tol2, int pq, hipStream_t st);
-// as launch_cg_check, and while running copies sc[rzn] to sc[nxt]
-void launch_cg_check2(double* sc, int flag, int iter, int rr, int tol2, int pq, int rzn, int nxt,
-                      hipStream_t st);
 // real-vector kernels (phase field)
 int launch_rdot(long long n, const double* a, const double* b, double* partial, hipStream_t st);
 // pq = <p, w + 2 S p>

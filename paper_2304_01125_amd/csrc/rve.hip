@@ -269,6 +269,8 @@ enum { SC_K = 0,        // 28 constitutive sums (21 gK, g w, 6 g sigma)
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+
+
 // Bump allocation of every buffer; with h->base == nullptr only the size is summed.
 void layout(rve_s* h) {
   const long long N = h->g.nvox, NH = h->g.nspec;
@@ -375,14 +377,25 @@ struct Ops {
   }
   // q = B p = - i xi~ . F{ gK : F^-1{ sym(i xi~ (x) p) } }; every launch is skipped
   // once *stop is non-zero (device-side Krylov termination).
-  void matvec(const C* p, C* q, const double* stop = nullptr) {
-    launch_sym_grad<R>(h->pl, p, NH, W, NH, st, stop);
-    launch_fft_yz<R>(h->pl, W, NH, 6, 2, true, st, stop);
+  // With the fused z passes, `scratch` (3 NH) receives the copy of p the inverse pass
+  // stores as the updated direction, and the partials of <p, q> are left unused.
+  void matvec(const C* p, C* q, C* scratch, const double* stop = nullptr) {
+    const bool fz = fused_z_available<R>(h->pl);
+    if (fz) {
+      launch_zgrad_inv<R>(h->pl, p, p, scratch, NH, h->scal, SC_ZERO, SC_ONE, W, st, stop);
+    } else {
+      launch_sym_grad<R>(h->pl, p, NH, W, NH, st, stop);
+      launch_fft_yz<R>(h->pl, W, NH, 6, 2, true, st, stop);
+    }
     launch_fft_yz<R>(h->pl, W, NH, 6, 1, true, st, stop);
     launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
     launch_fft_yz<R>(h->pl, W, NH, 6, 1, false, st, stop);
-    launch_fft_yz<R>(h->pl, W, NH, 6, 2, false, st, stop);
-    launch_div<R>(h->pl, W, NH, q, NH, -1.0, st, stop);
+    if (fz) {
+      launch_zdiv_fwd<R>(h->pl, W, q, p, NH, h->partial, st, stop);
+    } else {
+      launch_fft_yz<R>(h->pl, W, NH, 6, 2, false, st, stop);
+      launch_div<R>(h->pl, W, NH, q, NH, -1.0, st, stop);
+    }
   }
   // mean tangent from the constitutive sums
   void kbar() { launch_rscale(21, h->scal + SC_K, 1.0 / (double)N, h->scal + SC_KBAR, st); }
@@ -433,6 +446,10 @@ struct Ops {
     HIPCHK(hipMemcpyAsync(sc + SC_FLAG, h->hs + SC_FLAG, 3 * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(sc + SC_ZERO, h->hs + SC_ZERO, 2 * sizeof(double), hipMemcpyHostToDevice, st));
     const double* stop = sc + SC_FLAG;
+    // With the fused z passes the direction alternates between two buffers (the
+    // right-hand side is no longer needed once r = b): each iteration reads p_old and
+    // writes p_new while other blocks still read p_old.
+    const bool fz = fused_z_available<R>(h->pl);
     int queued = 0, batch = 4;
     while (queued < h->d.max_krylov) {
       const int nq = std::min(batch, h->d.max_krylov - queued);
@@ -440,20 +457,31 @@ struct Ops {
         const int k = queued + kk;
         const int cur = SC_RZ0 + (k & 1), prv = SC_RZ0 + ((k + 1) & 1);
         // p = z + beta p (beta = rz_k / rz_{k-1}, 0 on the first iteration), gradient
-        if (k == 0) launch_grad_cgp<R>(h->pl, p, z, NH, sc, SC_ZERO, SC_ONE, W, st, stop);
-        else launch_grad_cgp<R>(h->pl, p, z, NH, sc, cur, prv, W, st, stop);
-        launch_fft_yz<R>(h->pl, W, NH, 6, 2, true, st, stop);
+        const int ia = (k == 0) ? SC_ZERO : cur, ib = (k == 0) ? SC_ONE : prv;
+        C* pk = p;
+        if (fz) {
+          C* pold = (k & 1) ? b : p;
+          pk = (k & 1) ? p : b;
+          launch_zgrad_inv<R>(h->pl, z, pold, pk, NH, sc, ia, ib, W, st, stop);
+        } else {
+          launch_grad_cgp<R>(h->pl, p, z, NH, sc, ia, ib, W, st, stop);
+          launch_fft_yz<R>(h->pl, W, NH, 6, 2, true, st, stop);
+        }
         launch_fft_yz<R>(h->pl, W, NH, 6, 1, true, st, stop);
         launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
         launch_fft_yz<R>(h->pl, W, NH, 6, 1, false, st, stop);
-        launch_fft_yz<R>(h->pl, W, NH, 6, 2, false, st, stop);
-        nb = launch_div_dot<R>(h->pl, W, q, p, NH, h->partial, st, stop);
-        launch_reduce(h->partial, nb, 1, 0, sc + SC_PQ, st, stop);
-        launch_herm_proj<R>(h->pl, q, NH, 3, st, stop);
-        nb = launch_cg_update<R>(h->pl, x, r, p, q, z, NH, sc + SC_KBAR, sc, cur, SC_PQ,
-                                 h->partial, st, stop);
-        launch_reduce(h->partial, nb, 2, 0, sc + SC_RRN, st, stop);
-        launch_cg_check2(sc, SC_FLAG, SC_ITER, SC_RRN, SC_TOL2, SC_PQ, SC_RZN, prv, st);
+        // q = -i xi~ . sigma^ and <p, q> into sc[SC_PQ] (flag 2 if not positive)
+        if (fz) {
+          nb = launch_zdiv_fwd<R>(h->pl, W, q, pk, NH, h->partial, st, stop);
+        } else {
+          launch_fft_yz<R>(h->pl, W, NH, 6, 2, false, st, stop);
+          nb = launch_div_dot<R>(h->pl, W, q, p, NH, h->partial, st, stop);
+        }
+        launch_reduce_pq(h->partial, nb, sc, SC_PQ, SC_FLAG, st);
+        // x, r, z updates, <r, r>, <r, z> and the convergence test
+        nb = launch_cg_step<R>(h->pl, x, r, pk, q, z, NH, sc + SC_KBAR, sc, cur, SC_PQ,
+                               h->partial, st, stop);
+        launch_reduce_check(h->partial, nb, sc, SC_ITER, prv, SC_FLAG, SC_TOL2, st);
       }
       queued += nq;
       rc = sync_read(h, SC_FLAG, 2);
@@ -731,7 +759,11 @@ int rve_create(const rve_desc* d, void* dev_arena, size_t arena_bytes, void* hip
   upload_reg_twiddles(h->st);
   double Q[81];
   gnd_q(Q);
+  for (int i = 0; i < SC_N; ++i) h->hs[i] = 0.0;
+  h->hs[SC_ONE] = 1.0;
   if (hipMemcpyAsync(h->Q81, Q, 81 * 8, hipMemcpyHostToDevice, h->st) != hipSuccess ||
+      hipMemcpyAsync(h->scal, h->hs, SC_N * sizeof(double), hipMemcpyHostToDevice, h->st) !=
+          hipSuccess ||
       hipStreamSynchronize(h->st) != hipSuccess) {
     (void)hipHostFree(h->hs);
     delete h;
@@ -917,7 +949,14 @@ static int diag_pass(rve_s* h, int pass_id, int reps, double* bytes) {
         launch_precond<R>(h->pl, o.v(1), o.v(2), h->g.nspec, h->scal + SC_KBAR, h->partial, st);
         break;
       case RVE_PASS_CONSTITUTIVE: o.cur_dt = 1.0; o.constitutive(nullptr, 0.0, h->phi); break;
-      case RVE_PASS_MATVEC: o.matvec(o.v(3), o.v(4)); break;
+      case RVE_PASS_MATVEC: o.matvec(o.v(3), o.v(4), o.v(5)); break;
+      case RVE_PASS_ZGRAD:
+        launch_zgrad_inv<R>(h->pl, o.v(2), o.v(3), o.v(5), h->g.nspec, h->scal, SC_ONE, SC_ONE,
+                            o.W, st);
+        break;
+      case RVE_PASS_ZDIV:
+        launch_zdiv_fwd<R>(h->pl, o.W, o.v(4), o.v(3), h->g.nspec, h->partial, st);
+        break;
     }
   }
   switch (pass_id) {
@@ -926,7 +965,11 @@ static int diag_pass(rve_s* h, int pass_id, int reps, double* bytes) {
     case RVE_PASS_GRAD: case RVE_PASS_DIV: b = 9 * NH * cb; break;
     case RVE_PASS_PRECOND: b = 6 * NH * cb; break;
     case RVE_PASS_CONSTITUTIVE: b = N * (4 * 6 * 8 + 3 * 8 + 4 + 6 * 8 + 21 * rb); break;
-    case RVE_PASS_MATVEC: b = (9 + 4 * 12 + 12 + 9) * NH * cb + 21 * N * rb; break;
+    case RVE_PASS_MATVEC:
+      b = (fused_z_available<R>(h->pl) ? 5 * 12 : 9 + 4 * 12 + 12 + 9) * NH * cb + 21 * N * rb;
+      break;
+    case RVE_PASS_ZGRAD: b = 15 * NH * cb; break;
+    case RVE_PASS_ZDIV: b = 12 * NH * cb; break;
   }
   if (bytes) *bytes = b;
   HIPCHK(hipGetLastError());
@@ -997,7 +1040,7 @@ static int diag_op(rve_s* h, const double* u3, double* v3) {
   hipStream_t st = h->st;
   HIPCHK(hipMemcpyAsync(h->rbuf, u3, 3 * N * 8, hipMemcpyHostToDevice, st));
   o.fwd(h->rbuf, true, N, 3, o.v(3));
-  o.matvec(o.v(3), o.v(4));
+  o.matvec(o.v(3), o.v(4), o.v(5));
   launch_precond<R>(h->pl, o.v(4), o.v(2), NH, h->scal + SC_KBAR, h->partial, st);
   HIPCHK(hipMemcpyAsync(o.W, o.v(2), 3 * NH * sizeof(C), hipMemcpyDeviceToDevice, st));
   o.inv(o.W, 3, h->rbuf, true, N, 1.0 / (double)N, 0);
@@ -1010,7 +1053,10 @@ static int diag_op(rve_s* h, const double* u3, double* v3) {
 extern "C" {
 
 int rve_diag_pass(rve_s* h, int32_t pass_id, int32_t reps, double* bytes) {
-  if (!h || reps < 0 || pass_id < 0 || pass_id > RVE_PASS_MATVEC) return fail(RVE_E_ARG, "bad argument");
+  if (!h || reps < 0 || pass_id < 0 || pass_id > RVE_PASS_ZDIV) return fail(RVE_E_ARG, "bad argument");
+  if ((pass_id == RVE_PASS_ZGRAD || pass_id == RVE_PASS_ZDIV) &&
+      !(h->f64 ? fused_z_available<double>(h->pl) : fused_z_available<float>(h->pl)))
+    return fail(RVE_E_ARG, "no fused z pass for this grid");
   if (pass_id == RVE_PASS_CONSTITUTIVE && !h->micro) return fail(RVE_E_STATE, "microstructure not set");
   return h->f64 ? diag_pass<double>(h, pass_id, reps, bytes) : diag_pass<float>(h, pass_id, reps, bytes);
 }

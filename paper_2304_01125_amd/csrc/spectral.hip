@@ -9,13 +9,6 @@
 
 namespace rvefft {
 
-static constexpr double kTwoPi = 6.283185307179586476925286766559;
-
-__device__ __forceinline__ double freq(int k, int N, double L, bool tilde) {
-  if (tilde && (N % 2 == 0) && k == N / 2) return 0.0;
-  int m = (k <= (N - 1) / 2) ? k : k - N;
-  return kTwoPi * (double)m / L;
-}
 
 static int grid_for(long long n);
 
@@ -138,10 +131,6 @@ __device__ __forceinline__ int mandel_index(int i, int j) {
   return s == 3 ? 3 : (s == 2 ? 4 : 5);
 }
 
-// Parseval weight of a half-spectrum bin (x-bins 0 and N1/2 stand for themselves).
-__device__ __forceinline__ double parseval_w(int kx, int n1) {
-  return (kx == 0 || (n1 % 2 == 0 && kx == n1 / 2)) ? 1.0 : 2.0;
-}
 
 // Fourth-order mean tangent from its 21 Mandel entries into LDS (81 values).
 __device__ __forceinline__ void load_kbar4(double* K4, const double* __restrict__ kbar21) {
@@ -258,30 +247,52 @@ k_div_dot(const cplx<R>* __restrict__ s, long long scs, cplx<R>* __restrict__ ou
   block_partial_sum(acc, partial, red);
 }
 
-// alpha = sc[ia] / sc[ib]; x += alpha p; r -= alpha q; z = M r; block partials of
-// <r, r> and <r, z> (Parseval weights) at partial[0][blk], partial[1][blk].
+template <typename R>
+void launch_grad_cgp(const Plans& p, cplx<R>* pv, const cplx<R>* z, long long cs, const double* sc,
+                     int ia, int ib, cplx<R>* e, hipStream_t st, const double* stop) {
+  hipLaunchKernelGGL((k_grad_cgp<R>), dim3(grid_for(p.g.nspec)), dim3(256), 0, st, pv, z, cs, sc,
+                     ia, ib, e, cs, p.g, stop);
+}
+template <typename R>
+int launch_div_dot(const Plans& p, const cplx<R>* s, cplx<R>* q, const cplx<R>* pv, long long cs,
+                   double* partial, hipStream_t st, const double* stop) {
+  const int nb = grid_for(p.g.nspec);
+  hipLaunchKernelGGL((k_div_dot<R>), dim3(nb), dim3(256), 0, st, s, cs, q, cs, pv, p.g, partial,
+                     stop);
+  return nb;
+}
+
+// One CG step (see launch_cg_step in kernels.h).
 template <typename R>
 __global__ void __launch_bounds__(256)
-k_cg_update(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __restrict__ pv,
-            const cplx<R>* __restrict__ qv, cplx<R>* __restrict__ z, long long cs,
-            const double* __restrict__ kbar21, const double* __restrict__ sc, int ia, int ib,
-            Grid g, double* __restrict__ partial, const double* __restrict__ stop) {
+k_cg_step(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __restrict__ pv,
+          const cplx<R>* __restrict__ qv, cplx<R>* __restrict__ z, long long cs,
+          const double* __restrict__ kbar21, const double* __restrict__ sc, int cur, int ipq,
+          Grid g, double* __restrict__ partial, const double* __restrict__ stop) {
   if (stop && *stop != 0.0) return;
   __shared__ double K4[81];
-  __shared__ double red[2][16];
+  __shared__ double red[16];
   load_kbar4(K4, kbar21);
   __syncthreads();
-  const double al = sc[ia] / sc[ib];
+  const double al = sc[cur] / sc[ipq];
+  const bool even = (g.n1 % 2 == 0);
   double rr = 0.0, rz = 0.0;
   for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < g.nspec;
        b += (long long)gridDim.x * blockDim.x) {
     const Bin q = bin_of(b, g);
     const double t[3] = {freq(q.kx, g.n1, g.L1, true), freq(q.ky, g.n2, g.L2, true),
                          freq(q.kz, g.n3, g.L3, true)};
+    const bool selfconj = (q.kx == 0) || (even && q.kx == g.n1 / 2);
+    const long long bp = selfconj ? partner_bin(q, g) : b;
     cplx<R> rv[3], zo[3];
     for (int c = 0; c < 3; ++c) {
       const long long i = c * cs + b;
-      const cplx<R> pp = pv[i], qq = qv[i];
+      const cplx<R> pp = pv[i];
+      cplx<R> qq = qv[i];
+      if (selfconj) {
+        const cplx<R> qo = qv[c * cs + bp];
+        qq = cplx<R>{R(0.5) * (qq.x + qo.x), R(0.5) * (qq.y - qo.y)};
+      }
       cplx<R> xx = x[i], rr_ = r[i];
       xx.x = (R)((double)xx.x + al * (double)pp.x);
       xx.y = (R)((double)xx.y + al * (double)pp.y);
@@ -307,46 +318,37 @@ k_cg_update(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __r
     rz += __shfl_down(rz, off, 64);
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) { red[0][wid] = rr; red[1][wid] = rz; }
+  if (lane == 0) { red[wid] = rr; red[8 + wid] = rz; }
   __syncthreads();
   if (threadIdx.x < 2) {
     double sum = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += red[threadIdx.x][w];
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += red[8 * threadIdx.x + w];
     partial[(long long)threadIdx.x * gridDim.x + blockIdx.x] = sum;
   }
 }
 
 template <typename R>
-void launch_grad_cgp(const Plans& p, cplx<R>* pv, const cplx<R>* z, long long cs, const double* sc,
-                     int ia, int ib, cplx<R>* e, hipStream_t st, const double* stop) {
-  hipLaunchKernelGGL((k_grad_cgp<R>), dim3(grid_for(p.g.nspec)), dim3(256), 0, st, pv, z, cs, sc,
-                     ia, ib, e, cs, p.g, stop);
-}
-template <typename R>
-int launch_div_dot(const Plans& p, const cplx<R>* s, cplx<R>* q, const cplx<R>* pv, long long cs,
-                   double* partial, hipStream_t st, const double* stop) {
+int launch_cg_step(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, const cplx<R>* q,
+                   cplx<R>* z, long long cs, const double* kbar21, const double* sc, int cur,
+                   int ipq, double* partial, hipStream_t st, const double* stop) {
   const int nb = grid_for(p.g.nspec);
-  hipLaunchKernelGGL((k_div_dot<R>), dim3(nb), dim3(256), 0, st, s, cs, q, cs, pv, p.g, partial,
-                     stop);
+  hipLaunchKernelGGL((k_cg_step<R>), dim3(nb), dim3(256), 0, st, x, r, pv, q, z, cs, kbar21, sc,
+                     cur, ipq, p.g, partial, stop);
   return nb;
 }
-template <typename R>
-int launch_cg_update(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, const cplx<R>* q,
-                     cplx<R>* z, long long cs, const double* kbar21, const double* sc, int ia,
-                     int ib, double* partial, hipStream_t st, const double* stop) {
-  const int nb = grid_for(p.g.nspec);
-  hipLaunchKernelGGL((k_cg_update<R>), dim3(nb), dim3(256), 0, st, x, r, pv, q, z, cs, kbar21, sc,
-                     ia, ib, p.g, partial, stop);
-  return nb;
-}
+template int launch_cg_step<double>(const Plans&, cplx<double>*, cplx<double>*,
+                                    const cplx<double>*, const cplx<double>*, cplx<double>*,
+                                    long long, const double*, const double*, int, int, double*,
+                                    hipStream_t, const double*);
+template int launch_cg_step<float>(const Plans&, cplx<float>*, cplx<float>*, const cplx<float>*,
+                                   const cplx<float>*, cplx<float>*, long long, const double*,
+                                   const double*, int, int, double*, hipStream_t, const double*);
 #define RVE_CG_INST(R)                                                                           \
   template void launch_grad_cgp<R>(const Plans&, cplx<R>*, const cplx<R>*, long long,             \
                                    const double*, int, int, cplx<R>*, hipStream_t, const double*); \
   template int launch_div_dot<R>(const Plans&, const cplx<R>*, cplx<R>*, const cplx<R>*,          \
-                                 long long, double*, hipStream_t, const double*);                \
-  template int launch_cg_update<R>(const Plans&, cplx<R>*, cplx<R>*, const cplx<R>*,              \
-                                   const cplx<R>*, cplx<R>*, long long, const double*,           \
-                                   const double*, int, int, double*, hipStream_t, const double*);
+                                 long long, double*, hipStream_t, const double*);
+
 RVE_CG_INST(double)
 RVE_CG_INST(float)
 

@@ -42,6 +42,56 @@ void launch_reduce(const double* partial, int nblk, int ncomp, int op_max, doubl
   hipLaunchKernelGGL(k_reduce, dim3(ncomp), dim3(256), 0, st, partial, nblk, op_max, out, stop);
 }
 
+// Fixed-order sum of a[0..n) by one block of 256 threads (result valid in thread 0).
+__device__ double block_sum256(const double* __restrict__ a, int n, double* sh) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < n; b += 256) s += a[b];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_reduce_pq(const double* __restrict__ partial, int nblk,
+                                                   double* __restrict__ sc, int ipq, int iflag) {
+  if (sc[iflag] != 0.0) return;
+  __shared__ double sh[256];
+  const double pq = block_sum256(partial, nblk, sh);
+  if (threadIdx.x == 0) {
+    sc[ipq] = pq;
+    if (!(pq > 0.0) || !isfinite(pq)) sc[iflag] = 2.0;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_reduce_check(const double* __restrict__ partial, int nblk,
+                                                      double* __restrict__ sc, int iiter, int nxt,
+                                                      int iflag, int itol2) {
+  if (sc[iflag] != 0.0) return;
+  __shared__ double sh[256];
+  const double rr = block_sum256(partial, nblk, sh);
+  __syncthreads();
+  const double rz = block_sum256(partial + nblk, nblk, sh);
+  if (threadIdx.x == 0) {
+    sc[iiter] += 1.0;
+    sc[nxt] = rz;
+    if (!isfinite(rr)) sc[iflag] = 2.0;
+    else if (rr <= sc[itol2]) sc[iflag] = 1.0;
+  }
+}
+
+void launch_reduce_pq(const double* partial, int nblk, double* sc, int ipq, int iflag,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_pq, dim3(1), dim3(256), 0, st, partial, nblk, sc, ipq, iflag);
+}
+void launch_reduce_check(const double* partial, int nblk, double* sc, int iiter, int nxt,
+                         int iflag, int itol2, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_check, dim3(1), dim3(256), 0, st, partial, nblk, sc, iiter, nxt,
+                     iflag, itol2);
+}
+
 __device__ __forceinline__ double pw_weight(long long b, const Grid& g) {
   const int kx = (int)(b % g.n1h);
   return (kx == 0 || (g.n1 % 2 == 0 && kx == g.n1 / 2)) ? 1.0 : 2.0;
@@ -74,112 +124,10 @@ int launch_sdot(const Plans& p, const cplx<R>* a, const cplx<R>* b, long long cs
   return nb;
 }
 
-template <typename R>
-__global__ void __launch_bounds__(256) k_cg_xr(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r,
-                        const cplx<R>* __restrict__ pv, const cplx<R>* __restrict__ q, long long cs,
-                        const double* __restrict__ sc, int ia, int ib, Grid g,
-                        double* __restrict__ partial, const double* __restrict__ stop) {
-  if (stop && *stop != 0.0) return;
-  __shared__ double red[16];
-  const double al = sc[ia] / sc[ib];
-  double acc = 0.0;
-  for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < g.nspec;
-       b += (long long)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int c = 0; c < 3; ++c) {
-      const long long i = c * cs + b;
-      const cplx<R> pp = pv[i], qq = q[i];
-      cplx<R> xx = x[i], rr = r[i];
-      xx.x = (R)((double)xx.x + al * (double)pp.x);
-      xx.y = (R)((double)xx.y + al * (double)pp.y);
-      rr.x = (R)((double)rr.x - al * (double)qq.x);
-      rr.y = (R)((double)rr.y - al * (double)qq.y);
-      x[i] = xx;
-      r[i] = rr;
-      s += (double)rr.x * (double)rr.x + (double)rr.y * (double)rr.y;
-    }
-    acc += pw_weight(b, g) * s;
-  }
-  block_partial_sum(acc, partial, red);
-}
-
-template <typename R>
-int launch_cg_xr(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, const cplx<R>* q,
-                 long long cs, const double* sc, int ia, int ib, double* partial, hipStream_t st,
-                 const double* stop) {
-  const int nb = vgrid(p.g.nspec);
-  hipLaunchKernelGGL((k_cg_xr<R>), dim3(nb), dim3(256), 0, st, x, r, pv, q, cs, sc, ia, ib, p.g,
-                     partial, stop);
-  return nb;
-}
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_cg_p(cplx<R>* __restrict__ pv, const cplx<R>* __restrict__ z, long long cs,
-                       const double* __restrict__ sc, int ia, int ib, long long nspec,
-                       const double* __restrict__ stop) {
-  if (stop && *stop != 0.0) return;
-  const double be = sc[ia] / sc[ib];
-  for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < nspec;
-       b += (long long)gridDim.x * blockDim.x) {
-    for (int c = 0; c < 3; ++c) {
-      const long long i = c * cs + b;
-      const cplx<R> zz = z[i], pp = pv[i];
-      pv[i] = cplx<R>{(R)((double)zz.x + be * (double)pp.x), (R)((double)zz.y + be * (double)pp.y)};
-    }
-  }
-}
-
-template <typename R>
-void launch_cg_p(const Plans& p, cplx<R>* pv, const cplx<R>* z, long long cs, const double* sc,
-                 int ia, int ib, hipStream_t st, const double* stop) {
-  hipLaunchKernelGGL((k_cg_p<R>), dim3(vgrid(p.g.nspec)), dim3(256), 0, st, pv, z, cs, sc, ia, ib,
-                     p.g.nspec, stop);
-}
-
-// Convergence test of one CG iteration on the device.  sc[flag] = 0 while running,
-// 1 when converged (sc[rr] <= sc[tol2]), 2 on breakdown (non-positive curvature or a
-// non-finite residual); sc[iter] counts the iterations that ran.
-__global__ void k_cg_check(double* __restrict__ sc, int flag, int iter, int rr, int tol2, int pq) {
-  if (threadIdx.x != 0 || sc[flag] != 0.0) return;
-  sc[iter] += 1.0;
-  const double r = sc[rr];
-  if (!(sc[pq] > 0.0) || !isfinite(r)) sc[flag] = 2.0;
-  else if (r <= sc[tol2]) sc[flag] = 1.0;
-}
-
-void launch_cg_check(double* sc, int flag, int iter, int rr, int tol2, int pq, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(64), 0, st, sc, flag, iter, rr, tol2, pq);
-}
-
-__global__ void k_cg_check2(double* __restrict__ sc, int flag, int iter, int rr, int tol2, int pq,
-                            int rzn, int nxt) {
-  if (threadIdx.x != 0 || sc[flag] != 0.0) return;
-  sc[iter] += 1.0;
-  sc[nxt] = sc[rzn];
-  const double r = sc[rr];
-  if (!(sc[pq] > 0.0) || !isfinite(r)) sc[flag] = 2.0;
-  else if (r <= sc[tol2]) sc[flag] = 1.0;
-}
-
-void launch_cg_check2(double* sc, int flag, int iter, int rr, int tol2, int pq, int rzn, int nxt,
-                      hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_check2, dim3(1), dim3(64), 0, st, sc, flag, iter, rr, tol2, pq, rzn, nxt);
-}
-
 template int launch_sdot<double>(const Plans&, const cplx<double>*, const cplx<double>*, long long,
                                  int, double*, hipStream_t, const double*);
 template int launch_sdot<float>(const Plans&, const cplx<float>*, const cplx<float>*, long long,
                                 int, double*, hipStream_t, const double*);
-template int launch_cg_xr<double>(const Plans&, cplx<double>*, cplx<double>*, const cplx<double>*,
-                                  const cplx<double>*, long long, const double*, int, int, double*,
-                                  hipStream_t, const double*);
-template int launch_cg_xr<float>(const Plans&, cplx<float>*, cplx<float>*, const cplx<float>*,
-                                 const cplx<float>*, long long, const double*, int, int, double*,
-                                 hipStream_t, const double*);
-template void launch_cg_p<double>(const Plans&, cplx<double>*, const cplx<double>*, long long,
-                                  const double*, int, int, hipStream_t, const double*);
-template void launch_cg_p<float>(const Plans&, cplx<float>*, const cplx<float>*, long long,
-                                 const double*, int, int, hipStream_t, const double*);
 
 // ---- real vectors (phase field) -------------------------------------------------------
 __global__ void __launch_bounds__(256) k_rdot(long long n, const double* __restrict__ a, const double* __restrict__ b,

@@ -23,7 +23,7 @@ FIELDS = [  # (name, bit, components) in the order rve_fields writes them
 ]
 FIELD_BITS = {n: (b, c) for n, b, c in FIELDS}
 PASSES = {"fft_z": 0, "fft_y": 1, "x_tangent": 2, "grad": 3, "div": 4, "precond": 5,
-          "constitutive": 6, "matvec": 7}
+          "constitutive": 6, "matvec": 7, "zgrad": 8, "zdiv": 9}
 
 
 class RveDesc(ctypes.Structure):
