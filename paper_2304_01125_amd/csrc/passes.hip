@@ -658,10 +658,8 @@ k_zgrad_inv(const cplx<R>* __restrict__ zv, const cplx<R>* __restrict__ pold,
 }
 
 // Component i of q = -i xi~ . F_z{s} and the block partial of the Parseval-weighted
-// <p, q>, in two rounds: xi~_z F_z{s_iz} and F_z{xi~_x s_ix + xi~_y s_iy} (whose x and y
-// factors are constant along z).  The first round's result waits in LDS.  Blocks 0 and
-// 1 of a unit take the z round first and block 2 takes it last, so each shared stress
-// component (xy; xz; yz) is read by two blocks in the same round.
+// <p, q>, in two rounds: xi~_z F_z{s_iz} first (its result waits in LDS), then
+// F_z{xi~_x s_ix + xi~_y s_iy}, whose x and y factors are constant along z.
 template <typename R, int N, int TX, int NT>
 __global__ void __launch_bounds__(NT)
 k_zdiv_fwd(const cplx<R>* __restrict__ s, cplx<R>* __restrict__ q, const cplx<R>* __restrict__ pv,
@@ -696,8 +694,9 @@ k_zdiv_fwd(const cplx<R>* __restrict__ s, cplx<R>* __restrict__ q, const cplx<R>
   };
   double acc = 0.0;
   __syncthreads();
+#pragma unroll
   for (int round = 0; round < 2; ++round) {
-    const bool zr = (i == 2) ? (round == 1) : (round == 0);    // the xi~_z round
+    const bool zr = (round == 0);                               // the xi~_z round
     for (int t = threadIdx.x; t < P * Nb; t += NT) {
       const int x = t % P, n1 = t / P;
       const int cx = col(x);

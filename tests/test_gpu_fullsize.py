@@ -1,0 +1,85 @@
+"""Parity at the full size of the benchmark workload: the 128^3 polycrystal with 512
+log-normal Laguerre grains, on the kernels the benchmark times (fused z passes, register
+FFTs, 128-point x tangent pass).  A whole 128^3 oracle solve is too slow for a test, so
+the first increment is checked on what the oracle can compute voxel by voxel and on
+properties that hold at any size:
+
+* the imposed macroscopic strain is the mean strain;
+* at 4096 sampled voxels, the GPU stress, slip increments (through eps_p) and slip
+  resistance equal the oracle's return map at the GPU strain (state at t = 0 is known);
+* the degraded stress is equilibrated: its Fourier divergence i xi~ . sigma^ vanishes;
+* the mixed-precision increment reproduces the FP64 macroscopic stress within 1e-4.
+"""
+import numpy as np
+import pytest
+
+from synth import workload, make_inputs
+
+pytestmark = pytest.mark.gpu
+NAME = "laguerre-128-g512"
+
+
+def _first_increment(precision, parity=True):
+    from paper_2304_01125_amd import RVE
+    w = workload(NAME)
+    if parity:
+        w = w.parity()
+    inp = make_inputs(w)
+    r = RVE(w.desc(), precision)
+    r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+    st = r.step([0, inp["deps"][0], 0, 0, 0, 0], inp["dt"][0])
+    print(f"  {NAME} precision {precision}: newton {st['newton_iters']} krylov "
+          f"{st['krylov_iters']} stag {st['stag_iters']}", flush=True)
+    return w, inp, r, st
+
+
+def test_first_increment_at_full_size_matches_oracle_on_sampled_voxels():
+    from oracle import GrainTables, return_map, to_mandel2, Grid
+    from oracle.increment import from_tensor6
+    from paper_2304_01125_amd import RVE_FP64
+    w, inp, r, st = _first_increment(RVE_FP64)
+    f = r.fields(("strain", "stress", "stress_eff", "eps_p", "g", "damage"))
+    r.close()
+    N = w.nvox
+    # imposed macro strain
+    ebar = np.array([0.0, inp["deps"][0], 0.0, 0.0, 0.0, 0.0])
+    assert np.abs(f["strain"].mean(0) - ebar).max() <= 1e-15
+    assert np.abs(f["damage"]).max() == 0.0
+    # sampled voxels against the oracle's return map at the GPU strain
+    idx = np.random.default_rng(11).choice(N, 4096, replace=False)
+    tab = GrainTables(inp["quat"], w.C11, w.C12, w.C44)
+    gid = inp["grain"][idx]
+    g0 = np.asarray(inp["tau_c0"])[gid] if inp["tau_c0"] is not None else np.full(len(idx), w.tau_c0)
+    epsM = to_mandel2(from_tensor6(f["strain"][idx]))
+    sig, dgam, K, _ = return_map(epsM, np.zeros_like(epsM), g0, inp["dt"][0], tab.C[gid],
+                                 tab.S[gid], tab.P[gid], w.gdot0, w.n_exp)
+    sig_gpu = to_mandel2(from_tensor6(f["stress_eff"][idx]))
+    e_sig = np.linalg.norm(sig_gpu - sig) / np.linalg.norm(sig)
+    epsp_o = np.einsum("ma,mai->mi", dgam, tab.P[gid])
+    epsp_g = to_mandel2(from_tensor6(f["eps_p"][idx]))
+    e_ep = np.linalg.norm(epsp_g - epsp_o) / np.linalg.norm(epsp_o)
+    g1 = g0 + w.h_lin * np.abs(dgam).sum(1)
+    e_g = np.abs(f["g"][idx] - g1).max() / g1.max()
+    print(f"  sampled voxels: stress {e_sig:.2e}, eps_p {e_ep:.2e}, g {e_g:.2e}", flush=True)
+    assert e_sig <= 1e-10 and e_ep <= 1e-8 and e_g <= 1e-12
+    # equilibrium of the degraded stress
+    grid = Grid(w.n, w.h)
+    sh = grid.fft(grid.to_grid(from_tensor6(f["stress"])))
+    div = np.abs(grid.div_hat(sh)).max() / (np.abs(sh).max() * np.abs(grid.xit).max())
+    print(f"  equilibrium: max |i xi~ . sigma^| / (max |sigma^| max |xi~|) = {div:.2e}", flush=True)
+    assert div <= 1e-9
+
+
+def test_mixed_precision_at_full_size_reproduces_fp64_macro_stress():
+    from paper_2304_01125_amd import RVE_FP64, RVE_MIXED
+    ms = {}
+    fields = {}
+    for prec in (RVE_FP64, RVE_MIXED):
+        w, inp, r, st = _first_increment(prec, parity=False)
+        ms[prec] = np.array(st["macro_stress"])
+        fields[prec] = r.fields(("stress",))["stress"]
+        r.close()
+    err = np.abs(ms[RVE_MIXED] - ms[RVE_FP64]).max() / np.abs(ms[RVE_FP64]).max()
+    e_field = np.linalg.norm(fields[RVE_MIXED] - fields[RVE_FP64]) / np.linalg.norm(fields[RVE_FP64])
+    print(f"  mixed vs FP64: macro stress {err:.2e}, stress field rel. L2 {e_field:.2e}", flush=True)
+    assert err <= 1e-4
