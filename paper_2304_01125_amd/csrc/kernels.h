@@ -13,8 +13,10 @@ struct Plans {
   const void* tw_ptr(int axis, bool f64) const { return f64 ? tw64[axis] : tw32[axis]; }
 };
 
-// Upload the constant twiddle tables of the register DFTs (current device).
-void upload_reg_twiddles(hipStream_t st);
+// Fill the constant twiddle tables of the register DFTs (current device), in every
+// translation unit that holds a copy; synchronises the stream.
+hipError_t upload_reg_twiddles(hipStream_t st);
+hipError_t upload_reg_twiddles_zfused(hipStream_t st);
 
 // Radix schedule of a length 2^a 3^b; returns false for other lengths.
 bool make_axis_plan(int n, AxisPlan* out);

@@ -8,13 +8,35 @@
 // Every small DFT is fully unrolled; its twiddles are compile-time table entries.
 #pragma once
 #include "common.h"
+#include <cmath>
 
 namespace rvefft {
 
 // exp(-2 pi i k / 256) and exp(-2 pi i k / 192), k < 256 / 192: every register DFT
-// length used here divides one of them.
-extern __constant__ double c_tw256[2 * 256];
-extern __constant__ double c_tw192[2 * 192];
+// length used here divides one of them.  The library is built without relocatable
+// device code, so each translation unit that uses the register DFTs holds its own copy
+// of the tables and fills it with its own fill_reg_twiddles (at handle creation).
+static __constant__ double c_tw256[2 * 256];
+static __constant__ double c_tw192[2 * 192];
+
+static inline hipError_t fill_reg_twiddles(hipStream_t st) {
+  double t256[512], t192[384];
+  for (int k = 0; k < 256; ++k) {
+    t256[2 * k] = std::cos(-2.0 * M_PI * k / 256.0);
+    t256[2 * k + 1] = std::sin(-2.0 * M_PI * k / 256.0);
+  }
+  for (int k = 0; k < 192; ++k) {
+    t192[2 * k] = std::cos(-2.0 * M_PI * k / 192.0);
+    t192[2 * k + 1] = std::sin(-2.0 * M_PI * k / 192.0);
+  }
+  hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_tw256), t256, sizeof(t256), 0,
+                                        hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_tw192), t192, sizeof(t192), 0, hipMemcpyHostToDevice,
+                               st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e;
+}
 
 template <typename R, int L>
 __device__ __forceinline__ cplx<R> ctw(int a) {   // exp(-2 pi i a / L), a compile-time

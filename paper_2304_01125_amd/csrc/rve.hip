@@ -756,7 +756,11 @@ int rve_create(const rve_desc* d, void* dev_arena, size_t arena_bytes, void* hip
       return fail(RVE_E_DEVICE, "twiddle upload failed");
     }
   }
-  upload_reg_twiddles(h->st);
+  if (upload_reg_twiddles(h->st) != hipSuccess) {
+    (void)hipHostFree(h->hs);
+    delete h;
+    return fail(RVE_E_DEVICE, "register DFT table upload failed");
+  }
   double Q[81];
   gnd_q(Q);
   for (int i = 0; i < SC_N; ++i) h->hs[i] = 0.0;
