@@ -102,7 +102,7 @@ def measured_traffic(kernel, n):
     if not os.path.exists(path):
         return None
     txt = open(path).read()
-    src = re.search(r"source: `([^`]+)` sha256 `([0-9a-f]{64})`", txt)
+    src = re.search(r"(?i)source: `([^`]+)` sha256 `([0-9a-f]{64})`", txt)
     val = re.search(r"measured traffic per launch: ([0-9.]+) MB", txt)
     if not src or not val:
         return None

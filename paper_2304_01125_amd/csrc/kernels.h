@@ -66,7 +66,7 @@ void launch_grad_cgp(const Plans& p, cplx<R>* pv, const cplx<R>* z, long long cs
 template <typename R>
 int launch_div_dot(const Plans& p, const cplx<R>* s, cplx<R>* q, const cplx<R>* pv, long long cs,
                    double* partial, hipStream_t st, const double* stop = nullptr);
-// z passes fused with the operator's end points (passes.hip); available for even n1 and
+// z passes fused with the operator's end points (zfused.hip); available for even n1 and
 // n3 in the register-DFT set.  zgrad_inv: p_new = z + (sc[ia]/sc[ib]) p_old (stored),
 // e = F_z^-1{sym(i xi~ (x) p_new)}.  zdiv_fwd: q = -i xi~ . F_z{s} and block partials of
 // <p, q>; returns #blocks.
@@ -165,12 +165,12 @@ void launch_clamp(long long N, const double* x, const double* phi_t, double* phi
 // out[c] = sum (or max) over b < nblk of partial[c*nblk + b], fixed order.
 // CG reductions with the device-side control: reduce_pq sums the partials of <p, q>
 // into sc[ipq] and sets sc[iflag] = 2 unless it is positive and finite; reduce_check
-// sums <r, r> and <r, z>, counts the iteration in sc[iiter], stores <r, z> in sc[nxt]
-// and sets sc[iflag] to 1 when <r, r> <= sc[itol2] or 2 when it is not finite.  Both are
-// no-ops once sc[iflag] is non-zero.
+// sums <r, r> and <r, z>, counts the iteration in sc[iiter], stores <r, z> in sc[nxt] and
+// <r, r> in sc[irr], and sets sc[iflag] to 1 when <r, r> <= sc[itol2] or 2 when it is not
+// finite.  Both are no-ops once sc[iflag] is non-zero.
 void launch_reduce_pq(const double* partial, int nblk, double* sc, int ipq, int iflag,
                       hipStream_t st);
-void launch_reduce_check(const double* partial, int nblk, double* sc, int iiter, int nxt,
+void launch_reduce_check(const double* partial, int nblk, double* sc, int iiter, int nxt, int irr,
                          int iflag, int itol2, hipStream_t st);
 void launch_reduce(const double* partial, int nblk, int ncomp, int op_max, double* out,
                    hipStream_t st, const double* stop = nullptr);

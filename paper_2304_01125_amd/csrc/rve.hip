@@ -251,6 +251,10 @@ struct rve_s {
   double* partial;        // reduction partials
   double* scal;           // device scalars
   int* failc;
+  // HIP graphs of one CG iteration of each parity (captured at first use; the
+  // launches of an iteration depend on the handle and the parity only)
+  bool use_graphs = true;
+  hipGraphExec_t cg_exec[2] = {nullptr, nullptr};
   double* hs = nullptr;   // pinned host scalars
   bool micro = false;
   int n_grains = 0;
@@ -450,47 +454,86 @@ struct Ops {
     // right-hand side is no longer needed once r = b): each iteration reads p_old and
     // writes p_new while other blocks still read p_old.
     const bool fz = fused_z_available<R>(h->pl);
-    int queued = 0, batch = 4;
+    // the launches of CG iteration k (those of k >= 1 depend on the parity of k only)
+    auto enqueue_iter = [&](int k) {
+      const int cur = SC_RZ0 + (k & 1), prv = SC_RZ0 + ((k + 1) & 1);
+      // p = z + beta p (beta = rz_k / rz_{k-1}, 0 on the first iteration), gradient
+      const int ia = (k == 0) ? SC_ZERO : cur, ib = (k == 0) ? SC_ONE : prv;
+      C* pk = p;
+      if (fz) {
+        C* pold = (k & 1) ? b : p;
+        pk = (k & 1) ? p : b;
+        launch_zgrad_inv<R>(h->pl, z, pold, pk, NH, sc, ia, ib, W, st, stop);
+      } else {
+        launch_grad_cgp<R>(h->pl, p, z, NH, sc, ia, ib, W, st, stop);
+        launch_fft_yz<R>(h->pl, W, NH, 6, 2, true, st, stop);
+      }
+      launch_fft_yz<R>(h->pl, W, NH, 6, 1, true, st, stop);
+      launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
+      launch_fft_yz<R>(h->pl, W, NH, 6, 1, false, st, stop);
+      // q = -i xi~ . sigma^ and <p, q> into sc[SC_PQ] (flag 2 if not positive)
+      if (fz) {
+        nb = launch_zdiv_fwd<R>(h->pl, W, q, pk, NH, h->partial, st, stop);
+      } else {
+        launch_fft_yz<R>(h->pl, W, NH, 6, 2, false, st, stop);
+        nb = launch_div_dot<R>(h->pl, W, q, p, NH, h->partial, st, stop);
+      }
+      launch_reduce_pq(h->partial, nb, sc, SC_PQ, SC_FLAG, st);
+      // x, r, z updates, <r, r>, <r, z> and the convergence test
+      nb = launch_cg_step<R>(h->pl, x, r, pk, q, z, NH, sc + SC_KBAR, sc, cur, SC_PQ,
+                             h->partial, st, stop);
+      launch_reduce_check(h->partial, nb, sc, SC_ITER, prv, SC_RRN, SC_FLAG, SC_TOL2, st);
+    };
+    int queued = 0, batch = 4, it_ref = 0;
+    double rr_ref = bb;
     while (queued < h->d.max_krylov) {
       const int nq = std::min(batch, h->d.max_krylov - queued);
       for (int kk = 0; kk < nq; ++kk) {
         const int k = queued + kk;
-        const int cur = SC_RZ0 + (k & 1), prv = SC_RZ0 + ((k + 1) & 1);
-        // p = z + beta p (beta = rz_k / rz_{k-1}, 0 on the first iteration), gradient
-        const int ia = (k == 0) ? SC_ZERO : cur, ib = (k == 0) ? SC_ONE : prv;
-        C* pk = p;
-        if (fz) {
-          C* pold = (k & 1) ? b : p;
-          pk = (k & 1) ? p : b;
-          launch_zgrad_inv<R>(h->pl, z, pold, pk, NH, sc, ia, ib, W, st, stop);
-        } else {
-          launch_grad_cgp<R>(h->pl, p, z, NH, sc, ia, ib, W, st, stop);
-          launch_fft_yz<R>(h->pl, W, NH, 6, 2, true, st, stop);
+        if (k == 0 || !h->use_graphs) {
+          enqueue_iter(k);
+          continue;
         }
-        launch_fft_yz<R>(h->pl, W, NH, 6, 1, true, st, stop);
-        launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
-        launch_fft_yz<R>(h->pl, W, NH, 6, 1, false, st, stop);
-        // q = -i xi~ . sigma^ and <p, q> into sc[SC_PQ] (flag 2 if not positive)
-        if (fz) {
-          nb = launch_zdiv_fwd<R>(h->pl, W, q, pk, NH, h->partial, st, stop);
-        } else {
-          launch_fft_yz<R>(h->pl, W, NH, 6, 2, false, st, stop);
-          nb = launch_div_dot<R>(h->pl, W, q, p, NH, h->partial, st, stop);
+        // iterations k >= 1 replay the captured graph of their parity
+        hipGraphExec_t& ex = h->cg_exec[k & 1];
+        if (!ex) {
+          hipGraph_t gr = nullptr;
+          bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+          if (ok) {
+            enqueue_iter(k);
+            ok = hipStreamEndCapture(st, &gr) == hipSuccess && gr != nullptr;
+          }
+          if (ok) ok = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) == hipSuccess;
+          if (gr) (void)hipGraphDestroy(gr);
+          if (!ok) {                         // no graphs on this stream: launch eagerly
+            (void)hipGetLastError();
+            ex = nullptr;
+            h->use_graphs = false;
+            enqueue_iter(k);
+            continue;
+          }
         }
-        launch_reduce_pq(h->partial, nb, sc, SC_PQ, SC_FLAG, st);
-        // x, r, z updates, <r, r>, <r, z> and the convergence test
-        nb = launch_cg_step<R>(h->pl, x, r, pk, q, z, NH, sc + SC_KBAR, sc, cur, SC_PQ,
-                               h->partial, st, stop);
-        launch_reduce_check(h->partial, nb, sc, SC_ITER, prv, SC_FLAG, SC_TOL2, st);
+        HIPCHK(hipGraphLaunch(ex, st));
       }
       queued += nq;
-      rc = sync_read(h, SC_FLAG, 2);
+      rc = sync_read(h, SC_FLAG, SC_RRN - SC_FLAG + 1);
       if (rc) return rc;
       iters = (int)h->hs[SC_ITER];
       if (g_debug) std::fprintf(stderr, "  pcg queued %d ran %d flag %g\n", queued, iters, h->hs[SC_FLAG]);
       if (h->hs[SC_FLAG] == 1.0) return RVE_OK;
       if (h->hs[SC_FLAG] == 2.0) return fail(RVE_E_NOCONV, "momentum CG breakdown");
+      // next batch: the iterations the residual's recent rate of decrease still needs,
+      // plus two, at least 4 and at most 16 (the launches of a batch that follow
+      // convergence return at once; each batch costs one host round trip)
+      const double rr = h->hs[SC_RRN];
       batch = std::min(2 * batch, 16);
+      if (iters > it_ref && rr > 0.0 && rr < rr_ref) {
+        const double rate = std::log(rr / rr_ref) / (double)(iters - it_ref);   // < 0
+        const double need = std::log(h->hs[SC_TOL2] / rr) / rate;
+        if (std::isfinite(need)) batch = std::max(4, std::min(16, (int)std::ceil(need) + 2));
+      }
+      rr_ref = rr;
+      it_ref = iters;
     }
     return fail(RVE_E_NOCONV, "momentum Krylov solver reached max_krylov");
   }
@@ -730,6 +773,10 @@ int rve_create(const rve_desc* d, void* dev_arena, size_t arena_bytes, void* hip
   h->st = (hipStream_t)hip_stream;
   (void)hipGetDevice(&h->device);
   crystal_frame(h->d.C11, h->d.C12, h->d.C44, &h->cf);
+  {
+    const char* ev = std::getenv("RVE_GRAPHS");
+    h->use_graphs = (h->st != nullptr) && !(ev && ev[0] == '0');
+  }
   if (hipHostMalloc((void**)&h->hs, SC_N * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     delete h;
     return fail(RVE_E_DEVICE, "hipHostMalloc failed");
@@ -926,6 +973,8 @@ int rve_destroy(rve_s* h) {
   if (!h) return RVE_OK;
   if (h->st) (void)hipStreamSynchronize(h->st);
   else (void)hipDeviceSynchronize();
+  for (hipGraphExec_t& e : h->cg_exec)
+    if (e) (void)hipGraphExecDestroy(e);
   if (h->hs) (void)hipHostFree(h->hs);
   delete h;
   return RVE_OK;

@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(256) k_reduce_pq(const double* __restrict__ pa
 
 __global__ void __launch_bounds__(256) k_reduce_check(const double* __restrict__ partial, int nblk,
                                                       double* __restrict__ sc, int iiter, int nxt,
-                                                      int iflag, int itol2) {
+                                                      int irr, int iflag, int itol2) {
   if (sc[iflag] != 0.0) return;
   __shared__ double sh[256];
   const double rr = block_sum256(partial, nblk, sh);
@@ -77,6 +77,7 @@ __global__ void __launch_bounds__(256) k_reduce_check(const double* __restrict__
   if (threadIdx.x == 0) {
     sc[iiter] += 1.0;
     sc[nxt] = rz;
+    sc[irr] = rr;
     if (!isfinite(rr)) sc[iflag] = 2.0;
     else if (rr <= sc[itol2]) sc[iflag] = 1.0;
   }
@@ -86,10 +87,10 @@ void launch_reduce_pq(const double* partial, int nblk, double* sc, int ipq, int 
                       hipStream_t st) {
   hipLaunchKernelGGL(k_reduce_pq, dim3(1), dim3(256), 0, st, partial, nblk, sc, ipq, iflag);
 }
-void launch_reduce_check(const double* partial, int nblk, double* sc, int iiter, int nxt,
+void launch_reduce_check(const double* partial, int nblk, double* sc, int iiter, int nxt, int irr,
                          int iflag, int itol2, hipStream_t st) {
   hipLaunchKernelGGL(k_reduce_check, dim3(1), dim3(256), 0, st, partial, nblk, sc, iiter, nxt,
-                     iflag, itol2);
+                     irr, iflag, itol2);
 }
 
 __device__ __forceinline__ double pw_weight(long long b, const Grid& g) {

@@ -215,7 +215,11 @@ class RVE:
             raise RveError(RVE_E_ARG, lib.rve_last_error().decode())
         self.device = torch.device("cuda", device)
         self.arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # the library works on its own stream (default priority), so that its CG
+        # iterations can be replayed as HIP graphs; that stream first waits for the
+        # work torch has queued on the arena's allocation stream
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         self.h = rve_create(self._d, self.arena.data_ptr(), nbytes, self.stream.cuda_stream)
         self.footprint = nbytes
 
