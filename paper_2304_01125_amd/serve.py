@@ -188,7 +188,7 @@ class Server:
         return out, time.perf_counter() - t0
 
 
-def run_serial(items, precision, keep_fields=False):
+def run_serial(items, precision, keep_fields=False, log=None):
     """Each request alone, back to back (no queueing): per-request solve times."""
     import torch
     from .rve import RVE
@@ -211,6 +211,9 @@ def run_serial(items, precision, keep_fields=False):
             rec["fields"] = r.fields(("strain", "stress", "damage"))
         out.append(rec)
         r.close()
+        if log:
+            log(f"serial request {i} ({w.n[0]}^3): status {rec['status']}, "
+                f"{1e3 * rec['latency']:.1f} ms")
     return out, time.perf_counter() - t0
 
 
@@ -228,7 +231,9 @@ def serve_benchmark(n_req=400, slots=8, seed=4, workers=8, log=None):
     from . import RVE_FP64, RVE_MIXED
     factor, gaps, reqs = serving_requests(n_req, seed)
     items = prepare(reqs, workers)
-    serial, wall_s = run_serial(items, RVE_FP64)
+    if log:
+        log(f"prepared {len(items)} requests")
+    serial, wall_s = run_serial(items, RVE_FP64, log=log)
     cap = len(serial) / wall_s
     lam = factor * cap
     arrivals = np.cumsum(gaps) / lam
