@@ -35,6 +35,47 @@ __device__ inline void block_partial_sum(double v, double* partial, double* red)
   }
 }
 
+// Fixed-order sum of a[0..n) computed by every block of a kernel (so that each block
+// holds the grid reduction of the previous kernel without another launch): thread t adds
+// a[t], a[t + blockDim], ..., then wave shuffles and the waves in order.  Returns the same
+// value to every thread of every block.  `red` is LDS of blockDim.x/64 doubles.
+__device__ inline double block_sum_all(const double* __restrict__ a, int n, double* red) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += a[i];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// Convergence test of a CG iteration, as every block of the next kernel sees it: sums
+// the step's partials of <r, r> and <r, z> (2 x nb), and block 0 records <r, r> in
+// sc[irr], <r, z> in sc[irz] and the flag (1 converged: <r, r> <= sc[itol2]; 2 not
+// finite).  Returns true when the solve is over.  Idempotent: a second test of the same
+// iteration writes the same values (the iterations are counted by the step itself).
+struct CgCheck {
+  const double* part;   // step partials, nullptr: no test in this kernel
+  int nb, iflag, itol2, irr, irz;
+};
+__device__ inline bool cg_check_inline(const CgCheck& ck, double* sc, double* red, double& rz) {
+  const double rr = block_sum_all(ck.part, ck.nb, red);
+  rz = block_sum_all(ck.part + ck.nb, ck.nb, red);
+  const bool bad = !isfinite(rr);
+  const bool done = bad || rr <= sc[ck.itol2];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[ck.irr] = rr;
+    sc[ck.irz] = rz;
+    if (bad) sc[ck.iflag] = 2.0;
+    else if (done) sc[ck.iflag] = 1.0;
+  }
+  return done;
+}
+
 // --- spectral passes (spectral.hip) ------------------------------------------------
 template <typename R>
 void launch_x_r2c(const Plans& p, const void* in, bool in_f64, long long in_cs, const double* phi,
@@ -72,10 +113,12 @@ int launch_div_dot(const Plans& p, const cplx<R>* s, cplx<R>* q, const cplx<R>* 
 // <p, q>; returns #blocks.
 template <typename R>
 bool fused_z_available(const Plans& p);
+// With ck.part set, zgrad_inv first runs the convergence test of the previous CG
+// iteration (cg_check_inline) and takes beta = <r, z> / sc[ib] from it.
 template <typename R>
 void launch_zgrad_inv(const Plans& p, const cplx<R>* z, const cplx<R>* pold, cplx<R>* pnew,
-                      long long cs, const double* sc, int ia, int ib, cplx<R>* e, hipStream_t st,
-                      const double* stop = nullptr);
+                      long long cs, double* sc, int ia, int ib, cplx<R>* e, hipStream_t st,
+                      const double* stop = nullptr, CgCheck ck = CgCheck{nullptr, 0, 0, 0, 0, 0});
 template <typename R>
 int launch_zdiv_fwd(const Plans& p, const cplx<R>* s, cplx<R>* q, const cplx<R>* pv, long long cs,
                     double* partial, hipStream_t st, const double* stop = nullptr);
@@ -83,10 +126,16 @@ int launch_zdiv_fwd(const Plans& p, const cplx<R>* s, cplx<R>* q, const cplx<R>*
 // r -= alpha h(q), with h the Hermitian projection of the self-conjugate x-planes
 // applied on the fly; z = M r; block partials of <r, r> and <r, z> at partial[0][blk],
 // partial[1][blk].  Returns #blocks.
+// With pq_part set, every block first sums the nb_pq partials of <p, q> itself (and
+// block 0 stores the sum in sc[ipq], the breakdown flag in sc[iflag] and counts the
+// iteration in sc[iiter]); otherwise <p, q> is read from sc[ipq].  max_blocks bounds the
+// grid (and so the partials).
 template <typename R>
 int launch_cg_step(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, const cplx<R>* q,
-                   cplx<R>* z, long long cs, const double* kbar21, const double* sc, int cur,
-                   int ipq, double* partial, hipStream_t st, const double* stop);
+                   cplx<R>* z, long long cs, const double* kbar21, double* sc, int cur, int ipq,
+                   double* partial, hipStream_t st, const double* stop,
+                   const double* pq_part = nullptr, int nb_pq = 0, int iflag = 0, int iiter = 0,
+                   int max_blocks = 1 << 30);
 // Hermitian projection of the self-conjugate x-planes (spectra of real fields)
 template <typename R>
 void launch_herm_proj(const Plans& p, cplx<R>* v, long long cs, int ncomp, hipStream_t st,
@@ -170,6 +219,9 @@ void launch_clamp(long long N, const double* x, const double* phi_t, double* phi
 // finite.  Both are no-ops once sc[iflag] is non-zero.
 void launch_reduce_pq(const double* partial, int nblk, double* sc, int ipq, int iflag,
                       hipStream_t st);
+// cg_check_inline in one block (the test of a batch's last iteration); no-op once
+// sc[ck.iflag] is non-zero
+void launch_cg_check_tail(double* sc, const CgCheck& ck, hipStream_t st);
 void launch_reduce_check(const double* partial, int nblk, double* sc, int iiter, int nxt, int irr,
                          int iflag, int itol2, hipStream_t st);
 void launch_reduce(const double* partial, int nblk, int ncomp, int op_max, double* out,

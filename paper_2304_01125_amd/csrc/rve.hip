@@ -273,6 +273,11 @@ enum { SC_K = 0,        // 28 constitutive sums (21 gK, g w, 6 g sigma)
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Reduction buffer: the divergence pass's partials from 0, the CG step's from
+// kCgPartial (at most 2 x kCgMaxBlocks: every block of the next inverse z pass sums them).
+constexpr long long kCgPartial = (long long)kMaxRedBlocks * 16;
+constexpr int kCgMaxBlocks = 512;
+
 
 
 // Bump allocation of every buffer; with h->base == nullptr only the size is summed.
@@ -454,33 +459,46 @@ struct Ops {
     // right-hand side is no longer needed once r = b): each iteration reads p_old and
     // writes p_new while other blocks still read p_old.
     const bool fz = fused_z_available<R>(h->pl);
+    // With the fused z passes an iteration is six launches: the convergence test of the
+    // previous iteration runs inside the inverse z pass and the sum of <p, q> inside the
+    // CG step (each block reduces the previous kernel's partials itself).
+    double* cg_part = h->partial + kCgPartial;
+    int nb_cg = 0;
+    auto check_of = [&](int k) {        // the test of iteration k (after its CG step)
+      return CgCheck{cg_part, nb_cg, SC_FLAG, SC_TOL2, SC_RRN, SC_RZ0 + ((k + 1) & 1)};
+    };
     // the launches of CG iteration k (those of k >= 1 depend on the parity of k only)
     auto enqueue_iter = [&](int k) {
       const int cur = SC_RZ0 + (k & 1), prv = SC_RZ0 + ((k + 1) & 1);
       // p = z + beta p (beta = rz_k / rz_{k-1}, 0 on the first iteration), gradient
       const int ia = (k == 0) ? SC_ZERO : cur, ib = (k == 0) ? SC_ONE : prv;
-      C* pk = p;
       if (fz) {
         C* pold = (k & 1) ? b : p;
-        pk = (k & 1) ? p : b;
-        launch_zgrad_inv<R>(h->pl, z, pold, pk, NH, sc, ia, ib, W, st, stop);
-      } else {
-        launch_grad_cgp<R>(h->pl, p, z, NH, sc, ia, ib, W, st, stop);
-        launch_fft_yz<R>(h->pl, W, NH, 6, 2, true, st, stop);
+        C* pk = (k & 1) ? p : b;
+        if (k == 0) launch_zgrad_inv<R>(h->pl, z, pold, pk, NH, sc, ia, ib, W, st, stop);
+        else launch_zgrad_inv<R>(h->pl, z, pold, pk, NH, sc, ia, ib, W, st, stop, check_of(k - 1));
+        launch_fft_yz<R>(h->pl, W, NH, 6, 1, true, st, stop);
+        launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
+        launch_fft_yz<R>(h->pl, W, NH, 6, 1, false, st, stop);
+        // q = -i xi~ . sigma^ with the partials of <p, q>; the step sums them
+        const int nbd = launch_zdiv_fwd<R>(h->pl, W, q, pk, NH, h->partial, st, stop);
+        nb_cg = launch_cg_step<R>(h->pl, x, r, pk, q, z, NH, sc + SC_KBAR, sc, cur, SC_PQ,
+                                  cg_part, st, stop, h->partial, nbd, SC_FLAG, SC_ITER,
+                                  kCgMaxBlocks);
+        return;
       }
+      // unfused operator (grids without a register DFT length)
+      launch_grad_cgp<R>(h->pl, p, z, NH, sc, ia, ib, W, st, stop);
+      launch_fft_yz<R>(h->pl, W, NH, 6, 2, true, st, stop);
       launch_fft_yz<R>(h->pl, W, NH, 6, 1, true, st, stop);
       launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
       launch_fft_yz<R>(h->pl, W, NH, 6, 1, false, st, stop);
+      launch_fft_yz<R>(h->pl, W, NH, 6, 2, false, st, stop);
       // q = -i xi~ . sigma^ and <p, q> into sc[SC_PQ] (flag 2 if not positive)
-      if (fz) {
-        nb = launch_zdiv_fwd<R>(h->pl, W, q, pk, NH, h->partial, st, stop);
-      } else {
-        launch_fft_yz<R>(h->pl, W, NH, 6, 2, false, st, stop);
-        nb = launch_div_dot<R>(h->pl, W, q, p, NH, h->partial, st, stop);
-      }
+      nb = launch_div_dot<R>(h->pl, W, q, p, NH, h->partial, st, stop);
       launch_reduce_pq(h->partial, nb, sc, SC_PQ, SC_FLAG, st);
       // x, r, z updates, <r, r>, <r, z> and the convergence test
-      nb = launch_cg_step<R>(h->pl, x, r, pk, q, z, NH, sc + SC_KBAR, sc, cur, SC_PQ,
+      nb = launch_cg_step<R>(h->pl, x, r, p, q, z, NH, sc + SC_KBAR, sc, cur, SC_PQ,
                              h->partial, st, stop);
       launch_reduce_check(h->partial, nb, sc, SC_ITER, prv, SC_RRN, SC_FLAG, SC_TOL2, st);
     };
@@ -516,10 +534,14 @@ struct Ops {
         HIPCHK(hipGraphLaunch(ex, st));
       }
       queued += nq;
-      rc = sync_read(h, SC_FLAG, SC_RRN - SC_FLAG + 1);
+      if (fz) launch_cg_check_tail(sc, check_of(queued - 1), st);
+      rc = sync_read(h, SC_RZ0, SC_RRN - SC_RZ0 + 1);
       if (rc) return rc;
       iters = (int)h->hs[SC_ITER];
-      if (g_debug) std::fprintf(stderr, "  pcg queued %d ran %d flag %g\n", queued, iters, h->hs[SC_FLAG]);
+      if (g_debug)
+        std::fprintf(stderr, "  pcg queued %d ran %d flag %g rr %.3e tol2 %.3e pq %.3e\n", queued, iters,
+                     h->hs[SC_FLAG], h->hs[SC_RRN], h->hs[SC_TOL2], h->hs[SC_PQ]);
+      if (g_debug) std::fprintf(stderr, "    rz0 %.6e rz1 %.6e\n", h->hs[SC_RZ0], h->hs[SC_RZ1]);
       if (h->hs[SC_FLAG] == 1.0) return RVE_OK;
       if (h->hs[SC_FLAG] == 2.0) return fail(RVE_E_NOCONV, "momentum CG breakdown");
       // next batch: the iterations the residual's recent rate of decrease still needs,

@@ -7,6 +7,8 @@
 // of a real field); |xi|^2 keeps it.
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace rvefft {
 
 
@@ -267,14 +269,28 @@ template <typename R>
 __global__ void __launch_bounds__(256)
 k_cg_step(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __restrict__ pv,
           const cplx<R>* __restrict__ qv, cplx<R>* __restrict__ z, long long cs,
-          const double* __restrict__ kbar21, const double* __restrict__ sc, int cur, int ipq,
-          Grid g, double* __restrict__ partial, const double* __restrict__ stop) {
+          const double* __restrict__ kbar21, double* __restrict__ sc, int cur, int ipq,
+          Grid g, double* __restrict__ partial, const double* __restrict__ stop,
+          const double* __restrict__ pq_part, int nb_pq, int iflag, int iiter) {
   if (stop && *stop != 0.0) return;
   __shared__ double K4[81];
   __shared__ double red[16];
+  double pq;
+  if (pq_part) {
+    pq = block_sum_all(pq_part, nb_pq, red);
+    const bool bad = !(pq > 0.0) || !isfinite(pq);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc[ipq] = pq;
+      if (bad) sc[iflag] = 2.0;
+      else sc[iiter] += 1.0;
+    }
+    if (bad) return;
+  } else {
+    pq = sc[ipq];
+  }
   load_kbar4(K4, kbar21);
   __syncthreads();
-  const double al = sc[cur] / sc[ipq];
+  const double al = sc[cur] / pq;
   const bool even = (g.n1 % 2 == 0);
   double rr = 0.0, rz = 0.0;
   for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < g.nspec;
@@ -329,20 +345,23 @@ k_cg_step(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __res
 
 template <typename R>
 int launch_cg_step(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, const cplx<R>* q,
-                   cplx<R>* z, long long cs, const double* kbar21, const double* sc, int cur,
-                   int ipq, double* partial, hipStream_t st, const double* stop) {
-  const int nb = grid_for(p.g.nspec);
+                   cplx<R>* z, long long cs, const double* kbar21, double* sc, int cur, int ipq,
+                   double* partial, hipStream_t st, const double* stop, const double* pq_part,
+                   int nb_pq, int iflag, int iiter, int max_blocks) {
+  const int nb = std::min(grid_for(p.g.nspec), max_blocks);
   hipLaunchKernelGGL((k_cg_step<R>), dim3(nb), dim3(256), 0, st, x, r, pv, q, z, cs, kbar21, sc,
-                     cur, ipq, p.g, partial, stop);
+                     cur, ipq, p.g, partial, stop, pq_part, nb_pq, iflag, iiter);
   return nb;
 }
 template int launch_cg_step<double>(const Plans&, cplx<double>*, cplx<double>*,
                                     const cplx<double>*, const cplx<double>*, cplx<double>*,
-                                    long long, const double*, const double*, int, int, double*,
-                                    hipStream_t, const double*);
+                                    long long, const double*, double*, int, int, double*,
+                                    hipStream_t, const double*, const double*, int, int, int,
+                                    int);
 template int launch_cg_step<float>(const Plans&, cplx<float>*, cplx<float>*, const cplx<float>*,
                                    const cplx<float>*, cplx<float>*, long long, const double*,
-                                   const double*, int, int, double*, hipStream_t, const double*);
+                                   double*, int, int, double*, hipStream_t, const double*,
+                                   const double*, int, int, int, int);
 #define RVE_CG_INST(R)                                                                           \
   template void launch_grad_cgp<R>(const Plans&, cplx<R>*, const cplx<R>*, long long,             \
                                    const double*, int, int, cplx<R>*, hipStream_t, const double*); \

@@ -83,6 +83,17 @@ __global__ void __launch_bounds__(256) k_reduce_check(const double* __restrict__
   }
 }
 
+__global__ void __launch_bounds__(256) k_cg_check_tail(double* __restrict__ sc, CgCheck ck) {
+  if (sc[ck.iflag] != 0.0) return;
+  __shared__ double red[4];
+  double rz;
+  (void)cg_check_inline(ck, sc, red, rz);
+}
+
+void launch_cg_check_tail(double* sc, const CgCheck& ck, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_check_tail, dim3(1), dim3(256), 0, st, sc, ck);
+}
+
 void launch_reduce_pq(const double* partial, int nblk, double* sc, int ipq, int iflag,
                       hipStream_t st) {
   hipLaunchKernelGGL(k_reduce_pq, dim3(1), dim3(256), 0, st, partial, nblk, sc, ipq, iflag);

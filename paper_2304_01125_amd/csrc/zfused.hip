@@ -54,10 +54,19 @@ __device__ __forceinline__ void z_freqs(const Grid& g, int kx0, int tile, int TX
 template <typename R, int N, int TX, int NT>
 __global__ void __launch_bounds__(NT)
 k_zgrad_inv(const cplx<R>* __restrict__ zv, const cplx<R>* __restrict__ pold,
-            cplx<R>* __restrict__ pnew, long long cs, const double* __restrict__ sc, int ia,
-            int ib, cplx<R>* __restrict__ e, Grid g, const cplx<R>* __restrict__ tw_g,
-            const double* __restrict__ stop) {
+            cplx<R>* __restrict__ pnew, long long cs, double* __restrict__ sc, int ia, int ib,
+            cplx<R>* __restrict__ e, Grid g, const cplx<R>* __restrict__ tw_g,
+            const double* __restrict__ stop, CgCheck ck) {
   if (stop && *stop != 0.0) return;
+  __shared__ double red[NT / 64];
+  double be;
+  if (ck.part) {
+    double rz;
+    if (cg_check_inline(ck, sc, red, rz)) return;
+    be = rz / sc[ib];
+  } else {
+    be = sc[ia] / sc[ib];
+  }
   constexpr int P = TX + 1;                       // the Nyquist column rides in tile 0
   constexpr int Na = ZSplit<N>::Na, Nb = ZSplit<N>::Nb;
   constexpr int PITCH = N + 1;
@@ -77,7 +86,6 @@ k_zgrad_inv(const cplx<R>* __restrict__ zv, const cplx<R>* __restrict__ pold,
   // component c = (a, b): xx, yy, zz, yz, xz, xy
   const int ca = (c < 3) ? c : (c == 3 ? 1 : 0);
   const int cb = (c < 3) ? c : (c == 5 ? 1 : 2);
-  const double be = sc[ia] / sc[ib];
   auto col = [&](int x) -> int {
     if (x < TX) return kx0 + x;
     return (tile == 0) ? g.n1 / 2 : -1;
@@ -265,7 +273,8 @@ k_zdiv_fwd(const cplx<R>* __restrict__ s, cplx<R>* __restrict__ q, const cplx<R>
 // LDS bytes of the fused z kernels
 template <typename R>
 constexpr size_t zgrad_lds(int N, int P) {
-  return ((size_t)P * (N + 1) + N) * sizeof(cplx<R>) + (size_t)(N + P) * sizeof(R);
+  return ((size_t)P * (N + 1) + N) * sizeof(cplx<R>) + (size_t)(N + P) * sizeof(R) +
+         16 * sizeof(double);
 }
 template <typename R>
 constexpr size_t zdiv_lds(int N, int P) {
@@ -302,8 +311,8 @@ bool fused_z_available(const Plans& p) {
 
 template <typename R>
 void launch_zgrad_inv(const Plans& p, const cplx<R>* z, const cplx<R>* pold, cplx<R>* pnew,
-                      long long cs, const double* sc, int ia, int ib, cplx<R>* e, hipStream_t st,
-                      const double* stop) {
+                      long long cs, double* sc, int ia, int ib, cplx<R>* e, hipStream_t st,
+                      const double* stop, CgCheck ck) {
   const Grid& g = p.g;
   const cplx<R>* tw = (const cplx<R>*)p.tw_ptr(2, sizeof(R) == 8);
   with_length(g.n3, [&]<int NC>() {
@@ -313,7 +322,7 @@ void launch_zgrad_inv(const Plans& p, const cplx<R>* z, const cplx<R>* pold, cpl
         constexpr int NT = threads_for<(T + 1) * ZSplit<NC>::Nb>();
         const int nblk = (g.n1 / 2 / T) * g.n2 * 6;
         hipLaunchKernelGGL((k_zgrad_inv<R, NC, T, NT>), dim3(nblk), dim3(NT), 0, st, z, pold,
-                           pnew, cs, sc, ia, ib, e, g, tw, stop);
+                           pnew, cs, sc, ia, ib, e, g, tw, stop, ck);
       };
       if (TX == 32) {
         if constexpr (zgrad_lds<R>(NC, 33) <= kRegLdsMax) go.template operator()<32>();
@@ -358,8 +367,8 @@ hipError_t upload_reg_twiddles_zfused(hipStream_t st) { return fill_reg_twiddles
 #define RVE_ZFUSED_INST(R)                                                                       \
   template bool fused_z_available<R>(const Plans&);                                              \
   template void launch_zgrad_inv<R>(const Plans&, const cplx<R>*, const cplx<R>*, cplx<R>*,       \
-                                    long long, const double*, int, int, cplx<R>*, hipStream_t,   \
-                                    const double*);                                              \
+                                    long long, double*, int, int, cplx<R>*, hipStream_t,         \
+                                    const double*, CgCheck);                                     \
   template int launch_zdiv_fwd<R>(const Plans&, const cplx<R>*, cplx<R>*, const cplx<R>*,         \
                                   long long, double*, hipStream_t, const double*);
 
