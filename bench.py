@@ -157,7 +157,7 @@ def cpu_baseline(w, inp, gpu_stats, n_apply=6, stride=64):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_2304_01125_amd import RVE, RVE_FP64, RVE_MIXED

@@ -63,8 +63,22 @@ struct CgCheck {
   int nb, iflag, itol2, irr, irz;
 };
 __device__ inline bool cg_check_inline(const CgCheck& ck, double* sc, double* red, double& rz) {
-  const double rr = block_sum_all(ck.part, ck.nb, red);
-  rz = block_sum_all(ck.part + ck.nb, ck.nb, red);
+  // both sums in one pass: thread-strided, wave shuffles, waves in order
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < ck.nb; i += blockDim.x) {
+    a += ck.part[i];
+    b += ck.part[ck.nb + i];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_down(a, off, 64);
+    b += __shfl_down(b, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) { red[wid] = a; red[nw + wid] = b; }
+  __syncthreads();
+  double rr = 0.0;
+  rz = 0.0;
+  for (int w = 0; w < nw; ++w) { rr += red[w]; rz += red[nw + w]; }
   const bool bad = !isfinite(rr);
   const bool done = bad || rr <= sc[ck.itol2];
   if (blockIdx.x == 0 && threadIdx.x == 0) {

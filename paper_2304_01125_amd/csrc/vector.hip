@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(256) k_reduce_check(const double* __restrict__
 
 __global__ void __launch_bounds__(256) k_cg_check_tail(double* __restrict__ sc, CgCheck ck) {
   if (sc[ck.iflag] != 0.0) return;
-  __shared__ double red[4];
+  __shared__ double red[8];
   double rz;
   (void)cg_check_inline(ck, sc, red, rz);
 }

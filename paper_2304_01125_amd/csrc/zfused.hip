@@ -58,7 +58,7 @@ k_zgrad_inv(const cplx<R>* __restrict__ zv, const cplx<R>* __restrict__ pold,
             cplx<R>* __restrict__ e, Grid g, const cplx<R>* __restrict__ tw_g,
             const double* __restrict__ stop, CgCheck ck) {
   if (stop && *stop != 0.0) return;
-  __shared__ double red[NT / 64];
+  __shared__ double red[2 * (NT / 64)];
   double be;
   if (ck.part) {
     double rz;
@@ -274,7 +274,7 @@ k_zdiv_fwd(const cplx<R>* __restrict__ s, cplx<R>* __restrict__ q, const cplx<R>
 template <typename R>
 constexpr size_t zgrad_lds(int N, int P) {
   return ((size_t)P * (N + 1) + N) * sizeof(cplx<R>) + (size_t)(N + P) * sizeof(R) +
-         16 * sizeof(double);
+         32 * sizeof(double);
 }
 template <typename R>
 constexpr size_t zdiv_lds(int N, int P) {

@@ -72,7 +72,7 @@ def load():
     import torch  # noqa: F401  (the HIP runtime must be torch's)
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
-                           "(run __graft_entry__.build())")
+                           "(build it with python paper_2304_01125_amd/build.py)")
     lib = ctypes.CDLL(LIB_PATH)
     lib.rve_footprint_bytes.restype = ctypes.c_size_t
     lib.rve_footprint_bytes.argtypes = [ctypes.POINTER(RveDesc)]
