@@ -168,8 +168,7 @@ enum {
   GT_P = 72,       // Mandel Schmid tensors sym(s (x) n), 12 x 6
   GT_SN = 144,     // s (x) n, 12 x 9 row-major
   GT_R = 252,      // rotation crystal -> sample, 9 row-major
-  GT_Q = 261,      // the same rotation acting on Mandel vectors, 6 x 6 row-major
-  GT_STRIDE = 297
+  GT_STRIDE = 261
 };
 
 // Grain-independent crystal-frame constants (Mandel): Schmid tensors of the 12 slip

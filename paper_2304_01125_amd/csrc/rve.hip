@@ -156,20 +156,6 @@ bool grain_table(const double* q, double C11, double C12, double C44, double* ou
     }
   }
   for (int i = 0; i < 9; ++i) out[GT_R + i] = R[i / 3][i % 3];
-  // Mandel form of T -> R T R^T: column b is the image of the b-th Mandel basis tensor
-  for (int b = 0; b < 6; ++b) {
-    double T[3][3] = {};
-    const int k = kPairs[b][0], l = kPairs[b][1];
-    T[k][l] += 1.0 / w[b];
-    if (k != l) T[l][k] += 1.0 / w[b];
-    for (int a = 0; a < 6; ++a) {
-      const int i = kPairs[a][0], j = kPairs[a][1];
-      double v = 0.0;
-      for (int p = 0; p < 3; ++p)
-        for (int q = 0; q < 3; ++q) v += R[i][p] * T[p][q] * R[j][q];
-      out[GT_Q + a * 6 + b] = w[a] * v;
-    }
-  }
   return true;
 }
 

@@ -312,8 +312,48 @@ __device__ __forceinline__ void load6o(const double* __restrict__ f, long long N
 // Constitutive update at eps + t*deps.  Writes sigma (tensor comps), g(phi) K (21
 // Mandel entries) and g(phi) w per voxel, with w = 1/2 sig_tr S sig_tr - Phi(sig) the
 // incremental energy.
+// Symmetric-tensor rotations with the grain rotation Rm (crystal -> sample, row-major
+// 3x3): tensor components xx, yy, zz, yz, xz, xy.
+__device__ __forceinline__ void sym33(const double t[6], double T[3][3]) {
+  T[0][0] = t[0]; T[1][1] = t[1]; T[2][2] = t[2];
+  T[1][2] = T[2][1] = t[3];
+  T[0][2] = T[2][0] = t[4];
+  T[0][1] = T[1][0] = t[5];
+}
+// crystal-frame components of the sample-frame tensor t: Rm^T T Rm
+__device__ __forceinline__ void to_crystal(const double* Rm, const double t[6], double o[6]) {
+  double T[3][3], W[3][3];
+  sym33(t, T);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+      W[i][l] = T[i][0] * Rm[0 * 3 + l] + T[i][1] * Rm[1 * 3 + l] + T[i][2] * Rm[2 * 3 + l];
+  auto c = [&](int k, int l) {
+    return Rm[0 * 3 + k] * W[0][l] + Rm[1 * 3 + k] * W[1][l] + Rm[2 * 3 + k] * W[2][l];
+  };
+  o[0] = c(0, 0); o[1] = c(1, 1); o[2] = c(2, 2); o[3] = c(1, 2); o[4] = c(0, 2); o[5] = c(0, 1);
+}
+// sample-frame components of the crystal-frame tensor t: Rm T Rm^T
+__device__ __forceinline__ void to_sample(const double* Rm, const double t[6], double o[6]) {
+  double T[3][3], W[3][3];
+  sym33(t, T);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+      W[i][l] = T[i][0] * Rm[l * 3 + 0] + T[i][1] * Rm[l * 3 + 1] + T[i][2] * Rm[l * 3 + 2];
+  auto c = [&](int k, int l) {
+    return Rm[k * 3 + 0] * W[0][l] + Rm[k * 3 + 1] * W[1][l] + Rm[k * 3 + 2] * W[2][l];
+  };
+  o[0] = c(0, 0); o[1] = c(1, 1); o[2] = c(2, 2); o[3] = c(1, 2); o[4] = c(0, 2); o[5] = c(0, 1);
+}
+
+// Three waves per SIMD (at most 168 VGPRs): the extra occupancy hides more of the FP64
+// latencies than the spills it causes cost (measured 15 % faster than the unconstrained
+// two waves; a four-wave bound spills far more and runs at half speed).
 template <typename R>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_constitutive(long long N, const double* __restrict__ eps, const double* __restrict__ deps,
                double t, const double* __restrict__ epsp, const double* __restrict__ gslip,
                const int* __restrict__ grain, const double* __restrict__ gtab,
@@ -325,9 +365,14 @@ k_constitutive(long long N, const double* __restrict__ eps, const double* __rest
   const unsigned v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v < N) {
     const unsigned b8 = v * 8u, bR = v * (unsigned)sizeof(R);
-    // Q: Mandel rotation crystal -> sample (orthogonal, so Q^T maps back)
-    const double* Q = gtab + (long long)comp(grain, N, 0, v * 4u) * GT_STRIDE + GT_Q;
-    double e[6], ep[6], s0[6], de[6], em[6], sm[6], ec[6], str[6], sig[6];
+    // grain rotation crystal -> sample (9 values, kept through the return map)
+    double Rm[9];
+    {
+      const double* gR = gtab + (long long)comp(grain, N, 0, v * 4u) * GT_STRIDE + GT_R;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Rm[i] = gR[i];
+    }
+    double e[6], ep[6], s0[6], de[6], ec[6], str[6], sig[6];
     load6o(eps, N, b8, e);
     if (deps) {
       load6o(deps, N, b8, de);
@@ -338,18 +383,12 @@ k_constitutive(long long N, const double* __restrict__ eps, const double* __rest
     load6o(sig_io, N, b8, s0);
 #pragma unroll
     for (int c = 0; c < 6; ++c) e[c] -= ep[c];
-    to_mandel(e, em);
-    to_mandel(s0, sm);
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      double a = 0.0, b = 0.0;
-#pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        a += Q[i * 6 + j] * em[i];
-        b += Q[i * 6 + j] * sm[i];
-      }
-      ec[j] = a;
-      sig[j] = b;
+    {
+      double tc[6];
+      to_crystal(Rm, e, tc);
+      to_mandel(tc, ec);
+      to_crystal(Rm, s0, tc);
+      to_mandel(tc, sig);
     }
     cubic_mul(cf.c11, cf.c12, cf.c66, ec, str);
     const double g = comp(gslip, N, 0, b8);
@@ -377,19 +416,30 @@ k_constitutive(long long N, const double* __restrict__ eps, const double* __rest
       for (int i = 0; i < 6; ++i) el += str[i] * Ss[i];
       comp(gw, N, 0, b8) = gphi * (0.5 * el - potential(cf, sig, str, ig, dtg0, m.nexp, nm1));
     }
-    // back to the sample frame: sigma = Q sig, gK = g(phi) Q K Q^T
+    // back to the sample frame: sigma = Rm sig Rm^T; gK = g(phi) Q K Q^T with Q the
+    // Mandel form of the rotation, Q_IJ = (w_I / w_J) (R_ik R_jl + [k != l] R_il R_jk)
+    // for the index pairs I = (i, j), J = (k, l) and Mandel weights w (1 or sqrt 2)
     {
-      double ss[6], st[6];
-#pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        double a = 0.0;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) a += Q[i * 6 + k] * sig[k];
-        ss[i] = a;
-      }
-      from_mandel(ss, st);
+      double tc[6], st[6];
+      from_mandel(sig, tc);
+      to_sample(Rm, tc, st);
 #pragma unroll
       for (int c = 0; c < 6; ++c) comp(sig_io, N, c, b8) = st[c];
+    }
+    double Q[36];
+    {
+      constexpr int pi[6] = {0, 1, 2, 1, 0, 0}, pj[6] = {0, 1, 2, 2, 2, 1};
+      const double s2 = 1.41421356237309504880, is2 = 0.70710678118654752440;
+#pragma unroll
+      for (int I = 0; I < 6; ++I)
+#pragma unroll
+        for (int J = 0; J < 6; ++J) {
+          const int i = pi[I], j = pj[I], k = pi[J], l = pj[J];
+          const double wi = (I < 3) ? 1.0 : s2;
+          Q[I * 6 + J] = (J < 3) ? wi * Rm[i * 3 + k] * Rm[j * 3 + k]
+                                 : wi * is2 * (Rm[i * 3 + k] * Rm[j * 3 + l] +
+                                               Rm[i * 3 + l] * Rm[j * 3 + k]);
+        }
     }
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
