@@ -93,10 +93,12 @@ __device__ inline bool cg_check_inline(const CgCheck& ck, double* sc, double* re
 // --- spectral passes (spectral.hip) ------------------------------------------------
 template <typename R>
 void launch_x_r2c(const Plans& p, const void* in, bool in_f64, long long in_cs, const double* phi,
-                  double kres, cplx<R>* out, long long out_cs, int ncomp, hipStream_t st);
+                  double kres, cplx<R>* out, long long out_cs, int ncomp, hipStream_t st,
+                  const double* stop = nullptr);
 template <typename R>
 void launch_x_c2r(const Plans& p, const cplx<R>* in, long long in_cs, void* out, bool out_f64,
-                  long long out_cs, int ncomp, double scale, int accumulate, hipStream_t st);
+                  long long out_cs, int ncomp, double scale, int accumulate, hipStream_t st,
+                  const double* stop = nullptr);
 template <typename R>
 void launch_x_tangent(const Plans& p, cplx<R>* data, long long cs, const R* gK, double scale,
                       hipStream_t st, const double* stop = nullptr);
@@ -155,7 +157,8 @@ template <typename R>
 void launch_herm_proj(const Plans& p, cplx<R>* v, long long cs, int ncomp, hipStream_t st,
                       const double* stop = nullptr);
 template <typename R>
-void launch_pf_scale(const Plans& p, cplx<R>* d, double ell, double scale, hipStream_t st);
+void launch_pf_scale(const Plans& p, cplx<R>* d, double ell, double scale, hipStream_t st,
+                     const double* stop = nullptr);
 template <typename R>
 void launch_curl_reg(const Plans& p, cplx<R>* b9, long long cs, double ell_fp, double scale,
                      hipStream_t st);
@@ -243,17 +246,24 @@ void launch_reduce(const double* partial, int nblk, int ncomp, int op_max, doubl
 template <typename R>
 int launch_sdot(const Plans& p, const cplx<R>* a, const cplx<R>* b, long long cs, int ncomp,
                 double* partial, hipStream_t st, const double* stop = nullptr);
-// real-vector kernels (phase field)
-int launch_rdot(long long n, const double* a, const double* b, double* partial, hipStream_t st);
+// real-vector kernels (phase field); every one is a no-op once *stop is non-zero
+int launch_rdot(long long n, const double* a, const double* b, double* partial, hipStream_t st,
+                const double* stop = nullptr);
 // pq = <p, w + 2 S p>
 int launch_pf_pq(long long n, const double* p, const double* w, const double* S, double* partial,
-                 hipStream_t st);
+                 hipStream_t st, const double* stop = nullptr);
 // x += a p ; r -= a (w + 2 S p) ; partial <r,r>
 int launch_pf_xr(long long n, double* x, double* r, const double* p, const double* w,
-                 const double* S, const double* sc, int ia, int ib, double* partial, hipStream_t st);
+                 const double* S, const double* sc, int ia, int ib, double* partial, hipStream_t st,
+                 const double* stop = nullptr);
 // p = z + b p ; w = r + b w
 void launch_pf_pw(long long n, double* p, double* w, const double* z, const double* r,
-                  const double* sc, int ia, int ib, hipStream_t st);
+                  const double* sc, int ia, int ib, hipStream_t st, const double* stop = nullptr);
+// convergence test of a phase-field CG iteration (flag as launch_reduce_check): counts the
+// iteration in sc[iiter], sets sc[iflag] to 2 unless sc[ipq] > 0 and sc[irr] is finite, else
+// to 1 when sc[irr] <= sc[itol2]
+void launch_pf_check(double* sc, int iflag, int iiter, int ipq, int irr, int itol2,
+                     hipStream_t st);
 // y = a * x (real)
 void launch_rscale(long long n, const double* x, double a, double* y, hipStream_t st);
 // zero a complex/real buffer of `bytes` bytes with a fill kernel

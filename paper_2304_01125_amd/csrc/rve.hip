@@ -638,37 +638,55 @@ int run_increment(rve_s* h, const double de[6], double dt, rve_stats* out) {
         const double bb = 4.0 * sumS2;
         const double tol2 = h->d.tol_lin * h->d.tol_lin * bb;
         launch_rscale(N, h->S, 2.0, Rr, st);
-        auto prec = [&](const double* in, double* outp) {
-          launch_x_r2c<R>(h->pl, in, true, N, nullptr, 0.0, W1, o.NH, 1, st);
-          launch_fft_yz<R>(h->pl, W1, o.NH, 1, 1, false, st);
-          launch_fft_yz<R>(h->pl, W1, o.NH, 1, 2, false, st);
-          launch_pf_scale<R>(h->pl, W1, h->d.ell, invN, st);
-          launch_fft_yz<R>(h->pl, W1, o.NH, 1, 2, true, st);
-          launch_fft_yz<R>(h->pl, W1, o.NH, 1, 1, true, st);
-          launch_x_c2r<R>(h->pl, W1, o.NH, outp, true, N, 1, 1.0, 0, st);
+        // convergence control on the device, as in the momentum CG: iterations are enqueued
+        // in batches and the test turns the rest of a batch into no-ops
+        double* sc = h->scal;
+        h->hs[SC_FLAG] = 0.0;
+        h->hs[SC_ITER] = 0.0;
+        h->hs[SC_TOL2] = tol2;
+        HIPCHK(hipMemcpyAsync(sc + SC_FLAG, h->hs + SC_FLAG, 3 * sizeof(double),
+                              hipMemcpyHostToDevice, st));
+        const double* stop = sc + SC_FLAG;
+        auto prec = [&](const double* in, double* outp, const double* stp) {
+          launch_x_r2c<R>(h->pl, in, true, N, nullptr, 0.0, W1, o.NH, 1, st, stp);
+          launch_fft_yz<R>(h->pl, W1, o.NH, 1, 1, false, st, stp);
+          launch_fft_yz<R>(h->pl, W1, o.NH, 1, 2, false, st, stp);
+          launch_pf_scale<R>(h->pl, W1, h->d.ell, invN, st, stp);
+          launch_fft_yz<R>(h->pl, W1, o.NH, 1, 2, true, st, stp);
+          launch_fft_yz<R>(h->pl, W1, o.NH, 1, 1, true, st, stp);
+          launch_x_c2r<R>(h->pl, W1, o.NH, outp, true, N, 1, 1.0, 0, st, stp);
         };
-        prec(Rr, Z);
+        prec(Rr, Z, nullptr);
         int nb = launch_rdot(N, Rr, Z, h->partial, st);
-        launch_reduce(h->partial, nb, 1, 0, h->scal + SC_RZ0, st);
+        launch_reduce(h->partial, nb, 1, 0, sc + SC_RZ0, st);
         HIPCHK(hipMemcpyAsync(P, Z, N * 8, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(Wv, Rr, N * 8, hipMemcpyDeviceToDevice, st));
-        int cur = SC_RZ0, nxt = SC_RZ1;
         bool ok = false;
-        for (int k = 0; k < h->d.max_krylov; ++k) {
-          nb = launch_pf_pq(N, P, Wv, h->S, h->partial, st);
-          launch_reduce(h->partial, nb, 1, 0, h->scal + SC_PQ, st);
-          nb = launch_pf_xr(N, X, Rr, P, Wv, h->S, h->scal, cur, SC_PQ, h->partial, st);
-          launch_reduce(h->partial, nb, 1, 0, h->scal + SC_RR, st);
-          if ((rc = sync_read(h, SC_PQ, 2))) return rc;
-          s.pf_iters++;
-          if (!(h->hs[SC_PQ] > 0.0) || !std::isfinite(h->hs[SC_RR])) break;
-          if (h->hs[SC_RR] <= tol2) { ok = true; break; }
-          prec(Rr, Z);
-          nb = launch_rdot(N, Rr, Z, h->partial, st);
-          launch_reduce(h->partial, nb, 1, 0, h->scal + nxt, st);
-          launch_pf_pw(N, P, Wv, Z, Rr, h->scal, nxt, cur, st);
-          std::swap(cur, nxt);
+        int queued = 0, batch = 4;
+        while (queued < h->d.max_krylov) {
+          const int nq = std::min(batch, h->d.max_krylov - queued);
+          for (int kk = 0; kk < nq; ++kk) {
+            const int k = queued + kk;
+            const int cur = SC_RZ0 + (k & 1), nxt = SC_RZ0 + ((k + 1) & 1);
+            nb = launch_pf_pq(N, P, Wv, h->S, h->partial, st, stop);
+            launch_reduce(h->partial, nb, 1, 0, sc + SC_PQ, st, stop);
+            nb = launch_pf_xr(N, X, Rr, P, Wv, h->S, sc, cur, SC_PQ, h->partial, st, stop);
+            launch_reduce(h->partial, nb, 1, 0, sc + SC_RR, st, stop);
+            launch_pf_check(sc, SC_FLAG, SC_ITER, SC_PQ, SC_RR, SC_TOL2, st);
+            prec(Rr, Z, stop);
+            nb = launch_rdot(N, Rr, Z, h->partial, st, stop);
+            launch_reduce(h->partial, nb, 1, 0, sc + nxt, st, stop);
+            launch_pf_pw(N, P, Wv, Z, Rr, sc, nxt, cur, st, stop);
+          }
+          queued += nq;
+          if ((rc = sync_read(h, SC_FLAG, 2))) return rc;
+          if (h->hs[SC_FLAG] != 0.0) {
+            ok = h->hs[SC_FLAG] == 1.0;
+            break;
+          }
+          batch = std::min(2 * batch, 16);
         }
+        s.pf_iters += (int)h->hs[SC_ITER];
         if (!ok) {
           s.ms_phase_field += now_ms() - tp;
           rc = fail(RVE_E_NOCONV, "phase-field Krylov solver did not converge");

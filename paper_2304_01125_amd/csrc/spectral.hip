@@ -452,7 +452,9 @@ __global__ void __launch_bounds__(256) k_precond(const cplx<R>* __restrict__ r, 
 
 // d *= scale / (1 + l^2 |xi|^2)  (1 component)
 template <typename R>
-__global__ void __launch_bounds__(256) k_pf_scale(cplx<R>* __restrict__ d, double ell, double scale, Grid g) {
+__global__ void __launch_bounds__(256) k_pf_scale(cplx<R>* __restrict__ d, double ell, double scale, Grid g,
+                                                  const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
   for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < g.nspec;
        b += (long long)gridDim.x * blockDim.x) {
     const Bin q = bin_of(b, g);
@@ -526,9 +528,10 @@ int launch_precond(const Plans& p, const cplx<R>* r, cplx<R>* z, long long cs, c
 }
 
 template <typename R>
-void launch_pf_scale(const Plans& p, cplx<R>* d, double ell, double scale, hipStream_t st) {
+void launch_pf_scale(const Plans& p, cplx<R>* d, double ell, double scale, hipStream_t st,
+                     const double* stop) {
   hipLaunchKernelGGL((k_pf_scale<R>), dim3(grid_for(p.g.nspec)), dim3(256), 0, st, d, ell, scale,
-                     p.g);
+                     p.g, stop);
 }
 
 template <typename R>
@@ -545,7 +548,8 @@ void launch_curl_reg(const Plans& p, cplx<R>* b9, long long cs, double ell_fp, d
                               double, hipStream_t, const double*);                               \
   template int launch_precond<R>(const Plans&, const cplx<R>*, cplx<R>*, long long,               \
                                  const double*, double*, hipStream_t, const double*);            \
-  template void launch_pf_scale<R>(const Plans&, cplx<R>*, double, double, hipStream_t);          \
+  template void launch_pf_scale<R>(const Plans&, cplx<R>*, double, double, hipStream_t,          \
+                                   const double*);                                               \
   template void launch_curl_reg<R>(const Plans&, cplx<R>*, long long, double, double, hipStream_t);
 
 RVE_INST(double)

@@ -143,7 +143,8 @@ template int launch_sdot<float>(const Plans&, const cplx<float>*, const cplx<flo
 
 // ---- real vectors (phase field) -------------------------------------------------------
 __global__ void __launch_bounds__(256) k_rdot(long long n, const double* __restrict__ a, const double* __restrict__ b,
-                       double* __restrict__ partial) {
+                       double* __restrict__ partial, const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
   __shared__ double red[16];
   double acc = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -152,14 +153,17 @@ __global__ void __launch_bounds__(256) k_rdot(long long n, const double* __restr
   block_partial_sum(acc, partial, red);
 }
 
-int launch_rdot(long long n, const double* a, const double* b, double* partial, hipStream_t st) {
+int launch_rdot(long long n, const double* a, const double* b, double* partial, hipStream_t st,
+                const double* stop) {
   const int nb = vgrid(n);
-  hipLaunchKernelGGL(k_rdot, dim3(nb), dim3(256), 0, st, n, a, b, partial);
+  hipLaunchKernelGGL(k_rdot, dim3(nb), dim3(256), 0, st, n, a, b, partial, stop);
   return nb;
 }
 
 __global__ void __launch_bounds__(256) k_pf_pq(long long n, const double* __restrict__ p, const double* __restrict__ w,
-                        const double* __restrict__ S, double* __restrict__ partial) {
+                        const double* __restrict__ S, double* __restrict__ partial,
+                        const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
   __shared__ double red[16];
   double acc = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -169,16 +173,17 @@ __global__ void __launch_bounds__(256) k_pf_pq(long long n, const double* __rest
 }
 
 int launch_pf_pq(long long n, const double* p, const double* w, const double* S, double* partial,
-                 hipStream_t st) {
+                 hipStream_t st, const double* stop) {
   const int nb = vgrid(n);
-  hipLaunchKernelGGL(k_pf_pq, dim3(nb), dim3(256), 0, st, n, p, w, S, partial);
+  hipLaunchKernelGGL(k_pf_pq, dim3(nb), dim3(256), 0, st, n, p, w, S, partial, stop);
   return nb;
 }
 
 __global__ void __launch_bounds__(256) k_pf_xr(long long n, double* __restrict__ x, double* __restrict__ r,
                         const double* __restrict__ p, const double* __restrict__ w,
                         const double* __restrict__ S, const double* __restrict__ sc, int ia, int ib,
-                        double* __restrict__ partial) {
+                        double* __restrict__ partial, const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
   __shared__ double red[16];
   const double al = sc[ia] / sc[ib];
   double acc = 0.0;
@@ -194,15 +199,19 @@ __global__ void __launch_bounds__(256) k_pf_xr(long long n, double* __restrict__
 }
 
 int launch_pf_xr(long long n, double* x, double* r, const double* p, const double* w,
-                 const double* S, const double* sc, int ia, int ib, double* partial, hipStream_t st) {
+                 const double* S, const double* sc, int ia, int ib, double* partial, hipStream_t st,
+                 const double* stop) {
   const int nb = vgrid(n);
-  hipLaunchKernelGGL(k_pf_xr, dim3(nb), dim3(256), 0, st, n, x, r, p, w, S, sc, ia, ib, partial);
+  hipLaunchKernelGGL(k_pf_xr, dim3(nb), dim3(256), 0, st, n, x, r, p, w, S, sc, ia, ib, partial,
+                     stop);
   return nb;
 }
 
 __global__ void __launch_bounds__(256) k_pf_pw(long long n, double* __restrict__ p, double* __restrict__ w,
                         const double* __restrict__ z, const double* __restrict__ r,
-                        const double* __restrict__ sc, int ia, int ib) {
+                        const double* __restrict__ sc, int ia, int ib,
+                        const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
   const double be = sc[ia] / sc[ib];
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -212,8 +221,22 @@ __global__ void __launch_bounds__(256) k_pf_pw(long long n, double* __restrict__
 }
 
 void launch_pf_pw(long long n, double* p, double* w, const double* z, const double* r,
-                  const double* sc, int ia, int ib, hipStream_t st) {
-  hipLaunchKernelGGL(k_pf_pw, dim3(vgrid(n)), dim3(256), 0, st, n, p, w, z, r, sc, ia, ib);
+                  const double* sc, int ia, int ib, hipStream_t st, const double* stop) {
+  hipLaunchKernelGGL(k_pf_pw, dim3(vgrid(n)), dim3(256), 0, st, n, p, w, z, r, sc, ia, ib, stop);
+}
+
+__global__ void k_pf_check(double* __restrict__ sc, int iflag, int iiter, int ipq, int irr,
+                           int itol2) {
+  if (threadIdx.x != 0 || sc[iflag] != 0.0) return;
+  sc[iiter] += 1.0;
+  const double rr = sc[irr];
+  if (!(sc[ipq] > 0.0) || !isfinite(rr)) sc[iflag] = 2.0;
+  else if (rr <= sc[itol2]) sc[iflag] = 1.0;
+}
+
+void launch_pf_check(double* sc, int iflag, int iiter, int ipq, int irr, int itol2,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_pf_check, dim3(1), dim3(64), 0, st, sc, iflag, iiter, ipq, irr, itol2);
 }
 
 __global__ void __launch_bounds__(256) k_rscale(long long n, const double* __restrict__ x, double a, double* __restrict__ y) {

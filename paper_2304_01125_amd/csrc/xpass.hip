@@ -12,7 +12,8 @@ template <typename R, typename TI, int NC>
 __global__ void __launch_bounds__(256)
 k_x_r2c(const TI* __restrict__ in, long long in_cs, const double* __restrict__ phi, double kres,
         cplx<R>* __restrict__ out, long long out_cs, int ncomp, Grid g, AxisPlan pl,
-        const cplx<R>* __restrict__ tw_g, int P) {
+        const cplx<R>* __restrict__ tw_g, int P, const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
   extern __shared__ unsigned char smem_raw[];
   __shared__ RowPair rp[kMaxRowPairs];
   const int N = NC > 0 ? NC : g.n1;
@@ -63,7 +64,8 @@ template <typename R, typename TO, int NC>
 __global__ void __launch_bounds__(256)
 k_x_c2r(const cplx<R>* __restrict__ in, long long in_cs, TO* __restrict__ out, long long out_cs,
         int ncomp, double scale, int accumulate, Grid g, AxisPlan pl,
-        const cplx<R>* __restrict__ tw_g, int P) {
+        const cplx<R>* __restrict__ tw_g, int P, const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
   extern __shared__ unsigned char smem_raw[];
   __shared__ RowPair rp[kMaxRowPairs];
   const int N = NC > 0 ? NC : g.n1;
@@ -249,7 +251,8 @@ k_x_tangent_ip(cplx<R>* __restrict__ data, long long cs, const R* __restrict__ g
 
 template <typename R>
 void launch_x_r2c(const Plans& p, const void* in, bool in_f64, long long in_cs, const double* phi,
-                  double kres, cplx<R>* out, long long out_cs, int ncomp, hipStream_t st) {
+                  double kres, cplx<R>* out, long long out_cs, int ncomp, hipStream_t st,
+                  const double* stop) {
   const Grid& g = p.g;
   const int P = pick_rows<R>(g.n1, 16);
   const long long pairs = ((long long)g.n2 * g.n3 * ncomp + 1) / 2;
@@ -259,16 +262,17 @@ void launch_x_r2c(const Plans& p, const void* in, bool in_f64, long long in_cs, 
   with_length(g.n1, [&]<int NC>() {
     if (in_f64)
       hipLaunchKernelGGL((k_x_r2c<R, double, NC>), dim3(nblk), dim3(256), sm, st,
-                         (const double*)in, in_cs, phi, kres, out, out_cs, ncomp, g, p.ax[0], tw, P);
+                         (const double*)in, in_cs, phi, kres, out, out_cs, ncomp, g, p.ax[0], tw, P, stop);
     else
       hipLaunchKernelGGL((k_x_r2c<R, float, NC>), dim3(nblk), dim3(256), sm, st, (const float*)in,
-                         in_cs, phi, kres, out, out_cs, ncomp, g, p.ax[0], tw, P);
+                         in_cs, phi, kres, out, out_cs, ncomp, g, p.ax[0], tw, P, stop);
   });
 }
 
 template <typename R>
 void launch_x_c2r(const Plans& p, const cplx<R>* in, long long in_cs, void* out, bool out_f64,
-                  long long out_cs, int ncomp, double scale, int accumulate, hipStream_t st) {
+                  long long out_cs, int ncomp, double scale, int accumulate, hipStream_t st,
+                  const double* stop) {
   const Grid& g = p.g;
   const int P = pick_rows<R>(g.n1, 16);
   const long long pairs = ((long long)g.n2 * g.n3 * ncomp + 1) / 2;
@@ -278,10 +282,10 @@ void launch_x_c2r(const Plans& p, const cplx<R>* in, long long in_cs, void* out,
   with_length(g.n1, [&]<int NC>() {
     if (out_f64)
       hipLaunchKernelGGL((k_x_c2r<R, double, NC>), dim3(nblk), dim3(256), sm, st, in, in_cs,
-                         (double*)out, out_cs, ncomp, scale, accumulate, g, p.ax[0], tw, P);
+                         (double*)out, out_cs, ncomp, scale, accumulate, g, p.ax[0], tw, P, stop);
     else
       hipLaunchKernelGGL((k_x_c2r<R, float, NC>), dim3(nblk), dim3(256), sm, st, in, in_cs,
-                         (float*)out, out_cs, ncomp, scale, accumulate, g, p.ax[0], tw, P);
+                         (float*)out, out_cs, ncomp, scale, accumulate, g, p.ax[0], tw, P, stop);
   });
 }
 
@@ -319,9 +323,9 @@ void launch_x_tangent(const Plans& p, cplx<R>* data, long long cs, const R* gK, 
 
 #define RVE_XPASS_INST(R)                                                                        \
   template void launch_x_r2c<R>(const Plans&, const void*, bool, long long, const double*, double, \
-                                cplx<R>*, long long, int, hipStream_t);                          \
+                                cplx<R>*, long long, int, hipStream_t, const double*);           \
   template void launch_x_c2r<R>(const Plans&, const cplx<R>*, long long, void*, bool, long long,  \
-                                int, double, int, hipStream_t);                                  \
+                                int, double, int, hipStream_t, const double*);                   \
   template void launch_x_tangent<R>(const Plans&, cplx<R>*, long long, const R*, double,          \
                                     hipStream_t, const double*);
 
