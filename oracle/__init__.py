@@ -8,8 +8,10 @@ common dependency is the seeded input generator package ``synth``.
 What it computes (Lucarini, Dunne & Martinez-Paneda, 2023), in the
 small-strain specialisation (symmetric strain/stress, 6x6 tangents):
 
-* per-voxel crystal plasticity (Sec. 2.1; flow rule replaced by a power law,
-  linear hardening, backward Euler with the strength frozen over the step);
+* per-voxel crystal plasticity (Sec. 2.1) with either a power-law flow rule and
+  linear hardening, or the thermally activated flow rule (eq. flowrule) with
+  Taylor hardening on the SSD and GND densities; backward Euler with the
+  strength frozen over the step;
 * the hybrid momentum balance div[g(phi) sigma] = 0 solved in Fourier space by
   Newton + GMRES on the displacement correction (Sec. 3.1, eqs. momentum,
   fdef, newton), preconditioned by the inverse acoustic tensor of the
@@ -29,7 +31,8 @@ force and invariants live in ``tests/test_oracle_*.py``.
 from .crystal import (quat_to_rot, cubic_stiffness, rotate4, fcc_slip_systems,
                       screw_directions, to_mandel2, from_mandel2, to_mandel4, from_mandel4,
                       gnd_matrix)
-from .constitutive import GrainTables, return_map, slip_increments
+from .constitutive import (GrainTables, return_map, slip_increments, PowerLaw, DunneLaw,
+                           flow_law)
 from .spectral import Grid
 from .mechanics import solve_mechanics, momentum_operator
 from .phasefield import split_positive, we_plus, solve_phase_field
@@ -38,7 +41,7 @@ from .increment import OracleRVE
 
 __all__ = ["quat_to_rot", "cubic_stiffness", "rotate4", "fcc_slip_systems", "screw_directions",
            "to_mandel2", "from_mandel2", "to_mandel4", "from_mandel4", "gnd_matrix",
-           "GrainTables", "return_map", "slip_increments", "Grid", "solve_mechanics",
+           "GrainTables", "return_map", "slip_increments", "PowerLaw", "DunneLaw", "flow_law", "Grid", "solve_mechanics",
            "momentum_operator",
            "split_positive", "we_plus", "solve_phase_field", "nye_tensor", "gnd_density",
            "OracleRVE"]

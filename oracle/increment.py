@@ -9,7 +9,9 @@ Algorithm 1 of the paper, small-strain form:
       and  max|phi_i - phi_{i-1}| / max|phi_i - phi_t| <= tol   (0/0 read as 0)
 followed by the history commit of the internal variables:
     eps_p, beta_p += sum dgamma (P_a, s_a (x) n_a)
-    g       += h_lin sum |dgamma|                 (linear hardening)
+    g       += h_lin sum |dgamma|                 (linear hardening, power law)
+    g        = tau_c0 + mu b sqrt(rho_SSD + rho_GND)   (Taylor hardening, thermally
+               activated flow; from the committed densities, GND included)
     rho_SSD += lambda sqrt(2/3 dLp : dLp)          (SSD evolution, Sec. 2.1)
     W_p     += sigma : d eps_p                     (plastic work, eq. tot)
     G_s     += xi sigma : d eps_p / sqrt(rho_SSD + rho_GND)     (stored energy)
@@ -18,11 +20,12 @@ followed by the history commit of the internal variables:
 and the lagged GND density from the committed plastic distortion.
 Readings: phi is also capped at 1; the driving state uses the threshold and the
 trigger flag of the start of the increment; rho_GND enters G_s one increment
-late.
+late; the Taylor strength of an increment is that of the densities committed at
+the end of the previous one (g frozen over the step, as for the power law).
 """
 import numpy as np
 
-from .constitutive import GrainTables, return_map
+from .constitutive import GrainTables, return_map, flow_law
 from .crystal import to_mandel2, from_mandel2
 from .spectral import Grid
 from .mechanics import solve_mechanics
@@ -69,12 +72,18 @@ class OracleRVE:
         self.eps = np.zeros((M, 3, 3))
         self.epsp = np.zeros((M, 3, 3))
         self.beta = np.zeros((M, 3, 3))
-        self.g = tau[self.gid].astype(np.float64)
+        self.law = flow_law(d)
+        self.taylor = int(d.get("material", 0)) == 1
+        self.tau0 = tau[self.gid].astype(np.float64)
         self.phi = np.zeros(M) if phi0 is None else np.asarray(phi0, dtype=float).copy()
+        self.rho_ssd = np.full(M, d["rho0"])
+        if self.taylor:
+            self.g = self.tau0 + d["mu"] * d["burgers"] * np.sqrt(self.rho_ssd)
+        else:
+            self.g = self.tau0.copy()
         # voxels pre-set to full damage are the paper's geometric crack: a linear
         # elastic region (no slip) whose stiffness g(1) C = k C
         self.g[self.phi >= 1.0] = np.inf
-        self.rho_ssd = np.full(M, d["rho0"])
         self.rho_gnd = np.zeros(M)
         self.Wp = np.zeros(M)
         self.Gs = np.zeros(M)
@@ -90,7 +99,7 @@ class OracleRVE:
         t = self.tab
         gid = self.gid
         out = return_map(epsM, to_mandel2(self.epsp), self.g, dt, t.C[gid], t.S[gid],
-                         t.P[gid], self.d["gdot0"], self.d["n_exp"], sig0=self.sig_ws)
+                         t.P[gid], sig0=self.sig_ws, law=self.law)
         self.sig_ws = out[0]
         return out
 
@@ -139,7 +148,8 @@ class OracleRVE:
         dbeta = np.einsum("ma,maij->mij", dgam, t.SN[gid])
         self.epsp = epsp_tr
         self.beta = self.beta + dbeta
-        self.g = self.g + d["h_lin"] * np.abs(dgam).sum(1)
+        if not self.taylor:
+            self.g = self.g + d["h_lin"] * np.abs(dgam).sum(1)
         self.rho_ssd = self.rho_ssd + d["lambda_ssd"] * np.sqrt(
             2.0 / 3.0 * np.einsum("mij,mij->m", dbeta, dbeta))
         dw = (tau * dgam).sum(1)
@@ -151,6 +161,9 @@ class OracleRVE:
         self.trig = self.trig | newly
         lam = nye_tensor(grid, self.beta, d["ell_fp"])
         self.rho_gnd = gnd_density(lam, t.R[gid], d["burgers"])
+        if self.taylor:
+            self.g = np.where(np.isfinite(self.g), self.tau0 + d["mu"] * d["burgers"] *
+                              np.sqrt(self.rho_ssd + self.rho_gnd), np.inf)
         gphi = self.degradation(self.phi)
         stats["macro_stress"] = tensor6((gphi[:, None, None] * from_mandel2(sig)).mean(0,
                                         keepdims=True))[0]

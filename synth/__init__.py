@@ -10,11 +10,11 @@ sharing any computation.
 from .microstructure import (periodic_voronoi, periodic_laguerre, shoemake_quaternions,
                              lognormal_laguerre_weights, notch_mask)
 from .loading import triangular_waveform
-from .workloads import (Workload, workload, WORKLOADS, make_inputs, small_polycrystal,
+from .workloads import (Workload, workload, WORKLOADS, make_inputs, small_polycrystal, cmsx4,
                         single_crystal)
 from .serving import serving_requests, request_workload
 
 __all__ = ["periodic_voronoi", "periodic_laguerre", "shoemake_quaternions",
            "lognormal_laguerre_weights", "notch_mask", "triangular_waveform", "Workload",
-           "workload", "WORKLOADS", "make_inputs", "small_polycrystal", "single_crystal",
+           "workload", "WORKLOADS", "make_inputs", "small_polycrystal", "cmsx4", "single_crystal",
            "serving_requests", "request_workload"]

@@ -7,6 +7,13 @@ and fracture toughness drawn uniformly in [0.5, 1.5] J/m^2 per run.  Constants
 the workloads leave open are taken from the paper's Table 1 and its numerical
 setup (Burgers vector 3.5e-10 m, SSD coefficient 1.5e14 m^-2, voxel 0.78 um,
 strain rate 1e-3/s, regularisation length of the plastic distortion 2 voxels).
+
+Workloads with ``material = 1`` use the paper's thermally activated flow rule with
+Taylor hardening and its Table 1 constants (CMSX-4 at room temperature: C11/C12/C44
+= 250/161/129 GPa, initial CRSS 350 MPa, b = 3.5e-10 m, v_D = 1e11 1/s,
+k = 1.4e-23 J/K, dF = 4.9e-20 J, rho_m = 5e12 1/m^2, lambda = 1.5e14 1/m^2, T = 295 K).
+The paper gives neither the activation volume nor the shear modulus of the Taylor
+term: dV = 20 b^3 and mu = C44 here.
 """
 import dataclasses
 import numpy as np
@@ -51,6 +58,15 @@ class Workload:
     k_res: float = 1e-5
     ell_fp_vox: float = 2.0
     rate: float = 1e-3
+    # thermally activated flow + Taylor hardening (material = 1)
+    material: int = 0
+    rho_m: float = 5e12
+    v_D: float = 1e11
+    dF: float = 4.9e-20
+    k_B: float = 1.4e-23
+    T: float = 295.0
+    dV_b3: float = 20.0               # activation volume in units of b^3
+    mu: float = None                  # Taylor shear modulus; C44 when None
     # solver (paper's production tolerances by default)
     tol_stag: float = 5e-3
     tol_newton: float = 5e-3
@@ -96,7 +112,10 @@ class Workload:
                     G_crit=self.G_crit, k_res=self.k_res, ell_fp=self.ell_fp,
                     tol_stag=self.tol_stag, tol_newton=self.tol_newton, tol_lin=self.tol_lin,
                     max_stag=self.max_stag, max_newton=self.max_newton,
-                    max_krylov=self.max_krylov, gmres_restart=self.gmres_restart)
+                    max_krylov=self.max_krylov, gmres_restart=self.gmres_restart,
+                    material=int(self.material), rho_m=self.rho_m, v_D=self.v_D, dF=self.dF,
+                    k_B=self.k_B, T=self.T, dV=self.dV_b3 * self.burgers ** 3,
+                    mu=self.C44 if self.mu is None else self.mu)
 
 
 def make_inputs(w):
@@ -135,6 +154,15 @@ def single_crystal(n=16, seed=0, notch=True, **kw):
                     amplitude=0.005, ratio=-1, cycles=2, incs_per_cycle=20, notch=notch, **kw)
 
 
+def cmsx4(**kw):
+    """Table 1 constants (thermally activated flow, Taylor hardening) and the paper's
+    load: strain ratio 0, amplitude 2 %, strain rate 1e-3/s."""
+    base = dict(material=1, C11=250e9, C12=161e9, C44=129e9, tau_c0=350e6, h_lin=0.0,
+                amplitude=0.02, ratio=0)
+    base.update(kw)
+    return base
+
+
 def small_polycrystal(n=16, n_grains=8, seed=11, **kw):
     base = dict(amplitude=0.006, ratio=0, cycles=3, incs_per_cycle=20)
     base.update(kw)
@@ -160,6 +188,14 @@ WORKLOADS = {
     "voronoi-256-g4096-hard": Workload(name="voronoi-256-g4096-hard", n=(256, 256, 256),
                                        n_grains=4096, seed=3, amplitude=0.007, ratio=0,
                                        cycles=2, incs_per_cycle=16, hard_fraction=0.05),
+    # thermally activated flow with Taylor hardening (Table 1): 16^3 Voronoi, 4 grains
+    # (the oracle takes about a minute for the first six increments at tight tolerances)
+    "cmsx4-voronoi-16-g4": Workload(name="cmsx4-voronoi-16-g4", n=(16, 16, 16), n_grains=4,
+                                    seed=3, cycles=1, incs_per_cycle=20, **cmsx4()),
+    # thermally activated flow with Taylor hardening (Table 1), 128^3, 512 Laguerre grains
+    "cmsx4-laguerre-128-g512": Workload(name="cmsx4-laguerre-128-g512", n=(128, 128, 128),
+                                        n_grains=512, seed=5, cycles=1, incs_per_cycle=20,
+                                        laguerre_sigma=0.4, **cmsx4()),
 }
 
 

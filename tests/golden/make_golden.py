@@ -9,8 +9,12 @@ Only ``oracle`` (and the seeded input generators in ``synth``) are called.  Outp
   median (beyond that the crack path may bifurcate and several answers are correct).
 * voronoi64.npz -- the 64^3 Voronoi polycrystal (64 grains), tight tolerances, the
   first increments, fields at 4096 seeded sample voxels and the macro stress.
+* cmsx4_16.npz -- the 16^3 four-grain polycrystal with the thermally activated flow
+  rule and Taylor hardening (Table 1 constants), tight tolerances, the first six
+  increments (elastic, then yielding): every field after increments 3 and 5, macro stress
+  and iteration counts of each.
 
-Usage: python tests/golden/make_golden.py [notched16|voronoi64] ...
+Usage: python tests/golden/make_golden.py [notched16|voronoi64|cmsx4_16] ...
 """
 import os
 import sys
@@ -25,6 +29,7 @@ from oracle import OracleRVE          # noqa: E402
 from synth import workload, make_inputs   # noqa: E402
 
 FIELDS = ("strain", "stress", "damage", "gs", "wp", "rho_gnd")
+FIELDS_CMSX4 = FIELDS + ("rho_ssd", "g", "eps_p")
 
 
 def notched16(max_inc=40, snaps=(5, 11, 13, 15, 19, 25, 31, 39)):
@@ -86,6 +91,27 @@ def voronoi64(n_inc=2, n_sample=4096):
                             **{k2: np.asarray(v) for k2, v in out.items()})
 
 
+def cmsx4_16(n_inc=6, snaps=(3, 5)):
+    w = workload("cmsx4-voronoi-16-g4").parity()
+    inp = make_inputs(w)
+    o = OracleRVE(w.desc(), inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+    out = {"macro_stress": [], "newton": [], "stag": []}
+    t0 = time.time()
+    for k in range(n_inc):
+        st = o.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k])
+        print(f"inc {k}: {time.time() - t0:.0f}s stag {st['stag']} newton {st['newton']}",
+              flush=True)
+        out["macro_stress"].append(st["macro_stress"])
+        out["newton"].append(st["newton"])
+        out["stag"].append(st["stag"])
+        if k in snaps:
+            f = o.fields()
+            for name in FIELDS_CMSX4:
+                out[f"inc{k}_{name}"] = f[name]
+    np.savez_compressed(os.path.join(HERE, "cmsx4_16.npz"), last=n_inc - 1,
+                        **{k2: np.asarray(v) for k2, v in out.items()})
+
+
 if __name__ == "__main__":
-    for name in sys.argv[1:] or ["notched16", "voronoi64"]:
+    for name in sys.argv[1:] or ["notched16", "voronoi64", "cmsx4_16"]:
         globals()[name]()
