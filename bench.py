@@ -13,7 +13,9 @@ included).  Inputs are resident on the GPU before timing starts.
 
 Printed: one JSON line with the FP64 rate, the mixed-precision rate and its macro
 stress error against the FP64 run, the roofline of the dominant operator kernel
-(HIP events on the library's stream) and the CPU oracle timed on a bounded sample.
+(HIP events on the library's stream), the FP64 rate of the same grid with the paper's
+thermally activated flow rule and Table 1 material in yielding increments, and the CPU
+oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -38,6 +40,8 @@ def parse():
     ap.add_argument("--workload", default="laguerre-128-g512")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-material", action="store_true",
+                    help="skip the thermally-activated-flow leg (Table 1 material)")
     ap.add_argument("--pass-reps", type=int, default=20)
     return ap.parse_args()
 
@@ -140,7 +144,7 @@ def cpu_baseline(w, inp, gpu_stats, n_apply=6, stride=64):
     gid = o.gid[sub]
     t0 = time.perf_counter()
     return_map(to_mandel2(eps), np.zeros((len(sub), 6)), o.g[sub], inp["dt"][0], t.C[gid], t.S[gid],
-               t.P[gid], w.gdot0, w.n_exp)
+               t.P[gid], law=o.law)
     t_const = (time.perf_counter() - t0) * M / len(sub)
     n_mv = np.mean([s["krylov_iters"] for s in gpu_stats])
     n_cs = np.mean([s["newton_iters"] + s["ls_cuts"] + s["stag_iters"] for s in gpu_stats])
@@ -152,6 +156,31 @@ def cpu_baseline(w, inp, gpu_stats, n_apply=6, stride=64):
                        f"{stride} of its voxels ({t_const:.1f} s per full-grid call, scaled); "
                        f"one increment projected with the GPU run's counts ({n_mv:.0f} operator "
                        f"applications, {n_cs:.0f} constitutive calls) = {t_inc:.0f} s")}
+
+
+def material_leg(RVE, precision, torch, name="cmsx4-laguerre-128-g512", warmup=2, steps=2):
+    """The same increment with the thermally activated flow rule and Taylor hardening
+    (Table 1 constants): the first increments stay elastic and serve as warm-up, the
+    timed ones yield.  Also times the constitutive kernel at the yielded state."""
+    from synth import workload, make_inputs
+    from paper_2304_01125_amd.rve import PASSES
+    w = workload(name)
+    inp = make_inputs(w)
+    r, dt, kry, stats, _ = run_leg(RVE, precision, w.desc(), inp, warmup, steps, torch)
+    s = r.stream
+    r.launch_pass(PASSES["constitutive"], 1)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    r.launch_pass(PASSES["constitutive"], 5)
+    e1.record(s)
+    e1.synchronize()
+    r.close()
+    return {"workload": name, "flow": "thermally activated (eq. flowrule), Taylor hardening",
+            "value": round(w.nvox * kry / dt, 1), "unit": "voxel-iters/s",
+            "ms_per_step": round(1e3 * dt / steps, 2), "increments": f"{warmup}..{warmup + steps - 1}",
+            "krylov_iters": kry, "newton_iters": int(sum(x["newton_iters"] for x in stats)),
+            "constitutive_ms": round(e0.elapsed_time(e1) / 5, 4)}
 
 
 def main():
@@ -206,6 +235,8 @@ def main():
                         "macro_stress_rel_err_vs_fp64": float(err.max()),
                         "passes": {k: {"ms": round(v["ms"], 5), "GB/s": round(v["gbs"], 1)}
                                    for k, v in p32.items()}}
+    if not a.no_material:
+        out["material"] = material_leg(RVE, RVE_FP64, torch)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, inp, st64)
     print(json.dumps(out), flush=True)

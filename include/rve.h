@@ -45,6 +45,14 @@ enum {
 };
 
 enum { RVE_FP64 = 0, RVE_MIXED = 1 };
+/* Constitutive model (Sec. 2.1).  RVE_MAT_POWER: power-law flow
+ *   dgamma = dt gdot0 sign(tau) |tau/g|^n_exp with linear hardening g += h_lin sum |dgamma|.
+ * RVE_MAT_DUNNE: thermally activated glide over obstacles (eq. flowrule)
+ *   dgamma = dt A sign(tau) sinh(<|tau| - g> dV / kT),  A = rho_m b^2 v_D exp(-dF / kT),
+ *   no slip while |tau| <= g, with Taylor hardening g = tau_c0 + mu b sqrt(rho_SSD + rho_GND)
+ *   from the densities committed at the end of the previous increment (initially
+ *   tau_c0 + mu b sqrt(rho0)). */
+enum { RVE_MAT_POWER = 0, RVE_MAT_DUNNE = 1 };
 
 /* Field selection bits for rve_fields(); fields are written in increasing bit order. */
 enum {
@@ -86,6 +94,11 @@ typedef struct rve_desc {
   double tol_lin;           /* relative Krylov tolerance (paper: 1e-5)                  */
   int32_t max_stag, max_newton, max_krylov;
   int32_t max_grains;       /* capacity of the per-grain tables (>= n_grains)           */
+  int32_t material;         /* RVE_MAT_POWER (gdot0, n_exp, h_lin) or RVE_MAT_DUNNE     */
+  double rho_m, v_D;        /* mobile dislocation density [1/m^2], jump attempt rate [1/s] */
+  double dF, k_B, T;        /* activation energy [J], Boltzmann constant [J/K], temperature [K] */
+  double dV;                /* activation volume [m^3]                                 */
+  double mu;                /* shear modulus of the Taylor term [Pa]                    */
 } rve_desc;
 
 /* Per-increment report, filled by rve_step_increment (also on RVE_E_NOCONV). */

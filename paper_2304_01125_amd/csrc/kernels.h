@@ -171,7 +171,8 @@ enum {
   GT_P = 72,       // Mandel Schmid tensors sym(s (x) n), 12 x 6
   GT_SN = 144,     // s (x) n, 12 x 9 row-major
   GT_R = 252,      // rotation crystal -> sample, 9 row-major
-  GT_STRIDE = 261
+  GT_TAU0 = 261,   // initial critical resolved shear stress
+  GT_STRIDE = 262
 };
 
 // Grain-independent crystal-frame constants (Mandel): Schmid tensors of the 12 slip
@@ -181,9 +182,17 @@ struct CrystalFrame {
   double c11, c12, c66, s11, s12, s66;
 };
 
+// Flow rules: power law dgamma = dt gdot0 sign(tau) |tau/g|^n (linear hardening), or
+// thermally activated glide dgamma = dt A sign(tau) sinh(beta <|tau| - g>) with
+// A = rho_m b^2 v_D exp(-dF/kT), beta = dV/kT (eq. flowrule; Taylor hardening).
+enum { FLOW_POWER = 0, FLOW_DUNNE = 1 };
+
 struct Material {
   double dt, gdot0, nexp, kres, h_lin, lambda_ssd, xi_store, G_crit, ell, Gc, burgers;
   int nexp_int;   // nexp when it is an integer in [1, 64], else 0 (then pow is used)
+  int flow;       // FLOW_POWER or FLOW_DUNNE
+  double A, beta; // thermally activated rule: rate prefactor [1/s], dV/kT [1/Pa]
+  double mu_b;    // Taylor hardening: shear modulus times Burgers vector [Pa m]
 };
 
 // number of reduction values written by each voxel kernel per block
@@ -204,6 +213,9 @@ void launch_source(long long N, const double* eps, const double* sig, const doub
                    const double* gslip, const int* grain, const double* gtab, const double* wp,
                    const double* trig, const double* wcrit, double* S, double* wep,
                    const Material& m, double* partial, hipStream_t st);
+// Taylor hardening g = tau_c0 + mu b sqrt(rho_SSD + rho_GND) of the voxels that can slip
+void launch_taylor(long long N, double* gslip, const double* rho_ssd, const double* rho_gnd,
+                   const int* grain, const double* gtab, double mu_b, hipStream_t st);
 void launch_commit(long long N, const double* sig, double* gslip, double* epsp, double* beta,
                    double* rho_ssd, const double* rho_gnd, double* wp, double* gs, double* H,
                    double* wcrit, double* trig, const double* wep, const double* phi,

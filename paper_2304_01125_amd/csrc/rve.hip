@@ -304,10 +304,26 @@ int validate(const rve_desc* d) {
     if (!smooth23(d->n[a])) return fail(RVE_E_ARG, "grid sizes must be 2^p 3^q in [1, 512]");
   if (d->precision != RVE_FP64 && d->precision != RVE_MIXED)
     return fail(RVE_E_ARG, "precision must be RVE_FP64 or RVE_MIXED");
-  const double pos[] = {d->h, d->C44, d->gdot0, d->n_exp, d->tau_c0, d->rho0, d->burgers, d->ell,
+  const double pos[] = {d->h, d->C44, d->tau_c0, d->rho0, d->burgers, d->ell,
                         d->Gc, d->k_res, d->tol_stag, d->tol_newton, d->tol_lin};
   for (double v : pos)
     if (!(v > 0.0) || !std::isfinite(v)) return fail(RVE_E_ARG, "non-positive or non-finite constant");
+  if (d->material != RVE_MAT_POWER && d->material != RVE_MAT_DUNNE)
+    return fail(RVE_E_ARG, "material must be RVE_MAT_POWER or RVE_MAT_DUNNE");
+  if (d->material == RVE_MAT_POWER) {
+    if (!(d->gdot0 > 0.0) || !std::isfinite(d->gdot0) || !(d->n_exp > 0.0) ||
+        !std::isfinite(d->n_exp))
+      return fail(RVE_E_ARG, "non-positive or non-finite power-law constant");
+  } else {
+    const double th[] = {d->rho_m, d->v_D, d->dF, d->k_B, d->T, d->dV, d->mu};
+    for (double v : th)
+      if (!(v > 0.0) || !std::isfinite(v))
+        return fail(RVE_E_ARG, "non-positive or non-finite constant of the thermally activated rule");
+    const double kT = d->k_B * d->T;
+    const double A = d->rho_m * d->burgers * d->burgers * d->v_D * std::exp(-d->dF / kT);
+    if (!(A > 0.0) || !std::isfinite(A) || !std::isfinite(d->dV / kT))
+      return fail(RVE_E_ARG, "rate prefactor of the thermally activated rule out of range");
+  }
   const double nonneg[] = {d->h_lin, d->lambda_ssd, d->xi_store, d->G_crit, d->ell_fp};
   for (double v : nonneg)
     if (!(v >= 0.0) || !std::isfinite(v)) return fail(RVE_E_ARG, "negative or non-finite constant");
@@ -411,6 +427,13 @@ struct Ops {
     m.G_crit = h->d.G_crit; m.ell = h->d.ell; m.Gc = h->d.Gc; m.burgers = h->d.burgers;
     const double ne = h->d.n_exp;
     m.nexp_int = (ne == std::floor(ne) && ne >= 1.0 && ne <= 64.0) ? (int)ne : 0;
+    m.flow = h->d.material == RVE_MAT_DUNNE ? FLOW_DUNNE : FLOW_POWER;
+    const double kT = h->d.k_B * h->d.T;
+    m.A = m.flow == FLOW_DUNNE
+              ? h->d.rho_m * h->d.burgers * h->d.burgers * h->d.v_D * std::exp(-h->d.dF / kT)
+              : 0.0;
+    m.beta = m.flow == FLOW_DUNNE ? h->d.dV / kT : 0.0;
+    m.mu_b = h->d.mu * h->d.burgers;
     return m;
   }
 
@@ -731,6 +754,8 @@ int run_increment(rve_s* h, const double de[6], double dt, rve_stats* out) {
     launch_curl_reg<R>(h->pl, B9, o.NH, h->d.ell_fp, invN, st);
     o.inv(B9, 9, h->rbuf, true, N, 1.0, 0);
     launch_gnd(N, h->rbuf, h->grain, h->gtab, h->Q81, h->d.burgers, h->rho_gnd, st);
+    if (m.flow == FLOW_DUNNE)
+      launch_taylor(N, h->gslip, h->rho_ssd, h->rho_gnd, h->grain, h->gtab, m.mu_b, st);
     if ((rc = sync_read(h, SC_MISC, 15))) return rc;
     for (int c = 0; c < 6; ++c) {
       s.macro_stress[c] = h->hs[SC_MISC + c] * invN;
@@ -865,14 +890,18 @@ int rve_set_microstructure(rve_s* h, const int32_t* grain, int32_t n_grains, con
     if (tau0 && !(tau0[gi] > 0.0 && std::isfinite(tau0[gi]))) return fail(RVE_E_ARG, "bad tau_c0");
     if (!grain_table(q, h->d.C11, h->d.C12, h->d.C44, tab.data() + (size_t)gi * GT_STRIDE))
       return fail(RVE_E_ARG, "singular stiffness");
+    tab[(size_t)gi * GT_STRIDE + GT_TAU0] = tau0 ? tau0[gi] : h->d.tau_c0;
   }
+  // initial strength: tau_c0, plus the Taylor term of the initial SSD density
+  const double taylor0 =
+      h->d.material == RVE_MAT_DUNNE ? h->d.mu * h->d.burgers * std::sqrt(h->d.rho0) : 0.0;
   std::vector<double> g((size_t)N), ph((size_t)N, 0.0), rho((size_t)N, h->d.rho0);
   for (long long v = 0; v < N; ++v) {
     if (phi0) {
       if (!(phi0[v] >= 0.0 && phi0[v] <= 1.0)) return fail(RVE_E_ARG, "phi0 outside [0,1]");
       ph[v] = phi0[v];
     }
-    g[v] = (ph[v] >= 1.0) ? INFINITY : (tau0 ? tau0[grain[v]] : h->d.tau_c0);
+    g[v] = (ph[v] >= 1.0) ? INFINITY : (tau0 ? tau0[grain[v]] : h->d.tau_c0) + taylor0;
   }
   hipStream_t st = h->st;
   HIPCHK(hipMemcpyAsync(h->gtab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, st));

@@ -1,9 +1,12 @@
 // Per-voxel kernels: crystal-plasticity update with consistent tangent, the
 // phase-field driving state, the history commit and the GND density (Sec. 2).
 //
-// Constitutive model (small-strain form of Sec. 2.1 with a power-law flow rule):
-//   dgamma_a = dt gdot0 sign(tau_a) |tau_a / g|^n,  tau_a = P_a : sigma,
-//   P_a = sym(s_a (x) n_a); backward Euler on sigma with g frozen over the step:
+// Constitutive model (small-strain form of Sec. 2.1): tau_a = P_a : sigma with
+// P_a = sym(s_a (x) n_a), and one of two flow rules for the slip increment,
+//   power law:             dgamma_a = dt gdot0 sign(tau_a) |tau_a / g|^n,
+//   thermally activated:   dgamma_a = dt A sign(tau_a) sinh(beta <|tau_a| - g>)
+//                          (eq. flowrule, A = rho_m b^2 v_D exp(-dF/kT), beta = dV/kT);
+// backward Euler on sigma with g frozen over the step:
 //   R(sigma) = C^-1 (sigma - sigma_tr) + sum_a dgamma_a P_a = 0,
 //   sigma_tr = C (eps - eps_p).
 // R is the gradient of a strictly convex potential Phi; the root is found by a
@@ -68,22 +71,81 @@ __device__ __forceinline__ double pow_e(double x, double e, int ei) {
   return pow(x, e);
 }
 
-// Slip increments at stress sig (Mandel): tau, dgamma, d dgamma / d tau.
+// Flow-rule constants of one voxel over one step: c0 = dt gdot0 (power law) or dt A
+// (thermally activated), c1 = n or beta; g the slip resistance (critical resolved shear
+// stress), ig = 1/g (0 for a voxel that cannot slip, g = inf).
+struct Flow {
+  double c0, c1, g, ig;
+  int nm1;   // n - 1 when n is a small integer (binary powering), else -1
+};
+
+__device__ __forceinline__ Flow make_flow(const Material& m, double g) {
+  Flow f;
+  const bool th = m.flow == FLOW_DUNNE;
+  f.c0 = m.dt * (th ? m.A : m.gdot0);
+  f.c1 = th ? m.beta : m.nexp;
+  f.g = g;
+  f.ig = 1.0 / g;
+  f.nm1 = m.nexp_int > 0 ? m.nexp_int - 1 : -1;
+  return f;
+}
+
+// Slip increment dg of one system at resolved shear stress t, and d dg / d t.
+template <int F>
+__device__ __forceinline__ void slip_law(const Flow& f, double t, double& dg, double& ddg) {
+  if constexpr (F == FLOW_POWER) {
+    const double x = t * f.ig;
+    const double ax = fabs(x);
+    const double pw = pow_e(ax, f.c1 - 1.0, f.nm1);       // |x|^(n-1)
+    dg = f.c0 * copysign(ax * pw, x);
+    ddg = f.c0 * f.c1 * f.ig * pw;
+  } else {
+    const double o = fabs(t) - f.g;                       // overstress; -inf if g = inf
+    if (o > 0.0) {
+      const double sh = sinh(f.c1 * o);
+      dg = f.c0 * copysign(sh, t);
+      ddg = f.c0 * f.c1 * sqrt(1.0 + sh * sh);            // cosh
+    } else {
+      dg = 0.0;
+      ddg = 0.0;
+    }
+  }
+}
+
+// One system's share of the dissipation potential, without the factor pot_scale:
+// |t| |t/g|^n (power law), sinh(beta <|t| - g> / 2)^2 = (cosh(beta <|t| - g>) - 1) / 2
+// (thermally activated; no cancellation near the threshold).
+template <int F>
+__device__ __forceinline__ double slip_pot(const Flow& f, double t) {
+  if constexpr (F == FLOW_POWER) {
+    const double ax = fabs(t * f.ig);
+    return fabs(t) * ax * pow_e(ax, f.c1 - 1.0, f.nm1);
+  } else {
+    const double o = fabs(t) - f.g;
+    if (!(o > 0.0)) return 0.0;
+    const double sh = sinh(0.5 * f.c1 * o);
+    return sh * sh;
+  }
+}
+template <int F>
+__device__ __forceinline__ double pot_scale(const Flow& f) {
+  return F == FLOW_POWER ? f.c0 / (f.c1 + 1.0) : 2.0 * f.c0 / f.c1;
+}
+
+// Slip increments at stress sig (Mandel) with the flow rule of m: tau and dgamma.
 __device__ __forceinline__ void slip(const double* __restrict__ P, const double sig[6], double g,
-                                     double dtg0, double nexp, int nm1, double tau[12],
-                                     double dg[12], double ddg[12], double axn[12]) {
+                                     const Material& m, double tau[12], double dg[12]) {
+  const Flow f = make_flow(m, g);
 #pragma unroll
   for (int a = 0; a < 12; ++a) {
     double s = 0.0;
 #pragma unroll
     for (int b = 0; b < 6; ++b) s += P[a * 6 + b] * sig[b];
     tau[a] = s;
-    const double x = s / g;
-    const double ax = fabs(x);
-    const double pw = pow_e(ax, nexp - 1.0, nm1);   // |x|^(n-1)
-    axn[a] = ax * pw;                              // |x|^n
-    dg[a] = dtg0 * copysign(axn[a], x);
-    ddg[a] = dtg0 * nexp / g * pw;
+    double d, dd;
+    if (m.flow == FLOW_DUNNE) slip_law<FLOW_DUNNE>(f, s, d, dd);
+    else slip_law<FLOW_POWER>(f, s, d, dd);
+    dg[a] = d;
   }
 }
 
@@ -109,10 +171,10 @@ __device__ __forceinline__ void cubic_mul(double a, double b, double c, const do
   y[5] = c * x[5];
 }
 
-// Phi(sig) = 1/2 (sig-sig_tr) S (sig-sig_tr) + dt gdot0/(n+1) sum |tau| |tau/g|^n
+// Phi(sig) = 1/2 (sig-sig_tr) S (sig-sig_tr) + sum of the systems' potential shares
+template <int F>
 __device__ __forceinline__ double potential(const CrystalFrame& cf, const double sig[6],
-                                            const double str[6], double ig, double dtg0,
-                                            double nexp, int nm1) {
+                                            const double str[6], const Flow& f) {
   double d[6], Sd[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) d[i] = sig[i] - str[i];
@@ -126,17 +188,17 @@ __device__ __forceinline__ double potential(const CrystalFrame& cf, const double
     double t = 0.0;
 #pragma unroll
     for (int b = 0; b < 6; ++b) t += cf.P[a * 6 + b] * sig[b];
-    const double ax = fabs(t * ig);
-    pl += fabs(t) * ax * pow_e(ax, nexp - 1.0, nm1);
+    pl += slip_pot<F>(f, t);
   }
-  return 0.5 * el + dtg0 / (nexp + 1.0) * pl;
+  return 0.5 * el + pot_scale<F>(f) * pl;
 }
 
 // Residual R = S (sig - sig_tr) + sum dgamma P and packed Jacobian J (21), accumulated
 // slip system by slip system.
+template <int F>
 __device__ __forceinline__ void resjac(const CrystalFrame& cf, const double sig[6],
-                                       const double str[6], double ig, double dtg0, double nexp,
-                                       int nm1, double Rv[6], double J[21]) {
+                                       const double str[6], const Flow& f, double Rv[6],
+                                       double J[21]) {
   double d[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) d[i] = sig[i] - str[i];
@@ -151,11 +213,8 @@ __device__ __forceinline__ void resjac(const CrystalFrame& cf, const double sig[
     double t = 0.0;
 #pragma unroll
     for (int b = 0; b < 6; ++b) t += cf.P[a * 6 + b] * sig[b];
-    const double x = t * ig;
-    const double ax = fabs(x);
-    const double pw = pow_e(ax, nexp - 1.0, nm1);       // |x|^(n-1)
-    const double dg = dtg0 * copysign(ax * pw, x);
-    const double ddg = dtg0 * nexp * ig * pw;
+    double dg, ddg;
+    slip_law<F>(f, t, dg, ddg);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
       Rv[i] += dg * cf.P[a * 6 + i];
@@ -232,26 +291,49 @@ __device__ __forceinline__ void chol6p_inverse(const double U[21], double K[21])
     }
 }
 
-// Solve the return map from the warm start in sig (crystal-frame Mandel, in/out) with
-// Newton steps and a backtracking line search on Phi.  Returns the number of Newton
-// iterations, or -1 if it did not converge.
-__device__ int return_map(const CrystalFrame& cf, const double str[6], double g, double dtg0,
-                          double nexp, int nm1, double sig[6]) {
-  const double ig = 1.0 / g;
+// Solve the return map with Newton steps and a backtracking line search on Phi.  sig
+// (crystal-frame Mandel, in/out) holds a warm start; the iteration starts from it or
+// from the trial stress scaled into the elastic range, whichever has the lower
+// potential (far above the threshold of the exponential rule the Newton steps shrink
+// to the rule's stress scale 1/beta).  Returns the number of Newton iterations, or -1
+// if it did not converge.
+template <int F>
+__device__ int return_map(const CrystalFrame& cf, const double str[6], const Flow& f,
+                          double sig[6]) {
+  {
+    double tmax = 0.0;
+#pragma unroll 1
+    for (int a = 0; a < 12; ++a) {
+      double t = 0.0;
+#pragma unroll
+      for (int b = 0; b < 6; ++b) t += cf.P[a * 6 + b] * str[b];
+      tmax = fmax(tmax, fabs(t));
+    }
+    const double sc = fmin(1.0, 1.0 / fmax(tmax * f.ig, 1e-300));
+    double sd[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) sd[i] = sc * str[i];
+    const double pw = potential<F>(cf, sig, str, f);
+    const double pd = potential<F>(cf, sd, str, f);
+    if (!(pw <= pd)) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) sig[i] = sd[i];
+    }
+  }
   double scale = 0.0;
 #pragma unroll
   for (int i = 0; i < 6; ++i) scale = fmax(scale, fabs(str[i]));
-  scale += g;
+  scale += f.g;
   int it;
   bool conv = false;
   for (it = 0; it < 400; ++it) {
     double Rv[6], J[21], d[6], mR[6];
-    resjac(cf, sig, str, ig, dtg0, nexp, nm1, Rv, J);
+    resjac<F>(cf, sig, str, f, Rv, J);
     if (!chol6p(J)) return -1;
 #pragma unroll
     for (int i = 0; i < 6; ++i) mR[i] = -Rv[i];
     chol6p_solve(J, mR, d);
-    const double phi0 = potential(cf, sig, str, ig, dtg0, nexp, nm1);
+    const double phi0 = potential<F>(cf, sig, str, f);
     double slope = 0.0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) slope += Rv[i] * d[i];
@@ -260,7 +342,7 @@ __device__ int return_map(const CrystalFrame& cf, const double str[6], double g,
       double c[6];
 #pragma unroll
       for (int i = 0; i < 6; ++i) c[i] = sig[i] + t * d[i];
-      const double phi1 = potential(cf, c, str, ig, dtg0, nexp, nm1);
+      const double phi1 = potential<F>(cf, c, str, f);   // inf past an overflow: halve
       if (phi1 <= phi0 + 1e-4 * t * slope + 1e-13 * fabs(phi0)) break;
       t *= 0.5;
     }
@@ -277,7 +359,7 @@ __device__ int return_map(const CrystalFrame& cf, const double str[6], double g,
   // one polishing Newton step at the root
   {
     double Rv[6], J[21], d[6];
-    resjac(cf, sig, str, ig, dtg0, nexp, nm1, Rv, J);
+    resjac<F>(cf, sig, str, f, Rv, J);
     if (!chol6p(J)) return -1;
     chol6p_solve(J, Rv, d);
 #pragma unroll
@@ -352,15 +434,13 @@ __device__ __forceinline__ void to_sample(const double* Rm, const double t[6], d
 // Three waves per SIMD (at most 168 VGPRs): the extra occupancy hides more of the FP64
 // latencies than the spills it causes cost (measured 15 % faster than the unconstrained
 // two waves; a four-wave bound spills far more and runs at half speed).
-template <typename R>
+template <typename R, int F>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_constitutive(long long N, const double* __restrict__ eps, const double* __restrict__ deps,
                double t, const double* __restrict__ epsp, const double* __restrict__ gslip,
                const int* __restrict__ grain, const double* __restrict__ gtab,
                double* __restrict__ sig_io, const double* __restrict__ phi, R* __restrict__ gK,
                double* __restrict__ gw, CrystalFrame cf, Material m, int* __restrict__ fail) {
-  const double dtg0 = m.dt * m.gdot0;
-  const int nm1 = m.nexp_int > 0 ? m.nexp_int - 1 : -1;
   // one voxel per thread (N < 2^29, so byte offsets fit 32 bits)
   const unsigned v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v < N) {
@@ -391,13 +471,12 @@ k_constitutive(long long N, const double* __restrict__ eps, const double* __rest
       to_mandel(tc, sig);
     }
     cubic_mul(cf.c11, cf.c12, cf.c66, ec, str);
-    const double g = comp(gslip, N, 0, b8);
-    const int its = return_map(cf, str, g, dtg0, m.nexp, nm1, sig);
+    const Flow f = make_flow(m, comp(gslip, N, 0, b8));
+    const int its = return_map<F>(cf, str, f, sig);
     if (its < 0) atomicAdd(fail, 1);
-    const double ig = 1.0 / g;
     // tangent at the root, crystal frame
     double Rv[6], J[21];
-    resjac(cf, sig, str, ig, dtg0, m.nexp, nm1, Rv, J);
+    resjac<F>(cf, sig, str, f, Rv, J);
     double K[21];
     if (chol6p(J)) chol6p_inverse(J, K);
     else {
@@ -414,7 +493,7 @@ k_constitutive(long long N, const double* __restrict__ eps, const double* __rest
       double el = 0.0;
 #pragma unroll
       for (int i = 0; i < 6; ++i) el += str[i] * Ss[i];
-      comp(gw, N, 0, b8) = gphi * (0.5 * el - potential(cf, sig, str, ig, dtg0, m.nexp, nm1));
+      comp(gw, N, 0, b8) = gphi * (0.5 * el - potential<F>(cf, sig, str, f));
     }
     // back to the sample frame: sigma = Rm sig Rm^T; gK = g(phi) Q K Q^T with Q the
     // Mandel form of the rotation, Q_IJ = (w_I / w_J) (R_ik R_jl + [k != l] R_il R_jk)
@@ -491,8 +570,12 @@ void launch_constitutive(long long N, const double* eps, const double* deps, dou
                          const CrystalFrame& cf, const Material& m, double* partial, int* fail,
                          hipStream_t st) {
   const long long nb = (N + 255) / 256;
-  hipLaunchKernelGGL((k_constitutive<R>), dim3((int)(nb < 1 ? 1 : nb)), dim3(256), 0, st, N, eps,
-                     deps, t, epsp, gslip, grain, gtab, sig, phi, gK, gw, cf, m, fail);
+  if (m.flow == FLOW_DUNNE)
+    hipLaunchKernelGGL((k_constitutive<R, FLOW_DUNNE>), dim3((int)(nb < 1 ? 1 : nb)), dim3(256), 0,
+                       st, N, eps, deps, t, epsp, gslip, grain, gtab, sig, phi, gK, gw, cf, m, fail);
+  else
+    hipLaunchKernelGGL((k_constitutive<R, FLOW_POWER>), dim3((int)(nb < 1 ? 1 : nb)), dim3(256), 0,
+                       st, N, eps, deps, t, epsp, gslip, grain, gtab, sig, phi, gK, gw, cf, m, fail);
   hipLaunchKernelGGL((k_const_sums<R>), dim3(voxel_grid(N)), dim3(256), 0, st, N, gK, gw, sig,
                      phi, m.kres, partial);
 }
@@ -582,7 +665,6 @@ __global__ void __launch_bounds__(256) k_source(long long N, const double* __res
                          const double* __restrict__ wcrit, double* __restrict__ S_out,
                          double* __restrict__ wep_out, Material m, double* __restrict__ partial) {
   double acc[RED_SOURCE] = {0.0, 0.0};
-  const double dtg0 = m.dt * m.gdot0;
   for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
        v += (long long)gridDim.x * blockDim.x) {
     const double* gt = gtab + (long long)grain[v] * GT_STRIDE;
@@ -592,8 +674,8 @@ __global__ void __launch_bounds__(256) k_source(long long N, const double* __res
     load6(eps, N, v, e);
     load6(epsp, N, v, ep);
     to_mandel(st, sm);
-    double tau[12], dg[12], ddg[12], axn[12];
-    slip(P, sm, gslip[v], dtg0, m.nexp, m.nexp_int > 0 ? m.nexp_int - 1 : -1, tau, dg, ddg, axn);
+    double tau[12], dg[12];
+    slip(P, sm, gslip[v], m, tau, dg);
     double dpm[6] = {0, 0, 0, 0, 0, 0};
     double dw = 0.0;
 #pragma unroll
@@ -627,7 +709,8 @@ void launch_source(long long N, const double* eps, const double* sig, const doub
 }
 
 // History commit of one converged increment (FP64), Sec. 2.1-2.3:
-// eps_p, beta_p, g (linear hardening), rho_SSD, W_p, G_s, H = max W_e+, W_crit.
+// eps_p, beta_p, g (linear hardening of the power law), rho_SSD, W_p, G_s, H = max W_e+,
+// W_crit.
 // Partials: sums of g(phi) sigma (6), eps (6) and the trigger flag; maxima of phi
 // and of phi over voxels that can slip.
 __global__ void __launch_bounds__(256) k_commit(long long N, const double* __restrict__ sig, double* __restrict__ gslip,
@@ -643,7 +726,6 @@ __global__ void __launch_bounds__(256) k_commit(long long N, const double* __res
   double mx[2] = {0.0, 0.0};
 #pragma unroll
   for (int c = 0; c < 13; ++c) acc[c] = 0.0;
-  const double dtg0 = m.dt * m.gdot0;
   for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
        v += (long long)gridDim.x * blockDim.x) {
     const double* gt = gtab + (long long)grain[v] * GT_STRIDE;
@@ -653,8 +735,8 @@ __global__ void __launch_bounds__(256) k_commit(long long N, const double* __res
     load6(sig, N, v, st);
     to_mandel(st, sm);
     const double g = gslip[v];
-    double tau[12], dg[12], ddg[12], axn[12];
-    slip(P, sm, g, dtg0, m.nexp, m.nexp_int > 0 ? m.nexp_int - 1 : -1, tau, dg, ddg, axn);
+    double tau[12], dg[12];
+    slip(P, sm, g, m, tau, dg);
     double dpm[6] = {0, 0, 0, 0, 0, 0};
     double db[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     double dw = 0.0, sabs = 0.0;
@@ -677,7 +759,7 @@ __global__ void __launch_bounds__(256) k_commit(long long N, const double* __res
       beta[i * N + v] += db[i];
       db2 += db[i] * db[i];
     }
-    gslip[v] = g + m.h_lin * sabs;
+    if (m.flow == FLOW_POWER) gslip[v] = g + m.h_lin * sabs;   // else: Taylor, after the GND
     const double rs = rho_ssd[v] + m.lambda_ssd * sqrt(2.0 / 3.0 * db2);
     rho_ssd[v] = rs;
     const double wpn = wp[v] + dw;
@@ -716,6 +798,26 @@ void launch_commit(long long N, const double* sig, double* gslip, double* epsp, 
   hipLaunchKernelGGL(k_commit, dim3(voxel_grid(N)), dim3(256), 0, st, N, sig, gslip, epsp, beta,
                      rho_ssd, rho_gnd, wp, gs, H, wcrit, trig, wep, phi, eps, grain, gtab, m,
                      partial);
+}
+
+// Taylor hardening (Sec. 2.1): g = tau_c0 + mu b sqrt(rho_SSD + rho_GND) from the
+// committed densities; voxels that cannot slip (g = inf) keep their strength.
+__global__ void __launch_bounds__(256) k_taylor(long long N, double* __restrict__ gslip,
+                         const double* __restrict__ rho_ssd, const double* __restrict__ rho_gnd,
+                         const int* __restrict__ grain, const double* __restrict__ gtab,
+                         double mu_b) {
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x) {
+    if (!isfinite(gslip[v])) continue;
+    const double tau0 = gtab[(long long)grain[v] * GT_STRIDE + GT_TAU0];
+    gslip[v] = tau0 + mu_b * sqrt(rho_ssd[v] + rho_gnd[v]);
+  }
+}
+
+void launch_taylor(long long N, double* gslip, const double* rho_ssd, const double* rho_gnd,
+                   const int* grain, const double* gtab, double mu_b, hipStream_t st) {
+  hipLaunchKernelGGL(k_taylor, dim3(voxel_grid(N)), dim3(256), 0, st, N, gslip, rho_ssd, rho_gnd,
+                     grain, gtab, mu_b);
 }
 
 // rho_GND = sqrt(vec(Lc)^T Q vec(Lc)) / b with Lc = R^T Lambda R (crystal frame) and

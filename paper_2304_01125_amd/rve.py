@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_HERE, "librve.so")
 
 RVE_OK, RVE_E_ARG, RVE_E_NOMEM, RVE_E_DEVICE, RVE_E_NOCONV, RVE_E_STATE = 0, -1, -2, -3, -4, -5
 RVE_FP64, RVE_MIXED = 0, 1
+RVE_MAT_POWER, RVE_MAT_DUNNE = 0, 1
 
 FIELDS = [  # (name, bit, components) in the order rve_fields writes them
     ("strain", 1 << 0, 6), ("stress", 1 << 1, 6), ("stress_eff", 1 << 2, 6),
@@ -38,7 +39,10 @@ class RveDesc(ctypes.Structure):
                 ("tol_stag", ctypes.c_double), ("tol_newton", ctypes.c_double),
                 ("tol_lin", ctypes.c_double), ("max_stag", ctypes.c_int32),
                 ("max_newton", ctypes.c_int32), ("max_krylov", ctypes.c_int32),
-                ("max_grains", ctypes.c_int32)]
+                ("max_grains", ctypes.c_int32), ("material", ctypes.c_int32),
+                ("rho_m", ctypes.c_double), ("v_D", ctypes.c_double), ("dF", ctypes.c_double),
+                ("k_B", ctypes.c_double), ("T", ctypes.c_double), ("dV", ctypes.c_double),
+                ("mu", ctypes.c_double)]
 
 
 class RveStats(ctypes.Structure):
@@ -146,6 +150,10 @@ def make_desc(desc, precision=RVE_FP64, max_grains=4096):
     d.max_newton = int(desc["max_newton"])
     d.max_krylov = int(desc["max_krylov"])
     d.max_grains = int(max_grains)
+    d.material = int(desc.get("material", RVE_MAT_POWER))
+    if d.material == RVE_MAT_DUNNE:
+        for k in ("rho_m", "v_D", "dF", "k_B", "T", "dV", "mu"):
+            setattr(d, k, float(desc[k]))
     return d
 
 

@@ -1,0 +1,102 @@
+"""The thermally activated flow rule with Taylor hardening (eq. flowrule, Sec. 2.1, Table 1
+constants) on the GPU against the CPU oracle: the per-voxel return map and tangent at
+strains on both sides of the threshold, and the first six increments of the 16^3
+four-grain polycrystal (elastic, then yielding) against stored oracle results at tight
+tolerances, in FP64 and in mixed precision."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import GrainTables, return_map, flow_law, to_mandel2, from_mandel2
+from oracle.increment import tensor6, from_tensor6
+from synth import small_polycrystal, cmsx4, workload, make_inputs
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def rel_l2(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_constitutive_matches_oracle(prec):
+    from paper_2304_01125_amd import RVE
+    print(f"thermally activated constitutive 8x6x4 precision {prec}", flush=True)
+    w = small_polycrystal(n=(8, 6, 4), n_grains=4, seed=3, **cmsx4())
+    d = w.desc()
+    inp = make_inputs(w)
+    r = RVE(d, prec)
+    r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+    rng = np.random.default_rng(5)
+    M = w.nvox
+    eps = rng.uniform(-2.5e-3, 2.5e-3, (M, 6))             # about 60 % of the voxels yield
+    eps[:, 1] += 3e-3
+    dt = 2.0
+    sig_g, gk_g = r.constitutive(eps, dt)
+    r.close()
+    t = GrainTables(inp["quat"], d["C11"], d["C12"], d["C44"])
+    gid = inp["grain"]
+    g = np.asarray(inp["tau_c0"])[gid] + d["mu"] * d["burgers"] * np.sqrt(d["rho0"])
+    sig_o, dg, K, _ = return_map(to_mandel2(from_tensor6(eps)), np.zeros((M, 6)), g, dt,
+                                 t.C[gid], t.S[gid], t.P[gid], law=flow_law(d))
+    plastic = np.abs(dg).max(1) > 0
+    print(f"  plastic voxels {plastic.mean():.2f}", flush=True)
+    assert 0.1 < plastic.mean() < 0.95
+    sig_o6 = tensor6(from_mandel2(sig_o))
+    err = np.abs(sig_g - sig_o6).max() / np.abs(sig_o6).max()
+    iu = np.triu_indices(6)
+    Ko = (1.0 + d["k_res"]) * K[:, iu[0], iu[1]]
+    errk = np.abs(gk_g - Ko).max() / np.abs(Ko).max()
+    print(f"  stress {err:.2e} tangent {errk:.2e}", flush=True)
+    assert err <= 1e-12
+    assert errk <= (1e-10 if prec == 0 else 1e-6)
+
+
+def _run(prec, parity=True):
+    from paper_2304_01125_amd import RVE
+    ref = np.load(os.path.join(GOLDEN, "cmsx4_16.npz"))
+    w = workload("cmsx4-voronoi-16-g4")
+    if parity:
+        w = w.parity()
+    inp = make_inputs(w)
+    r = RVE(w.desc(), prec)
+    r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+    return ref, inp, r
+
+
+def test_cmsx4_16_fp64_matches_stored_oracle():
+    ref, inp, r = _run(0)
+    names = ("strain", "stress", "damage", "gs", "wp", "rho_gnd", "rho_ssd", "g", "eps_p")
+    for k in range(int(ref["last"]) + 1):
+        st = r.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k])
+        ms = np.array(st["macro_stress"])
+        e_ms = np.abs(ms - ref["macro_stress"][k]).max() / np.abs(ref["macro_stress"][k]).max()
+        print(f"  inc {k}: newton {st['newton_iters']} (oracle {int(ref['newton'][k])}) krylov "
+              f"{st['krylov_iters']} stag {st['stag_iters']} macro stress {e_ms:.2e}", flush=True)
+        assert e_ms <= 1e-9
+        if f"inc{k}_strain" in ref.files:
+            f = r.fields(names)
+            errs = {n: rel_l2(f[n], ref[f"inc{k}_{n}"]) for n in names if n != "damage"}
+            errs["damage"] = np.abs(f["damage"] - ref[f"inc{k}_damage"]).max()
+            print(f"  inc {k} fields:", {n: f"{v:.2e}" for n, v in errs.items()}, flush=True)
+            assert errs["strain"] <= 1e-9 and errs["stress"] <= 1e-9
+            assert errs["g"] <= 1e-9 and errs["rho_ssd"] <= 1e-9      # g = tau0 + mu b sqrt(rho)
+            assert errs["eps_p"] <= 1e-8 and errs["gs"] <= 1e-8 and errs["wp"] <= 1e-8
+            assert errs["rho_gnd"] <= 1e-8 and errs["damage"] <= 1e-8
+            assert np.abs(f["eps_p"]).max() > 1e-4          # the grains have yielded
+    r.close()
+
+
+def test_cmsx4_16_mixed_reproduces_oracle_macro_stress():
+    # FP32 FFTs, operator and tangent at the paper's tolerances against the FP64 oracle
+    # at tight tolerances
+    ref, inp, r = _run(1, parity=False)
+    for k in range(int(ref["last"]) + 1):
+        st = r.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k])
+        ms = np.array(st["macro_stress"])
+        e_ms = np.abs(ms - ref["macro_stress"][k]).max() / np.abs(ref["macro_stress"][k]).max()
+        print(f"  inc {k}: krylov {st['krylov_iters']} macro stress {e_ms:.2e}", flush=True)
+        assert e_ms <= 1e-4
+    r.close()
