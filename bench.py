@@ -116,12 +116,13 @@ def measured_traffic(kernel, n):
     return float(val.group(1)) * 1e6
 
 
-def cpu_baseline(w, inp, gpu_stats, n_apply=6, stride=64):
+def cpu_baseline(w, inp, gpu_stats, first, n_apply=6, stride=64):
     """The CPU oracle on a bounded sample of the same workload, scaled to voxel-iters/s.
 
     Sample: (a) n_apply applications of the oracle's preconditioned momentum operator on
     the full grid with the elastic tangent of the microstructure, and (b) the oracle's
-    return map on every stride-th voxel at the first increment's strain.  The oracle
+    return map on every stride-th voxel at the macroscopic strain of the first timed
+    increment (increment index ``first``).  The oracle
     time of one increment is projected with the operator-application and
     constitutive-call counts of the GPU FP64 increments (same tolerances), and the
     rate is voxels x operator applications / projected time.
@@ -138,7 +139,7 @@ def cpu_baseline(w, inp, gpu_stats, n_apply=6, stride=64):
     t_apply = (time.perf_counter() - t0) / n_apply
     sub = np.arange(0, M, stride)
     eps = np.zeros((len(sub), 3, 3))
-    eps[:, 1, 1] = inp["deps"][0]
+    eps[:, 1, 1] = np.sum(inp["deps"][:first + 1])
     from oracle import return_map
     t = o.tab
     gid = o.gid[sub]
@@ -238,7 +239,7 @@ def main():
     if not a.no_material:
         out["material"] = material_leg(RVE, RVE_FP64, torch)
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, inp, st64)
+        out["cpu_baseline"] = cpu_baseline(w, inp, st64, a.warmup)
     print(json.dumps(out), flush=True)
 
 
