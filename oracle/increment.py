@@ -1,7 +1,10 @@
 """One time increment by non-linear alternating minimisation (oracle).
 
 Algorithm 1 of the paper, small-strain form:
-    eps_0 = eps_t + d eps_bar (uniform),  phi_0 = phi_t
+    eps_0 = eps_t + d eps_bar (uniform; under mixed control only the strain-controlled
+            components move, the stress-controlled ones are unknowns of the momentum
+            Newton system with target macro stress = that of t plus the increment),
+    phi_0 = phi_t
     repeat  i = 1, 2, ...
         eps_i  = momentum balance by Newton-Krylov at phi_{i-1}, from eps_{i-1}
         phi_i  = phase-field balance at eps_i, then phi_i = max(phi_i, phi_t)
@@ -92,6 +95,7 @@ class OracleRVE:
         self.trig = np.zeros(M, dtype=bool)
         self.sig = np.zeros((M, 6))         # effective stress (Mandel), last converged
         self.sig_ws = None                  # warm start of the return map
+        self.macro_sig = np.zeros(6)        # macro stress mean(g sigma) at t
         self.history = []
 
     # --- per-voxel constitutive update --------------------------------------------
@@ -107,13 +111,23 @@ class OracleRVE:
         return (1.0 - phi) ** 2 + self.d["k_res"]
 
     # --- Algorithm 1 -------------------------------------------------------------
-    def step(self, deps6, dt):
+    def step(self, deps6, dt, dsig6=None, stress_mask=0):
+        """One increment.  Components c (order xx, yy, zz, yz, xz, xy) with bit c set in
+        stress_mask follow the macro stress increment dsig6[c] (mixed control); the
+        others follow the macro strain increment deps6[c]."""
         d = self.d
         grid = self.grid
         t = self.tab
         gid = self.gid
         stats = {}
-        dE = from_tensor6(np.asarray(deps6, dtype=float))[0]
+        free = [c for c in range(6) if (stress_mask >> c) & 1]
+        de6 = np.array(deps6, dtype=float)
+        de6[free] = 0.0
+        dE = from_tensor6(de6)[0]
+        target = self.macro_sig.copy()
+        if free:
+            target[free] += np.asarray(dsig6, dtype=float)[free]
+        tgtM = to_mandel2(from_tensor6(target))[0]
         eps_t = self.eps.copy()
         phi_t = self.phi.copy()
         eps_prev = eps_t + dE[None]
@@ -122,7 +136,8 @@ class OracleRVE:
         for it in range(d["max_stag"]):
             eps_i, sig, dgam = solve_mechanics(grid, eps_prev, eps_t, self.degradation(phi_prev),
                                                constit, d["tol_newton"], d["tol_lin"],
-                                               d["max_newton"], d["max_krylov"], stats)
+                                               d["max_newton"], d["max_krylov"], stats,
+                                               free=free, sig_target=tgtM)
             epsp_tr = self.epsp + from_mandel2(np.einsum("ma,mai->mi", dgam, t.P[gid]))
             tau = np.einsum("mai,mi->ma", t.P[gid], sig)
             wp_tr = self.Wp + (tau * dgam).sum(1)
@@ -167,6 +182,7 @@ class OracleRVE:
         gphi = self.degradation(self.phi)
         stats["macro_stress"] = tensor6((gphi[:, None, None] * from_mandel2(sig)).mean(0,
                                         keepdims=True))[0]
+        self.macro_sig = stats["macro_stress"].copy()
         stats["macro_strain"] = tensor6(self.eps.mean(0, keepdims=True))[0]
         stats["max_phi"] = float(self.phi.max())
         stats["n_trig"] = int(self.trig.sum())

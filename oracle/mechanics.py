@@ -20,6 +20,18 @@ Readings:
   state is the same equilibrium, and full steps are taken near it.
 * Newton stops when max|sym grad du| <= tol * max|eps_i - eps_t| (the paper's
   criterion, with the applied step).
+
+Mixed control (the DBFFT mixed extension the paper relies on, Sec. 3.1): for the
+macroscopic components in ``free`` (Mandel indices) the macro stress mean(g sigma) is
+prescribed (``sig_target``, Mandel) and the macro strain E_F is an unknown.  The Newton
+system gains those unknowns; with
+    eps = E + eps~(u),
+the linearised operator on (du, dE_F) is the Hessian of
+    Pi(u, E_F) = sum_v g w(eps) - N sig_target . E_F,
+    [ -div(gK : (eps~(du) + dE)) ;  sum_v (gK : (eps~(du) + dE))_F ],
+symmetric positive definite in the Euclidean inner product (spectral gradient and
+divergence are negative adjoints), preconditioned block-diagonally by the inverse
+acoustic tensor and (N Kbar_FF)^-1.
 """
 import numpy as np
 from scipy.sparse.linalg import LinearOperator, cg
@@ -55,35 +67,75 @@ def momentum_operator(grid, gK):
 
 
 def solve_mechanics(grid, eps0, eps_t, gphi, constit, tol_newton, tol_lin, max_newton,
-                    max_krylov, stats=None):
+                    max_krylov, stats=None, free=(), sig_target=None):
     """Equilibrated strain (M,3,3) starting from ``eps0``.
 
     constit(eps_mandel) -> (sig_mandel, dgam, K_mandel, w) is the per-voxel update.
-    gphi: (M,) degradation g(phi).  Returns (eps, sig_mandel, dgam) at the solution.
+    gphi: (M,) degradation g(phi).  free: Mandel indices of the macro components under
+    stress control, sig_target: (6,) Mandel macro stress they must reach.  Returns
+    (eps, sig_mandel, dgam) at the solution.
     """
     n = grid.n
+    free = np.asarray(sorted(free), dtype=np.int64)
+    nf = len(free)
     gphi = np.asarray(gphi, dtype=np.float64)
     eps = np.array(eps0, dtype=np.float64, copy=True)
     sigM, dgam, KM, w = constit(to_mandel2(eps))
-    Pi = np.mean(gphi * w)
+    M = len(gphi)
+    tgt = np.zeros(6) if sig_target is None else np.asarray(sig_target, dtype=np.float64)
+    # external work of the prescribed macro stress: - N sig_target . E_F, as a mean
+    ext = lambda e: -tgt[free] @ to_mandel2(e).mean(0)[free] if nf else 0.0
+    Pi = np.mean(gphi * w) + ext(eps)
     for it in range(max_newton):
-        matvec, prec, count = momentum_operator(grid, gphi[:, None, None] * KM)
+        gKM = gphi[:, None, None] * KM
+        matvec, prec, count = momentum_operator(grid, gKM)
         gsig = grid.to_grid(gphi[:, None, None] * from_mandel2(sigM))
         rhs = grid.ifft(grid.div_hat(grid.fft(gsig))).ravel()
-        N = rhs.size
-        A = LinearOperator((N, N), matvec=matvec, dtype=np.float64)
-        P = LinearOperator((N, N), matvec=prec, dtype=np.float64)
-        du, info = cg(A, rhs, rtol=tol_lin, atol=0.0, maxiter=max_krylov, M=P)
+        Nu = rhs.size
+        if nf:
+            sumK = gKM.sum(0)
+            Kff_inv = np.linalg.inv(sumK[np.ix_(free, free)])
+            gsigM = gphi[:, None] * sigM
+            rhs = np.concatenate([rhs, -(gsigM.sum(0)[free] - M * tgt[free])])
+            gK_g = grid.to_grid(gKM)
+
+            def mv(x, matvec=matvec, gKM=gKM, gK_g=gK_g):
+                u, dE = x[:Nu], x[Nu:]
+                E6 = np.zeros(6)
+                E6[free] = dE
+                # fluctuation rows: -div(gK : (eps~(u) + dE)) = matvec(u) - div(gK : dE)
+                sE = from_mandel2(np.einsum("...ij,j->...i", gK_g, E6))
+                fl = matvec(u) - grid.ifft(grid.div_hat(grid.fft(sE))).ravel()
+                de = grid.to_flat(grid.ifft(grid.sym_grad_hat(grid.fft(u.reshape(n + (3,))))))
+                tot = to_mandel2(de) + E6[None]
+                mac = np.einsum("mij,mj->i", gKM, tot)[free]
+                return np.concatenate([fl, mac])
+
+            def pc(x, prec=prec, Kff_inv=Kff_inv):
+                return np.concatenate([prec(x[:Nu]), Kff_inv @ x[Nu:]])
+
+            A = LinearOperator((Nu + nf, Nu + nf), matvec=mv, dtype=np.float64)
+            P = LinearOperator((Nu + nf, Nu + nf), matvec=pc, dtype=np.float64)
+        else:
+            A = LinearOperator((Nu, Nu), matvec=matvec, dtype=np.float64)
+            P = LinearOperator((Nu, Nu), matvec=prec, dtype=np.float64)
+        sol, info = cg(A, rhs, rtol=tol_lin, atol=0.0, maxiter=max_krylov, M=P)
         if info != 0:
             raise RuntimeError(f"Krylov solve did not converge (info={info})")
+        du = sol[:Nu]
         de = grid.to_flat(grid.ifft(grid.sym_grad_hat(grid.fft(du.reshape(n + (3,))))))
+        if nf:
+            E6 = np.zeros(6)
+            E6[free] = sol[Nu:]
+            de = de + from_mandel2(E6[None])
         # backtracking on the incremental energy along de
-        slope = np.mean(gphi * np.einsum("mi,mi->m", sigM, to_mandel2(de)))
+        slope = np.mean(gphi * np.einsum("mi,mi->m", sigM, to_mandel2(de))) + \
+            (ext(de) if nf else 0.0)
         t = 1.0
         for _ls in range(40):
             trial = eps + t * de
             s_t, dg_t, K_t, w_t = constit(to_mandel2(trial))
-            Pi_t = np.mean(gphi * w_t)
+            Pi_t = np.mean(gphi * w_t) + ext(trial)
             if Pi_t - Pi <= 1e-4 * t * slope + 1e-13 * abs(Pi):
                 break
             t *= 0.5
