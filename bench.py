@@ -13,9 +13,10 @@ included).  Inputs are resident on the GPU before timing starts.
 
 Printed: one JSON line with the FP64 rate, the mixed-precision rate and its macro
 stress error against the FP64 run, the roofline of the dominant operator kernel
-(HIP events on the library's stream), the FP64 rate of the same grid with the paper's
-thermally activated flow rule and Table 1 material in yielding increments, and the CPU
-oracle timed on a bounded sample.
+(HIP events on the library's stream), the FP64 rate of the same increments under
+uniaxial stress (mixed macroscopic control), the FP64 rate of the same grid with the
+paper's thermally activated flow rule and Table 1 material in yielding increments, and
+the CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -42,23 +43,26 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-material", action="store_true",
                     help="skip the thermally-activated-flow leg (Table 1 material)")
+    ap.add_argument("--no-stress-control", action="store_true",
+                    help="skip the uniaxial-stress (mixed control) leg")
     ap.add_argument("--pass-reps", type=int, default=20)
     return ap.parse_args()
 
 
-def run_leg(RVE, precision, desc, inp, warmup, steps, torch):
+def run_leg(RVE, precision, desc, inp, warmup, steps, torch, stress_mask=0):
     r = RVE(desc, precision)
     r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
     macro = []
+    kw = dict(dsig6=np.zeros(6), stress_mask=stress_mask) if stress_mask else {}
     for k in range(warmup):
-        st = r.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k])
+        st = r.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k], **kw)
         macro.append(st["macro_stress"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     kry = 0
     stats = []
     for k in range(warmup, warmup + steps):
-        st = r.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k])
+        st = r.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k], **kw)
         kry += st["krylov_iters"]
         stats.append(st)
         macro.append(st["macro_stress"])
@@ -184,6 +188,20 @@ def material_leg(RVE, precision, torch, name="cmsx4-laguerre-128-g512", warmup=2
             "constitutive_ms": round(e0.elapsed_time(e1) / 5, 4)}
 
 
+def stress_control_leg(RVE, precision, w, inp, warmup, steps, torch):
+    """The headline increments under uniaxial stress: the macro yy strain follows the
+    load, every other macro stress component is held at zero (mixed control)."""
+    r, dt, kry, stats, macro = run_leg(RVE, precision, w.desc(), inp, warmup, steps, torch,
+                                       stress_mask=0b111101)
+    r.close()
+    lat = np.abs(macro[:, [0, 2, 3, 4, 5]]).max() / np.abs(macro[:, 1]).max()
+    return {"control": "uniaxial stress along y (mixed: yy strain, other macro stresses 0)",
+            "value": round(w.nvox * kry / dt, 1), "unit": "voxel-iters/s",
+            "ms_per_step": round(1e3 * dt / steps, 2), "krylov_iters": kry,
+            "newton_iters": int(sum(x["newton_iters"] for x in stats)),
+            "max_lateral_macro_stress_rel": float(lat)}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -236,6 +254,8 @@ def main():
                         "macro_stress_rel_err_vs_fp64": float(err.max()),
                         "passes": {k: {"ms": round(v["ms"], 5), "GB/s": round(v["gbs"], 1)}
                                    for k, v in p32.items()}}
+    if not a.no_stress_control:
+        out["stress_control"] = stress_control_leg(RVE, RVE_FP64, w, inp, a.warmup, a.steps, torch)
     if not a.no_material:
         out["material"] = material_leg(RVE, RVE_FP64, torch)
     if not a.no_cpu:

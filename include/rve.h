@@ -148,6 +148,20 @@ int rve_set_microstructure(struct rve_s* h, const int32_t* grain_of_voxel, int32
  * RVE_E_STATE (no microstructure), RVE_E_NOCONV, RVE_E_DEVICE. */
 int rve_step_increment(struct rve_s* h, const double deps_macro[6], double dt, rve_stats* st);
 
+/* One load increment under mixed macroscopic control (the DBFFT mixed extension the
+ * paper relies on, Sec. 3.1; e.g. uniaxial stress: every component but one stress
+ * controlled).  Components c (order xx, yy, zz, yz, xz, xy; tensor components) with
+ * bit c of stress_mask set follow the macro stress: the volume average of g(phi) sigma
+ * reaches that of time t plus dsig_macro[c]; the others follow the macro strain
+ * increment deps_macro[c] as in rve_step_increment, which is this call with
+ * stress_mask 0.  The stress-controlled macro strain components become unknowns of
+ * the momentum Newton-Krylov system (its operator stays symmetric positive definite).
+ * dsig_macro may be NULL when stress_mask is 0.  Same state semantics and errors as
+ * rve_step_increment; RVE_E_ARG for a mask outside 0..63 or a non-finite increment. */
+int rve_step_increment_mixed(struct rve_s* h, const double deps_macro[6],
+                             const double dsig_macro[6], int32_t stress_mask, double dt,
+                             rve_stats* st);
+
 /* Copy the fields selected by field_mask to host_out (n_doubles capacity), each as
  * SoA components of N values in increasing bit order.  Errors: RVE_E_ARG if the
  * buffer is too small, RVE_E_STATE before rve_set_microstructure. */

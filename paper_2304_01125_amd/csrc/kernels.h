@@ -113,7 +113,8 @@ void launch_div(const Plans& p, const cplx<R>* s, long long scs, cplx<R>* out, l
                 double sign, hipStream_t st, const double* stop = nullptr);
 template <typename R>
 int launch_precond(const Plans& p, const cplx<R>* r, cplx<R>* z, long long cs, const double* kbar21,
-                   double* partial, hipStream_t st, const double* stop = nullptr);
+                   double* partial, hipStream_t st, const double* stop = nullptr,
+                   const double* m0 = nullptr);
 // Fused conjugate-gradient kernels (spectral.hip):
 // p = z + (sc[ia]/sc[ib]) p, then e = sym(i xi~ (x) p)
 template <typename R>
@@ -146,12 +147,14 @@ int launch_zdiv_fwd(const Plans& p, const cplx<R>* s, cplx<R>* q, const cplx<R>*
 // block 0 stores the sum in sc[ipq], the breakdown flag in sc[iflag] and counts the
 // iteration in sc[iiter]); otherwise <p, q> is read from sc[ipq].  max_blocks bounds the
 // grid (and so the partials).
+// With m0 set (mixed macroscopic control) the zero bin holds the macro unknowns: it is
+// not projected and z(0) = m0 r(0) (6 x 6 on the bin's six reals).
 template <typename R>
 int launch_cg_step(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, const cplx<R>* q,
                    cplx<R>* z, long long cs, const double* kbar21, double* sc, int cur, int ipq,
                    double* partial, hipStream_t st, const double* stop,
                    const double* pq_part = nullptr, int nb_pq = 0, int iflag = 0, int iiter = 0,
-                   int max_blocks = 1 << 30);
+                   int max_blocks = 1 << 30, const double* m0 = nullptr);
 // Hermitian projection of the self-conjugate x-planes (spectra of real fields)
 template <typename R>
 void launch_herm_proj(const Plans& p, cplx<R>* v, long long cs, int ncomp, hipStream_t st,
@@ -162,6 +165,31 @@ void launch_pf_scale(const Plans& p, cplx<R>* d, double ell, double scale, hipSt
 template <typename R>
 void launch_curl_reg(const Plans& p, cplx<R>* b9, long long cs, double ell_fp, double scale,
                      hipStream_t st);
+
+// --- mixed strain/stress macroscopic control (macro.hip) --------------------------------
+// Six doubles passed by value to a kernel.
+struct Six6 {
+  double v[6];
+};
+// e_c += s E_c on the stress-controlled components (mask bit c, order xx yy zz yz xz xy),
+// E the Mandel macro unknowns in the zero bin of pv; nz = 1: at the zero bin, nz = N3: along
+// the (0, 0) z column (z still spatial, zstride apart).  de_out: (s/N) E, or nullptr.
+template <typename R>
+void launch_macro_strain(cplx<R>* e, long long ecs, const cplx<R>* pv, long long pcs, double s,
+                         double de_scale, int mask, int nz, long long zstride, double* de_out,
+                         hipStream_t st, const double* stop = nullptr);
+// q(0) = s sigma^_M(0) on the stress-controlled components, and the zero-bin term of
+// <p, q> at pq_out (sigma^(0): sum of the (0, 0) z column for nz = N3, the zero bin for 1).
+template <typename R>
+void launch_macro_stress(const cplx<R>* sg, long long scs, cplx<R>* q, const cplx<R>* pv,
+                         long long cs, double s, int mask, int nz, long long zstride,
+                         double* pq_out, hipStream_t st, const double* stop = nullptr);
+// b(0) = -s (sigma^_M(0) - n sigma*_M) from the full spectrum of g sigma.
+template <typename R>
+void launch_macro_rhs(const cplx<R>* sg, long long scs, cplx<R>* b, long long cs, double s,
+                      double n, const double tgt[6], int mask, hipStream_t st);
+// m0 = (s2 Kbar_FF)^-1 (36 doubles, zero outside the stress-controlled block)
+void launch_macro_prec(const double* kbar21, double s2, int mask, double* m0, hipStream_t st);
 
 // --- voxel kernels (voxel.hip) -------------------------------------------------------
 // Per-grain table: GT_STRIDE doubles per grain.

@@ -241,6 +241,10 @@ struct rve_s {
   // launches of an iteration depend on the handle and the parity only)
   bool use_graphs = true;
   hipGraphExec_t cg_exec[2] = {nullptr, nullptr};
+  int graph_mask = 0;     // stress-control mask the captured graphs were built for
+  // macro stress and strain at time t (tensor components), the reference of the next
+  // increment's stress-controlled components
+  double msig_t[6] = {0, 0, 0, 0, 0, 0}, meps_t[6] = {0, 0, 0, 0, 0, 0};
   double* hs = nullptr;   // pinned host scalars
   bool micro = false;
   int n_grains = 0;
@@ -255,7 +259,9 @@ enum { SC_K = 0,        // 28 constitutive sums (21 gK, g w, 6 g sigma)
        SC_FLAG = 61, SC_ITER = 62, SC_TOL2 = 63,
        SC_ZERO = 80, SC_ONE = 81, SC_RRN = 82, SC_RZN = 83,
        SC_MISC = 64,    // generic reduce outputs (16)
-       SC_N = 96 };
+       SC_M0 = 96,      // 36: macro-block preconditioner (mixed control)
+       SC_DE = 132,     // 6: macro strain increment of a Newton step (mixed control)
+       SC_N = 144 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -372,6 +378,12 @@ struct Ops {
   C* v(int i) { return (C*)h->cg[i]; }
   R* gK() { return (R*)h->gK; }
 
+  // mixed macroscopic control: stress-controlled components (bit c for xx yy zz yz xz
+  // xy; 0 = strain control) and the scale s of the macro unknowns in the zero bin
+  int mask = 0;
+  double s_mac = 0.0;
+  const double* m0() const { return mask ? h->scal + SC_M0 : nullptr; }
+
   explicit Ops(rve_s* hh) : h(hh), st(hh->st), N(hh->g.nvox), NH(hh->g.nspec) { W = (C*)h->spec; }
 
   // forward 3-D real FFT of ncomp real comps (stride in_cs) into spec comps
@@ -449,7 +461,7 @@ struct Ops {
     HIPCHK(hipMemcpyAsync(r, b, bytes, hipMemcpyDeviceToDevice, st));
     int nb = launch_sdot<R>(h->pl, b, b, NH, 3, h->partial, st);
     launch_reduce(h->partial, nb, 1, 0, sc + SC_BB, st);
-    nb = launch_precond<R>(h->pl, r, z, NH, sc + SC_KBAR, h->partial, st);
+    nb = launch_precond<R>(h->pl, r, z, NH, sc + SC_KBAR, h->partial, st, nullptr, m0());
     launch_reduce(h->partial, nb, 1, 0, sc + SC_RZ0, st);
     int rc = sync_read(h, SC_BB, 1);
     if (rc) return rc;
@@ -468,6 +480,13 @@ struct Ops {
     // right-hand side is no longer needed once r = b): each iteration reads p_old and
     // writes p_new while other blocks still read p_old.
     const bool fz = fused_z_available<R>(h->pl);
+    // the captured graphs hold the macro launches of one stress-control mask
+    if (h->graph_mask != mask) {
+      for (auto& ex : h->cg_exec)
+        if (ex) { (void)hipGraphExecDestroy(ex); ex = nullptr; }
+      h->graph_mask = mask;
+    }
+    const long long zst = (long long)h->g.n1h * h->g.n2;   // z stride of the half spectrum
     // With the fused z passes an iteration is six launches: the convergence test of the
     // previous iteration runs inside the inverse z pass and the sum of <p, q> inside the
     // CG step (each block reduces the previous kernel's partials itself).
@@ -486,18 +505,26 @@ struct Ops {
         C* pk = (k & 1) ? p : b;
         if (k == 0) launch_zgrad_inv<R>(h->pl, z, pold, pk, NH, sc, ia, ib, W, st, stop);
         else launch_zgrad_inv<R>(h->pl, z, pold, pk, NH, sc, ia, ib, W, st, stop, check_of(k - 1));
+        if (mask)   // macro strain along the (0, 0) z column (z already inverse transformed)
+          launch_macro_strain<R>(W, NH, pk, NH, s_mac, 0.0, mask, h->g.n3, zst, nullptr, st, stop);
         launch_fft_yz<R>(h->pl, W, NH, 6, 1, true, st, stop);
         launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
         launch_fft_yz<R>(h->pl, W, NH, 6, 1, false, st, stop);
         // q = -i xi~ . sigma^ with the partials of <p, q>; the step sums them
-        const int nbd = launch_zdiv_fwd<R>(h->pl, W, q, pk, NH, h->partial, st, stop);
+        int nbd = launch_zdiv_fwd<R>(h->pl, W, q, pk, NH, h->partial, st, stop);
+        if (mask) {  // q(0) from the macro stress (z still spatial), its term of <p, q>
+          launch_macro_stress<R>(W, NH, q, pk, NH, s_mac, mask, h->g.n3, zst, h->partial + nbd, st,
+                                 stop);
+          ++nbd;
+        }
         nb_cg = launch_cg_step<R>(h->pl, x, r, pk, q, z, NH, sc + SC_KBAR, sc, cur, SC_PQ,
                                   cg_part, st, stop, h->partial, nbd, SC_FLAG, SC_ITER,
-                                  kCgMaxBlocks);
+                                  kCgMaxBlocks, m0());
         return;
       }
       // unfused operator (grids without a register DFT length)
       launch_grad_cgp<R>(h->pl, p, z, NH, sc, ia, ib, W, st, stop);
+      if (mask) launch_macro_strain<R>(W, NH, p, NH, s_mac, 0.0, mask, 1, 0, nullptr, st, stop);
       launch_fft_yz<R>(h->pl, W, NH, 6, 2, true, st, stop);
       launch_fft_yz<R>(h->pl, W, NH, 6, 1, true, st, stop);
       launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
@@ -505,10 +532,14 @@ struct Ops {
       launch_fft_yz<R>(h->pl, W, NH, 6, 2, false, st, stop);
       // q = -i xi~ . sigma^ and <p, q> into sc[SC_PQ] (flag 2 if not positive)
       nb = launch_div_dot<R>(h->pl, W, q, p, NH, h->partial, st, stop);
+      if (mask) {
+        launch_macro_stress<R>(W, NH, q, p, NH, s_mac, mask, 1, 0, h->partial + nb, st, stop);
+        ++nb;
+      }
       launch_reduce_pq(h->partial, nb, sc, SC_PQ, SC_FLAG, st);
       // x, r, z updates, <r, r>, <r, z> and the convergence test
       nb = launch_cg_step<R>(h->pl, x, r, p, q, z, NH, sc + SC_KBAR, sc, cur, SC_PQ,
-                             h->partial, st, stop);
+                             h->partial, st, stop, nullptr, 0, 0, 0, 1 << 30, m0());
       launch_reduce_check(h->partial, nb, sc, SC_ITER, prv, SC_RRN, SC_FLAG, SC_TOL2, st);
     };
     int queued = 0, batch = 4, it_ref = 0;
@@ -571,12 +602,35 @@ struct Ops {
 };
 
 template <typename R>
-int run_increment(rve_s* h, const double de[6], double dt, rve_stats* out) {
+int run_increment(rve_s* h, const double de_in[6], const double* dsig, int mask, double dt,
+                  rve_stats* out) {
   Ops<R> o(h);
   o.cur_dt = dt;
   hipStream_t st = h->st;
   const long long N = h->g.nvox;
   const double invN = 1.0 / (double)N;
+  // mixed control: the stress-controlled components of the macro strain are unknowns;
+  // their target macro stress is that of t plus the increment (Mandel values)
+  static constexpr double kRt2 = 1.41421356237309504880;
+  double de[6], tgt[6], Ecur[6];
+  for (int c = 0; c < 6; ++c) {
+    const bool f = (mask >> c) & 1;
+    const double w = c < 3 ? 1.0 : kRt2;
+    de[c] = f ? 0.0 : de_in[c];
+    tgt[c] = f ? w * (h->msig_t[c] + dsig[c]) : 0.0;
+    Ecur[c] = f ? w * h->meps_t[c] : 0.0;      // stress-controlled macro strain (Mandel)
+  }
+  o.mask = mask;
+  {
+    const double lmax = h->d.h * (double)std::max(h->g.n1, std::max(h->g.n2, h->g.n3));
+    o.s_mac = (double)N * 6.283185307179586476925286766559 / lmax;
+  }
+  // external work of the prescribed macro stress per voxel, - sigma*_F . E_F
+  auto ext = [&](const double* E, double t, const double* dE) {
+    double a = 0.0;
+    for (int c = 0; c < 6; ++c) a -= tgt[c] * (E[c] + (dE ? t * dE[c] : 0.0));
+    return a;
+  };
   rve_stats s;
   std::memset(&s, 0, sizeof(s));
   const double t0 = now_ms();
@@ -599,27 +653,39 @@ int run_increment(rve_s* h, const double de[6], double dt, rve_stats* out) {
     o.constitutive(nullptr, 0.0, h->phi_prev);
     if ((rc = sync_read(h, SC_K, 28))) return rc;
     s.ms_constitutive += now_ms() - tc;
-    double Pi = h->hs[SC_K + 21] * invN;
+    double Pi = h->hs[SC_K + 21] * invN + ext(Ecur, 0.0, nullptr);
     bool newton_ok = false;
     for (int nit = 0; nit < h->d.max_newton; ++nit) {
       s.newton_iters++;
       double tk = now_ms();
       o.kbar();
+      if (mask) launch_macro_prec(h->scal + SC_KBAR, o.s_mac * o.s_mac, mask, h->scal + SC_M0, st);
       // c = i xi~ . F{ g sigma }
       o.fwd(h->sig, true, N, 6, o.W, h->phi_prev);
       launch_div<R>(h->pl, o.W, o.NH, o.v(5), o.NH, 1.0, st);
       launch_herm_proj<R>(h->pl, o.v(5), o.NH, 3, st);
+      // zero bin: -s (sum g sigma - N sigma*) on the stress-controlled components
+      if (mask) launch_macro_rhs<R>(o.W, o.NH, o.v(5), o.NH, o.s_mac, (double)N, tgt, mask, st);
       int kit = 0;
       rc = o.pcg(kit);
       s.krylov_iters += kit;
       if (rc) { s.ms_mech_krylov += now_ms() - tk; goto fail_out; }
       // deps = F^-1{ sym(i xi~ (x) du) }
       launch_sym_grad<R>(h->pl, o.v(0), o.NH, o.W, o.NH, st);
+      if (mask)   // + the macro strain increment at the zero bin, recorded in SC_DE
+        launch_macro_strain<R>(o.W, o.NH, o.v(0), o.NH, o.s_mac, o.s_mac * invN, mask, 1, 0,
+                               h->scal + SC_DE, st);
       o.inv(o.W, 6, h->deps, true, N, invN, 0);
       launch_slope(N, h->sig, h->deps, h->phi_prev, h->d.k_res, h->partial, st);
       launch_reduce(h->partial, voxel_grid(N), 1, 0, h->scal + SC_MISC, st);
       if ((rc = sync_read(h, SC_MISC, 1))) return rc;
-      const double slope = h->hs[SC_MISC] * invN;
+      double slope = h->hs[SC_MISC] * invN;
+      double dE[6] = {0, 0, 0, 0, 0, 0};
+      if (mask) {
+        if ((rc = sync_read(h, SC_DE, 6))) return rc;
+        for (int c = 0; c < 6; ++c) dE[c] = h->hs[SC_DE + c];
+        slope += ext(dE, 0.0, nullptr);          // - sigma*_F . dE_F
+      }
       s.ms_mech_krylov += now_ms() - tk;
       // backtracking on the incremental energy
       tc = now_ms();
@@ -628,7 +694,7 @@ int run_increment(rve_s* h, const double de[6], double dt, rve_stats* out) {
       for (int ls = 0; ls < 40; ++ls) {
         o.constitutive(h->deps, t, h->phi_prev);
         if ((rc = sync_read(h, SC_K, 28))) return rc;
-        Pit = h->hs[SC_K + 21] * invN;
+        Pit = h->hs[SC_K + 21] * invN + ext(Ecur, t, dE);
         if (Pit - Pi <= 1e-4 * t * slope + 1e-13 * std::fabs(Pi)) { acc = true; break; }
         t *= 0.5;
         s.ls_cuts++;
@@ -636,6 +702,7 @@ int run_increment(rve_s* h, const double de[6], double dt, rve_stats* out) {
       s.ms_constitutive += now_ms() - tc;
       if (!acc) { rc = fail(RVE_E_NOCONV, "Newton line search failed"); goto fail_out; }
       Pi = Pit;
+      for (int c = 0; c < 6; ++c) Ecur[c] += t * dE[c];
       launch_eps_update(N, h->eps, h->deps, t, h->eps_t, h->partial, st);
       launch_reduce(h->partial, voxel_grid(N), 2, 1, h->scal + SC_MISC, st);
       if ((rc = sync_read(h, SC_MISC, 2))) return rc;
@@ -764,6 +831,10 @@ int run_increment(rve_s* h, const double de[6], double dt, rve_stats* out) {
     s.n_triggered = h->hs[SC_MISC + 12];
     s.max_phi = h->hs[SC_MISC + 13];
     s.max_phi_slip = h->hs[SC_MISC + 14];
+    for (int c = 0; c < 6; ++c) {
+      h->msig_t[c] = s.macro_stress[c];
+      h->meps_t[c] = s.macro_strain[c];
+    }
     s.ms_commit = now_ms() - tcm;
   }
   s.ms_total = now_ms() - t0;
@@ -916,21 +987,34 @@ int rve_set_microstructure(rve_s* h, const int32_t* grain, int32_t n_grains, con
   for (double* p : zero1) launch_zero(p, N * 8, st);
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
+  for (int c = 0; c < 6; ++c) h->msig_t[c] = h->meps_t[c] = 0.0;
   h->micro = true;
   h->n_grains = n_grains;
   return RVE_OK;
 }
 
-int rve_step_increment(rve_s* h, const double deps[6], double dt, rve_stats* st) {
+int rve_step_increment_mixed(rve_s* h, const double deps[6], const double dsig[6],
+                             int32_t stress_mask, double dt, rve_stats* st) {
   if (!h || !deps) return fail(RVE_E_ARG, "null argument");
   if (!h->micro) return fail(RVE_E_STATE, "microstructure not set");
-  for (int c = 0; c < 6; ++c)
-    if (!std::isfinite(deps[c])) return fail(RVE_E_ARG, "non-finite strain increment");
+  if (stress_mask < 0 || stress_mask > 63) return fail(RVE_E_ARG, "stress_mask outside 0..63");
+  if (stress_mask && !dsig) return fail(RVE_E_ARG, "null stress increment");
+  double ds[6] = {0, 0, 0, 0, 0, 0};
+  for (int c = 0; c < 6; ++c) {
+    const bool f = (stress_mask >> c) & 1;
+    if (f) ds[c] = dsig[c];
+    if (!std::isfinite(f ? ds[c] : deps[c])) return fail(RVE_E_ARG, "non-finite macro increment");
+  }
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RVE_E_ARG, "dt must be positive and finite");
   g_err.clear();
   int cur = -1;
   if (hipGetDevice(&cur) == hipSuccess && cur != h->device) HIPCHK(hipSetDevice(h->device));
-  return h->f64 ? run_increment<double>(h, deps, dt, st) : run_increment<float>(h, deps, dt, st);
+  return h->f64 ? run_increment<double>(h, deps, ds, stress_mask, dt, st)
+                : run_increment<float>(h, deps, ds, stress_mask, dt, st);
+}
+
+int rve_step_increment(rve_s* h, const double deps[6], double dt, rve_stats* st) {
+  return rve_step_increment_mixed(h, deps, nullptr, 0, dt, st);
 }
 
 int rve_pool_step(rve_s* const* hs, int32_t n, const double* deps, const double* dt,

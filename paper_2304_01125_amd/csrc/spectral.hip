@@ -148,6 +148,25 @@ __device__ __forceinline__ void load_kbar4(double* K4, const double* __restrict_
   }
 }
 
+// Zero bin under mixed macroscopic control: zo = m0 ri on the bin's six reals
+// (Mandel macro components xx, yy, zz, yz, xz, xy held as x: (xx, xy), y: (yy, yz),
+// z: (zz, xz)).
+template <typename R>
+__device__ __forceinline__ void apply_M0(const double* __restrict__ m0, const cplx<R> ri[3],
+                                         cplx<R> zo[3]) {
+  const double rm[6] = {(double)ri[0].x, (double)ri[1].x, (double)ri[2].x,
+                        (double)ri[1].y, (double)ri[2].y, (double)ri[0].y};
+  double zm[6];
+  for (int i = 0; i < 6; ++i) {
+    double a = 0.0;
+    for (int j = 0; j < 6; ++j) a += m0[i * 6 + j] * rm[j];
+    zm[i] = a;
+  }
+  zo[0] = cplx<R>{(R)zm[0], (R)zm[5]};
+  zo[1] = cplx<R>{(R)zm[1], (R)zm[3]};
+  zo[2] = cplx<R>{(R)zm[2], (R)zm[4]};
+}
+
 // zo = [t . K . t]^-1 ri (zero where t = 0), t = xi~ of the bin.
 template <typename R>
 __device__ __forceinline__ void apply_M(const double t[3], const double* K4, const cplx<R> ri[3],
@@ -271,7 +290,8 @@ k_cg_step(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __res
           const cplx<R>* __restrict__ qv, cplx<R>* __restrict__ z, long long cs,
           const double* __restrict__ kbar21, double* __restrict__ sc, int cur, int ipq,
           Grid g, double* __restrict__ partial, const double* __restrict__ stop,
-          const double* __restrict__ pq_part, int nb_pq, int iflag, int iiter) {
+          const double* __restrict__ pq_part, int nb_pq, int iflag, int iiter,
+          const double* __restrict__ m0) {
   if (stop && *stop != 0.0) return;
   __shared__ double K4[81];
   __shared__ double red[16];
@@ -298,7 +318,8 @@ k_cg_step(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __res
     const Bin q = bin_of(b, g);
     const double t[3] = {freq(q.kx, g.n1, g.L1, true), freq(q.ky, g.n2, g.L2, true),
                          freq(q.kz, g.n3, g.L3, true)};
-    const bool selfconj = (q.kx == 0) || (even && q.kx == g.n1 / 2);
+    const bool mac = m0 && b == 0;           // macro unknowns: no projection, z = m0 r
+    const bool selfconj = !mac && ((q.kx == 0) || (even && q.kx == g.n1 / 2));
     const long long bp = selfconj ? partner_bin(q, g) : b;
     cplx<R> rv[3], zo[3];
     for (int c = 0; c < 3; ++c) {
@@ -318,7 +339,8 @@ k_cg_step(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __res
       r[i] = rr_;
       rv[c] = rr_;
     }
-    apply_M(t, K4, rv, zo);
+    if (mac) apply_M0(m0, rv, zo);
+    else apply_M(t, K4, rv, zo);
     double a = 0.0, bz = 0.0;
     for (int c = 0; c < 3; ++c) {
       z[c * cs + b] = zo[c];
@@ -347,21 +369,21 @@ template <typename R>
 int launch_cg_step(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, const cplx<R>* q,
                    cplx<R>* z, long long cs, const double* kbar21, double* sc, int cur, int ipq,
                    double* partial, hipStream_t st, const double* stop, const double* pq_part,
-                   int nb_pq, int iflag, int iiter, int max_blocks) {
+                   int nb_pq, int iflag, int iiter, int max_blocks, const double* m0) {
   const int nb = std::min(grid_for(p.g.nspec), max_blocks);
   hipLaunchKernelGGL((k_cg_step<R>), dim3(nb), dim3(256), 0, st, x, r, pv, q, z, cs, kbar21, sc,
-                     cur, ipq, p.g, partial, stop, pq_part, nb_pq, iflag, iiter);
+                     cur, ipq, p.g, partial, stop, pq_part, nb_pq, iflag, iiter, m0);
   return nb;
 }
 template int launch_cg_step<double>(const Plans&, cplx<double>*, cplx<double>*,
                                     const cplx<double>*, const cplx<double>*, cplx<double>*,
                                     long long, const double*, double*, int, int, double*,
                                     hipStream_t, const double*, const double*, int, int, int,
-                                    int);
+                                    int, const double*);
 template int launch_cg_step<float>(const Plans&, cplx<float>*, cplx<float>*, const cplx<float>*,
                                    const cplx<float>*, cplx<float>*, long long, const double*,
                                    double*, int, int, double*, hipStream_t, const double*,
-                                   const double*, int, int, int, int);
+                                   const double*, int, int, int, int, const double*);
 #define RVE_CG_INST(R)                                                                           \
   template void launch_grad_cgp<R>(const Plans&, cplx<R>*, const cplx<R>*, long long,             \
                                    const double*, int, int, cplx<R>*, hipStream_t, const double*); \
@@ -377,7 +399,7 @@ RVE_CG_INST(float)
 template <typename R>
 __global__ void __launch_bounds__(256) k_precond(const cplx<R>* __restrict__ r, cplx<R>* __restrict__ z, long long cs,
                           const double* __restrict__ kbar21, Grid g, double* __restrict__ partial,
-                          const double* __restrict__ stop) {
+                          const double* __restrict__ stop, const double* __restrict__ m0) {
   if (stop && *stop != 0.0) return;
   __shared__ double K4[81];
   __shared__ double red[1024 / 64];
@@ -399,7 +421,8 @@ __global__ void __launch_bounds__(256) k_precond(const cplx<R>* __restrict__ r, 
     const double t[3] = {freq(q.kx, g.n1, g.L1, true), freq(q.ky, g.n2, g.L2, true),
                          freq(q.kz, g.n3, g.L3, true)};
     cplx<R> ri[3] = {r[b], r[cs + b], r[2 * cs + b]};
-    if (q.kx == 0 || (g.n1 % 2 == 0 && q.kx == g.n1 / 2)) {
+    const bool mac = m0 && b == 0;           // macro unknowns: no projection, z = m0 r
+    if (!mac && (q.kx == 0 || (g.n1 % 2 == 0 && q.kx == g.n1 / 2))) {
       // self-conjugate x-planes: keep the Hermitian part r(k) = conj r(-k) only
       const long long bp = partner_bin(q, g);
       for (int c = 0; c < 3; ++c) {
@@ -408,7 +431,9 @@ __global__ void __launch_bounds__(256) k_precond(const cplx<R>* __restrict__ r, 
       }
     }
     cplx<R> zo[3] = {{0, 0}, {0, 0}, {0, 0}};
-    if (t[0] != 0.0 || t[1] != 0.0 || t[2] != 0.0) {
+    if (mac) {
+      apply_M0(m0, ri, zo);
+    } else if (t[0] != 0.0 || t[1] != 0.0 || t[2] != 0.0) {
       double A[3][3];
       for (int i = 0; i < 3; ++i)
         for (int k = i; k < 3; ++k) {
@@ -520,10 +545,10 @@ void launch_div(const Plans& p, const cplx<R>* s, long long scs, cplx<R>* out, l
 
 template <typename R>
 int launch_precond(const Plans& p, const cplx<R>* r, cplx<R>* z, long long cs, const double* kbar21,
-                   double* partial, hipStream_t st, const double* stop) {
+                   double* partial, hipStream_t st, const double* stop, const double* m0) {
   const int nb = grid_for(p.g.nspec);
   hipLaunchKernelGGL((k_precond<R>), dim3(nb), dim3(256), 0, st, r, z, cs, kbar21, p.g, partial,
-                     stop);
+                     stop, m0);
   return nb;
 }
 
@@ -547,7 +572,8 @@ void launch_curl_reg(const Plans& p, cplx<R>* b9, long long cs, double ell_fp, d
   template void launch_div<R>(const Plans&, const cplx<R>*, long long, cplx<R>*, long long,       \
                               double, hipStream_t, const double*);                               \
   template int launch_precond<R>(const Plans&, const cplx<R>*, cplx<R>*, long long,               \
-                                 const double*, double*, hipStream_t, const double*);            \
+                                 const double*, double*, hipStream_t, const double*,             \
+                                 const double*);                                                 \
   template void launch_pf_scale<R>(const Plans&, cplx<R>*, double, double, hipStream_t,          \
                                    const double*);                                               \
   template void launch_curl_reg<R>(const Plans&, cplx<R>*, long long, double, double, hipStream_t);

@@ -88,6 +88,9 @@ def load():
                                            _D, _D, _D]
     lib.rve_step_increment.restype = ctypes.c_int
     lib.rve_step_increment.argtypes = [_P, _D, ctypes.c_double, ctypes.POINTER(RveStats)]
+    lib.rve_step_increment_mixed.restype = ctypes.c_int
+    lib.rve_step_increment_mixed.argtypes = [_P, _D, _D, ctypes.c_int32, ctypes.c_double,
+                                             ctypes.POINTER(RveStats)]
     lib.rve_fields.restype = ctypes.c_int
     lib.rve_fields.argtypes = [_P, ctypes.c_uint32, _D, ctypes.c_size_t]
     lib.rve_fields_count.restype = ctypes.c_size_t
@@ -116,7 +119,7 @@ def load():
 def exported_symbols():
     """Names of the C ABI entry points (as declared in include/rve.h)."""
     return ["rve_footprint_bytes", "rve_create", "rve_set_microstructure", "rve_step_increment",
-            "rve_fields", "rve_fields_count", "rve_destroy", "rve_last_error", "rve_diag_rfft",
+            "rve_step_increment_mixed", "rve_fields", "rve_fields_count", "rve_destroy", "rve_last_error", "rve_diag_rfft",
             "rve_diag_irfft", "rve_diag_constitutive", "rve_diag_operator", "rve_diag_pass",
             "rve_pool_step"]
 
@@ -184,6 +187,15 @@ def rve_step_increment(h, deps6, dt):
     return rc, st.as_dict()
 
 
+def rve_step_increment_mixed(h, deps6, dsig6, stress_mask, dt):
+    de = np.ascontiguousarray(deps6, dtype=np.float64)
+    ds = np.ascontiguousarray(np.zeros(6) if dsig6 is None else dsig6, dtype=np.float64)
+    st = RveStats()
+    rc = load().rve_step_increment_mixed(h, _dptr(de), _dptr(ds), int(stress_mask), float(dt),
+                                         ctypes.byref(st))
+    return rc, st.as_dict()
+
+
 def rve_fields(h, mask, nvox):
     n = load().rve_fields_count(h, mask)
     out = np.empty(n, dtype=np.float64)
@@ -234,8 +246,13 @@ class RVE:
     def set_microstructure(self, grain, quat, tau_c0=None, phi0=None):
         rve_set_microstructure(self.h, grain, quat, tau_c0, phi0)
 
-    def step(self, deps6, dt, check=True):
-        rc, st = rve_step_increment(self.h, deps6, dt)
+    def step(self, deps6, dt, check=True, dsig6=None, stress_mask=0):
+        """One increment; components with bit c of stress_mask set follow the macro stress
+        increment dsig6[c] (mixed control), the others the strain increment deps6[c]."""
+        if stress_mask:
+            rc, st = rve_step_increment_mixed(self.h, deps6, dsig6, stress_mask, dt)
+        else:
+            rc, st = rve_step_increment(self.h, deps6, dt)
         st["status"] = rc
         if check:
             _check(rc)
