@@ -67,19 +67,19 @@ k_macro_strain(cplx<R>* __restrict__ e, long long ecs, const cplx<R>* __restrict
 // q(0) = s sigma^_M(0) on the stress-controlled components (0 on the others) and the
 // zero-frequency term of <p, q> at pq_out.  sigma^(0) is the sum of the (0, 0) z column
 // when z is still spatial (nz = N3), else the zero-frequency bin (nz = 1).
+// One wave per component: lanes take every 64th z, then a fixed-order shuffle sum.
 template <typename R>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(384)
 k_macro_stress(const cplx<R>* __restrict__ sg, long long scs, cplx<R>* __restrict__ q,
                const cplx<R>* __restrict__ pv, long long cs, double s, int mask, int nz,
                long long zstride, double* __restrict__ pq_out, const double* __restrict__ stop) {
   if (stop && *stop != 0.0) return;
   __shared__ double qm[6];
-  if (threadIdx.x < 6) {
-    const int c = threadIdx.x;
-    double sum = 0.0;
-    for (int z = 0; z < nz; ++z) sum += (double)sg[c * scs + (long long)z * zstride].x;
-    qm[c] = ((mask >> c) & 1) ? s * sum * (c < 3 ? 1.0 : kS2) : 0.0;
-  }
+  const int c = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double sum = 0.0;
+  for (int z = lane; z < nz; z += 64) sum += (double)sg[c * scs + (long long)z * zstride].x;
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
+  if (lane == 0) qm[c] = ((mask >> c) & 1) ? s * sum * (c < 3 ? 1.0 : kS2) : 0.0;
   __syncthreads();
   if (threadIdx.x == 0) {
     double m[6], pq = 0.0;
@@ -107,41 +107,46 @@ k_macro_rhs(const cplx<R>* __restrict__ sg, long long scs, cplx<R>* __restrict__
   mput(b, cs, m);
 }
 
-// M0 = (s^2 Kbar_FF)^-1 on the stress-controlled components (6 x 6, zero elsewhere), by
-// Gauss-Jordan elimination with partial pivoting (Kbar_FF is symmetric positive definite).
+// M0 = (s^2 Kbar_FF)^-1 on the stress-controlled components (6 x 6, zero elsewhere): the
+// strain-controlled rows and columns are replaced by those of the identity, the 6 x 6 is
+// inverted by Gauss-Jordan elimination without pivoting (symmetric positive definite),
+// fully unrolled so that it stays in registers, and those rows and columns are cleared.
 __global__ void __launch_bounds__(64)
 k_macro_prec(const double* __restrict__ kbar21, double s2, int mask, double* __restrict__ m0) {
   if (threadIdx.x != 0) return;
-  int F[6], nf = 0;
-  for (int c = 0; c < 6; ++c)
-    if ((mask >> c) & 1) F[nf++] = c;
-  double A[6][12];
-  for (int i = 0; i < nf; ++i)
-    for (int j = 0; j < nf; ++j) {
-      A[i][j] = s2 * kbar21[pk6(F[i], F[j])];
-      A[i][6 + j] = (i == j) ? 1.0 : 0.0;
+  double A[6][6], B[6][6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const bool fi = (mask >> i) & 1, fj = (mask >> j) & 1;
+      A[i][j] = (fi && fj) ? s2 * kbar21[pk6(i, j)] : (i == j ? 1.0 : 0.0);
+      B[i][j] = (i == j) ? 1.0 : 0.0;
     }
-  for (int k = 0; k < nf; ++k) {
-    int piv = k;
-    for (int i = k + 1; i < nf; ++i)
-      if (fabs(A[i][k]) > fabs(A[piv][k])) piv = i;
-    if (piv != k)
-      for (int j = 0; j < 12; ++j) {
-        const double t = A[k][j];
-        A[k][j] = A[piv][j];
-        A[piv][j] = t;
-      }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
     const double d = 1.0 / A[k][k];
-    for (int j = 0; j < 12; ++j) A[k][j] *= d;
-    for (int i = 0; i < nf; ++i) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      A[k][j] *= d;
+      B[k][j] *= d;
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
       if (i == k) continue;
       const double f = A[i][k];
-      for (int j = 0; j < 12; ++j) A[i][j] -= f * A[k][j];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        A[i][j] -= f * A[k][j];
+        B[i][j] -= f * B[k][j];
+      }
     }
   }
-  for (int i = 0; i < 36; ++i) m0[i] = 0.0;
-  for (int i = 0; i < nf; ++i)
-    for (int j = 0; j < nf; ++j) m0[F[i] * 6 + F[j]] = A[i][6 + j];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      m0[i * 6 + j] = (((mask >> i) & 1) && ((mask >> j) & 1)) ? B[i][j] : 0.0;
 }
 
 template <typename R>
@@ -155,8 +160,8 @@ template <typename R>
 void launch_macro_stress(const cplx<R>* sg, long long scs, cplx<R>* q, const cplx<R>* pv,
                          long long cs, double s, int mask, int nz, long long zstride,
                          double* pq_out, hipStream_t st, const double* stop) {
-  hipLaunchKernelGGL((k_macro_stress<R>), dim3(1), dim3(64), 0, st, sg, scs, q, pv, cs, s, mask, nz,
-                     zstride, pq_out, stop);
+  hipLaunchKernelGGL((k_macro_stress<R>), dim3(1), dim3(384), 0, st, sg, scs, q, pv, cs, s, mask,
+                     nz, zstride, pq_out, stop);
 }
 template <typename R>
 void launch_macro_rhs(const cplx<R>* sg, long long scs, cplx<R>* b, long long cs, double s,

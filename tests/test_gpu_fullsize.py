@@ -83,3 +83,41 @@ def test_mixed_precision_at_full_size_reproduces_fp64_macro_stress():
     e_field = np.linalg.norm(fields[RVE_MIXED] - fields[RVE_FP64]) / np.linalg.norm(fields[RVE_FP64])
     print(f"  mixed vs FP64: macro stress {err:.2e}, stress field rel. L2 {e_field:.2e}", flush=True)
     assert err <= 1e-4
+
+
+def test_uniaxial_stress_at_full_size():
+    """Mixed control at the benchmark size: the first increment under uniaxial stress at
+    parity tolerances; the lateral macro stresses vanish, the yy macro strain is the
+    imposed one, the degraded stress is equilibrated, and at 4096 sampled voxels the GPU
+    stress equals the oracle's return map at the GPU strain."""
+    from oracle import GrainTables, return_map, to_mandel2, Grid
+    from oracle.increment import from_tensor6
+    from paper_2304_01125_amd import RVE, RVE_FP64
+    w = workload(NAME).parity()
+    inp = make_inputs(w)
+    r = RVE(w.desc(), RVE_FP64)
+    r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+    st = r.step([0, inp["deps"][0], 0, 0, 0, 0], inp["dt"][0], dsig6=np.zeros(6),
+                stress_mask=0b111101)
+    ms, me = np.array(st["macro_stress"]), np.array(st["macro_strain"])
+    print(f"  uniaxial stress: newton {st['newton_iters']} krylov {st['krylov_iters']}, "
+          f"macro stress {ms.tolist()}, macro strain {me.tolist()}", flush=True)
+    assert np.abs(ms[[0, 2, 3, 4, 5]]).max() <= 1e-9 * abs(ms[1])
+    assert abs(me[1] - inp["deps"][0]) <= 1e-15
+    f = r.fields(("strain", "stress", "stress_eff"))
+    r.close()
+    assert np.abs(f["strain"].mean(0) - me).max() <= 1e-15
+    idx = np.random.default_rng(12).choice(w.nvox, 4096, replace=False)
+    tab = GrainTables(inp["quat"], w.C11, w.C12, w.C44)
+    gid = inp["grain"][idx]
+    g0 = np.asarray(inp["tau_c0"])[gid]
+    epsM = to_mandel2(from_tensor6(f["strain"][idx]))
+    sig, _, _, _ = return_map(epsM, np.zeros_like(epsM), g0, inp["dt"][0], tab.C[gid],
+                              tab.S[gid], tab.P[gid], w.gdot0, w.n_exp)
+    e_sig = np.linalg.norm(to_mandel2(from_tensor6(f["stress_eff"][idx])) - sig) / np.linalg.norm(sig)
+    grid = Grid(w.n, w.h)
+    sh = grid.fft(grid.to_grid(from_tensor6(f["stress"])))
+    div = np.abs(grid.div_hat(sh)).max() / (np.abs(sh).max() * np.abs(grid.xit).max())
+    print(f"  sampled voxels: stress {e_sig:.2e}; equilibrium {div:.2e}", flush=True)
+    assert e_sig <= 1e-10 and div <= 1e-9
+
