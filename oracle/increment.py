@@ -65,7 +65,7 @@ class OracleRVE:
     def __init__(self, desc, grain, quat, tau_c0=None, phi0=None):
         self.d = dict(desc)
         d = self.d
-        self.grid = Grid(d["n"], d["h"])
+        self.grid = Grid(d["n"], d["h"], d.get("scheme", 0))
         M = self.grid.M
         self.gid = np.asarray(grain, dtype=np.int64)
         quat = np.atleast_2d(np.asarray(quat, dtype=np.float64))
