@@ -13,8 +13,8 @@ included).  Inputs are resident on the GPU before timing starts.
 
 Printed: one JSON line with the FP64 rate, the mixed-precision rate and its macro
 stress error against the FP64 run, the roofline of the dominant operator kernel
-(HIP events on the library's stream), the FP64 rate of the same increments under
-uniaxial stress (mixed macroscopic control), the FP64 rate of the same grid with the
+(HIP events on the library's stream), the FP64 rate of the same increments with the
+rotated-scheme discrete derivative and under uniaxial stress (mixed macroscopic control), the FP64 rate of the same grid with the
 paper's thermally activated flow rule and Table 1 material in yielding increments, and
 the CPU oracle timed on a bounded sample.
 """
@@ -45,6 +45,10 @@ def parse():
                     help="skip the thermally-activated-flow leg (Table 1 material)")
     ap.add_argument("--no-stress-control", action="store_true",
                     help="skip the uniaxial-stress (mixed control) leg")
+    ap.add_argument("--no-rotated", action="store_true",
+                    help="skip the rotated-scheme (discrete derivative) leg")
+    ap.add_argument("--deriv", choices=["spectral", "rotated"], default="spectral",
+                    help="derivative of the FP64 and mixed legs")
     ap.add_argument("--pass-reps", type=int, default=20)
     return ap.parse_args()
 
@@ -202,6 +206,17 @@ def stress_control_leg(RVE, precision, w, inp, warmup, steps, torch):
             "max_lateral_macro_stress_rel": float(lat)}
 
 
+def rotated_leg(RVE, precision, w, inp, warmup, steps, torch):
+    """The headline increments with the rotated-scheme discrete derivative."""
+    desc = dict(w.desc(), scheme=1)
+    r, dt, kry, stats, macro = run_leg(RVE, precision, desc, inp, warmup, steps, torch)
+    r.close()
+    return {"derivative": "rotated finite differences (gradient, divergence, acoustic tensor)",
+            "value": round(w.nvox * kry / dt, 1), "unit": "voxel-iters/s",
+            "ms_per_step": round(1e3 * dt / steps, 2), "krylov_iters": kry,
+            "newton_iters": int(sum(x["newton_iters"] for x in stats))}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -213,7 +228,7 @@ def main():
 
     w = workload(a.workload)
     inp = make_inputs(w)
-    desc = w.desc()
+    desc = dict(w.desc(), scheme=1 if a.deriv == "rotated" else 0)
     r64, dt64, kry64, st64, macro64 = run_leg(RVE, RVE_FP64, desc, inp, a.warmup, a.steps, torch)
     value = w.nvox * kry64 / dt64
     passes = time_passes(r64, torch, a.pass_reps)
@@ -234,6 +249,7 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
            "config": {"workload": w.name, "grid": list(w.n), "grains": w.n_grains,
+                      "derivative": a.deriv,
                       "load": f"R={w.ratio}, +-{w.amplitude * 100:.1f}%, increments "
                               f"{a.warmup}..{a.warmup + a.steps - 1}",
                       "tolerances": {"lin": w.tol_lin, "newton": w.tol_newton,
@@ -254,6 +270,8 @@ def main():
                         "macro_stress_rel_err_vs_fp64": float(err.max()),
                         "passes": {k: {"ms": round(v["ms"], 5), "GB/s": round(v["gbs"], 1)}
                                    for k, v in p32.items()}}
+    if not a.no_rotated and a.deriv == "spectral":
+        out["rotated"] = rotated_leg(RVE, RVE_FP64, w, inp, a.warmup, a.steps, torch)
     if not a.no_stress_control:
         out["stress_control"] = stress_control_leg(RVE, RVE_FP64, w, inp, a.warmup, a.steps, torch)
     if not a.no_material:

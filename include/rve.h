@@ -53,6 +53,13 @@ enum { RVE_FP64 = 0, RVE_MIXED = 1 };
  *   from the densities committed at the end of the previous increment (initially
  *   tau_c0 + mu b sqrt(rho0)). */
 enum { RVE_MAT_POWER = 0, RVE_MAT_DUNNE = 1 };
+/* Discrete derivative of the gradient, divergence and acoustic tensor of the momentum
+ * balance (Sec. 3.1 names discrete derivatives as the remedy for Gibbs oscillations at
+ * high phase contrast).  RVE_DERIV_ROTATED: k_a = D(theta_a) prod_{b != a} A(theta_b) with
+ * D = (e^{i theta} - 1)/h, A = (1 + e^{i theta})/2, theta = 2 pi k / N (A = 0 at the
+ * Nyquist index): a forward difference along a averaged over the four parallel voxel
+ * edges; the gradient is sym(k (x) u^), the divergence conj(k) . sigma^. */
+enum { RVE_DERIV_SPECTRAL = 0, RVE_DERIV_ROTATED = 1 };
 
 /* Field selection bits for rve_fields(); fields are written in increasing bit order. */
 enum {
@@ -99,6 +106,11 @@ typedef struct rve_desc {
   double dF, k_B, T;        /* activation energy [J], Boltzmann constant [J/K], temperature [K] */
   double dV;                /* activation volume [m^3]                                 */
   double mu;                /* shear modulus of the Taylor term [Pa]                    */
+  int32_t deriv;            /* derivative of the momentum operator: RVE_DERIV_SPECTRAL
+                               (i xi~, Nyquist index zeroed) or RVE_DERIV_ROTATED (the
+                               rotated finite-difference scheme, Sec. 3.1's discrete
+                               derivative remedy); the phase field and the GND curl stay
+                               spectral                                                 */
 } rve_desc;
 
 /* Per-increment report, filled by rve_step_increment (also on RVE_E_NOCONV). */

@@ -47,6 +47,8 @@ struct Grid {
   long long nspec;          // n1h*n2*n3
   double h;                 // voxel edge [m]
   double L1, L2, L3;        // box lengths [m]
+  int sch;                  // derivative of the momentum operator: 0 spectral (i xi~),
+                            // 1 rotated finite differences (rot_factors)
 };
 
 // Angular frequency of index k on an axis of N points and length L (signed, numpy
@@ -57,6 +59,39 @@ __device__ __forceinline__ double freq(int k, int N, double L, bool tilde) {
   const int m = (k <= (N - 1) / 2) ? k : k - N;
   return 6.283185307179586476925286766559 * (double)m / L;
 }
+
+// Rotated-scheme discrete derivative: k_a = D(theta_a) prod_{b != a} A(theta_b), the
+// symbol of a forward difference along a averaged over the four parallel voxel edges,
+// D = (e^{i theta} - 1) / h, A = (1 + e^{i theta}) / 2, theta = 2 pi k / N; A = 0 exactly
+// at the Nyquist index (a derivative across it has no real-valued average).
+__device__ __forceinline__ void rot_factors(int k, int N, double h, cplx<double>& D,
+                                           cplx<double>& A) {
+  double s, c;
+  sincospi(2.0 * (double)k / (double)N, &s, &c);
+  if (2 * k == N) { s = 0.0; c = -1.0; }
+  if (k == 0) { s = 0.0; c = 1.0; }
+  D = cplx<double>{(c - 1.0) / h, s / h};
+  A = cplx<double>{0.5 * (1.0 + c), 0.5 * s};
+}
+
+// The three derivative symbols of bin (kx, ky, kz): i xi~ (spectral) or the rotated k.
+__device__ __forceinline__ void kvec(const Grid& g, int kx, int ky, int kz, cplx<double> k[3]) {
+  if (g.sch == 0) {
+    k[0] = cplx<double>{0.0, freq(kx, g.n1, g.L1, true)};
+    k[1] = cplx<double>{0.0, freq(ky, g.n2, g.L2, true)};
+    k[2] = cplx<double>{0.0, freq(kz, g.n3, g.L3, true)};
+    return;
+  }
+  cplx<double> Dx, Ax, Dy, Ay, Dz, Az;
+  rot_factors(kx, g.n1, g.h, Dx, Ax);
+  rot_factors(ky, g.n2, g.h, Dy, Ay);
+  rot_factors(kz, g.n3, g.h, Dz, Az);
+  k[0] = cmul(Dx, cmul(Ay, Az));
+  k[1] = cmul(Ax, cmul(Dy, Az));
+  k[2] = cmul(Ax, cmul(Ay, Dz));
+}
+
+__device__ __forceinline__ cplx<double> cconj(cplx<double> a) { return {a.x, -a.y}; }
 
 // Parseval weight of a half-spectrum bin (x-bins 0 and N1/2 stand for themselves).
 __device__ __forceinline__ double parseval_w(int kx, int n1) {

@@ -314,6 +314,8 @@ int validate(const rve_desc* d) {
                         d->Gc, d->k_res, d->tol_stag, d->tol_newton, d->tol_lin};
   for (double v : pos)
     if (!(v > 0.0) || !std::isfinite(v)) return fail(RVE_E_ARG, "non-positive or non-finite constant");
+  if (d->deriv != RVE_DERIV_SPECTRAL && d->deriv != RVE_DERIV_ROTATED)
+    return fail(RVE_E_ARG, "deriv must be RVE_DERIV_SPECTRAL or RVE_DERIV_ROTATED");
   if (d->material != RVE_MAT_POWER && d->material != RVE_MAT_DUNNE)
     return fail(RVE_E_ARG, "material must be RVE_MAT_POWER or RVE_MAT_DUNNE");
   if (d->material == RVE_MAT_POWER) {
@@ -348,6 +350,7 @@ void init_grid(rve_s* h) {
   g.nspec = (long long)g.n1h * g.n2 * g.n3;
   g.h = h->d.h;
   g.L1 = g.n1 * g.h; g.L2 = g.n2 * g.h; g.L3 = g.n3 * g.h;
+  g.sch = h->d.deriv;
   h->pl.g = g;
   for (int a = 0; a < 3; ++a) make_axis_plan(h->d.n[a], &h->pl.ax[a]);
   h->f64 = (h->d.precision == RVE_FP64);

@@ -28,6 +28,36 @@ __device__ __forceinline__ Bin bin_of(long long e, const Grid& g) {
   return b;
 }
 
+// General derivative symbols k (kvec): e = sym(k (x) u), and sum_j c_j s_ij with c =
+// conj(k) (the adjoint of the gradient) for the divergence-type operators.
+template <typename R>
+__device__ __forceinline__ void sym_grad_k(const cplx<double> k[3], const cplx<R> u[3],
+                                           cplx<R> e[6]) {
+  cplx<double> ud[3];
+  for (int c = 0; c < 3; ++c) ud[c] = cplx<double>{(double)u[c].x, (double)u[c].y};
+  auto cv = [](cplx<double> a) { return cplx<R>{(R)a.x, (R)a.y}; };
+  e[0] = cv(cmul(k[0], ud[0]));
+  e[1] = cv(cmul(k[1], ud[1]));
+  e[2] = cv(cmul(k[2], ud[2]));
+  e[3] = cv(cscale(cadd(cmul(k[1], ud[2]), cmul(k[2], ud[1])), 0.5));
+  e[4] = cv(cscale(cadd(cmul(k[0], ud[2]), cmul(k[2], ud[0])), 0.5));
+  e[5] = cv(cscale(cadd(cmul(k[0], ud[1]), cmul(k[1], ud[0])), 0.5));
+}
+template <typename R>
+__device__ __forceinline__ void adj_div_k(const cplx<double> k[3], const cplx<R> sg[6],
+                                          cplx<double> d[3]) {
+  // stress components xx yy zz yz xz xy; row i of sigma: (i, x), (i, y), (i, z)
+  constexpr int row[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
+  for (int i = 0; i < 3; ++i) {
+    cplx<double> a{0.0, 0.0};
+    for (int j = 0; j < 3; ++j) {
+      const cplx<R> v = sg[row[i][j]];
+      a = cadd(a, cmul(cconj(k[j]), cplx<double>{(double)v.x, (double)v.y}));
+    }
+    d[i] = a;
+  }
+}
+
 // e = sym(i xi~ (x) u)  (3 -> 6 components)
 template <typename R>
 __global__ void __launch_bounds__(256) k_sym_grad(const cplx<R>* __restrict__ u, long long ucs, cplx<R>* __restrict__ e,
@@ -36,6 +66,15 @@ __global__ void __launch_bounds__(256) k_sym_grad(const cplx<R>* __restrict__ u,
   for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < g.nspec;
        b += (long long)gridDim.x * blockDim.x) {
     const Bin q = bin_of(b, g);
+    if (g.sch) {
+      cplx<double> k[3];
+      kvec(g, q.kx, q.ky, q.kz, k);
+      const cplx<R> uu[3] = {u[b], u[ucs + b], u[2 * ucs + b]};
+      cplx<R> ee[6];
+      sym_grad_k(k, uu, ee);
+      for (int c = 0; c < 6; ++c) e[c * ecs + b] = ee[c];
+      continue;
+    }
     const R t1 = (R)freq(q.kx, g.n1, g.L1, true);
     const R t2 = (R)freq(q.ky, g.n2, g.L2, true);
     const R t3 = (R)freq(q.kz, g.n3, g.L3, true);
@@ -63,6 +102,15 @@ __global__ void __launch_bounds__(256) k_div(const cplx<R>* __restrict__ s, long
   for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < g.nspec;
        b += (long long)gridDim.x * blockDim.x) {
     const Bin q = bin_of(b, g);
+    if (g.sch) {      // out = -sign conj(k) . s (= sign i xi~ . s for the spectral symbol)
+      cplx<double> k[3], d[3];
+      kvec(g, q.kx, q.ky, q.kz, k);
+      const cplx<R> sg6[6] = {s[b], s[scs + b], s[2 * scs + b], s[3 * scs + b], s[4 * scs + b],
+                              s[5 * scs + b]};
+      adj_div_k(k, sg6, d);
+      for (int c = 0; c < 3; ++c) out[c * ocs + b] = cplx<R>{(R)(-sign * d[c].x), (R)(-sign * d[c].y)};
+      continue;
+    }
     const R t1 = (R)freq(q.kx, g.n1, g.L1, true);
     const R t2 = (R)freq(q.ky, g.n2, g.L2, true);
     const R t3 = (R)freq(q.kz, g.n3, g.L3, true);
@@ -203,6 +251,44 @@ __device__ __forceinline__ void apply_M(const double t[3], const double* K4, con
   }
 }
 
+// zo = [conj(k) . K . k]^-1 ri (zero where k = 0): the Hermitian acoustic tensor of the
+// general derivative symbol, inverted by its adjugate.
+template <typename R>
+__device__ __forceinline__ void apply_Mk(const cplx<double> k[3], const double* K4,
+                                         const cplx<R> ri[3], cplx<R> zo[3]) {
+  zo[0] = zo[1] = zo[2] = cplx<R>{0, 0};
+  if (k[0].x == 0.0 && k[0].y == 0.0 && k[1].x == 0.0 && k[1].y == 0.0 && k[2].x == 0.0 &&
+      k[2].y == 0.0)
+    return;
+  cplx<double> A[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int m = 0; m < 3; ++m) {
+      cplx<double> s{0.0, 0.0};
+      for (int j = 0; j < 3; ++j)
+        for (int l = 0; l < 3; ++l)
+          s = cadd(s, cscale(cmul(cconj(k[j]), k[l]), K4[((i * 3 + j) * 3 + m) * 3 + l]));
+      A[i][m] = s;
+    }
+  auto c = [&](int i0, int j0, int i1, int j1) {   // A[i0][j0] A[i1][j1] - A[i0][j1] A[i1][j0]
+    return csub(cmul(A[i0][j0], A[i1][j1]), cmul(A[i0][j1], A[i1][j0]));
+  };
+  cplx<double> adj[3][3];
+  adj[0][0] = c(1, 1, 2, 2); adj[0][1] = c(0, 2, 2, 1); adj[0][2] = c(0, 1, 1, 2);
+  adj[1][0] = c(1, 2, 2, 0); adj[1][1] = c(0, 0, 2, 2); adj[1][2] = c(0, 2, 1, 0);
+  adj[2][0] = c(1, 0, 2, 1); adj[2][1] = c(0, 1, 2, 0); adj[2][2] = c(0, 0, 1, 1);
+  const cplx<double> det = cadd(cadd(cmul(A[0][0], adj[0][0]), cmul(A[0][1], adj[1][0])),
+                                cmul(A[0][2], adj[2][0]));
+  const double dd = det.x * det.x + det.y * det.y;
+  const cplx<double> idet{det.x / dd, -det.y / dd};
+  for (int i = 0; i < 3; ++i) {
+    cplx<double> z{0.0, 0.0};
+    for (int m = 0; m < 3; ++m)
+      z = cadd(z, cmul(adj[i][m], cplx<double>{(double)ri[m].x, (double)ri[m].y}));
+    z = cmul(z, idet);
+    zo[i] = cplx<R>{(R)z.x, (R)z.y};
+  }
+}
+
 // ---- fused conjugate-gradient kernels ---------------------------------------------
 // p = z + beta p (beta = sc[ia] / sc[ib]), then e = sym(i xi~ (x) p)  (3 -> 6 comps).
 template <typename R>
@@ -223,6 +309,14 @@ k_grad_cgp(cplx<R>* __restrict__ pv, const cplx<R>* __restrict__ z, long long cs
       const cplx<R> zz = z[c * cs + b], pp = pv[c * cs + b];
       u[c] = cplx<R>{(R)((double)zz.x + be * (double)pp.x), (R)((double)zz.y + be * (double)pp.y)};
       pv[c * cs + b] = u[c];
+    }
+    if (g.sch) {
+      cplx<double> k[3];
+      kvec(g, q.kx, q.ky, q.kz, k);
+      cplx<R> ee[6];
+      sym_grad_k(k, u, ee);
+      for (int c = 0; c < 6; ++c) e[c * ecs + b] = ee[c];
+      continue;
     }
     auto ic = [](R s, cplx<R> a) { return cplx<R>{-s * a.y, s * a.x}; };
     const R h = R(0.5);
@@ -247,6 +341,22 @@ k_div_dot(const cplx<R>* __restrict__ s, long long scs, cplx<R>* __restrict__ ou
   for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < g.nspec;
        b += (long long)gridDim.x * blockDim.x) {
     const Bin q = bin_of(b, g);
+    if (g.sch) {      // q = conj(k) . s
+      cplx<double> k[3], dd[3];
+      kvec(g, q.kx, q.ky, q.kz, k);
+      const cplx<R> sg6[6] = {s[b], s[scs + b], s[2 * scs + b], s[3 * scs + b], s[4 * scs + b],
+                              s[5 * scs + b]};
+      adj_div_k(k, sg6, dd);
+      double dot = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        const cplx<R> qq = {(R)dd[c].x, (R)dd[c].y};
+        out[c * ocs + b] = qq;
+        const cplx<R> pp = pv[c * ocs + b];
+        dot += (double)pp.x * (double)qq.x + (double)pp.y * (double)qq.y;
+      }
+      acc += parseval_w(q.kx, g.n1) * dot;
+      continue;
+    }
     const R t1 = (R)freq(q.kx, g.n1, g.L1, true);
     const R t2 = (R)freq(q.ky, g.n2, g.L2, true);
     const R t3 = (R)freq(q.kz, g.n3, g.L3, true);
@@ -283,8 +393,9 @@ int launch_div_dot(const Plans& p, const cplx<R>* s, cplx<R>* q, const cplx<R>* 
   return nb;
 }
 
-// One CG step (see launch_cg_step in kernels.h).
-template <typename R>
+// One CG step (see launch_cg_step in kernels.h); SCH: derivative symbol of the
+// preconditioner (0 spectral, 1 rotated).
+template <typename R, int SCH>
 __global__ void __launch_bounds__(256)
 k_cg_step(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __restrict__ pv,
           const cplx<R>* __restrict__ qv, cplx<R>* __restrict__ z, long long cs,
@@ -339,8 +450,15 @@ k_cg_step(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __res
       r[i] = rr_;
       rv[c] = rr_;
     }
-    if (mac) apply_M0(m0, rv, zo);
-    else apply_M(t, K4, rv, zo);
+    if (mac) {
+      apply_M0(m0, rv, zo);
+    } else if constexpr (SCH == 0) {
+      apply_M(t, K4, rv, zo);
+    } else {
+      cplx<double> kk[3];
+      kvec(g, q.kx, q.ky, q.kz, kk);
+      apply_Mk(kk, K4, rv, zo);
+    }
     double a = 0.0, bz = 0.0;
     for (int c = 0; c < 3; ++c) {
       z[c * cs + b] = zo[c];
@@ -371,8 +489,12 @@ int launch_cg_step(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, co
                    double* partial, hipStream_t st, const double* stop, const double* pq_part,
                    int nb_pq, int iflag, int iiter, int max_blocks, const double* m0) {
   const int nb = std::min(grid_for(p.g.nspec), max_blocks);
-  hipLaunchKernelGGL((k_cg_step<R>), dim3(nb), dim3(256), 0, st, x, r, pv, q, z, cs, kbar21, sc,
-                     cur, ipq, p.g, partial, stop, pq_part, nb_pq, iflag, iiter, m0);
+  if (p.g.sch)
+    hipLaunchKernelGGL((k_cg_step<R, 1>), dim3(nb), dim3(256), 0, st, x, r, pv, q, z, cs, kbar21,
+                       sc, cur, ipq, p.g, partial, stop, pq_part, nb_pq, iflag, iiter, m0);
+  else
+    hipLaunchKernelGGL((k_cg_step<R, 0>), dim3(nb), dim3(256), 0, st, x, r, pv, q, z, cs, kbar21,
+                       sc, cur, ipq, p.g, partial, stop, pq_part, nb_pq, iflag, iiter, m0);
   return nb;
 }
 template int launch_cg_step<double>(const Plans&, cplx<double>*, cplx<double>*,
@@ -433,6 +555,10 @@ __global__ void __launch_bounds__(256) k_precond(const cplx<R>* __restrict__ r, 
     cplx<R> zo[3] = {{0, 0}, {0, 0}, {0, 0}};
     if (mac) {
       apply_M0(m0, ri, zo);
+    } else if (g.sch) {
+      cplx<double> kk[3];
+      kvec(g, q.kx, q.ky, q.kz, kk);
+      apply_Mk(kk, K4, ri, zo);
     } else if (t[0] != 0.0 || t[1] != 0.0 || t[2] != 0.0) {
       double A[3][3];
       for (int i = 0; i < 3; ++i)

@@ -37,6 +37,29 @@ template <> struct ZSplit<96> { static constexpr int Na = 6, Nb = 16; };
 template <> struct ZSplit<128> { static constexpr int Na = 8, Nb = 16; };
 template <> struct ZSplit<256> { static constexpr int Na = 16, Nb = 16; };
 
+// Rotated-scheme factors of the block's x columns (with its ky) and of every kz, in LDS:
+// k_x = Pxy[0][x] Az[kz], k_y = Pxy[1][x] Az[kz], k_z = Pxy[2][x] Dz[kz], with
+// Pxy = (Dx Ay, Ax Dy, Ax Ay) (rot_factors).
+template <typename R, int N, int P, int NT>
+__device__ __forceinline__ void z_rot(const Grid& g, int kx0, int tile, int TX, int ky,
+                                      cplx<R>* pxy, cplx<R>* dz, cplx<R>* az) {
+  for (int t = threadIdx.x; t < N; t += NT) {
+    cplx<double> D, A;
+    rot_factors(t, g.n3, g.h, D, A);
+    dz[t] = cplx<R>{(R)D.x, (R)D.y};
+    az[t] = cplx<R>{(R)A.x, (R)A.y};
+  }
+  cplx<double> Dy, Ay;
+  rot_factors(ky, g.n2, g.h, Dy, Ay);
+  for (int t = threadIdx.x; t < P; t += NT) {
+    const int cx = (t < TX) ? kx0 + t : (tile == 0 ? g.n1 / 2 : -1);
+    cplx<double> Dx{0.0, 0.0}, Ax{0.0, 0.0};
+    if (cx >= 0) rot_factors(cx, g.n1, g.h, Dx, Ax);
+    const cplx<double> f[3] = {cmul(Dx, Ay), cmul(Ax, Dy), cmul(Ax, Ay)};
+    for (int a = 0; a < 3; ++a) pxy[a * P + t] = cplx<R>{(R)f[a].x, (R)f[a].y};
+  }
+}
+
 // xi~ of the block's x columns, its ky and every kz, in LDS (no divisions in the loops)
 template <typename R, int N, int P, int NT>
 __device__ __forceinline__ void z_freqs(const Grid& g, int kx0, int tile, int TX, int ky,
@@ -51,7 +74,7 @@ __device__ __forceinline__ void z_freqs(const Grid& g, int kx0, int tile, int TX
 
 // p_new = z + (sc[ia]/sc[ib]) p_old, then component c of e = sym(i xi~ (x) p_new) and its
 // inverse DFT along z.  The blocks of the diagonal components store p_new.
-template <typename R, int N, int TX, int NT>
+template <typename R, int N, int TX, int NT, int SCH>
 __global__ void __launch_bounds__(NT)
 k_zgrad_inv(const cplx<R>* __restrict__ zv, const cplx<R>* __restrict__ pold,
             cplx<R>* __restrict__ pnew, long long cs, double* __restrict__ sc, int ia, int ib,
@@ -72,7 +95,8 @@ k_zgrad_inv(const cplx<R>* __restrict__ zv, const cplx<R>* __restrict__ pold,
   constexpr int PITCH = N + 1;
   __shared__ cplx<R> A[P * PITCH];
   __shared__ cplx<R> tw[N];
-  __shared__ R tzs[N], txs[P];
+  __shared__ R tzs[SCH ? 1 : N], txs[SCH ? 1 : P];
+  __shared__ cplx<R> pxy[SCH ? 3 * P : 1], dzs[SCH ? N : 1], azs[SCH ? N : 1];
   for (int t = threadIdx.x; t < N; t += NT) tw[t] = tw_g[t];
   const int ntiles = (g.n1 / 2) / TX;
   int u, c;
@@ -81,8 +105,9 @@ k_zgrad_inv(const cplx<R>* __restrict__ zv, const cplx<R>* __restrict__ pold,
   const int kx0 = tile * TX;
   const long long stride_n = (long long)g.n1h * g.n2;
   const long long base = (long long)ky * g.n1h;
-  R ty;
-  z_freqs<R, N, P, NT>(g, kx0, tile, TX, ky, txs, tzs, ty);
+  R ty = R(0);
+  if constexpr (SCH == 0) z_freqs<R, N, P, NT>(g, kx0, tile, TX, ky, txs, tzs, ty);
+  else z_rot<R, N, P, NT>(g, kx0, tile, TX, ky, pxy, dzs, azs);
   // component c = (a, b): xx, yy, zz, yz, xz, xy
   const int ca = (c < 3) ? c : (c == 3 ? 1 : 0);
   const int cb = (c < 3) ? c : (c == 5 ? 1 : 2);
@@ -99,7 +124,7 @@ k_zgrad_inv(const cplx<R>* __restrict__ zv, const cplx<R>* __restrict__ pold,
     const int cx = col(x);
     cplx<R> v[Na];
     if (cx >= 0) {
-      const R tx = txs[x];
+      const R tx = SCH == 0 ? txs[x] : R(0);
       const long long i0 = base + (long long)n1 * stride_n + cx;
       const long long sm = (long long)Nb * stride_n;
       cplx<R> za[Na], pa[Na];
@@ -114,8 +139,13 @@ k_zgrad_inv(const cplx<R>* __restrict__ zv, const cplx<R>* __restrict__ pold,
 #pragma unroll
         for (int m = 0; m < Na; ++m) {
           pnew[ca * cs + i0 + m * sm] = v[m];
-          const R ta = (ca == 0) ? tx : (ca == 1 ? ty : tzs[n1 + Nb * m]);
-          v[m] = imul(ta, v[m]);
+          if constexpr (SCH == 0) {
+            const R ta = (ca == 0) ? tx : (ca == 1 ? ty : tzs[n1 + Nb * m]);
+            v[m] = imul(ta, v[m]);
+          } else {
+            const int kz = n1 + Nb * m;
+            v[m] = cmul(cmul(pxy[ca * P + x], ca == 2 ? dzs[kz] : azs[kz]), v[m]);
+          }
         }
       } else {
         cplx<R> zb[Na], pb[Na];
@@ -126,11 +156,18 @@ k_zgrad_inv(const cplx<R>* __restrict__ zv, const cplx<R>* __restrict__ pold,
         }
 #pragma unroll
         for (int m = 0; m < Na; ++m) {
-          const R tz = tzs[n1 + Nb * m];
-          const R ta = (ca == 0) ? tx : ty;                  // off the diagonal a < b, a < 2
-          const R tb = (cb == 1) ? ty : tz;
           const cplx<R> nb = upd(zb[m], pb[m]);
-          v[m] = cscale(cadd(imul(ta, nb), imul(tb, v[m])), R(0.5));
+          if constexpr (SCH == 0) {
+            const R tz = tzs[n1 + Nb * m];
+            const R ta = (ca == 0) ? tx : ty;                // off the diagonal a < b, a < 2
+            const R tb = (cb == 1) ? ty : tz;
+            v[m] = cscale(cadd(imul(ta, nb), imul(tb, v[m])), R(0.5));
+          } else {
+            const int kz = n1 + Nb * m;
+            const cplx<R> ka = cmul(pxy[ca * P + x], azs[kz]);          // a is x or y
+            const cplx<R> kb = cmul(pxy[cb * P + x], cb == 2 ? dzs[kz] : azs[kz]);
+            v[m] = cscale(cadd(cmul(ka, nb), cmul(kb, v[m])), R(0.5));
+          }
         }
       }
     } else {
@@ -164,7 +201,7 @@ k_zgrad_inv(const cplx<R>* __restrict__ zv, const cplx<R>* __restrict__ pold,
 // Component i of q = -i xi~ . F_z{s} and the block partial of the Parseval-weighted
 // <p, q>, in two rounds: xi~_z F_z{s_iz} first (its result waits in LDS), then
 // F_z{xi~_x s_ix + xi~_y s_iy}, whose x and y factors are constant along z.
-template <typename R, int N, int TX, int NT>
+template <typename R, int N, int TX, int NT, int SCH>
 __global__ void __launch_bounds__(NT)
 k_zdiv_fwd(const cplx<R>* __restrict__ s, cplx<R>* __restrict__ q, const cplx<R>* __restrict__ pv,
            long long cs, Grid g, const cplx<R>* __restrict__ tw_g, double* __restrict__ partial,
@@ -176,7 +213,8 @@ k_zdiv_fwd(const cplx<R>* __restrict__ s, cplx<R>* __restrict__ q, const cplx<R>
   __shared__ cplx<R> A[P * PITCH];
   __shared__ cplx<R> D[P * N];
   __shared__ cplx<R> tw[N];
-  __shared__ R tzs[N], txs[P];
+  __shared__ R tzs[SCH ? 1 : N], txs[SCH ? 1 : P];
+  __shared__ cplx<R> pxy[SCH ? 3 * P : 1], dzs[SCH ? N : 1], azs[SCH ? N : 1];
   __shared__ double red[NT / 64];
   for (int t = threadIdx.x; t < N; t += NT) tw[t] = tw_g[t];
   const int ntiles = (g.n1 / 2) / TX;
@@ -186,8 +224,9 @@ k_zdiv_fwd(const cplx<R>* __restrict__ s, cplx<R>* __restrict__ q, const cplx<R>
   const int kx0 = tile * TX;
   const long long stride_n = (long long)g.n1h * g.n2;
   const long long base = (long long)ky * g.n1h;
-  R ty;
-  z_freqs<R, N, P, NT>(g, kx0, tile, TX, ky, txs, tzs, ty);
+  R ty = R(0);
+  if constexpr (SCH == 0) z_freqs<R, N, P, NT>(g, kx0, tile, TX, ky, txs, tzs, ty);
+  else z_rot<R, N, P, NT>(g, kx0, tile, TX, ky, pxy, dzs, azs);
   // s_ix, s_iy, s_iz among xx, yy, zz, yz, xz, xy
   const int sx = (i == 0) ? 0 : (i == 1 ? 5 : 4);
   const int sy = (i == 0) ? 5 : (i == 1 ? 1 : 3);
@@ -212,15 +251,22 @@ k_zdiv_fwd(const cplx<R>* __restrict__ s, cplx<R>* __restrict__ q, const cplx<R>
 #pragma unroll
           for (int m = 0; m < Na; ++m) v[m] = s[sz * cs + i0 + m * sm];
         } else {
-          const R tx = txs[x];
           cplx<R> a[Na], b[Na];
 #pragma unroll
           for (int m = 0; m < Na; ++m) {
             a[m] = s[sx * cs + i0 + m * sm];
             b[m] = s[sy * cs + i0 + m * sm];
           }
+          if constexpr (SCH == 0) {
+            const R tx = txs[x];
 #pragma unroll
-          for (int m = 0; m < Na; ++m) v[m] = cadd(cscale(a[m], tx), cscale(b[m], ty));
+            for (int m = 0; m < Na; ++m) v[m] = cadd(cscale(a[m], tx), cscale(b[m], ty));
+          } else {      // conj(Dx Ay) s_ix + conj(Ax Dy) s_iy; conj(Az) follows the DFT
+            const cplx<R> fx = pxy[0 * P + x], fy = pxy[1 * P + x];
+            const cplx<R> cfx{fx.x, -fx.y}, cfy{fy.x, -fy.y};
+#pragma unroll
+            for (int m = 0; m < Na; ++m) v[m] = cadd(cmul(cfx, a[m]), cmul(cfy, b[m]));
+          }
         }
       } else {
 #pragma unroll
@@ -240,9 +286,20 @@ k_zdiv_fwd(const cplx<R>* __restrict__ s, cplx<R>* __restrict__ q, const cplx<R>
       for (int n1 = 0; n1 < Nb; ++n1) v[n1] = A[x * PITCH + n1 + Nb * k2];
       reg_dft<R, Nb, false>(v);
       if (cx < 0) continue;
-      if (zr) {
+      if constexpr (SCH == 0) {
+        if (zr) {
 #pragma unroll
-        for (int k1 = 0; k1 < Nb; ++k1) v[k1] = cscale(v[k1], tzs[k2 + Na * k1]);
+          for (int k1 = 0; k1 < Nb; ++k1) v[k1] = cscale(v[k1], tzs[k2 + Na * k1]);
+        }
+      } else {
+        // round 0: conj(Ax Ay) conj(Dz) F_z{s_iz}; round 1: conj(Az) F_z{...}
+        const cplx<R> fz = pxy[2 * P + x];
+#pragma unroll
+        for (int k1 = 0; k1 < Nb; ++k1) {
+          const int kz = k2 + Na * k1;
+          const cplx<R> f = zr ? cmul(fz, dzs[kz]) : azs[kz];
+          v[k1] = cmul(cplx<R>{f.x, -f.y}, v[k1]);
+        }
       }
       if (round == 0) {
         // D is private to the thread that owns item (x, k2) in both rounds
@@ -258,7 +315,8 @@ k_zdiv_fwd(const cplx<R>* __restrict__ s, cplx<R>* __restrict__ q, const cplx<R>
 #pragma unroll
         for (int k1 = 0; k1 < Nb; ++k1) {
           const cplx<R> dd = cadd(v[k1], D[x * N + k2 + Na * k1]);
-          const cplx<R> qq = {dd.y, -dd.x};                 // -i d
+          // spectral: q = -i d; rotated: the conj(k) factors are already applied
+          const cplx<R> qq = SCH == 0 ? cplx<R>{dd.y, -dd.x} : dd;
           q[i0 + k1 * sk] = qq;
           dot += (double)pp[k1].x * (double)qq.x + (double)pp[k1].y * (double)qq.y;
         }
@@ -271,15 +329,18 @@ k_zdiv_fwd(const cplx<R>* __restrict__ s, cplx<R>* __restrict__ q, const cplx<R>
 }
 
 // LDS bytes of the fused z kernels
+// LDS bytes of the fused z kernels (the rotated scheme adds its factor tables, 3 P + 2 N
+// complex)
 template <typename R>
-constexpr size_t zgrad_lds(int N, int P) {
+constexpr size_t zgrad_lds(int N, int P, int sch) {
   return ((size_t)P * (N + 1) + N) * sizeof(cplx<R>) + (size_t)(N + P) * sizeof(R) +
-         32 * sizeof(double);
+         (sch ? (size_t)(3 * P + 2 * N) * sizeof(cplx<R>) : 0) + 32 * sizeof(double);
 }
 template <typename R>
-constexpr size_t zdiv_lds(int N, int P) {
+constexpr size_t zdiv_lds(int N, int P, int sch) {
   return ((size_t)P * (N + 1) + (size_t)P * N + N) * sizeof(cplx<R>) +
-         (size_t)(N + P) * sizeof(R) + 16 * sizeof(double);
+         (size_t)(N + P) * sizeof(R) + (sch ? (size_t)(3 * P + 2 * N) * sizeof(cplx<R>) : 0) +
+         16 * sizeof(double);
 }
 
 // Largest x tile (32, 16 or 8 bins plus the Nyquist column) whose LDS fits; 0 if the
@@ -289,7 +350,7 @@ static int fused_tile(const Grid& g, bool div) {
   if (g.n1 % 2 != 0 || g.n3 != N) return 0;
   const int half = g.n1 / 2;
   for (int TX : {32, 16, 8}) {
-    const size_t lds = div ? zdiv_lds<R>(N, TX + 1) : zgrad_lds<R>(N, TX + 1);
+    const size_t lds = div ? zdiv_lds<R>(N, TX + 1, g.sch) : zgrad_lds<R>(N, TX + 1, g.sch);
     if (half % TX == 0 && lds <= kRegLdsMax) return TX;
   }
   return 0;
@@ -318,19 +379,21 @@ void launch_zgrad_inv(const Plans& p, const cplx<R>* z, const cplx<R>* pold, cpl
   with_length(g.n3, [&]<int NC>() {
     if constexpr (NC > 0) {
       const int TX = fused_tile<R, NC>(g, false);
-      auto go = [&]<int T>() {
-        constexpr int NT = threads_for<(T + 1) * ZSplit<NC>::Nb>();
-        const int nblk = (g.n1 / 2 / T) * g.n2 * 6;
-        hipLaunchKernelGGL((k_zgrad_inv<R, NC, T, NT>), dim3(nblk), dim3(NT), 0, st, z, pold,
-                           pnew, cs, sc, ia, ib, e, g, tw, stop, ck);
+      auto go = [&]<int T, int S>() {
+        if constexpr (zgrad_lds<R>(NC, T + 1, S) <= kRegLdsMax) {
+          constexpr int NT = threads_for<(T + 1) * ZSplit<NC>::Nb>();
+          const int nblk = (g.n1 / 2 / T) * g.n2 * 6;
+          hipLaunchKernelGGL((k_zgrad_inv<R, NC, T, NT, S>), dim3(nblk), dim3(NT), 0, st, z, pold,
+                             pnew, cs, sc, ia, ib, e, g, tw, stop, ck);
+        }
       };
-      if (TX == 32) {
-        if constexpr (zgrad_lds<R>(NC, 33) <= kRegLdsMax) go.template operator()<32>();
-      } else if (TX == 16) {
-        if constexpr (zgrad_lds<R>(NC, 17) <= kRegLdsMax) go.template operator()<16>();
-      } else if (TX == 8) {
-        if constexpr (zgrad_lds<R>(NC, 9) <= kRegLdsMax) go.template operator()<8>();
-      }
+      auto go2 = [&]<int T>() {
+        if (g.sch) go.template operator()<T, 1>();
+        else go.template operator()<T, 0>();
+      };
+      if (TX == 32) go2.template operator()<32>();
+      else if (TX == 16) go2.template operator()<16>();
+      else if (TX == 8) go2.template operator()<8>();
     }
   });
 }
@@ -344,19 +407,21 @@ int launch_zdiv_fwd(const Plans& p, const cplx<R>* s, cplx<R>* q, const cplx<R>*
   with_length(g.n3, [&]<int NC>() {
     if constexpr (NC > 0) {
       const int TX = fused_tile<R, NC>(g, true);
-      auto go = [&]<int T>() {
-        constexpr int NT = threads_for<(T + 1) * ZSplit<NC>::Nb>();
-        nblk = (g.n1 / 2 / T) * g.n2 * 3;
-        hipLaunchKernelGGL((k_zdiv_fwd<R, NC, T, NT>), dim3(nblk), dim3(NT), 0, st, s, q, pv, cs,
-                           g, tw, partial, stop);
+      auto go = [&]<int T, int S>() {
+        if constexpr (zdiv_lds<R>(NC, T + 1, S) <= kRegLdsMax) {
+          constexpr int NT = threads_for<(T + 1) * ZSplit<NC>::Nb>();
+          nblk = (g.n1 / 2 / T) * g.n2 * 3;
+          hipLaunchKernelGGL((k_zdiv_fwd<R, NC, T, NT, S>), dim3(nblk), dim3(NT), 0, st, s, q, pv,
+                             cs, g, tw, partial, stop);
+        }
       };
-      if (TX == 32) {
-        if constexpr (zdiv_lds<R>(NC, 33) <= kRegLdsMax) go.template operator()<32>();
-      } else if (TX == 16) {
-        if constexpr (zdiv_lds<R>(NC, 17) <= kRegLdsMax) go.template operator()<16>();
-      } else if (TX == 8) {
-        if constexpr (zdiv_lds<R>(NC, 9) <= kRegLdsMax) go.template operator()<8>();
-      }
+      auto go2 = [&]<int T>() {
+        if (g.sch) go.template operator()<T, 1>();
+        else go.template operator()<T, 0>();
+      };
+      if (TX == 32) go2.template operator()<32>();
+      else if (TX == 16) go2.template operator()<16>();
+      else if (TX == 8) go2.template operator()<8>();
     }
   });
   return nblk;

@@ -42,7 +42,7 @@ class RveDesc(ctypes.Structure):
                 ("max_grains", ctypes.c_int32), ("material", ctypes.c_int32),
                 ("rho_m", ctypes.c_double), ("v_D", ctypes.c_double), ("dF", ctypes.c_double),
                 ("k_B", ctypes.c_double), ("T", ctypes.c_double), ("dV", ctypes.c_double),
-                ("mu", ctypes.c_double)]
+                ("mu", ctypes.c_double), ("deriv", ctypes.c_int32)]
 
 
 class RveStats(ctypes.Structure):
@@ -153,6 +153,7 @@ def make_desc(desc, precision=RVE_FP64, max_grains=4096):
     d.max_newton = int(desc["max_newton"])
     d.max_krylov = int(desc["max_krylov"])
     d.max_grains = int(max_grains)
+    d.deriv = int(desc.get("scheme", 0))
     d.material = int(desc.get("material", RVE_MAT_POWER))
     if d.material == RVE_MAT_DUNNE:
         for k in ("rho_m", "v_D", "dF", "k_B", "T", "dV", "mu"):
