@@ -260,14 +260,25 @@ __device__ __forceinline__ void apply_Mk(const cplx<double> k[3], const double* 
   if (k[0].x == 0.0 && k[0].y == 0.0 && k[1].x == 0.0 && k[1].y == 0.0 && k[2].x == 0.0 &&
       k[2].y == 0.0)
     return;
+  // W_jl = conj(k_j) k_l (Hermitian), then the upper triangle of A_im = K_ijml W_jl
+  cplx<double> W[3][3];
+  for (int j = 0; j < 3; ++j)
+    for (int l = j; l < 3; ++l) {
+      W[j][l] = cmul(cconj(k[j]), k[l]);
+      W[l][j] = cconj(W[j][l]);
+    }
   cplx<double> A[3][3];
   for (int i = 0; i < 3; ++i)
-    for (int m = 0; m < 3; ++m) {
-      cplx<double> s{0.0, 0.0};
+    for (int m = i; m < 3; ++m) {
+      double sr = 0.0, si = 0.0;
       for (int j = 0; j < 3; ++j)
-        for (int l = 0; l < 3; ++l)
-          s = cadd(s, cscale(cmul(cconj(k[j]), k[l]), K4[((i * 3 + j) * 3 + m) * 3 + l]));
-      A[i][m] = s;
+        for (int l = 0; l < 3; ++l) {
+          const double kv = K4[((i * 3 + j) * 3 + m) * 3 + l];
+          sr += kv * W[j][l].x;
+          si += kv * W[j][l].y;
+        }
+      A[i][m] = cplx<double>{sr, si};
+      A[m][i] = cplx<double>{sr, -si};
     }
   auto c = [&](int i0, int j0, int i1, int j1) {   // A[i0][j0] A[i1][j1] - A[i0][j1] A[i1][j0]
     return csub(cmul(A[i0][j0], A[i1][j1]), cmul(A[i0][j1], A[i1][j0]));
