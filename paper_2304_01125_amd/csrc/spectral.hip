@@ -19,12 +19,15 @@ static int grid_for(long long n);
 struct Bin {
   int kx, ky, kz;
 };
+// (32-bit unsigned division: a half spectrum has fewer than 2^32 bins)
 __device__ __forceinline__ Bin bin_of(long long e, const Grid& g) {
   Bin b;
-  b.kx = (int)(e % g.n1h);
-  long long r = e / g.n1h;
-  b.ky = (int)(r % g.n2);
-  b.kz = (int)(r / g.n2);
+  const unsigned u = (unsigned)e, n1h = (unsigned)g.n1h, n2 = (unsigned)g.n2;
+  const unsigned r = u / n1h;
+  b.kx = (int)(u - r * n1h);
+  const unsigned kz = r / n2;
+  b.ky = (int)(r - kz * n2);
+  b.kz = (int)kz;
   return b;
 }
 

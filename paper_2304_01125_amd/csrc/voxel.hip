@@ -292,15 +292,16 @@ __device__ __forceinline__ void chol6p_inverse(const double U[21], double K[21])
 }
 
 // Solve the return map with Newton steps and a backtracking line search on Phi.  sig
-// (crystal-frame Mandel, in/out) holds a warm start; the iteration starts from it or
-// from the trial stress scaled into the elastic range, whichever has the lower
-// potential (far above the threshold of the exponential rule the Newton steps shrink
-// to the rule's stress scale 1/beta).  Returns the number of Newton iterations, or -1
-// if it did not converge.
+// (crystal-frame Mandel, in/out) holds a warm start.  With the thermally activated rule
+// the iteration starts from it or from the trial stress scaled into the elastic range,
+// whichever has the lower potential (far above the threshold of the exponential rule the
+// Newton steps shrink to the rule's stress scale 1/beta, or the potential overflows);
+// the power law starts from the warm start.  The root does not depend on the start.
+// Returns the number of Newton iterations, or -1 if it did not converge.
 template <int F>
 __device__ int return_map(const CrystalFrame& cf, const double str[6], const Flow& f,
                           double sig[6]) {
-  {
+  if constexpr (F == FLOW_DUNNE) {
     double tmax = 0.0;
 #pragma unroll 1
     for (int a = 0; a < 12; ++a) {
