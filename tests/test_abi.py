@@ -97,3 +97,25 @@ def test_null_handle_calls_fail_cleanly():
     assert lib.rve_step_increment(None, de.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1.0,
                                   ctypes.byref(st)) == p.RVE_E_ARG
     assert lib.rve_destroy(None) == p.RVE_OK
+
+
+def test_material_derivative_and_mixed_control_arguments_are_validated():
+    import paper_2304_01125_amd as p
+    from synth import workload, cmsx4, small_polycrystal
+    lib = p.load()
+    base = small_polycrystal(n=16, n_grains=4, **cmsx4()).desc()
+    assert p.rve_footprint_bytes(p.make_desc(base)) > 0
+    for key, val, msg in [("material", 2, "material"), ("scheme", 3, "deriv"),
+                          ("dV", 0.0, "thermally activated"), ("mu", -1.0, "thermally activated"),
+                          ("T", float("inf"), "thermally activated")]:
+        d = p.make_desc(dict(base, **{key: val}))
+        assert p.rve_footprint_bytes(d) == 0, key
+        assert msg in lib.rve_last_error().decode(), (key, lib.rve_last_error())
+    big = dict(workload("notched-crystal-16").desc(), n=(1024, 2, 2))
+    assert p.rve_footprint_bytes(p.make_desc(big)) == 0
+    one = dict(workload("notched-crystal-16").desc(), n=(1, 1, 1))
+    assert p.rve_footprint_bytes(p.make_desc(one)) > 0
+    de = np.zeros(6)
+    dp = de.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    st = p.rve.RveStats()
+    assert lib.rve_step_increment_mixed(None, dp, dp, 61, 1.0, ctypes.byref(st)) == p.RVE_E_ARG
