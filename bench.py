@@ -14,7 +14,9 @@ included).  Inputs are resident on the GPU before timing starts.
 Printed: one JSON line with the FP64 rate, the mixed-precision rate and its macro
 stress error against the FP64 run, the roofline of the dominant operator kernel
 (HIP events on the library's stream), the FP64 rate of the same increments with the
-rotated-scheme discrete derivative and under uniaxial stress (mixed macroscopic control), the FP64 rate of the same grid with the
+rotated-scheme discrete derivative and under uniaxial stress (mixed macroscopic control),
+a short serving run (a 40-request seeded stream of 32^3-96^3 solves: mixed-precision
+server against serial FP64 solves, solves/s and p50/p99 latency), the FP64 rate of the same grid with the
 paper's thermally activated flow rule and Table 1 material in yielding increments, and
 the CPU oracle timed on a bounded sample.
 """
@@ -49,6 +51,9 @@ def parse():
                     help="skip the rotated-scheme (discrete derivative) leg")
     ap.add_argument("--deriv", choices=["spectral", "rotated"], default="spectral",
                     help="derivative of the FP64 and mixed legs")
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="requests of the serving leg (0: skip); the committed serving "
+                         "summary uses 400")
     ap.add_argument("--pass-reps", type=int, default=20)
     return ap.parse_args()
 
@@ -276,6 +281,11 @@ def main():
         out["stress_control"] = stress_control_leg(RVE, RVE_FP64, w, inp, a.warmup, a.steps, torch)
     if not a.no_material:
         out["material"] = material_leg(RVE, RVE_FP64, torch)
+    if a.serve_requests > 0:
+        from paper_2304_01125_amd.serve import serve_benchmark
+        out["serving"] = serve_benchmark(a.serve_requests, 8, 4, min(16, os.cpu_count() or 1),
+                                         log=lambda m: print("# " + m, file=sys.stderr,
+                                                             flush=True))
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, inp, st64, a.warmup)
     print(json.dumps(out), flush=True)
