@@ -60,6 +60,12 @@ enum { RVE_MAT_POWER = 0, RVE_MAT_DUNNE = 1 };
  * Nyquist index): a forward difference along a averaged over the four parallel voxel
  * edges; the gradient is sym(k (x) u^), the divergence conj(k) . sigma^. */
 enum { RVE_DERIV_SPECTRAL = 0, RVE_DERIV_ROTATED = 1 };
+/* Krylov solver of the linearised momentum balance (eq. newton).  The operator is
+ * symmetric positive definite in the Parseval inner product (the return map keeps the
+ * tangent symmetric), so CG and GMRES reach the same Newton correction; RVE_KRYLOV_GMRES
+ * is the paper's restarted GMRES with the same preconditioner, its relative tolerance
+ * tol_lin applied to the preconditioned residual. */
+enum { RVE_KRYLOV_CG = 0, RVE_KRYLOV_GMRES = 1 };
 
 /* Field selection bits for rve_fields(); fields are written in increasing bit order. */
 enum {
@@ -106,6 +112,11 @@ typedef struct rve_desc {
   double dF, k_B, T;        /* activation energy [J], Boltzmann constant [J/K], temperature [K] */
   double dV;                /* activation volume [m^3]                                 */
   double mu;                /* shear modulus of the Taylor term [Pa]                    */
+  int32_t krylov;           /* momentum Krylov solver: RVE_KRYLOV_CG (default) or
+                               RVE_KRYLOV_GMRES (the paper's restarted GMRES, left
+                               preconditioned; strain control only)                    */
+  int32_t gmres_restart;    /* GMRES restart length m, 1..64 (basis of m + 1 vectors in
+                               the arena)                                               */
   int32_t deriv;            /* derivative of the momentum operator: RVE_DERIV_SPECTRAL
                                (i xi~, Nyquist index zeroed) or RVE_DERIV_ROTATED (the
                                rotated finite-difference scheme, Sec. 3.1's discrete

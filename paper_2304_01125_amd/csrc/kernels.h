@@ -166,6 +166,22 @@ template <typename R>
 void launch_curl_reg(const Plans& p, cplx<R>* b9, long long cs, double ell_fp, double scale,
                      hipStream_t st);
 
+// --- restarted GMRES(m) vector kernels (gmres.hip) -----------------------------------------
+constexpr int kGmChunk = 8;     // basis vectors per block dot / update launch
+// partial[i * nblk + blk]: block sums of the Parseval-weighted <V_i, w>, i < nv <= kGmChunk,
+// V_i = V + i * vs; returns nblk
+template <typename R>
+int launch_mdot(const Plans& p, const cplx<R>* V, long long vs, int nv, const cplx<R>* w,
+                long long cs, double* partial, hipStream_t st);
+// w += sign * sum_i coef[i] V_i (coef: nv <= kGmChunk device doubles)
+template <typename R>
+void launch_maxpy(const Plans& p, const cplx<R>* V, long long vs, int nv, const double* coef,
+                  double sign, cplx<R>* w, long long cs, hipStream_t st);
+// out = a in + b y (y may be null when b = 0)
+template <typename R>
+void launch_caxpby(const Plans& p, const cplx<R>* in, double a, const cplx<R>* y, double b,
+                   cplx<R>* out, long long cs, hipStream_t st);
+
 // --- mixed strain/stress macroscopic control (macro.hip) --------------------------------
 // Six doubles passed by value to a kernel.
 struct Six6 {

@@ -233,6 +233,7 @@ struct rve_s {
   void* gK;               // 21 N reals (R)
   void* spec;             // 9 NH complex (R): operator work and GND scratch
   void* cg[6];            // x, r, z, p, q, b : 3 NH complex each
+  void* gm_basis = nullptr;  // GMRES option: m + 1 basis vectors of 3 NH complex
   double* rbuf;           // 9 N doubles: phase-field vectors / Nye tensor
   double* partial;        // reduction partials
   double* scal;           // device scalars
@@ -261,7 +262,11 @@ enum { SC_K = 0,        // 28 constitutive sums (21 gK, g w, 6 g sigma)
        SC_MISC = 64,    // generic reduce outputs (16)
        SC_M0 = 96,      // 36: macro-block preconditioner (mixed control)
        SC_DE = 132,     // 6: macro strain increment of a Newton step (mixed control)
-       SC_N = 144 };
+       SC_GN = 140,     // GMRES: a norm
+       SC_GM = 144,     // GMRES: Gram-Schmidt coefficients, first pass (up to 65)
+       SC_GM2 = 216,    // GMRES: second pass
+       SC_GY = 288,     // GMRES: least-squares solution (up to 64)
+       SC_N = 360 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -294,6 +299,9 @@ void layout(rve_s* h) {
   h->gK = take((size_t)21 * N * rsz);
   h->spec = take((size_t)9 * NH * csz);
   for (int i = 0; i < 6; ++i) h->cg[i] = take((size_t)3 * NH * csz);
+  h->gm_basis = h->d.krylov == RVE_KRYLOV_GMRES
+                    ? take((size_t)(h->d.gmres_restart + 1) * 3 * NH * csz)
+                    : nullptr;
   h->rbuf = fd(9 * N);
   h->partial = fd((long long)kMaxRedBlocks * 32);
   h->scal = fd(SC_N);
@@ -314,6 +322,10 @@ int validate(const rve_desc* d) {
                         d->Gc, d->k_res, d->tol_stag, d->tol_newton, d->tol_lin};
   for (double v : pos)
     if (!(v > 0.0) || !std::isfinite(v)) return fail(RVE_E_ARG, "non-positive or non-finite constant");
+  if (d->krylov != RVE_KRYLOV_CG && d->krylov != RVE_KRYLOV_GMRES)
+    return fail(RVE_E_ARG, "krylov must be RVE_KRYLOV_CG or RVE_KRYLOV_GMRES");
+  if (d->krylov == RVE_KRYLOV_GMRES && (d->gmres_restart < 1 || d->gmres_restart > 64))
+    return fail(RVE_E_ARG, "gmres_restart must be in 1..64");
   if (d->deriv != RVE_DERIV_SPECTRAL && d->deriv != RVE_DERIV_ROTATED)
     return fail(RVE_E_ARG, "deriv must be RVE_DERIV_SPECTRAL or RVE_DERIV_ROTATED");
   if (d->material != RVE_MAT_POWER && d->material != RVE_MAT_DUNNE)
@@ -423,6 +435,104 @@ struct Ops {
       launch_div<R>(h->pl, W, NH, q, NH, -1.0, st, stop);
     }
   }
+  // Restarted GMRES(m) on M B du = M c (left preconditioning; the paper's Krylov solver):
+  // classical Gram-Schmidt with one re-orthogonalisation, kGmChunk basis vectors per
+  // block dot / update launch, Givens rotations and the small least-squares solve on the
+  // host; relative tolerance on the preconditioned residual.  Solution in cg[0]; iters
+  // counts operator applications.
+  int norm(const C* a, double& out) {
+    const int nb = launch_sdot<R>(h->pl, a, a, NH, 3, h->partial, st);
+    launch_reduce(h->partial, nb, 1, 0, h->scal + SC_GN, st);
+    const int rc = sync_read(h, SC_GN, 1);
+    out = std::sqrt(h->hs[SC_GN]);
+    return rc;
+  }
+  int gmres(int& iters) {
+    const int m = h->d.gmres_restart;
+    C *x = v(0), *w = v(1), *t = v(2), *scr = v(3), *b = v(5);
+    C* V = (C*)h->gm_basis;
+    const long long vs = 3 * NH;
+    double* sc = h->scal;
+    iters = 0;
+    launch_zero(x, (size_t)3 * NH * sizeof(C), st);
+    launch_precond<R>(h->pl, b, V, NH, sc + SC_KBAR, h->partial, st);    // r0 = M c
+    double beta;
+    int rc;
+    if ((rc = norm(V, beta))) return rc;
+    if (!(beta > 0.0)) return std::isfinite(beta) ? RVE_OK : fail(RVE_E_NOCONV, "non-finite residual");
+    const double tol = h->d.tol_lin * beta;
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m), hc(m + 1);
+    for (;;) {
+      launch_caxpby<R>(h->pl, V, 1.0 / beta, nullptr, 0.0, V, NH, st);
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int jl = -1;
+      bool conv = false;
+      for (int j = 0; j < m; ++j) {
+        // w = M P(B V_j), P the Hermitian projection of the self-conjugate planes
+        matvec(V + j * vs, t, scr);
+        launch_herm_proj<R>(h->pl, t, NH, 3, st);
+        launch_precond<R>(h->pl, t, w, NH, sc + SC_KBAR, h->partial, st);
+        for (int pass = 0; pass < 2; ++pass) {
+          const int base = pass ? SC_GM2 : SC_GM;
+          for (int c0 = 0; c0 <= j; c0 += kGmChunk) {
+            const int nv = std::min(kGmChunk, j + 1 - c0);
+            const int nb = launch_mdot<R>(h->pl, V + c0 * vs, vs, nv, w, NH, h->partial, st);
+            launch_reduce(h->partial, nb, nv, 0, sc + base + c0, st);
+          }
+          for (int c0 = 0; c0 <= j; c0 += kGmChunk) {
+            const int nv = std::min(kGmChunk, j + 1 - c0);
+            launch_maxpy<R>(h->pl, V + c0 * vs, vs, nv, sc + base + c0, -1.0, w, NH, st);
+          }
+        }
+        if ((rc = sync_read(h, SC_GM, SC_GM2 - SC_GM + j + 1))) return rc;
+        for (int i = 0; i <= j; ++i) hc[i] = h->hs[SC_GM + i] + h->hs[SC_GM2 + i];
+        double hn;
+        if ((rc = norm(w, hn))) return rc;
+        ++iters;
+        for (int i = 0; i < j; ++i) {          // previous rotations
+          const double a = cs[i] * hc[i] + sn[i] * hc[i + 1];
+          hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+          hc[i] = a;
+        }
+        const double den = std::hypot(hc[j], hn);
+        cs[j] = den > 0.0 ? hc[j] / den : 1.0;
+        sn[j] = den > 0.0 ? hn / den : 0.0;
+        hc[j] = den;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hc[i];
+        jl = j;
+        if (!std::isfinite(g[j + 1])) return fail(RVE_E_NOCONV, "momentum GMRES breakdown");
+        conv = std::fabs(g[j + 1]) <= tol || !(hn > 0.0);
+        if (conv || iters >= h->d.max_krylov) break;
+        launch_caxpby<R>(h->pl, w, 1.0 / hn, nullptr, 0.0, V + (j + 1) * vs, NH, st);
+      }
+      // x += V y with H y = g (upper triangular)
+      for (int i = jl; i >= 0; --i) {
+        double s = g[i];
+        for (int k = i + 1; k <= jl; ++k) s -= H[(size_t)i * m + k] * y[k];
+        y[i] = s / H[(size_t)i * m + i];
+      }
+      for (int i = 0; i <= jl; ++i) h->hs[SC_GY + i] = y[i];
+      HIPCHK(hipMemcpyAsync(sc + SC_GY, h->hs + SC_GY, (size_t)(jl + 1) * sizeof(double),
+                            hipMemcpyHostToDevice, st));
+      for (int c0 = 0; c0 <= jl; c0 += kGmChunk) {
+        const int nv = std::min(kGmChunk, jl + 1 - c0);
+        launch_maxpy<R>(h->pl, V + c0 * vs, vs, nv, sc + SC_GY + c0, 1.0, x, NH, st);
+      }
+      if (conv) return RVE_OK;
+      if (iters >= h->d.max_krylov) return fail(RVE_E_NOCONV, "momentum GMRES reached max_krylov");
+      // restart from the preconditioned residual M (c - P B x)
+      matvec(x, t, scr);
+      launch_herm_proj<R>(h->pl, t, NH, 3, st);
+      launch_caxpby<R>(h->pl, b, 1.0, t, -1.0, t, NH, st);
+      launch_precond<R>(h->pl, t, V, NH, sc + SC_KBAR, h->partial, st);
+      if ((rc = norm(V, beta))) return rc;
+      if (beta <= tol) return RVE_OK;
+    }
+  }
+
   // mean tangent from the constitutive sums
   void kbar() { launch_rscale(21, h->scal + SC_K, 1.0 / (double)N, h->scal + SC_KBAR, st); }
 
@@ -670,7 +780,7 @@ int run_increment(rve_s* h, const double de_in[6], const double* dsig, int mask,
       // zero bin: -s (sum g sigma - N sigma*) on the stress-controlled components
       if (mask) launch_macro_rhs<R>(o.W, o.NH, o.v(5), o.NH, o.s_mac, (double)N, tgt, mask, st);
       int kit = 0;
-      rc = o.pcg(kit);
+      rc = h->d.krylov == RVE_KRYLOV_GMRES ? o.gmres(kit) : o.pcg(kit);
       s.krylov_iters += kit;
       if (rc) { s.ms_mech_krylov += now_ms() - tk; goto fail_out; }
       // deps = F^-1{ sym(i xi~ (x) du) }
@@ -1002,6 +1112,8 @@ int rve_step_increment_mixed(rve_s* h, const double deps[6], const double dsig[6
   if (!h->micro) return fail(RVE_E_STATE, "microstructure not set");
   if (stress_mask < 0 || stress_mask > 63) return fail(RVE_E_ARG, "stress_mask outside 0..63");
   if (stress_mask && !dsig) return fail(RVE_E_ARG, "null stress increment");
+  if (stress_mask && h->d.krylov != RVE_KRYLOV_CG)
+    return fail(RVE_E_ARG, "mixed macroscopic control runs with the CG solver");
   double ds[6] = {0, 0, 0, 0, 0, 0};
   for (int c = 0; c < 6; ++c) {
     const bool f = (stress_mask >> c) & 1;

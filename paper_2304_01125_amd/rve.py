@@ -42,7 +42,8 @@ class RveDesc(ctypes.Structure):
                 ("max_grains", ctypes.c_int32), ("material", ctypes.c_int32),
                 ("rho_m", ctypes.c_double), ("v_D", ctypes.c_double), ("dF", ctypes.c_double),
                 ("k_B", ctypes.c_double), ("T", ctypes.c_double), ("dV", ctypes.c_double),
-                ("mu", ctypes.c_double), ("deriv", ctypes.c_int32)]
+                ("mu", ctypes.c_double), ("krylov", ctypes.c_int32),
+                ("gmres_restart", ctypes.c_int32), ("deriv", ctypes.c_int32)]
 
 
 class RveStats(ctypes.Structure):
@@ -154,6 +155,8 @@ def make_desc(desc, precision=RVE_FP64, max_grains=4096):
     d.max_krylov = int(desc["max_krylov"])
     d.max_grains = int(max_grains)
     d.deriv = int(desc.get("scheme", 0))
+    d.krylov = int(desc.get("krylov", 0))
+    d.gmres_restart = int(desc.get("gmres_restart", 30))
     d.material = int(desc.get("material", RVE_MAT_POWER))
     if d.material == RVE_MAT_DUNNE:
         for k in ("rho_m", "v_D", "dF", "k_B", "T", "dV", "mu"):

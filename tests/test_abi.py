@@ -103,11 +103,12 @@ def test_material_derivative_and_mixed_control_arguments_are_validated():
     import paper_2304_01125_amd as p
     from synth import workload, cmsx4, small_polycrystal
     lib = p.load()
-    base = small_polycrystal(n=16, n_grains=4, **cmsx4()).desc()
+    base = dict(small_polycrystal(n=16, n_grains=4, **cmsx4()).desc(), krylov=1)
     assert p.rve_footprint_bytes(p.make_desc(base)) > 0
     for key, val, msg in [("material", 2, "material"), ("scheme", 3, "deriv"),
                           ("dV", 0.0, "thermally activated"), ("mu", -1.0, "thermally activated"),
-                          ("T", float("inf"), "thermally activated")]:
+                          ("T", float("inf"), "thermally activated"),
+                          ("krylov", 2, "krylov"), ("gmres_restart", 0, "gmres_restart")]:
         d = p.make_desc(dict(base, **{key: val}))
         assert p.rve_footprint_bytes(d) == 0, key
         assert msg in lib.rve_last_error().decode(), (key, lib.rve_last_error())
