@@ -243,6 +243,15 @@ struct rve_s {
   bool use_graphs = true;
   hipGraphExec_t cg_exec[2] = {nullptr, nullptr};
   int graph_mask = 0;     // stress-control mask the captured graphs were built for
+  // live timing of the row (x) tangent pass inside the CG iterations (rve_diag_time_pass):
+  // an event pair around each launch, harvested after each batch; launches of a batch
+  // after convergence (no-ops) are not counted
+  bool time_xt = false;
+  std::vector<hipEvent_t> xt_ev;          // 2 per launch of the current batch
+  std::vector<int> xt_iter;               // CG iteration of each pair
+  int xt_used = 0;
+  long long xt_launches = 0;
+  double xt_ms = 0.0;
   // macro stress and strain at time t (tensor components), the reference of the next
   // increment's stress-controlled components
   double msig_t[6] = {0, 0, 0, 0, 0, 0}, meps_t[6] = {0, 0, 0, 0, 0, 0};
@@ -435,6 +444,40 @@ struct Ops {
       launch_div<R>(h->pl, W, NH, q, NH, -1.0, st, stop);
     }
   }
+  // The row tangent pass of CG iteration k, with an event pair around it while live timing
+  // is on.
+  void timed_x_tangent(int k, const double* stop) {
+    if (!h->time_xt) {
+      launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
+      return;
+    }
+    if ((int)h->xt_ev.size() < 2 * (h->xt_used + 1)) {
+      hipEvent_t a = nullptr, b = nullptr;
+      if (hipEventCreate(&a) == hipSuccess) h->xt_ev.push_back(a);
+      if (hipEventCreate(&b) == hipSuccess) h->xt_ev.push_back(b);
+      h->xt_iter.resize(h->xt_ev.size() / 2);
+    }
+    const bool ok = (int)h->xt_ev.size() >= 2 * (h->xt_used + 1);
+    if (ok) (void)hipEventRecord(h->xt_ev[2 * h->xt_used], st);
+    launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
+    if (ok) {
+      (void)hipEventRecord(h->xt_ev[2 * h->xt_used + 1], st);
+      h->xt_iter[h->xt_used++] = k;
+    }
+  }
+  // After a batch (stream synchronised): add the pairs of the iterations that ran.
+  int harvest_x_tangent(int iters_run) {
+    for (int i = 0; i < h->xt_used; ++i) {
+      if (h->xt_iter[i] >= iters_run) continue;
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, h->xt_ev[2 * i], h->xt_ev[2 * i + 1]));
+      h->xt_ms += ms;
+      ++h->xt_launches;
+    }
+    h->xt_used = 0;
+    return RVE_OK;
+  }
+
   // Restarted GMRES(m) on M B du = M c (left preconditioning; the paper's Krylov solver):
   // classical Gram-Schmidt with one re-orthogonalisation, kGmChunk basis vectors per
   // block dot / update launch, Givens rotations and the small least-squares solve on the
@@ -621,7 +664,7 @@ struct Ops {
         if (mask)   // macro strain along the (0, 0) z column (z already inverse transformed)
           launch_macro_strain<R>(W, NH, pk, NH, s_mac, 0.0, mask, h->g.n3, zst, nullptr, st, stop);
         launch_fft_yz<R>(h->pl, W, NH, 6, 1, true, st, stop);
-        launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
+        timed_x_tangent(k, stop);
         launch_fft_yz<R>(h->pl, W, NH, 6, 1, false, st, stop);
         // q = -i xi~ . sigma^ with the partials of <p, q>; the step sums them
         int nbd = launch_zdiv_fwd<R>(h->pl, W, q, pk, NH, h->partial, st, stop);
@@ -640,7 +683,7 @@ struct Ops {
       if (mask) launch_macro_strain<R>(W, NH, p, NH, s_mac, 0.0, mask, 1, 0, nullptr, st, stop);
       launch_fft_yz<R>(h->pl, W, NH, 6, 2, true, st, stop);
       launch_fft_yz<R>(h->pl, W, NH, 6, 1, true, st, stop);
-      launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
+      timed_x_tangent(k, stop);
       launch_fft_yz<R>(h->pl, W, NH, 6, 1, false, st, stop);
       launch_fft_yz<R>(h->pl, W, NH, 6, 2, false, st, stop);
       // q = -i xi~ . sigma^ and <p, q> into sc[SC_PQ] (flag 2 if not positive)
@@ -661,7 +704,7 @@ struct Ops {
       const int nq = std::min(batch, h->d.max_krylov - queued);
       for (int kk = 0; kk < nq; ++kk) {
         const int k = queued + kk;
-        if (k == 0 || !h->use_graphs) {
+        if (k == 0 || !h->use_graphs || h->time_xt) {
           enqueue_iter(k);
           continue;
         }
@@ -691,6 +734,7 @@ struct Ops {
       rc = sync_read(h, SC_RZ0, SC_RRN - SC_RZ0 + 1);
       if (rc) return rc;
       iters = (int)h->hs[SC_ITER];
+      if ((rc = harvest_x_tangent(iters))) return rc;
       if (g_debug)
         std::fprintf(stderr, "  pcg queued %d ran %d flag %g rr %.3e tol2 %.3e pq %.3e\n", queued, iters,
                      h->hs[SC_FLAG], h->hs[SC_RRN], h->hs[SC_TOL2], h->hs[SC_PQ]);
@@ -1229,6 +1273,7 @@ int rve_destroy(rve_s* h) {
   else (void)hipDeviceSynchronize();
   for (hipGraphExec_t& e : h->cg_exec)
     if (e) (void)hipGraphExecDestroy(e);
+  for (hipEvent_t e : h->xt_ev) (void)hipEventDestroy(e);
   if (h->hs) (void)hipHostFree(h->hs);
   delete h;
   return RVE_OK;
@@ -1366,6 +1411,22 @@ int rve_diag_pass(rve_s* h, int32_t pass_id, int32_t reps, double* bytes) {
     return fail(RVE_E_ARG, "no fused z pass for this grid");
   if (pass_id == RVE_PASS_CONSTITUTIVE && !h->micro) return fail(RVE_E_STATE, "microstructure not set");
   return h->f64 ? diag_pass<double>(h, pass_id, reps, bytes) : diag_pass<float>(h, pass_id, reps, bytes);
+}
+
+int rve_diag_time_pass(rve_s* h, int32_t pass_id, int32_t on) {
+  if (!h || pass_id != RVE_PASS_X_TANGENT) return fail(RVE_E_ARG, "only RVE_PASS_X_TANGENT is timed live");
+  h->time_xt = on != 0;
+  h->xt_used = 0;
+  return RVE_OK;
+}
+
+int rve_diag_pass_time(rve_s* h, int64_t* launches, double* total_ms) {
+  if (!h || !launches || !total_ms) return fail(RVE_E_ARG, "null argument");
+  *launches = h->xt_launches;
+  *total_ms = h->xt_ms;
+  h->xt_launches = 0;
+  h->xt_ms = 0.0;
+  return RVE_OK;
 }
 
 int rve_diag_rfft(rve_s* h, int32_t ncomp, const double* in, double* out) {

@@ -89,6 +89,11 @@ def load():
                                            _D, _D, _D]
     lib.rve_step_increment.restype = ctypes.c_int
     lib.rve_step_increment.argtypes = [_P, _D, ctypes.c_double, ctypes.POINTER(RveStats)]
+    lib.rve_diag_time_pass.restype = ctypes.c_int
+    lib.rve_diag_time_pass.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
+    lib.rve_diag_pass_time.restype = ctypes.c_int
+    lib.rve_diag_pass_time.argtypes = [_P, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_double)]
     lib.rve_step_increment_mixed.restype = ctypes.c_int
     lib.rve_step_increment_mixed.argtypes = [_P, _D, _D, ctypes.c_int32, ctypes.c_double,
                                              ctypes.POINTER(RveStats)]
@@ -122,6 +127,7 @@ def exported_symbols():
     return ["rve_footprint_bytes", "rve_create", "rve_set_microstructure", "rve_step_increment",
             "rve_step_increment_mixed", "rve_fields", "rve_fields_count", "rve_destroy", "rve_last_error", "rve_diag_rfft",
             "rve_diag_irfft", "rve_diag_constitutive", "rve_diag_operator", "rve_diag_pass",
+            "rve_diag_time_pass", "rve_diag_pass_time",
             "rve_pool_step"]
 
 
@@ -295,6 +301,18 @@ class RVE:
         gk = np.empty(21 * self.nvox)
         _check(load().rve_diag_constitutive(self.h, _dptr(e), float(dt), _dptr(sig), _dptr(gk)))
         return sig.reshape(6, self.nvox).T, gk.reshape(21, self.nvox).T
+
+    def time_pass(self, name="x_tangent", on=True):
+        """Live timing of a kernel inside the solver's CG iterations (HIP events on the
+        handle's stream; CG iterations launched eagerly while on)."""
+        _check(load().rve_diag_time_pass(self.h, PASSES[name], 1 if on else 0))
+
+    def pass_time(self):
+        """(timed launches, their summed ms) since the previous call."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(load().rve_diag_pass_time(self.h, ctypes.byref(n), ctypes.byref(ms)))
+        return int(n.value), float(ms.value)
 
     def operator(self, u3):
         u = np.ascontiguousarray(np.asarray(u3, dtype=np.float64).T).ravel()
