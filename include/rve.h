@@ -252,7 +252,8 @@ int rve_diag_pass(struct rve_s* h, int32_t pass_id, int32_t reps, double* bytes_
 
 /* Live timing of one operator kernel inside the solver's own CG iterations: while on
  * (on != 0), every launch of the row tangent pass (pass_id RVE_PASS_X_TANGENT; other ids:
- * RVE_E_ARG) is bracketed by a HIP event pair on the handle's stream and the CG iterations
+ * RVE_E_ARG) records its start and end into a HIP event pair (hipExtLaunchKernel on the
+ * handle's stream) and the CG iterations
  * are launched eagerly instead of replayed from graphs; launches that follow convergence
  * within a batch (which return at once) are not counted.  rve_diag_pass_time returns the
  * number of timed launches and their summed duration [ms] since its previous call, and

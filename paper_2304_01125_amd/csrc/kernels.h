@@ -101,7 +101,8 @@ void launch_x_c2r(const Plans& p, const cplx<R>* in, long long in_cs, void* out,
                   const double* stop = nullptr);
 template <typename R>
 void launch_x_tangent(const Plans& p, cplx<R>* data, long long cs, const R* gK, double scale,
-                      hipStream_t st, const double* stop = nullptr);
+                      hipStream_t st, const double* stop = nullptr, hipEvent_t ev0 = nullptr,
+                      hipEvent_t ev1 = nullptr);
 template <typename R>
 void launch_fft_yz(const Plans& p, cplx<R>* data, long long cs, int ncomp, int axis, bool inv,
                    hipStream_t st, const double* stop = nullptr);

@@ -444,8 +444,8 @@ struct Ops {
       launch_div<R>(h->pl, W, NH, q, NH, -1.0, st, stop);
     }
   }
-  // The row tangent pass of CG iteration k, with an event pair around it while live timing
-  // is on.
+  // The row tangent pass of CG iteration k, timing itself into an event pair while live
+  // timing is on.
   void timed_x_tangent(int k, const double* stop) {
     if (!h->time_xt) {
       launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
@@ -458,12 +458,14 @@ struct Ops {
       h->xt_iter.resize(h->xt_ev.size() / 2);
     }
     const bool ok = (int)h->xt_ev.size() >= 2 * (h->xt_used + 1);
-    if (ok) (void)hipEventRecord(h->xt_ev[2 * h->xt_used], st);
-    launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
-    if (ok) {
-      (void)hipEventRecord(h->xt_ev[2 * h->xt_used + 1], st);
-      h->xt_iter[h->xt_used++] = k;
+    if (!ok) {
+      launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
+      return;
     }
+    // the launch timestamps its own start and end into the pair
+    launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop, h->xt_ev[2 * h->xt_used],
+                        h->xt_ev[2 * h->xt_used + 1]);
+    h->xt_iter[h->xt_used++] = k;
   }
   // After a batch (stream synchronised): add the pairs of the iterations that ran.
   int harvest_x_tangent(int iters_run) {
