@@ -35,7 +35,7 @@ from .constitutive import (GrainTables, return_map, slip_increments, PowerLaw, D
                            flow_law)
 from .spectral import Grid
 from .mechanics import solve_mechanics, momentum_operator
-from .phasefield import split_positive, we_plus, solve_phase_field
+from .phasefield import split_positive, we_plus, solve_phase_field, solve_phase_field_dirichlet
 from .history import nye_tensor, gnd_density
 from .increment import OracleRVE
 
@@ -43,5 +43,5 @@ __all__ = ["quat_to_rot", "cubic_stiffness", "rotate4", "fcc_slip_systems", "scr
            "to_mandel2", "from_mandel2", "to_mandel4", "from_mandel4", "gnd_matrix",
            "GrainTables", "return_map", "slip_increments", "PowerLaw", "DunneLaw", "flow_law", "Grid", "solve_mechanics",
            "momentum_operator",
-           "split_positive", "we_plus", "solve_phase_field", "nye_tensor", "gnd_density",
+           "split_positive", "we_plus", "solve_phase_field", "solve_phase_field_dirichlet", "nye_tensor", "gnd_density",
            "OracleRVE"]

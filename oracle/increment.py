@@ -32,7 +32,7 @@ from .constitutive import GrainTables, return_map, flow_law
 from .crystal import to_mandel2, from_mandel2
 from .spectral import Grid
 from .mechanics import solve_mechanics
-from .phasefield import we_plus, solve_phase_field
+from .phasefield import we_plus, solve_phase_field, solve_phase_field_dirichlet
 from .history import nye_tensor, gnd_density
 
 T6 = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
@@ -87,6 +87,9 @@ class OracleRVE:
         # voxels pre-set to full damage are the paper's geometric crack: a linear
         # elastic region (no slip) whose stiffness g(1) C = k C
         self.g[self.phi >= 1.0] = np.inf
+        # optionally those voxels hold phi = 1 as a Dirichlet condition of the phase field
+        self.preset = ~np.isfinite(self.g)
+        self.pf_dirichlet = bool(d.get("pf_dirichlet", 0)) and bool(self.preset.any())
         self.rho_gnd = np.zeros(M)
         self.Wp = np.zeros(M)
         self.Gs = np.zeros(M)
@@ -144,8 +147,13 @@ class OracleRVE:
             we = we_plus(eps_i - epsp_tr, t.C4[gid])
             S = np.where(self.trig, d["ell"] / d["Gc"] * np.maximum(0.0, we + wp_tr - self.Wcrit),
                          0.0)
-            phi_sol = solve_phase_field(grid, S, d["ell"], x0=phi_prev, rtol=d["tol_lin"],
-                                        max_iter=d["max_krylov"], stats=stats)
+            if self.pf_dirichlet:
+                phi_sol = solve_phase_field_dirichlet(grid, S, d["ell"], self.preset,
+                                                      rtol=d["tol_lin"], max_iter=d["max_krylov"],
+                                                      stats=stats)
+            else:
+                phi_sol = solve_phase_field(grid, S, d["ell"], x0=phi_prev, rtol=d["tol_lin"],
+                                            max_iter=d["max_krylov"], stats=stats)
             phi_i = np.minimum(1.0, np.maximum(phi_t, phi_sol))
             r_e = _ratio(np.abs(tensor6(eps_i - eps_prev)).max(),
                          np.abs(tensor6(eps_i - eps_t)).max())

@@ -9,6 +9,8 @@ eqs. strpf / phase: (phi - l^2 lap phi) - 2 (1 - phi) S = 0, i.e.
     (1 + 2S) phi - l^2 lap phi = 2S,
 solved here by conjugate gradients (the operator is symmetric positive definite)
 with the preconditioner of eq. precph read as F^-1{ (1 + l^2 |xi|^2)^-1 F{.} }.
+Optionally the pre-set crack voxels hold phi = 1 as a Dirichlet condition of the balance
+(instead of entering it as free unknowns that the clamp to [phi_t, 1] resets).
 """
 import numpy as np
 from scipy.sparse.linalg import LinearOperator, cg
@@ -25,6 +27,43 @@ def we_plus(E, C4):
     """1/2 eps+ : C : eps+ with eps+ the positive part of E; C4 (M,3,3,3,3)."""
     Ep = split_positive(E)
     return 0.5 * np.einsum("mij,mijkl,mkl->m", Ep, C4, Ep)
+
+
+def solve_phase_field_dirichlet(grid, S, ell, fixed, rtol=1e-12, max_iter=2000, stats=None):
+    """The same balance with phi = 1 held on the voxels of the boolean mask ``fixed`` (a
+    pre-set crack as a Dirichlet condition): phi = u + 1_fixed with u = 0 on ``fixed`` and,
+    on the free voxels F, P A P u = P (2S - A 1_fixed), A = (1 + 2S) - l^2 lap, P the
+    restriction to F; conjugate gradients with the restricted preconditioner
+    P (1 + l^2 |xi|^2)^-1 P (symmetric positive definite on F)."""
+    S = np.asarray(S, dtype=np.float64)
+    n = grid.n
+    free = grid.to_grid(~np.asarray(fixed, dtype=bool)).astype(np.float64).ravel()
+    phiD = 1.0 - free
+    S_g = grid.to_grid(S).ravel()
+    sym = 1.0 + ell ** 2 * grid.xi2
+    count = [0]
+
+    def lap_op(x):                       # -l^2 lap x
+        return grid.ifft(ell ** 2 * grid.xi2 * grid.fft(x.reshape(n))).ravel()
+
+    def matvec(x):
+        count[0] += 1
+        u = free * x
+        return free * ((1.0 + 2.0 * S_g) * u + lap_op(u))
+
+    def prec(x):
+        return free * grid.ifft(grid.fft((free * x).reshape(n)) / sym).ravel()
+
+    rhs = free * (2.0 * S_g - ((1.0 + 2.0 * S_g) * phiD + lap_op(phiD)))
+    N = S.size
+    A = LinearOperator((N, N), matvec=matvec, dtype=np.float64)
+    P = LinearOperator((N, N), matvec=prec, dtype=np.float64)
+    u, info = cg(A, rhs, rtol=rtol, atol=0.0, maxiter=max_iter, M=P)
+    if info != 0:
+        raise RuntimeError(f"phase-field CG did not converge (info={info})")
+    if stats is not None:
+        stats["pf_iters"] = stats.get("pf_iters", 0) + count[0]
+    return grid.to_flat((free * u + phiD).reshape(n))
 
 
 def solve_phase_field(grid, S, ell, x0=None, rtol=1e-12, max_iter=2000, stats=None):

@@ -109,3 +109,39 @@ def test_gnd_density_is_frame_independent():
     ref = np.sqrt(np.einsum("mi,ij,mj->m", lam_c.reshape(4, 9),
                             np.linalg.inv(A @ A.T), lam_c.reshape(4, 9))) / 3.5e-10
     assert np.allclose(rho, ref, rtol=1e-12)
+
+
+def test_dirichlet_phase_field_against_dense_solve_and_point_green_function():
+    """Pre-set crack voxels held at phi = 1 (Dirichlet option): brute force on a small grid
+    (the operator assembled column by column, the free block solved densely), the point
+    condition closed form phi = G(x - x0) / G(0) with G the discrete Green function of
+    1 - l^2 lap (S = 0), and no fixed voxel reducing to the free solve."""
+    from oracle import Grid, solve_phase_field, solve_phase_field_dirichlet
+    g = Grid((8, 4, 3), 1.0)
+    ell = 1.3
+    M = g.M
+    rng = np.random.default_rng(4)
+    S = rng.uniform(0.0, 2.0, M)
+    fixed = np.zeros(M, dtype=bool)
+    fixed[[3, 17, 40]] = True
+    # dense operator A = (1 + 2S) - l^2 lap on flat vectors
+    A = np.zeros((M, M))
+    for j in range(M):
+        e = np.zeros(M); e[j] = 1.0
+        lap = g.to_flat(g.ifft(ell ** 2 * g.xi2 * g.fft(g.to_grid(e))))
+        A[:, j] = (1.0 + 2.0 * S) * e + lap
+    F = ~fixed
+    phi_ref = np.ones(M)
+    phi_ref[F] = np.linalg.solve(A[np.ix_(F, F)], 2.0 * S[F] - A[np.ix_(F, fixed)] @ np.ones(3))
+    phi = solve_phase_field_dirichlet(g, S, ell, fixed, rtol=1e-14)
+    assert np.abs(phi - phi_ref).max() <= 1e-12
+    # point condition, S = 0
+    one = np.zeros(M, dtype=bool); one[21] = True
+    phi = solve_phase_field_dirichlet(g, np.zeros(M), ell, one, rtol=1e-14)
+    delta = np.zeros(M); delta[21] = 1.0
+    G = g.to_flat(g.ifft(g.fft(g.to_grid(delta)) / (1.0 + ell ** 2 * g.xi2)))
+    assert np.abs(phi - G / G[21]).max() <= 1e-12
+    # no fixed voxel: the free solve
+    a = solve_phase_field_dirichlet(g, S, ell, np.zeros(M, dtype=bool), rtol=1e-14)
+    b = solve_phase_field(g, S, ell, rtol=1e-14)
+    assert np.abs(a - b).max() <= 1e-12
