@@ -122,6 +122,13 @@ typedef struct rve_desc {
                                rotated finite-difference scheme, Sec. 3.1's discrete
                                derivative remedy); the phase field and the GND curl stay
                                spectral                                                 */
+  int32_t pf_dirichlet;     /* 0: the pre-set crack (voxels with phi0 >= 1) enters the
+                               phase-field balance (eqs. strpf, phase) as free unknowns
+                               that the irreversibility clamp holds at 1; 1: it is a
+                               Dirichlet condition phi = 1 of that balance, solved on the
+                               other voxels by CG with the restricted preconditioner
+                               (the geometric crack and soft buffers of Secs. 4.1 and
+                               4.5 read as a boundary value of the damage)               */
 } rve_desc;
 
 /* Per-increment report, filled by rve_step_increment (also on RVE_E_NOCONV). */

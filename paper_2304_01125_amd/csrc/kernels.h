@@ -162,7 +162,7 @@ void launch_herm_proj(const Plans& p, cplx<R>* v, long long cs, int ncomp, hipSt
                       const double* stop = nullptr);
 template <typename R>
 void launch_pf_scale(const Plans& p, cplx<R>* d, double ell, double scale, hipStream_t st,
-                     const double* stop = nullptr);
+                     const double* stop = nullptr, int lap = 0);
 template <typename R>
 void launch_curl_reg(const Plans& p, cplx<R>* b9, long long cs, double ell_fp, double scale,
                      hipStream_t st);
@@ -282,6 +282,18 @@ void launch_stag_norms(long long N, const double* eps, const double* eps_prev, c
 void launch_add_uniform(long long N, double* eps, const double de[6], hipStream_t st);
 // phi = min(1, max(phi_t, x))
 void launch_clamp(long long N, const double* x, const double* phi_t, double* phi, hipStream_t st);
+// Phase field with the pre-set crack (voxels with an infinite slip resistance) held at 1
+// (pfdir.hip).  mode 0: y = P x;  1: y = 1 - P 1 (the indicator of the crack);
+// 2: y = P ((1 + 2S) x + w);  3: y = P (2S - ((1 + 2S) x + w)); P the restriction to the
+// free voxels.  Each is a no-op once *stop is non-zero.
+void launch_pfd(long long N, int mode, const double* x, const double* w, const double* S,
+                const double* gslip, double* y, hipStream_t st, const double* stop = nullptr);
+// y += a x  (a = sign * sc[ia] / sc[ib] when sc is set, else a = sign)
+void launch_pfd_axpy(long long N, const double* sc, int ia, int ib, double sign, const double* x,
+                     double* y, hipStream_t st, const double* stop = nullptr);
+// p = z + (sc[ia] / sc[ib]) p
+void launch_pfd_xpby(long long N, const double* z, const double* sc, int ia, int ib, double* p,
+                     hipStream_t st, const double* stop = nullptr);
 
 // --- reductions and vector kernels (vector.hip) ---------------------------------------
 // out[c] = sum (or max) over b < nblk of partial[c*nblk + b], fixed order.

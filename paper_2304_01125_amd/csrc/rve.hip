@@ -257,6 +257,7 @@ struct rve_s {
   double msig_t[6] = {0, 0, 0, 0, 0, 0}, meps_t[6] = {0, 0, 0, 0, 0, 0};
   double* hs = nullptr;   // pinned host scalars
   bool micro = false;
+  long long n_preset = 0; // voxels of the pre-set crack (phi0 = 1)
   int n_grains = 0;
   int device = 0;         // device current at creation
 };
@@ -337,6 +338,7 @@ int validate(const rve_desc* d) {
     return fail(RVE_E_ARG, "gmres_restart must be in 1..64");
   if (d->deriv != RVE_DERIV_SPECTRAL && d->deriv != RVE_DERIV_ROTATED)
     return fail(RVE_E_ARG, "deriv must be RVE_DERIV_SPECTRAL or RVE_DERIV_ROTATED");
+  if (d->pf_dirichlet != 0 && d->pf_dirichlet != 1) return fail(RVE_E_ARG, "pf_dirichlet must be 0 or 1");
   if (d->material != RVE_MAT_POWER && d->material != RVE_MAT_DUNNE)
     return fail(RVE_E_ARG, "material must be RVE_MAT_POWER or RVE_MAT_DUNNE");
   if (d->material == RVE_MAT_POWER) {
@@ -760,6 +762,92 @@ struct Ops {
   }
 };
 
+// Phase-field balance with the pre-set crack held at phi = 1 (Dirichlet option): phi =
+// X + 1_crack, X from CG on P A P u = P (2S - A 1_crack), A = (1 + 2S) - l^2 lap, with the
+// restricted preconditioner P (1 - l^2 lap)^-1 P; P restricts to the voxels that can slip.
+// The Laplacian and the preconditioner are FFT round trips; convergence control on the
+// device in batches, as in the other Krylov loops.  Writes phi before the clamp into X
+// (rbuf[0, N)); adds the matrix-vector products to *iters.
+template <typename R>
+int pf_dirichlet_solve(rve_s* h, Ops<R>& o, int* iters) {
+  typedef cplx<R> C;
+  hipStream_t st = h->st;
+  const long long N = h->g.nvox;
+  const double invN = 1.0 / (double)N;
+  C* W1 = (C*)h->spec;
+  double* X = h->rbuf;
+  double *Rr = h->rbuf + N, *Z = h->rbuf + 2 * N, *P = h->rbuf + 3 * N, *Wv = h->rbuf + 4 * N;
+  double *Q = h->rbuf + 5 * N, *Y = h->rbuf + 6 * N;
+  double* sc = h->scal;
+  // out = F^-1 f(xi) F in, f = l^2 |xi|^2 (lap) or (1 + l^2 |xi|^2)^-1
+  auto spec_op = [&](const double* in, double* outp, int lap, const double* stp) {
+    launch_x_r2c<R>(h->pl, in, true, N, nullptr, 0.0, W1, o.NH, 1, st, stp);
+    launch_fft_yz<R>(h->pl, W1, o.NH, 1, 1, false, st, stp);
+    launch_fft_yz<R>(h->pl, W1, o.NH, 1, 2, false, st, stp);
+    launch_pf_scale<R>(h->pl, W1, h->d.ell, invN, st, stp, lap);
+    launch_fft_yz<R>(h->pl, W1, o.NH, 1, 2, true, st, stp);
+    launch_fft_yz<R>(h->pl, W1, o.NH, 1, 1, true, st, stp);
+    launch_x_c2r<R>(h->pl, W1, o.NH, outp, true, N, 1, 1.0, 0, st, stp);
+  };
+  int rc;
+  launch_zero(X, N * 8, st);
+  launch_pfd(N, 1, nullptr, nullptr, nullptr, h->gslip, Y, st);
+  spec_op(Y, Wv, 1, nullptr);
+  launch_pfd(N, 3, Y, Wv, h->S, h->gslip, Rr, st);
+  int nb = launch_rdot(N, Rr, Rr, h->partial, st);
+  launch_reduce(h->partial, nb, 1, 0, sc + SC_BB, st);
+  if ((rc = sync_read(h, SC_BB, 1))) return rc;
+  const double bb = h->hs[SC_BB];
+  if (!std::isfinite(bb)) return fail(RVE_E_NOCONV, "non-finite phase-field residual");
+  if (bb > 0.0) {
+    h->hs[SC_FLAG] = 0.0;
+    h->hs[SC_ITER] = 0.0;
+    h->hs[SC_TOL2] = h->d.tol_lin * h->d.tol_lin * bb;
+    HIPCHK(hipMemcpyAsync(sc + SC_FLAG, h->hs + SC_FLAG, 3 * sizeof(double),
+                          hipMemcpyHostToDevice, st));
+    const double* stop = sc + SC_FLAG;
+    spec_op(Rr, Wv, 0, nullptr);
+    launch_pfd(N, 0, Wv, nullptr, nullptr, h->gslip, Z, st);
+    nb = launch_rdot(N, Rr, Z, h->partial, st);
+    launch_reduce(h->partial, nb, 1, 0, sc + SC_RZ0, st);
+    HIPCHK(hipMemcpyAsync(P, Z, N * 8, hipMemcpyDeviceToDevice, st));
+    bool ok = false;
+    int queued = 0, batch = 4;
+    while (queued < h->d.max_krylov) {
+      const int nq = std::min(batch, h->d.max_krylov - queued);
+      for (int kk = 0; kk < nq; ++kk) {
+        const int k = queued + kk;
+        const int cur = SC_RZ0 + (k & 1), nxt = SC_RZ0 + ((k + 1) & 1);
+        spec_op(P, Wv, 1, stop);
+        launch_pfd(N, 2, P, Wv, h->S, h->gslip, Q, st, stop);
+        nb = launch_rdot(N, P, Q, h->partial, st, stop);
+        launch_reduce(h->partial, nb, 1, 0, sc + SC_PQ, st, stop);
+        launch_pfd_axpy(N, sc, cur, SC_PQ, 1.0, P, X, st, stop);
+        launch_pfd_axpy(N, sc, cur, SC_PQ, -1.0, Q, Rr, st, stop);
+        nb = launch_rdot(N, Rr, Rr, h->partial, st, stop);
+        launch_reduce(h->partial, nb, 1, 0, sc + SC_RR, st, stop);
+        launch_pf_check(sc, SC_FLAG, SC_ITER, SC_PQ, SC_RR, SC_TOL2, st);
+        spec_op(Rr, Wv, 0, stop);
+        launch_pfd(N, 0, Wv, nullptr, nullptr, h->gslip, Z, st, stop);
+        nb = launch_rdot(N, Rr, Z, h->partial, st, stop);
+        launch_reduce(h->partial, nb, 1, 0, sc + nxt, st, stop);
+        launch_pfd_xpby(N, Z, sc, nxt, cur, P, st, stop);
+      }
+      queued += nq;
+      if ((rc = sync_read(h, SC_FLAG, 2))) return rc;
+      if (h->hs[SC_FLAG] != 0.0) {
+        ok = h->hs[SC_FLAG] == 1.0;
+        break;
+      }
+      batch = std::min(2 * batch, 16);
+    }
+    *iters += (int)h->hs[SC_ITER];
+    if (!ok) return fail(RVE_E_NOCONV, "phase-field Krylov solver did not converge");
+  }
+  launch_pfd_axpy(N, nullptr, 0, 0, 1.0, Y, X, st);
+  return RVE_OK;
+}
+
 template <typename R>
 int run_increment(rve_s* h, const double de_in[6], const double* dsig, int mask, double dt,
                   rve_stats* out) {
@@ -881,7 +969,12 @@ int run_increment(rve_s* h, const double de_in[6], const double* dsig, int mask,
       double* X = h->rbuf;
       double *Rr = h->rbuf + N, *Z = h->rbuf + 2 * N, *P = h->rbuf + 3 * N, *Wv = h->rbuf + 4 * N;
       launch_zero(X, N * 8, st);
-      if (sumS > 0.0) {
+      if (h->d.pf_dirichlet && h->n_preset > 0) {
+        if ((rc = pf_dirichlet_solve<R>(h, o, &s.pf_iters))) {
+          s.ms_phase_field += now_ms() - tp;
+          goto fail_out;
+        }
+      } else if (sumS > 0.0) {
         typedef cplx<R> C;
         C* W1 = (C*)h->spec;
         const double bb = 4.0 * sumS2;
@@ -1133,6 +1226,8 @@ int rve_set_microstructure(rve_s* h, const int32_t* grain, int32_t n_grains, con
     }
     g[v] = (ph[v] >= 1.0) ? INFINITY : (tau0 ? tau0[grain[v]] : h->d.tau_c0) + taylor0;
   }
+  h->n_preset = 0;
+  for (long long v = 0; v < N; ++v) h->n_preset += ph[v] >= 1.0;
   hipStream_t st = h->st;
   HIPCHK(hipMemcpyAsync(h->gtab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(h->grain, grain, N * 4, hipMemcpyHostToDevice, st));

@@ -617,15 +617,18 @@ __global__ void __launch_bounds__(256) k_precond(const cplx<R>* __restrict__ r, 
 
 // d *= scale / (1 + l^2 |xi|^2)  (1 component)
 template <typename R>
+// d *= scale / (1 + l^2 |xi|^2) (lap = 0: the phase-field preconditioner), or
+// d *= scale l^2 |xi|^2 (lap = 1: the operator -l^2 lap)
 __global__ void __launch_bounds__(256) k_pf_scale(cplx<R>* __restrict__ d, double ell, double scale, Grid g,
-                                                  const double* __restrict__ stop) {
+                                                  const double* __restrict__ stop, int lap) {
   if (stop && *stop != 0.0) return;
   for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < g.nspec;
        b += (long long)gridDim.x * blockDim.x) {
     const Bin q = bin_of(b, g);
     const double x1 = freq(q.kx, g.n1, g.L1, false), x2 = freq(q.ky, g.n2, g.L2, false),
                  x3 = freq(q.kz, g.n3, g.L3, false);
-    const double s = scale / (1.0 + ell * ell * (x1 * x1 + x2 * x2 + x3 * x3));
+    const double l2x2 = ell * ell * (x1 * x1 + x2 * x2 + x3 * x3);
+    const double s = lap ? scale * l2x2 : scale / (1.0 + l2x2);
     const cplx<R> v = d[b];
     d[b] = cplx<R>{(R)(s * (double)v.x), (R)(s * (double)v.y)};
   }
@@ -694,9 +697,9 @@ int launch_precond(const Plans& p, const cplx<R>* r, cplx<R>* z, long long cs, c
 
 template <typename R>
 void launch_pf_scale(const Plans& p, cplx<R>* d, double ell, double scale, hipStream_t st,
-                     const double* stop) {
+                     const double* stop, int lap) {
   hipLaunchKernelGGL((k_pf_scale<R>), dim3(grid_for(p.g.nspec)), dim3(256), 0, st, d, ell, scale,
-                     p.g, stop);
+                     p.g, stop, lap);
 }
 
 template <typename R>
@@ -715,7 +718,7 @@ void launch_curl_reg(const Plans& p, cplx<R>* b9, long long cs, double ell_fp, d
                                  const double*, double*, hipStream_t, const double*,             \
                                  const double*);                                                 \
   template void launch_pf_scale<R>(const Plans&, cplx<R>*, double, double, hipStream_t,          \
-                                   const double*);                                               \
+                                   const double*, int);                                          \
   template void launch_curl_reg<R>(const Plans&, cplx<R>*, long long, double, double, hipStream_t);
 
 RVE_INST(double)

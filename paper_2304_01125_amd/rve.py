@@ -43,7 +43,8 @@ class RveDesc(ctypes.Structure):
                 ("rho_m", ctypes.c_double), ("v_D", ctypes.c_double), ("dF", ctypes.c_double),
                 ("k_B", ctypes.c_double), ("T", ctypes.c_double), ("dV", ctypes.c_double),
                 ("mu", ctypes.c_double), ("krylov", ctypes.c_int32),
-                ("gmres_restart", ctypes.c_int32), ("deriv", ctypes.c_int32)]
+                ("gmres_restart", ctypes.c_int32), ("deriv", ctypes.c_int32),
+                ("pf_dirichlet", ctypes.c_int32)]
 
 
 class RveStats(ctypes.Structure):
@@ -161,6 +162,7 @@ def make_desc(desc, precision=RVE_FP64, max_grains=4096):
     d.max_krylov = int(desc["max_krylov"])
     d.max_grains = int(max_grains)
     d.deriv = int(desc.get("scheme", 0))
+    d.pf_dirichlet = int(desc.get("pf_dirichlet", 0))
     d.krylov = int(desc.get("krylov", 0))
     d.gmres_restart = int(desc.get("gmres_restart", 30))
     d.material = int(desc.get("material", RVE_MAT_POWER))

@@ -108,7 +108,8 @@ def test_material_derivative_and_mixed_control_arguments_are_validated():
     for key, val, msg in [("material", 2, "material"), ("scheme", 3, "deriv"),
                           ("dV", 0.0, "thermally activated"), ("mu", -1.0, "thermally activated"),
                           ("T", float("inf"), "thermally activated"),
-                          ("krylov", 2, "krylov"), ("gmres_restart", 0, "gmres_restart")]:
+                          ("krylov", 2, "krylov"), ("gmres_restart", 0, "gmres_restart"),
+                          ("pf_dirichlet", 2, "pf_dirichlet")]:
         d = p.make_desc(dict(base, **{key: val}))
         assert p.rve_footprint_bytes(d) == 0, key
         assert msg in lib.rve_last_error().decode(), (key, lib.rve_last_error())
