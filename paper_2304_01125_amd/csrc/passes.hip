@@ -166,8 +166,13 @@ k_fft_strided_reg(cplx<R>* __restrict__ data, long long cs, int axis, Grid g,
   __shared__ cplx<R> tw[N];
   for (int t = threadIdx.x; t < N; t += NT) tw[t] = tw_g[t];
   const int ntiles = NYQ ? (g.n1 / 2) / TX : (g.n1h + TX - 1) / TX;
-  const int tile = blockIdx.x % ntiles;
-  const int other = blockIdx.x / ntiles;
+  // blocks are dispatched to the 8 XCDs in turn: when the count allows, XCD j takes a
+  // contiguous range of (tile, line) units, so that the tiles of one line, whose row
+  // segments share the 128-B lines at the tile boundaries, meet in that XCD's L2
+  int unit = blockIdx.x;
+  if ((gridDim.x & 7) == 0) unit = (unit & 7) * (gridDim.x >> 3) + (unit >> 3);
+  const int tile = unit % ntiles;
+  const int other = unit / ntiles;
   const int kx0 = tile * TX;
   long long stride_n, base;
   if (axis == 1) { stride_n = g.n1h; base = (long long)other * g.n1h * g.n2; }

@@ -5,7 +5,9 @@
 // makes an extra trip through HBM.  A work unit is a tile of x-bins at one ky; each
 // block takes one component of one unit.  When the units come in multiples of 8, the
 // blocks of one unit are numbered 8 apart, so they are dispatched to the same XCD one
-// after the other and meet the operands they share in its L2.
+// after the other and meet the operands they share in its L2; each XCD takes a contiguous
+// range of units, so that the tiles of one row (whose segments share the 128-B lines at
+// the tile boundaries: rows of N1/2 + 1 bins do not start on a line) meet there too.
 #include "passutil.h"
 
 namespace rvefft {
@@ -15,7 +17,7 @@ __device__ __forceinline__ void unit_comp(int nunits, int ncomp, int& u, int& c)
   if ((nunits & 7) == 0) {
     const int x = bid & 7, s = bid >> 3;
     c = s % ncomp;
-    u = (s / ncomp) * 8 + x;
+    u = x * (nunits >> 3) + s / ncomp;
   } else {
     c = bid % ncomp;
     u = bid / ncomp;
@@ -199,8 +201,11 @@ k_zgrad_inv(const cplx<R>* __restrict__ zv, const cplx<R>* __restrict__ pold,
 }
 
 // Component i of q = -i xi~ . F_z{s} and the block partial of the Parseval-weighted
-// <p, q>, in two rounds: xi~_z F_z{s_iz} first (its result waits in LDS), then
-// F_z{xi~_x s_ix + xi~_y s_iy}, whose x and y factors are constant along z.
+// <p, q>, in two rounds: xi~_z F_z{s_iz} and F_z{xi~_x s_ix + xi~_y s_iy} (whose x and y
+// factors are constant along z); the first round's result waits in LDS.  Components x and
+// y take the z round first, component z the other: the three blocks of a work unit (one
+// XCD, dispatched together) then read each shared stress component (xz, yz, xy) in the
+// same round, so that the second read comes from L2.
 template <typename R, int N, int TX, int NT, int SCH>
 __global__ void __launch_bounds__(NT)
 k_zdiv_fwd(const cplx<R>* __restrict__ s, cplx<R>* __restrict__ q, const cplx<R>* __restrict__ pv,
@@ -239,7 +244,7 @@ k_zdiv_fwd(const cplx<R>* __restrict__ s, cplx<R>* __restrict__ q, const cplx<R>
   __syncthreads();
 #pragma unroll
   for (int round = 0; round < 2; ++round) {
-    const bool zr = (round == 0);                               // the xi~_z round
+    const bool zr = (i == 2) ? (round == 1) : (round == 0);     // the xi~_z round
     for (int t = threadIdx.x; t < P * Nb; t += NT) {
       const int x = t % P, n1 = t / P;
       const int cx = col(x);
