@@ -438,52 +438,82 @@ k_cg_step(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __res
   const double al = sc[cur] / pq;
   const bool even = (g.n1 % 2 == 0);
   double rr = 0.0, rz = 0.0;
-  for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < g.nspec;
-       b += (long long)gridDim.x * blockDim.x) {
-    const Bin q = bin_of(b, g);
-    const double t[3] = {freq(q.kx, g.n1, g.L1, true), freq(q.ky, g.n2, g.L2, true),
-                         freq(q.kz, g.n3, g.L3, true)};
-    const bool mac = m0 && b == 0;           // macro unknowns: no projection, z = m0 r
-    const bool selfconj = !mac && ((q.kx == 0) || (even && q.kx == g.n1 / 2));
-    const long long bp = selfconj ? partner_bin(q, g) : b;
-    cplx<R> rv[3], zo[3];
-    for (int c = 0; c < 3; ++c) {
-      const long long i = c * cs + b;
-      // streamed: x and r are touched here only, once per iteration; streaming p and q as
-      // well measured faster for the passes that follow
-      const cplx<R> pp = ld_stream(pv + i);
-      cplx<R> qq = ld_stream(qv + i);
-      if (selfconj) {
-        const cplx<R> qo = qv[c * cs + bp];
-        qq = cplx<R>{R(0.5) * (qq.x + qo.x), R(0.5) * (qq.y - qo.y)};
+  // FP32 vectors: two bins per thread and trip, one grid stride apart (coalescing as with
+  // one), all their loads issued first, so that twice the bytes are in flight per wave
+  constexpr int V = sizeof(R) == 4 ? 2 : 1;
+  const long long S = (long long)gridDim.x * blockDim.x;
+  for (long long b0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; b0 < g.nspec;
+       b0 += V * S) {
+    cplx<R> pl[V][3], ql[V][3], xl[V][3], rl[V][3];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const long long b = b0 + v * S;
+      if (b >= g.nspec) break;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        // streamed: x and r are touched here only, once per iteration; streaming p and q as
+        // well measured faster for the passes that follow
+        const long long i = c * cs + b;
+        pl[v][c] = ld_stream(pv + i);
+        ql[v][c] = ld_stream(qv + i);
+        xl[v][c] = ld_stream(x + i);
+        rl[v][c] = ld_stream(r + i);
       }
-      cplx<R> xx = ld_stream(x + i), rr_ = ld_stream(r + i);
-      xx.x = (R)((double)xx.x + al * (double)pp.x);
-      xx.y = (R)((double)xx.y + al * (double)pp.y);
-      rr_.x = (R)((double)rr_.x - al * (double)qq.x);
-      rr_.y = (R)((double)rr_.y - al * (double)qq.y);
-      st_stream(x + i, xx);
-      r[i] = rr_;
-      rv[c] = rr_;
     }
-    if (mac) {
-      apply_M0(m0, rv, zo);
-    } else if constexpr (SCH == 0) {
-      apply_M(t, K4, rv, zo);
-    } else {
-      cplx<double> kk[3];
-      kvec(g, q.kx, q.ky, q.kz, kk);
-      apply_Mk(kk, K4, rv, zo);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const long long b = b0 + v * S;
+      if (b >= g.nspec) break;
+      const Bin q = bin_of(b, g);
+      const double t[3] = {freq(q.kx, g.n1, g.L1, true), freq(q.ky, g.n2, g.L2, true),
+                           freq(q.kz, g.n3, g.L3, true)};
+      const bool mac = m0 && b == 0;           // macro unknowns: no projection, z = m0 r
+      const bool selfconj = !mac && ((q.kx == 0) || (even && q.kx == g.n1 / 2));
+      const long long bp = selfconj ? partner_bin(q, g) : b;
+      cplx<R> rv[3], zo[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const long long i = c * cs + b;
+        const cplx<R> pp = pl[v][c];
+        cplx<R> qq = ql[v][c];
+        if (selfconj) {
+          const cplx<R> qo = qv[c * cs + bp];
+          qq = cplx<R>{R(0.5) * (qq.x + qo.x), R(0.5) * (qq.y - qo.y)};
+        }
+        cplx<R> xx = xl[v][c], rr_ = rl[v][c];
+        xx.x = (R)((double)xx.x + al * (double)pp.x);
+        xx.y = (R)((double)xx.y + al * (double)pp.y);
+        rr_.x = (R)((double)rr_.x - al * (double)qq.x);
+        rr_.y = (R)((double)rr_.y - al * (double)qq.y);
+        st_stream(x + i, xx);
+        r[i] = rr_;
+        rv[c] = rr_;
+      }
+      // an offset the compiler cannot see through: it would otherwise hoist the 81
+      // loop-invariant K4 reads out of the loop into registers (169 VGPRs, two waves per
+      // SIMD); LDS reads per bin cost less than the lost occupancy
+      int koff = 0;
+      asm volatile("" : "+v"(koff));
+      const double* K4b = K4 + koff;
+      if (mac) {
+        apply_M0(m0, rv, zo);
+      } else if constexpr (SCH == 0) {
+        apply_M(t, K4b, rv, zo);
+      } else {
+        cplx<double> kk[3];
+        kvec(g, q.kx, q.ky, q.kz, kk);
+        apply_Mk(kk, K4b, rv, zo);
+      }
+      double a = 0.0, bz = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        z[c * cs + b] = zo[c];
+        a += (double)rv[c].x * (double)rv[c].x + (double)rv[c].y * (double)rv[c].y;
+        bz += (double)rv[c].x * (double)zo[c].x + (double)rv[c].y * (double)zo[c].y;
+      }
+      const double w = parseval_w(q.kx, g.n1);
+      rr += w * a;
+      rz += w * bz;
     }
-    double a = 0.0, bz = 0.0;
-    for (int c = 0; c < 3; ++c) {
-      z[c * cs + b] = zo[c];
-      a += (double)rv[c].x * (double)rv[c].x + (double)rv[c].y * (double)rv[c].y;
-      bz += (double)rv[c].x * (double)zo[c].x + (double)rv[c].y * (double)zo[c].y;
-    }
-    const double w = parseval_w(q.kx, g.n1);
-    rr += w * a;
-    rz += w * bz;
   }
   for (int off = 32; off > 0; off >>= 1) {
     rr += __shfl_down(rr, off, 64);
@@ -569,42 +599,17 @@ __global__ void __launch_bounds__(256) k_precond(const cplx<R>* __restrict__ r, 
       }
     }
     cplx<R> zo[3] = {{0, 0}, {0, 0}, {0, 0}};
+    int koff = 0;                            // keeps the K4 reads in the loop, see k_cg_step
+    asm volatile("" : "+v"(koff));
+    const double* K4b = K4 + koff;
     if (mac) {
       apply_M0(m0, ri, zo);
     } else if (g.sch) {
       cplx<double> kk[3];
       kvec(g, q.kx, q.ky, q.kz, kk);
-      apply_Mk(kk, K4, ri, zo);
-    } else if (t[0] != 0.0 || t[1] != 0.0 || t[2] != 0.0) {
-      double A[3][3];
-      for (int i = 0; i < 3; ++i)
-        for (int k = i; k < 3; ++k) {
-          double s = 0.0;
-          for (int j = 0; j < 3; ++j)
-            for (int l = 0; l < 3; ++l) s += t[j] * K4[((i * 3 + j) * 3 + k) * 3 + l] * t[l];
-          A[i][k] = s;
-          A[k][i] = s;
-        }
-      const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
-      const double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
-      const double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
-      const double det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
-      const double id = 1.0 / det;
-      double Mi[3][3];
-      Mi[0][0] = c00 * id;
-      Mi[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * id;
-      Mi[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * id;
-      Mi[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * id;
-      Mi[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * id;
-      Mi[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * id;
-      Mi[1][0] = Mi[0][1];
-      Mi[2][0] = Mi[0][2];
-      Mi[2][1] = Mi[1][2];
-      for (int i = 0; i < 3; ++i) {
-        double zx = 0, zy = 0;
-        for (int k = 0; k < 3; ++k) { zx += Mi[i][k] * (double)ri[k].x; zy += Mi[i][k] * (double)ri[k].y; }
-        zo[i] = cplx<R>{(R)zx, (R)zy};
-      }
+      apply_Mk(kk, K4b, ri, zo);
+    } else {
+      apply_M(t, K4b, ri, zo);
     }
     z[b] = zo[0];
     z[cs + b] = zo[1];
