@@ -292,9 +292,9 @@ static bool launch_strided_reg(const Plans& p, cplx<R>* data, long long cs, int 
   const Grid& g = p.g;
   const bool even = (g.n1 % 2 == 0);
   const int half = g.n1 / 2;
-  // FP64 pencils: 16-bin tiles (more blocks in flight) measured faster than 32 at 128^3;
-  // FP32: 32-bin tiles
-  const int cap = sizeof(R) == 8 ? 16 : 32;
+  // 16-bin tiles (more blocks in flight) measured fastest at 128^3 in both precisions
+  // (FP64: 33-35 us against 34-35 at 8 bins; FP32: 18-19 us against 19-21 at 32 or 8)
+  const int cap = 16;
   if (cap >= 32 && even && half % 32 == 0 && reg_lds<R>(N, 33) <= kRegLdsMax)
     launch_reg_tx<R, N, 32, true>(p, data, cs, ncomp, axis, inv, st, stop);
   else if (cap >= 16 && even && half % 16 == 0 && reg_lds<R>(N, 17) <= kRegLdsMax)
