@@ -328,6 +328,7 @@ void launch_x_tangent(const Plans& p, cplx<R>* data, long long cs, const R* gK, 
         }
       };
       if constexpr (NC <= 64) go.template operator()<8, 256>();
+      else if constexpr (NC >= 256) go.template operator()<1, 256>();   // 967 against 992 us at 256^3
       else go.template operator()<1, 128>();
     }
   });
