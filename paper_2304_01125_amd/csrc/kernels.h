@@ -141,17 +141,20 @@ template <typename R>
 int launch_zdiv_fwd(const Plans& p, const cplx<R>* s, cplx<R>* q, const cplx<R>* pv, long long cs,
                     double* partial, hipStream_t st, const double* stop = nullptr);
 // One CG step after the operator: alpha = sc[cur] / sc[ipq]; x += alpha p;
-// r -= alpha h(q), with h the Hermitian projection of the self-conjugate x-planes
-// applied on the fly; z = M r; block partials of <r, r> and <r, z> at partial[0][blk],
+// z -= alpha M h(q), with h the Hermitian projection of the self-conjugate x-planes
+// applied on the fly (the preconditioned residual z = M r, updated in place: M acts per
+// bin, so r itself is not stored); r = M^-1 z per bin (the acoustic tensor, zero on the
+// null bins where M is zero); block partials of <r, r> and <r, z> at partial[0][blk],
 // partial[1][blk].  Returns #blocks.
 // With pq_part set, every block first sums the nb_pq partials of <p, q> itself (and
 // block 0 stores the sum in sc[ipq], the breakdown flag in sc[iflag] and counts the
 // iteration in sc[iiter]); otherwise <p, q> is read from sc[ipq].  max_blocks bounds the
 // grid (and so the partials).
 // With m0 set (mixed macroscopic control) the zero bin holds the macro unknowns: it is
-// not projected and z(0) = m0 r(0) (6 x 6 on the bin's six reals).
+// not projected, z(0) -= alpha m0 q(0) and r(0) = m0[36..] z(0) (6 x 6 on the bin's six
+// reals: m0 and its inverse on the stress-controlled block).
 template <typename R>
-int launch_cg_step(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, const cplx<R>* q,
+int launch_cg_step(const Plans& p, cplx<R>* x, const cplx<R>* pv, const cplx<R>* q,
                    cplx<R>* z, long long cs, const double* kbar21, double* sc, int cur, int ipq,
                    double* partial, hipStream_t st, const double* stop,
                    const double* pq_part = nullptr, int nb_pq = 0, int iflag = 0, int iiter = 0,
@@ -205,7 +208,8 @@ void launch_macro_stress(const cplx<R>* sg, long long scs, cplx<R>* q, const cpl
 template <typename R>
 void launch_macro_rhs(const cplx<R>* sg, long long scs, cplx<R>* b, long long cs, double s,
                       double n, const double tgt[6], int mask, hipStream_t st);
-// m0 = (s2 Kbar_FF)^-1 (36 doubles, zero outside the stress-controlled block)
+// m0[0..36) = (s2 Kbar_FF)^-1 and m0[36..72) = s2 Kbar_FF (6 x 6 each, zero outside the
+// stress-controlled block)
 void launch_macro_prec(const double* kbar21, double s2, int mask, double* m0, hipStream_t st);
 
 // --- voxel kernels (voxel.hip) -------------------------------------------------------

@@ -111,6 +111,7 @@ k_macro_rhs(const cplx<R>* __restrict__ sg, long long scs, cplx<R>* __restrict__
 // strain-controlled rows and columns are replaced by those of the identity, the 6 x 6 is
 // inverted by Gauss-Jordan elimination without pivoting (symmetric positive definite),
 // fully unrolled so that it stays in registers, and those rows and columns are cleared.
+// The block s^2 Kbar_FF itself follows (the CG step recovers r(0) = M0^-1 z(0) with it).
 __global__ void __launch_bounds__(64)
 k_macro_prec(const double* __restrict__ kbar21, double s2, int mask, double* __restrict__ m0) {
   if (threadIdx.x != 0) return;
@@ -145,8 +146,11 @@ k_macro_prec(const double* __restrict__ kbar21, double s2, int mask, double* __r
 #pragma unroll
   for (int i = 0; i < 6; ++i)
 #pragma unroll
-    for (int j = 0; j < 6; ++j)
-      m0[i * 6 + j] = (((mask >> i) & 1) && ((mask >> j) & 1)) ? B[i][j] : 0.0;
+    for (int j = 0; j < 6; ++j) {
+      const bool f = ((mask >> i) & 1) && ((mask >> j) & 1);
+      m0[i * 6 + j] = f ? B[i][j] : 0.0;
+      m0[36 + i * 6 + j] = f ? s2 * kbar21[pk6(i, j)] : 0.0;   // the block itself
+    }
 }
 
 template <typename R>

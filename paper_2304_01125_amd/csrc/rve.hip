@@ -270,13 +270,13 @@ enum { SC_K = 0,        // 28 constitutive sums (21 gK, g w, 6 g sigma)
        SC_FLAG = 61, SC_ITER = 62, SC_TOL2 = 63,
        SC_ZERO = 80, SC_ONE = 81, SC_RRN = 82, SC_RZN = 83,
        SC_MISC = 64,    // generic reduce outputs (16)
-       SC_M0 = 96,      // 36: macro-block preconditioner (mixed control)
+       SC_M0 = 360,     // 72: macro-block preconditioner and the block it inverts (mixed control)
        SC_DE = 132,     // 6: macro strain increment of a Newton step (mixed control)
        SC_GN = 140,     // GMRES: a norm
        SC_GM = 144,     // GMRES: Gram-Schmidt coefficients, first pass (up to 65)
        SC_GM2 = 216,    // GMRES: second pass
        SC_GY = 288,     // GMRES: least-squares solution (up to 64)
-       SC_N = 360 };
+       SC_N = 432 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -613,15 +613,15 @@ struct Ops {
   // enqueued in batches; the convergence test runs on the device and turns the rest of
   // a batch into no-ops, so the host synchronises once per batch.
   int pcg(int& iters) {
-    C *x = v(0), *r = v(1), *z = v(2), *p = v(3), *q = v(4), *b = v(5);
+    C *x = v(0), *z = v(2), *p = v(3), *q = v(4), *b = v(5);
     const size_t bytes = (size_t)3 * NH * sizeof(C);
     double* sc = h->scal;
     launch_zero(x, bytes, st);
     launch_zero(p, bytes, st);      // the first iteration forms p = z + 0 * p
-    HIPCHK(hipMemcpyAsync(r, b, bytes, hipMemcpyDeviceToDevice, st));
     int nb = launch_sdot<R>(h->pl, b, b, NH, 3, h->partial, st);
     launch_reduce(h->partial, nb, 1, 0, sc + SC_BB, st);
-    nb = launch_precond<R>(h->pl, r, z, NH, sc + SC_KBAR, h->partial, st, nullptr, m0());
+    // z = M r with r = b; the steps update z in place (r is not stored)
+    nb = launch_precond<R>(h->pl, b, z, NH, sc + SC_KBAR, h->partial, st, nullptr, m0());
     launch_reduce(h->partial, nb, 1, 0, sc + SC_RZ0, st);
     int rc = sync_read(h, SC_BB, 1);
     if (rc) return rc;
@@ -637,7 +637,7 @@ struct Ops {
     HIPCHK(hipMemcpyAsync(sc + SC_ZERO, h->hs + SC_ZERO, 2 * sizeof(double), hipMemcpyHostToDevice, st));
     const double* stop = sc + SC_FLAG;
     // With the fused z passes the direction alternates between two buffers (the
-    // right-hand side is no longer needed once r = b): each iteration reads p_old and
+    // right-hand side is no longer needed once z = M b is formed): each iteration reads p_old and
     // writes p_new while other blocks still read p_old.
     const bool fz = fused_z_available<R>(h->pl);
     // the captured graphs hold the macro launches of one stress-control mask
@@ -677,7 +677,7 @@ struct Ops {
                                  stop);
           ++nbd;
         }
-        nb_cg = launch_cg_step<R>(h->pl, x, r, pk, q, z, NH, sc + SC_KBAR, sc, cur, SC_PQ,
+        nb_cg = launch_cg_step<R>(h->pl, x, pk, q, z, NH, sc + SC_KBAR, sc, cur, SC_PQ,
                                   cg_part, st, stop, h->partial, nbd, SC_FLAG, SC_ITER,
                                   kCgMaxBlocks, m0());
         return;
@@ -697,8 +697,8 @@ struct Ops {
         ++nb;
       }
       launch_reduce_pq(h->partial, nb, sc, SC_PQ, SC_FLAG, st);
-      // x, r, z updates, <r, r>, <r, z> and the convergence test
-      nb = launch_cg_step<R>(h->pl, x, r, p, q, z, NH, sc + SC_KBAR, sc, cur, SC_PQ,
+      // x and z updates, <r, r>, <r, z> and the convergence test
+      nb = launch_cg_step<R>(h->pl, x, p, q, z, NH, sc + SC_KBAR, sc, cur, SC_PQ,
                              h->partial, st, stop, nullptr, 0, 0, 0, 1 << 30, m0());
       launch_reduce_check(h->partial, nb, sc, SC_ITER, prv, SC_RRN, SC_FLAG, SC_TOL2, st);
     };

@@ -218,11 +218,31 @@ __device__ __forceinline__ void apply_M0(const double* __restrict__ m0, const cp
   zo[2] = cplx<R>{(R)zm[2], (R)zm[4]};
 }
 
-// zo = [t . K . t]^-1 ri (zero where t = 0), t = xi~ of the bin.
+// ro = F zi on the zero bin's six reals (as apply_M0), in FP64
+template <typename R>
+__device__ __forceinline__ void apply_F0(const double* __restrict__ f, const cplx<R> zi[3],
+                                         cplx<double> ro[3]) {
+  const double zm[6] = {(double)zi[0].x, (double)zi[1].x, (double)zi[2].x,
+                        (double)zi[1].y, (double)zi[2].y, (double)zi[0].y};
+  double rm[6];
+  for (int i = 0; i < 6; ++i) {
+    double a = 0.0;
+    for (int j = 0; j < 6; ++j) a += f[i * 6 + j] * zm[j];
+    rm[i] = a;
+  }
+  ro[0] = cplx<double>{rm[0], rm[5]};
+  ro[1] = cplx<double>{rm[1], rm[3]};
+  ro[2] = cplx<double>{rm[2], rm[4]};
+}
+
+// zo = [t . K . t]^-1 ri (zero where t = 0), t = xi~ of the bin; with As set, the acoustic
+// tensor t . K . t itself (upper triangle: 00 01 02 11 12 22; zero where t = 0).
 template <typename R>
 __device__ __forceinline__ void apply_M(const double t[3], const double* K4, const cplx<R> ri[3],
-                                        cplx<R> zo[3]) {
+                                        cplx<R> zo[3], double* As = nullptr) {
   zo[0] = zo[1] = zo[2] = cplx<R>{0, 0};
+  if (As)
+    for (int i = 0; i < 6; ++i) As[i] = 0.0;
   if (t[0] == 0.0 && t[1] == 0.0 && t[2] == 0.0) return;
   double A[3][3];
   for (int i = 0; i < 3; ++i)
@@ -233,6 +253,10 @@ __device__ __forceinline__ void apply_M(const double t[3], const double* K4, con
       A[i][k] = s;
       A[k][i] = s;
     }
+  if (As) {
+    As[0] = A[0][0]; As[1] = A[0][1]; As[2] = A[0][2];
+    As[3] = A[1][1]; As[4] = A[1][2]; As[5] = A[2][2];
+  }
   const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
   const double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
   const double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
@@ -258,8 +282,11 @@ __device__ __forceinline__ void apply_M(const double t[3], const double* K4, con
 // general derivative symbol, inverted by its adjugate.
 template <typename R>
 __device__ __forceinline__ void apply_Mk(const cplx<double> k[3], const double* K4,
-                                         const cplx<R> ri[3], cplx<R> zo[3]) {
+                                         const cplx<R> ri[3], cplx<R> zo[3],
+                                         cplx<double>* Ah = nullptr) {
   zo[0] = zo[1] = zo[2] = cplx<R>{0, 0};
+  if (Ah)
+    for (int i = 0; i < 6; ++i) Ah[i] = cplx<double>{0.0, 0.0};
   if (k[0].x == 0.0 && k[0].y == 0.0 && k[1].x == 0.0 && k[1].y == 0.0 && k[2].x == 0.0 &&
       k[2].y == 0.0)
     return;
@@ -283,6 +310,10 @@ __device__ __forceinline__ void apply_Mk(const cplx<double> k[3], const double* 
       A[i][m] = cplx<double>{sr, si};
       A[m][i] = cplx<double>{sr, -si};
     }
+  if (Ah) {
+    Ah[0] = A[0][0]; Ah[1] = A[0][1]; Ah[2] = A[0][2];
+    Ah[3] = A[1][1]; Ah[4] = A[1][2]; Ah[5] = A[2][2];
+  }
   auto c = [&](int i0, int j0, int i1, int j1) {   // A[i0][j0] A[i1][j1] - A[i0][j1] A[i1][j0]
     return csub(cmul(A[i0][j0], A[i1][j1]), cmul(A[i0][j1], A[i1][j0]));
   };
@@ -411,7 +442,7 @@ int launch_div_dot(const Plans& p, const cplx<R>* s, cplx<R>* q, const cplx<R>* 
 // preconditioner (0 spectral, 1 rotated).
 template <typename R, int SCH>
 __global__ void __launch_bounds__(256)
-k_cg_step(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __restrict__ pv,
+k_cg_step(cplx<R>* __restrict__ x, const cplx<R>* __restrict__ pv,
           const cplx<R>* __restrict__ qv, cplx<R>* __restrict__ z, long long cs,
           const double* __restrict__ kbar21, double* __restrict__ sc, int cur, int ipq,
           Grid g, double* __restrict__ partial, const double* __restrict__ stop,
@@ -444,20 +475,20 @@ k_cg_step(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __res
   const long long S = (long long)gridDim.x * blockDim.x;
   for (long long b0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; b0 < g.nspec;
        b0 += V * S) {
-    cplx<R> pl[V][3], ql[V][3], xl[V][3], rl[V][3];
+    cplx<R> pl[V][3], ql[V][3], xl[V][3], zl[V][3];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       const long long b = b0 + v * S;
       if (b >= g.nspec) break;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        // streamed: x and r are touched here only, once per iteration; streaming p and q as
-        // well measured faster for the passes that follow
+        // streamed: x is touched here only, once per iteration; streaming p and q as well
+        // measured faster for the passes that follow
         const long long i = c * cs + b;
         pl[v][c] = ld_stream(pv + i);
         ql[v][c] = ld_stream(qv + i);
         xl[v][c] = ld_stream(x + i);
-        rl[v][c] = ld_stream(r + i);
+        zl[v][c] = z[i];
       }
     }
 #pragma unroll
@@ -470,7 +501,7 @@ k_cg_step(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __res
       const bool mac = m0 && b == 0;           // macro unknowns: no projection, z = m0 r
       const bool selfconj = !mac && ((q.kx == 0) || (even && q.kx == g.n1 / 2));
       const long long bp = selfconj ? partner_bin(q, g) : b;
-      cplx<R> rv[3], zo[3];
+      cplx<R> hq[3], mq[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const long long i = c * cs + b;
@@ -480,14 +511,11 @@ k_cg_step(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __res
           const cplx<R> qo = qv[c * cs + bp];
           qq = cplx<R>{R(0.5) * (qq.x + qo.x), R(0.5) * (qq.y - qo.y)};
         }
-        cplx<R> xx = xl[v][c], rr_ = rl[v][c];
+        hq[c] = qq;
+        cplx<R> xx = xl[v][c];
         xx.x = (R)((double)xx.x + al * (double)pp.x);
         xx.y = (R)((double)xx.y + al * (double)pp.y);
-        rr_.x = (R)((double)rr_.x - al * (double)qq.x);
-        rr_.y = (R)((double)rr_.y - al * (double)qq.y);
         st_stream(x + i, xx);
-        r[i] = rr_;
-        rv[c] = rr_;
       }
       // an offset the compiler cannot see through: it would otherwise hoist the 81
       // loop-invariant K4 reads out of the loop into registers (169 VGPRs, two waves per
@@ -495,20 +523,59 @@ k_cg_step(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __res
       int koff = 0;
       asm volatile("" : "+v"(koff));
       const double* K4b = K4 + koff;
+      // z -= alpha M h(q) (M is per bin, so z = M r stays exact without storing r), then
+      // r = M^-1 z from the same per-bin tensor for <r, r> and <r, z>
+      cplx<R> zn[3];
+      cplx<double> rd[3];
+      auto z_update = [&]() {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          zn[c] = cplx<R>{(R)((double)zl[v][c].x - al * (double)mq[c].x),
+                          (R)((double)zl[v][c].y - al * (double)mq[c].y)};
+          z[c * cs + b] = zn[c];
+        }
+      };
       if (mac) {
-        apply_M0(m0, rv, zo);
+        apply_M0(m0, hq, mq);
+        z_update();
+        apply_F0(m0 + 36, zn, rd);
       } else if constexpr (SCH == 0) {
-        apply_M(t, K4b, rv, zo);
+        double As[6];
+        apply_M(t, K4b, hq, mq, As);
+        z_update();
+        const double A[3][3] = {{As[0], As[1], As[2]}, {As[1], As[3], As[4]},
+                                {As[2], As[4], As[5]}};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          double rx = 0.0, ry = 0.0;
+#pragma unroll
+          for (int m = 0; m < 3; ++m) {
+            rx += A[i][m] * (double)zn[m].x;
+            ry += A[i][m] * (double)zn[m].y;
+          }
+          rd[i] = cplx<double>{rx, ry};
+        }
       } else {
-        cplx<double> kk[3];
+        cplx<double> kk[3], Ah[6];
         kvec(g, q.kx, q.ky, q.kz, kk);
-        apply_Mk(kk, K4b, rv, zo);
+        apply_Mk(kk, K4b, hq, mq, Ah);
+        z_update();
+        const cplx<double> A[3][3] = {{Ah[0], Ah[1], Ah[2]},
+                                      {cconj(Ah[1]), Ah[3], Ah[4]},
+                                      {cconj(Ah[2]), cconj(Ah[4]), Ah[5]}};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          cplx<double> acc{0.0, 0.0};
+#pragma unroll
+          for (int m = 0; m < 3; ++m)
+            acc = cadd(acc, cmul(A[i][m], cplx<double>{(double)zn[m].x, (double)zn[m].y}));
+          rd[i] = acc;
+        }
       }
       double a = 0.0, bz = 0.0;
       for (int c = 0; c < 3; ++c) {
-        z[c * cs + b] = zo[c];
-        a += (double)rv[c].x * (double)rv[c].x + (double)rv[c].y * (double)rv[c].y;
-        bz += (double)rv[c].x * (double)zo[c].x + (double)rv[c].y * (double)zo[c].y;
+        a += rd[c].x * rd[c].x + rd[c].y * rd[c].y;
+        bz += rd[c].x * (double)zn[c].x + rd[c].y * (double)zn[c].y;
       }
       const double w = parseval_w(q.kx, g.n1);
       rr += w * a;
@@ -530,25 +597,25 @@ k_cg_step(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __res
 }
 
 template <typename R>
-int launch_cg_step(const Plans& p, cplx<R>* x, cplx<R>* r, const cplx<R>* pv, const cplx<R>* q,
+int launch_cg_step(const Plans& p, cplx<R>* x, const cplx<R>* pv, const cplx<R>* q,
                    cplx<R>* z, long long cs, const double* kbar21, double* sc, int cur, int ipq,
                    double* partial, hipStream_t st, const double* stop, const double* pq_part,
                    int nb_pq, int iflag, int iiter, int max_blocks, const double* m0) {
   const int nb = std::min(grid_for(p.g.nspec), max_blocks);
   if (p.g.sch)
-    hipLaunchKernelGGL((k_cg_step<R, 1>), dim3(nb), dim3(256), 0, st, x, r, pv, q, z, cs, kbar21,
+    hipLaunchKernelGGL((k_cg_step<R, 1>), dim3(nb), dim3(256), 0, st, x, pv, q, z, cs, kbar21,
                        sc, cur, ipq, p.g, partial, stop, pq_part, nb_pq, iflag, iiter, m0);
   else
-    hipLaunchKernelGGL((k_cg_step<R, 0>), dim3(nb), dim3(256), 0, st, x, r, pv, q, z, cs, kbar21,
+    hipLaunchKernelGGL((k_cg_step<R, 0>), dim3(nb), dim3(256), 0, st, x, pv, q, z, cs, kbar21,
                        sc, cur, ipq, p.g, partial, stop, pq_part, nb_pq, iflag, iiter, m0);
   return nb;
 }
-template int launch_cg_step<double>(const Plans&, cplx<double>*, cplx<double>*,
+template int launch_cg_step<double>(const Plans&, cplx<double>*,
                                     const cplx<double>*, const cplx<double>*, cplx<double>*,
                                     long long, const double*, double*, int, int, double*,
                                     hipStream_t, const double*, const double*, int, int, int,
                                     int, const double*);
-template int launch_cg_step<float>(const Plans&, cplx<float>*, cplx<float>*, const cplx<float>*,
+template int launch_cg_step<float>(const Plans&, cplx<float>*, const cplx<float>*,
                                    const cplx<float>*, cplx<float>*, long long, const double*,
                                    double*, int, int, double*, hipStream_t, const double*,
                                    const double*, int, int, int, int, const double*);
