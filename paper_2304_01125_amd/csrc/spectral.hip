@@ -469,118 +469,104 @@ k_cg_step(cplx<R>* __restrict__ x, const cplx<R>* __restrict__ pv,
   const double al = sc[cur] / pq;
   const bool even = (g.n1 % 2 == 0);
   double rr = 0.0, rz = 0.0;
-  // FP32 vectors: two bins per thread and trip, one grid stride apart (coalescing as with
-  // one), all their loads issued first, so that twice the bytes are in flight per wave
-  constexpr int V = sizeof(R) == 4 ? 2 : 1;
-  const long long S = (long long)gridDim.x * blockDim.x;
-  for (long long b0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; b0 < g.nspec;
-       b0 += V * S) {
-    cplx<R> pl[V][3], ql[V][3], xl[V][3], zl[V][3];
+  for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < g.nspec;
+       b += (long long)gridDim.x * blockDim.x) {
+    cplx<R> pl[3], ql[3], xl[3], zl[3];
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      const long long b = b0 + v * S;
-      if (b >= g.nspec) break;
+    for (int c = 0; c < 3; ++c) {
+      // streamed: x is touched here only, once per iteration; streaming p and q as well
+      // measured faster for the passes that follow
+      const long long i = c * cs + b;
+      pl[c] = ld_stream(pv + i);
+      ql[c] = ld_stream(qv + i);
+      xl[c] = ld_stream(x + i);
+      zl[c] = z[i];
+    }
+    const Bin q = bin_of(b, g);
+    const double t[3] = {freq(q.kx, g.n1, g.L1, true), freq(q.ky, g.n2, g.L2, true),
+                         freq(q.kz, g.n3, g.L3, true)};
+    const bool mac = m0 && b == 0;           // macro unknowns: no projection, z = m0 r
+    const bool selfconj = !mac && ((q.kx == 0) || (even && q.kx == g.n1 / 2));
+    const long long bp = selfconj ? partner_bin(q, g) : b;
+    cplx<R> hq[3], mq[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const long long i = c * cs + b;
+      const cplx<R> pp = pl[c];
+      cplx<R> qq = ql[c];
+      if (selfconj) {
+        const cplx<R> qo = qv[c * cs + bp];
+        qq = cplx<R>{R(0.5) * (qq.x + qo.x), R(0.5) * (qq.y - qo.y)};
+      }
+      hq[c] = qq;
+      cplx<R> xx = xl[c];
+      xx.x = (R)((double)xx.x + al * (double)pp.x);
+      xx.y = (R)((double)xx.y + al * (double)pp.y);
+      st_stream(x + i, xx);
+    }
+    // an offset the compiler cannot see through: it would otherwise hoist the 81
+    // loop-invariant K4 reads out of the loop into registers (169 VGPRs, two waves per
+    // SIMD); LDS reads per bin cost less than the lost occupancy
+    int koff = 0;
+    asm volatile("" : "+v"(koff));
+    const double* K4b = K4 + koff;
+    // z -= alpha M h(q) (M is per bin, so z = M r stays exact without storing r), then
+    // r = M^-1 z from the same per-bin tensor for <r, r> and <r, z>
+    cplx<R> zn[3];
+    cplx<double> rd[3];
+    auto z_update = [&]() {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        // streamed: x is touched here only, once per iteration; streaming p and q as well
-        // measured faster for the passes that follow
-        const long long i = c * cs + b;
-        pl[v][c] = ld_stream(pv + i);
-        ql[v][c] = ld_stream(qv + i);
-        xl[v][c] = ld_stream(x + i);
-        zl[v][c] = z[i];
+        zn[c] = cplx<R>{(R)((double)zl[c].x - al * (double)mq[c].x),
+                        (R)((double)zl[c].y - al * (double)mq[c].y)};
+        z[c * cs + b] = zn[c];
+      }
+    };
+    if (mac) {
+      apply_M0(m0, hq, mq);
+      z_update();
+      apply_F0(m0 + 36, zn, rd);
+    } else if constexpr (SCH == 0) {
+      double As[6];
+      apply_M(t, K4b, hq, mq, As);
+      z_update();
+      const double A[3][3] = {{As[0], As[1], As[2]}, {As[1], As[3], As[4]},
+                              {As[2], As[4], As[5]}};
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        double rx = 0.0, ry = 0.0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          rx += A[i][m] * (double)zn[m].x;
+          ry += A[i][m] * (double)zn[m].y;
+        }
+        rd[i] = cplx<double>{rx, ry};
+      }
+    } else {
+      cplx<double> kk[3], Ah[6];
+      kvec(g, q.kx, q.ky, q.kz, kk);
+      apply_Mk(kk, K4b, hq, mq, Ah);
+      z_update();
+      const cplx<double> A[3][3] = {{Ah[0], Ah[1], Ah[2]},
+                                    {cconj(Ah[1]), Ah[3], Ah[4]},
+                                    {cconj(Ah[2]), cconj(Ah[4]), Ah[5]}};
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        cplx<double> acc{0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+          acc = cadd(acc, cmul(A[i][m], cplx<double>{(double)zn[m].x, (double)zn[m].y}));
+        rd[i] = acc;
       }
     }
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      const long long b = b0 + v * S;
-      if (b >= g.nspec) break;
-      const Bin q = bin_of(b, g);
-      const double t[3] = {freq(q.kx, g.n1, g.L1, true), freq(q.ky, g.n2, g.L2, true),
-                           freq(q.kz, g.n3, g.L3, true)};
-      const bool mac = m0 && b == 0;           // macro unknowns: no projection, z = m0 r
-      const bool selfconj = !mac && ((q.kx == 0) || (even && q.kx == g.n1 / 2));
-      const long long bp = selfconj ? partner_bin(q, g) : b;
-      cplx<R> hq[3], mq[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const long long i = c * cs + b;
-        const cplx<R> pp = pl[v][c];
-        cplx<R> qq = ql[v][c];
-        if (selfconj) {
-          const cplx<R> qo = qv[c * cs + bp];
-          qq = cplx<R>{R(0.5) * (qq.x + qo.x), R(0.5) * (qq.y - qo.y)};
-        }
-        hq[c] = qq;
-        cplx<R> xx = xl[v][c];
-        xx.x = (R)((double)xx.x + al * (double)pp.x);
-        xx.y = (R)((double)xx.y + al * (double)pp.y);
-        st_stream(x + i, xx);
-      }
-      // an offset the compiler cannot see through: it would otherwise hoist the 81
-      // loop-invariant K4 reads out of the loop into registers (169 VGPRs, two waves per
-      // SIMD); LDS reads per bin cost less than the lost occupancy
-      int koff = 0;
-      asm volatile("" : "+v"(koff));
-      const double* K4b = K4 + koff;
-      // z -= alpha M h(q) (M is per bin, so z = M r stays exact without storing r), then
-      // r = M^-1 z from the same per-bin tensor for <r, r> and <r, z>
-      cplx<R> zn[3];
-      cplx<double> rd[3];
-      auto z_update = [&]() {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          zn[c] = cplx<R>{(R)((double)zl[v][c].x - al * (double)mq[c].x),
-                          (R)((double)zl[v][c].y - al * (double)mq[c].y)};
-          z[c * cs + b] = zn[c];
-        }
-      };
-      if (mac) {
-        apply_M0(m0, hq, mq);
-        z_update();
-        apply_F0(m0 + 36, zn, rd);
-      } else if constexpr (SCH == 0) {
-        double As[6];
-        apply_M(t, K4b, hq, mq, As);
-        z_update();
-        const double A[3][3] = {{As[0], As[1], As[2]}, {As[1], As[3], As[4]},
-                                {As[2], As[4], As[5]}};
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          double rx = 0.0, ry = 0.0;
-#pragma unroll
-          for (int m = 0; m < 3; ++m) {
-            rx += A[i][m] * (double)zn[m].x;
-            ry += A[i][m] * (double)zn[m].y;
-          }
-          rd[i] = cplx<double>{rx, ry};
-        }
-      } else {
-        cplx<double> kk[3], Ah[6];
-        kvec(g, q.kx, q.ky, q.kz, kk);
-        apply_Mk(kk, K4b, hq, mq, Ah);
-        z_update();
-        const cplx<double> A[3][3] = {{Ah[0], Ah[1], Ah[2]},
-                                      {cconj(Ah[1]), Ah[3], Ah[4]},
-                                      {cconj(Ah[2]), cconj(Ah[4]), Ah[5]}};
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          cplx<double> acc{0.0, 0.0};
-#pragma unroll
-          for (int m = 0; m < 3; ++m)
-            acc = cadd(acc, cmul(A[i][m], cplx<double>{(double)zn[m].x, (double)zn[m].y}));
-          rd[i] = acc;
-        }
-      }
-      double a = 0.0, bz = 0.0;
-      for (int c = 0; c < 3; ++c) {
-        a += rd[c].x * rd[c].x + rd[c].y * rd[c].y;
-        bz += rd[c].x * (double)zn[c].x + rd[c].y * (double)zn[c].y;
-      }
-      const double w = parseval_w(q.kx, g.n1);
-      rr += w * a;
-      rz += w * bz;
+    double a = 0.0, bz = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      a += rd[c].x * rd[c].x + rd[c].y * rd[c].y;
+      bz += rd[c].x * (double)zn[c].x + rd[c].y * (double)zn[c].y;
     }
+    const double w = parseval_w(q.kx, g.n1);
+    rr += w * a;
+    rz += w * bz;
   }
   for (int off = 32; off > 0; off >>= 1) {
     rr += __shfl_down(rr, off, 64);
