@@ -69,3 +69,27 @@ def test_mixed_precision_macro_stress():
     phi = gpu.fields(("damage",))["damage"]
     assert np.all(phi[phi0 >= 1.0] == 1.0)
     gpu.close()
+
+
+@pytest.mark.parametrize("free", [0, 1])
+def test_degenerate_cracks_match_oracle(free):
+    """The crack covers every voxel (nothing to solve: phi stays 1) or all but one."""
+    from paper_2304_01125_amd import RVE
+    print(f"Dirichlet crack covering all voxels but {free}, 8x8x4", flush=True)
+    w = small_polycrystal(n=(8, 8, 4), n_grains=2, seed=3).parity()
+    inp = make_inputs(w)
+    phi0 = np.ones(w.nvox)
+    if free:
+        phi0[37] = 0.0
+    gpu = RVE(dict(w.desc(), pf_dirichlet=1), 0)
+    gpu.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], phi0)
+    ora = OracleRVE(dict(w.desc(), pf_dirichlet=1), inp["grain"], inp["quat"], inp["tau_c0"], phi0)
+    for k in range(2):
+        de = [0, inp["deps"][k], 0, 0, 0, 0]
+        gpu.step(de, inp["dt"][k])
+        ora.step(de, inp["dt"][k])
+    phi = gpu.fields(("damage",))["damage"]
+    assert np.all(phi[phi0 >= 1.0] == 1.0)
+    assert np.abs(phi - ora.phi).max() <= 1e-8
+    compare(gpu, ora)
+    gpu.close()

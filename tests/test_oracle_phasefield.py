@@ -145,3 +145,24 @@ def test_dirichlet_phase_field_against_dense_solve_and_point_green_function():
     a = solve_phase_field_dirichlet(g, S, ell, np.zeros(M, dtype=bool), rtol=1e-14)
     b = solve_phase_field(g, S, ell, rtol=1e-14)
     assert np.abs(a - b).max() <= 1e-12
+
+
+def test_dirichlet_phase_field_degenerate_sets():
+    """Every voxel fixed: nothing to solve, phi = 1; a single free voxel: the scalar balance
+    (1 + 2S + l^2 lap_0) u = 2S - (1 + 2S) * 0 - l^2 (lap 1_fixed)_0 written out by hand."""
+    from oracle import Grid, solve_phase_field_dirichlet
+    g = Grid((4, 4, 2), 1.0)
+    M = g.M
+    S = np.linspace(0.0, 1.0, M)
+    phi = solve_phase_field_dirichlet(g, S, 0.7, np.ones(M, dtype=bool), rtol=1e-14)
+    assert np.all(phi == 1.0)
+    fixed = np.ones(M, dtype=bool)
+    fixed[5] = False
+    ell = 0.7
+    phi = solve_phase_field_dirichlet(g, S, ell, fixed, rtol=1e-14)
+    # diagonal of -l^2 lap (spectral): l^2 mean(|xi|^2); its action on 1_fixed at voxel 5:
+    # -l^2 lap 1 = 0 for the constant field, so -l^2 lap 1_fixed = l^2 lap e_5 = -diag e_5
+    d = ell ** 2 * g.xi2.mean()
+    u = (2.0 * S[5] + d) / (1.0 + 2.0 * S[5] + d)
+    assert abs(phi[5] - u) <= 1e-12
+    assert np.all(phi[fixed] == 1.0)
