@@ -64,6 +64,9 @@ def parse():
     return ap.parse_args()
 
 
+LIVE_EVERY = 8     # CG iterations per live-timed launch of the roofline kernel
+
+
 def run_leg(RVE, precision, desc, inp, warmup, steps, torch, stress_mask=0, live=False):
     r = RVE(desc, precision)
     r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
@@ -72,8 +75,9 @@ def run_leg(RVE, precision, desc, inp, warmup, steps, torch, stress_mask=0, live
     for k in range(warmup):
         st = r.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k], **kw)
         macro.append(st["macro_stress"])
-    if live:            # HIP events around every row tangent pass of the timed increments
-        r.time_pass("x_tangent", True)
+    if live:            # HIP events around the row tangent pass of every 8th CG iteration of
+        # the timed increments (a recording launch costs the kernels next to it a few us)
+        r.time_pass("x_tangent", True, every=LIVE_EVERY)
         r.pass_time()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -268,7 +272,8 @@ def main():
     dom = max(per_mv, key=lambda k: per_mv[k] * passes[k]["ms"])
     d = passes[dom]
     # the dominant kernel (the row tangent pass) timed live inside the timed increments:
-    # HIP events on the library's stream around each of its launches
+    # HIP events on the library's stream around its launch in every LIVE_EVERY-th CG
+    # iteration (the same kernel on the same data each time)
     n_live, ms_live = r64.live
     avg = ms_live / n_live if (dom == "x_tangent" and n_live) else d["ms"]
     gbs = d["bytes"] / (avg * 1e-3) / 1e9

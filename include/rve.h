@@ -258,13 +258,15 @@ enum {
 int rve_diag_pass(struct rve_s* h, int32_t pass_id, int32_t reps, double* bytes_per_launch);
 
 /* Live timing of one operator kernel inside the solver's own CG iterations: while on
- * (on != 0), every launch of the row tangent pass (pass_id RVE_PASS_X_TANGENT; other ids:
- * RVE_E_ARG) records its start and end into a HIP event pair (hipExtLaunchKernel on the
- * handle's stream) and the CG iterations
- * are launched eagerly instead of replayed from graphs; launches that follow convergence
- * within a batch (which return at once) are not counted.  rve_diag_pass_time returns the
- * number of timed launches and their summed duration [ms] since its previous call, and
- * resets both. */
+ * (on > 0), the launch of the row tangent pass (pass_id RVE_PASS_X_TANGENT; other ids:
+ * RVE_E_ARG) in every on-th CG iteration (k = 0, on, 2 on, ... of each solve; on = 1:
+ * every iteration) records its start and end into a HIP event pair (hipExtLaunchKernel on
+ * the handle's stream); those iterations are launched eagerly instead of replayed from
+ * graphs (the event-recording launch costs the kernels around it a few microseconds, which
+ * a sparse sample keeps out of most iterations).  on = 0 switches timing off; on < 0:
+ * RVE_E_ARG.  Launches that follow convergence within a batch (which return at once) are
+ * not counted.  rve_diag_pass_time returns the number of timed launches and their summed
+ * duration [ms] since its previous call, and resets both. */
 int rve_diag_time_pass(struct rve_s* h, int32_t pass_id, int32_t on);
 int rve_diag_pass_time(struct rve_s* h, int64_t* launches, double* total_ms);
 

@@ -244,9 +244,9 @@ struct rve_s {
   hipGraphExec_t cg_exec[2] = {nullptr, nullptr};
   int graph_mask = 0;     // stress-control mask the captured graphs were built for
   // live timing of the row (x) tangent pass inside the CG iterations (rve_diag_time_pass):
-  // an event pair around each launch, harvested after each batch; launches of a batch
-  // after convergence (no-ops) are not counted
-  bool time_xt = false;
+  // an event pair around the launch of every time_xt-th iteration (0: off), harvested
+  // after each batch; launches of a batch after convergence (no-ops) are not counted
+  int time_xt = 0;
   std::vector<hipEvent_t> xt_ev;          // 2 per launch of the current batch
   std::vector<int> xt_iter;               // CG iteration of each pair
   int xt_used = 0;
@@ -448,8 +448,9 @@ struct Ops {
   }
   // The row tangent pass of CG iteration k, timing itself into an event pair while live
   // timing is on.
+  bool timed_iter(int k) const { return h->time_xt > 0 && k % h->time_xt == 0; }
   void timed_x_tangent(int k, const double* stop) {
-    if (!h->time_xt) {
+    if (!timed_iter(k)) {
       launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
       return;
     }
@@ -708,7 +709,8 @@ struct Ops {
       const int nq = std::min(batch, h->d.max_krylov - queued);
       for (int kk = 0; kk < nq; ++kk) {
         const int k = queued + kk;
-        if (k == 0 || !h->use_graphs || h->time_xt) {
+        // timed iterations run eagerly (their launch records an event pair)
+        if (k == 0 || !h->use_graphs || timed_iter(k)) {
           enqueue_iter(k);
           continue;
         }
@@ -1148,8 +1150,12 @@ int rve_create(const rve_desc* d, void* dev_arena, size_t arena_bytes, void* hip
   (void)hipGetDevice(&h->device);
   crystal_frame(h->d.C11, h->d.C12, h->d.C44, &h->cf);
   {
+    // CG iterations replay captured graphs on small, launch-bound grids only: at 128^3
+    // eager launches measured faster (a replay leaves ~8 us before the next graph's first
+    // kernel); RVE_GRAPHS=1 / 0 forces either way
     const char* ev = std::getenv("RVE_GRAPHS");
-    h->use_graphs = (h->st != nullptr) && !(ev && ev[0] == '0');
+    const bool small = h->g.nvox <= 64LL * 64 * 64;
+    h->use_graphs = (h->st != nullptr) && (ev ? ev[0] == '1' : small);
   }
   if (hipHostMalloc((void**)&h->hs, SC_N * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     delete h;
@@ -1512,7 +1518,8 @@ int rve_diag_pass(rve_s* h, int32_t pass_id, int32_t reps, double* bytes) {
 
 int rve_diag_time_pass(rve_s* h, int32_t pass_id, int32_t on) {
   if (!h || pass_id != RVE_PASS_X_TANGENT) return fail(RVE_E_ARG, "only RVE_PASS_X_TANGENT is timed live");
-  h->time_xt = on != 0;
+  if (on < 0) return fail(RVE_E_ARG, "negative timing period");
+  h->time_xt = on;
   h->xt_used = 0;
   return RVE_OK;
 }

@@ -304,10 +304,11 @@ class RVE:
         _check(load().rve_diag_constitutive(self.h, _dptr(e), float(dt), _dptr(sig), _dptr(gk)))
         return sig.reshape(6, self.nvox).T, gk.reshape(21, self.nvox).T
 
-    def time_pass(self, name="x_tangent", on=True):
+    def time_pass(self, name="x_tangent", on=True, every=1):
         """Live timing of a kernel inside the solver's CG iterations (HIP events on the
-        handle's stream; CG iterations launched eagerly while on)."""
-        _check(load().rve_diag_time_pass(self.h, PASSES[name], 1 if on else 0))
+        handle's stream) in every `every`-th iteration of each solve; the timed
+        iterations are launched eagerly."""
+        _check(load().rve_diag_time_pass(self.h, PASSES[name], int(every) if on else 0))
 
     def pass_time(self):
         """(timed launches, their summed ms) since the previous call."""
