@@ -297,7 +297,7 @@ k_zdiv_fwd(const cplx<R>* __restrict__ s, cplx<R>* __restrict__ q, const cplx<R>
           for (int k1 = 0; k1 < Nb; ++k1) v[k1] = cscale(v[k1], tzs[k2 + Na * k1]);
         }
       } else {
-        // round 0: conj(Ax Ay) conj(Dz) F_z{s_iz}; round 1: conj(Az) F_z{...}
+        // z round: conj(Ax Ay) conj(Dz) F_z{s_iz}; x-y round: conj(Az) F_z{...}
         const cplx<R> fz = pxy[2 * P + x];
 #pragma unroll
         for (int k1 = 0; k1 < Nb; ++k1) {
