@@ -553,8 +553,10 @@ k_const_sums(long long N, const R* __restrict__ gK, const double* __restrict__ g
   for (int c = 0; c < RED_CONST; ++c) acc[c] = 0.0;
   for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
        v += (long long)gridDim.x * blockDim.x) {
+    // streamed: the tangent's next readers are the x passes (at 128^3: 132 against 153 us)
 #pragma unroll
-    for (int c = 0; c < 21; ++c) acc[c] += (double)gK[(long long)c * N + v];
+    for (int c = 0; c < 21; ++c)
+      acc[c] += (double)__builtin_nontemporal_load(gK + (long long)c * N + v);
     acc[21] += gw[v];
     const double q = 1.0 - phi[v];
     const double gphi = q * q + kres;
