@@ -286,6 +286,9 @@ void launch_stag_norms(long long N, const double* eps, const double* eps_prev, c
 void launch_add_uniform(long long N, double* eps, const double de[6], hipStream_t st);
 // phi = min(1, max(phi_t, x))
 void launch_clamp(long long N, const double* x, const double* phi_t, double* phi, hipStream_t st);
+// out = g(phi) sig on 6 components (the degraded stress), g(phi) = (1 - phi)^2 + kres
+void launch_degrade(long long N, const double* sig, const double* phi, double kres, double* out,
+                    hipStream_t st);
 // Phase field with the pre-set crack (voxels with an infinite slip resistance) held at 1
 // (pfdir.hip).  mode 0: y = P x;  1: y = 1 - P 1 (the indicator of the crack);
 // 2: y = P ((1 + 2S) x + w);  3: y = P (2S - ((1 + 2S) x + w)); P the restriction to the

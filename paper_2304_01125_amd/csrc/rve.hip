@@ -234,7 +234,7 @@ struct rve_s {
   void* spec;             // 9 NH complex (R): operator work and GND scratch
   void* cg[6];            // x, r, z, p, q, b : 3 NH complex each
   void* gm_basis = nullptr;  // GMRES option: m + 1 basis vectors of 3 NH complex
-  double* rbuf;           // 9 N doubles: phase-field vectors / Nye tensor
+  double* rbuf;           // 9 N doubles: phase-field vectors / Nye tensor / stress readback
   double* partial;        // reduction partials
   double* scal;           // device scalars
   int* failc;
@@ -1331,26 +1331,15 @@ int rve_fields(rve_s* h, uint32_t mask, double* out, size_t n) {
     return RVE_OK;
   };
   int rc = RVE_OK;
-  std::vector<double> phi;
   for (int b = 0; b < 14 && rc == RVE_OK; ++b) {
     const uint32_t bit = 1u << b;
     if (!(mask & bit)) continue;
     switch (bit) {
       case RVE_F_STRAIN: rc = cp(h->eps, 6); break;
-      case RVE_F_STRESS: {
-        double* dst = o;
-        rc = cp(h->sig, 6);
-        if (rc) break;
-        phi.resize((size_t)N);
-        HIPCHK(hipMemcpyAsync(phi.data(), h->phi, N * 8, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        for (int c = 0; c < 6; ++c)
-          for (long long v = 0; v < N; ++v) {
-            const double q = 1.0 - phi[v];
-            dst[c * N + v] *= q * q + h->d.k_res;
-          }
+      case RVE_F_STRESS:      // degraded on the device into the phase-field scratch
+        launch_degrade(N, h->sig, h->phi, h->d.k_res, h->rbuf, st);
+        rc = cp(h->rbuf, 6);
         break;
-      }
       case RVE_F_STRESS_EFF: rc = cp(h->sig, 6); break;
       case RVE_F_DAMAGE: rc = cp(h->phi, 1); break;
       case RVE_F_GS: rc = cp(h->gs, 1); break;

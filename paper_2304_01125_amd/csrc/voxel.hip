@@ -959,4 +959,21 @@ void launch_clamp(long long N, const double* x, const double* phi_t, double* phi
   hipLaunchKernelGGL(k_clamp, dim3(voxel_grid(N)), dim3(256), 0, st, N, x, phi_t, phi);
 }
 
+// out = g(phi) sig on 6 components, g(phi) = (1 - phi)^2 + k_res (eq. deg)
+__global__ void __launch_bounds__(256) k_degrade(long long N, const double* __restrict__ sig,
+                                                 const double* __restrict__ phi, double kres,
+                                                 double* __restrict__ out) {
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x) {
+    const double q = 1.0 - phi[v];
+    const double gp = q * q + kres;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) out[c * N + v] = gp * sig[c * N + v];
+  }
+}
+void launch_degrade(long long N, const double* sig, const double* phi, double kres, double* out,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_degrade, dim3(voxel_grid(N)), dim3(256), 0, st, N, sig, phi, kres, out);
+}
+
 }  // namespace rvefft
