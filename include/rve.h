@@ -232,6 +232,15 @@ int rve_diag_constitutive(struct rve_s* h, const double* eps6, double dt, double
  * rve_diag_constitutive (which sets the tangent field). */
 int rve_diag_operator(struct rve_s* h, const double* u3, double* v3);
 
+/* Layout of the handle's reduction-partials buffer for a description (no device call):
+ * out3[0] = the most partial sums one divergence pass of the momentum operator writes
+ * (one per block, plus one of the macro stress), out3[1] = the offset at which the CG step
+ * writes its own partials, out3[2] = the buffer's length in doubles.  The CG step's blocks
+ * write their partials while other blocks of the same launch still sum the divergence
+ * pass's, so out3[1] >= out3[0] and out3[2] >= out3[1] + 2048 hold for every valid grid.
+ * Errors: RVE_E_ARG (invalid description or null out3). */
+int rve_diag_partials(const rve_desc* d, int64_t* out3);
+
 /* Launch one building block of the momentum operator `reps` times on the handle's
  * stream and return without synchronising, so that a caller can time it with events
  * recorded on that stream.  Operands are the handle's own work buffers (their

@@ -281,9 +281,23 @@ enum { SC_K = 0,        // 28 constitutive sums (21 gK, g w, 6 g sigma)
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Reduction buffer: the divergence pass's partials from 0, the CG step's from
-// kCgPartial (at most 2 x kCgMaxBlocks: every block of the next inverse z pass sums them).
-constexpr long long kCgPartial = (long long)kMaxRedBlocks * 16;
+// cg_partial_offset() (at most 2 x kCgMaxBlocks: every block of the next inverse z pass sums
+// them).  The CG step's blocks write their partials while other blocks of the same launch
+// still sum the divergence pass's, so the two ranges must not overlap: the fused divergence
+// pass launches (N1/2/T) N2 3 blocks with tiles of T >= 8 bins (plus one partial of the macro
+// stress), at most 3 N1 N2 / 16 + 1.
+constexpr long long kCgPartialMin = (long long)kMaxRedBlocks * 16;
 constexpr int kCgMaxBlocks = 1024;   // 512 measured 4 us slower per FP32 iteration at 128^3
+
+long long max_div_partials(const Grid& g) {
+  const long long fused = 3LL * g.n1 * g.n2 / 16 + 1;
+  return fused > kMaxRedBlocks + 1 ? fused : kMaxRedBlocks + 1;
+}
+long long cg_partial_offset(const Grid& g) {
+  const long long need = (max_div_partials(g) + 63) / 64 * 64;
+  return need > kCgPartialMin ? need : kCgPartialMin;
+}
+long long partial_count(const Grid& g) { return cg_partial_offset(g) + kMaxRedBlocks * 16; }
 
 
 
@@ -313,7 +327,7 @@ void layout(rve_s* h) {
                     ? take((size_t)(h->d.gmres_restart + 1) * 3 * NH * csz)
                     : nullptr;
   h->rbuf = fd(9 * N);
-  h->partial = fd((long long)kMaxRedBlocks * 32);
+  h->partial = fd(partial_count(h->g));
   h->scal = fd(SC_N);
   h->failc = (int*)take(256);
   for (int a = 0; a < 3; ++a) {
@@ -651,7 +665,7 @@ struct Ops {
     // With the fused z passes an iteration is six launches: the convergence test of the
     // previous iteration runs inside the inverse z pass and the sum of <p, q> inside the
     // CG step (each block reduces the previous kernel's partials itself).
-    double* cg_part = h->partial + kCgPartial;
+    double* cg_part = h->partial + cg_partial_offset(h->g);
     int nb_cg = 0;
     auto check_of = [&](int k) {        // the test of iteration k (after its CG step)
       return CgCheck{cg_part, nb_cg, SC_FLAG, SC_TOL2, SC_RRN, SC_RZ0 + ((k + 1) & 1)};
@@ -1116,6 +1130,19 @@ fail_out:
 extern "C" {
 
 const char* rve_last_error(void) { return g_err.c_str(); }
+
+int rve_diag_partials(const rve_desc* d, int64_t* out3) {
+  if (!out3) return fail(RVE_E_ARG, "null output");
+  const int rc = validate(d);
+  if (rc) return rc;
+  rve_s tmp;
+  tmp.d = *d;
+  init_grid(&tmp);
+  out3[0] = max_div_partials(tmp.g);
+  out3[1] = cg_partial_offset(tmp.g);
+  out3[2] = partial_count(tmp.g);
+  return RVE_OK;
+}
 
 size_t rve_footprint_bytes(const rve_desc* d) {
   if (validate(d) != RVE_OK) return 0;

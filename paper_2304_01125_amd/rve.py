@@ -117,6 +117,8 @@ def load():
     lib.rve_pool_step.restype = ctypes.c_int
     lib.rve_pool_step.argtypes = [ctypes.POINTER(_P), ctypes.c_int32, _D, _D,
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(RveStats)]
+    lib.rve_diag_partials.restype = ctypes.c_int
+    lib.rve_diag_partials.argtypes = [ctypes.POINTER(RveDesc), ctypes.POINTER(ctypes.c_int64)]
     lib.rve_diag_operator.restype = ctypes.c_int
     lib.rve_diag_operator.argtypes = [_P, _D, _D]
     _lib = lib
@@ -128,7 +130,7 @@ def exported_symbols():
     return ["rve_footprint_bytes", "rve_create", "rve_set_microstructure", "rve_step_increment",
             "rve_step_increment_mixed", "rve_fields", "rve_fields_count", "rve_destroy", "rve_last_error", "rve_diag_rfft",
             "rve_diag_irfft", "rve_diag_constitutive", "rve_diag_operator", "rve_diag_pass",
-            "rve_diag_time_pass", "rve_diag_pass_time",
+            "rve_diag_time_pass", "rve_diag_pass_time", "rve_diag_partials",
             "rve_pool_step"]
 
 

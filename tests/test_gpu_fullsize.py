@@ -1,55 +1,74 @@
-"""Parity at the full size of the benchmark workload: the 128^3 polycrystal with 512
-log-normal Laguerre grains, on the kernels the benchmark times (fused z passes, register
-FFTs, 128-point x tangent pass).  A whole 128^3 oracle solve is too slow for a test, so
-the first increment is checked on what the oracle can compute voxel by voxel and on
-properties that hold at any size:
+"""Parity at the full sizes of the benchmark workloads: the 128^3 polycrystal with 512
+log-normal Laguerre grains (the benchmark's), the 256^3 Voronoi polycrystal with 4096 grains
+and 5 % hard grains, and a 512 x 512 x 16 plate-like polycrystal whose fused divergence pass
+writes more block partials (49152) than any other grid, on the kernels the benchmark times
+(fused z passes, register FFTs, row tangent passes of 128, 256 and 512 points).  A whole
+oracle solve at these sizes is too slow for a test, so the first increment is checked on
+what the oracle can compute voxel by voxel and on properties that hold at any size:
 
 * the imposed macroscopic strain is the mean strain;
 * at 4096 sampled voxels, the GPU stress, slip increments (through eps_p) and slip
   resistance equal the oracle's return map at the GPU strain (state at t = 0 is known);
 * the degraded stress is equilibrated: its Fourier divergence i xi~ . sigma^ vanishes;
+* the strain is compatible: the oracle's Green projection onto symmetric gradients of
+  periodic displacements, sym(i xi~ (x) u^) with u^ = -[xi~.K0.xi~]^-1 i xi~.(K0 : e^) for
+  an isotropic reference K0, reproduces the fluctuation e = eps - eps_bar;
 * the mixed-precision increment reproduces the FP64 macroscopic stress within 1e-4.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
-from synth import workload, make_inputs
+from synth import workload, make_inputs, small_polycrystal
 
 pytestmark = pytest.mark.gpu
 NAME = "laguerre-128-g512"
 
 
-def _first_increment(precision, parity=True):
+def _first_increment(precision, parity=True, w=None):
     from paper_2304_01125_amd import RVE
-    w = workload(NAME)
+    w = workload(NAME) if w is None else w
     if parity:
         w = w.parity()
     inp = make_inputs(w)
     r = RVE(w.desc(), precision)
     r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
     st = r.step([0, inp["deps"][0], 0, 0, 0, 0], inp["dt"][0])
-    print(f"  {NAME} precision {precision}: newton {st['newton_iters']} krylov "
+    print(f"  {w.name} precision {precision}: newton {st['newton_iters']} krylov "
           f"{st['krylov_iters']} stag {st['stag_iters']}", flush=True)
     return w, inp, r, st
 
 
-def test_first_increment_at_full_size_matches_oracle_on_sampled_voxels():
+def _compatibility_error(grid, strain, ebar):
+    """max |P(e^) - e^| / max |e^| over the spectrum of e = eps - eps_bar, with P the
+    oracle's projection onto compatible strains (isotropic reference medium)."""
+    from oracle.increment import from_tensor6
+    from oracle.crystal import cubic_stiffness
+    eh = grid.fft(grid.to_grid(from_tensor6(strain - ebar[None])))
+    K0 = cubic_stiffness(3.0, 1.0, 1.0)               # isotropic: C44 = (C11 - C12) / 2
+    uh = -np.einsum("...ik,...k->...i", grid.acoustic_inverse(K0),
+                    grid.div_hat(np.einsum("ijkl,...kl->...ij", K0, eh)))
+    del eh
+    ph = grid.sym_grad_hat(uh)
+    eh = grid.fft(grid.to_grid(from_tensor6(strain - ebar[None])))
+    return np.abs(ph - eh).max() / np.abs(eh).max()
+
+
+def _check_first_increment(w, inp, r, n_sample=4096, seed=11):
     from oracle import GrainTables, return_map, to_mandel2, Grid
     from oracle.increment import from_tensor6
-    from paper_2304_01125_amd import RVE_FP64
-    w, inp, r, st = _first_increment(RVE_FP64)
     f = r.fields(("strain", "stress", "stress_eff", "eps_p", "g", "damage"))
-    r.close()
     N = w.nvox
     # imposed macro strain
     ebar = np.array([0.0, inp["deps"][0], 0.0, 0.0, 0.0, 0.0])
     assert np.abs(f["strain"].mean(0) - ebar).max() <= 1e-15
     assert np.abs(f["damage"]).max() == 0.0
     # sampled voxels against the oracle's return map at the GPU strain
-    idx = np.random.default_rng(11).choice(N, 4096, replace=False)
+    idx = np.random.default_rng(seed).choice(N, n_sample, replace=False)
     tab = GrainTables(inp["quat"], w.C11, w.C12, w.C44)
     gid = inp["grain"][idx]
-    g0 = np.asarray(inp["tau_c0"])[gid] if inp["tau_c0"] is not None else np.full(len(idx), w.tau_c0)
+    g0 = np.asarray(inp["tau_c0"])[gid]
     epsM = to_mandel2(from_tensor6(f["strain"][idx]))
     sig, dgam, K, _ = return_map(epsM, np.zeros_like(epsM), g0, inp["dt"][0], tab.C[gid],
                                  tab.S[gid], tab.P[gid], w.gdot0, w.n_exp)
@@ -61,13 +80,48 @@ def test_first_increment_at_full_size_matches_oracle_on_sampled_voxels():
     g1 = g0 + w.h_lin * np.abs(dgam).sum(1)
     e_g = np.abs(f["g"][idx] - g1).max() / g1.max()
     print(f"  sampled voxels: stress {e_sig:.2e}, eps_p {e_ep:.2e}, g {e_g:.2e}", flush=True)
+    assert np.abs(dgam).max() > 1e-5           # yielding voxels among the samples
     assert e_sig <= 1e-10 and e_ep <= 1e-8 and e_g <= 1e-12
     # equilibrium of the degraded stress
     grid = Grid(w.n, w.h)
-    sh = grid.fft(grid.to_grid(from_tensor6(f["stress"])))
+    stress = f.pop("stress")
+    sh = grid.fft(grid.to_grid(from_tensor6(stress)))
+    del stress
     div = np.abs(grid.div_hat(sh)).max() / (np.abs(sh).max() * np.abs(grid.xit).max())
+    del sh
     print(f"  equilibrium: max |i xi~ . sigma^| / (max |sigma^| max |xi~|) = {div:.2e}", flush=True)
     assert div <= 1e-9
+    # compatibility of the strain
+    comp = _compatibility_error(grid, f["strain"], ebar)
+    print(f"  compatibility: max |P e^ - e^| / max |e^| = {comp:.2e}", flush=True)
+    assert comp <= 1e-12
+
+
+def test_first_increment_at_full_size_matches_oracle_on_sampled_voxels():
+    from paper_2304_01125_amd import RVE_FP64
+    w, inp, r, st = _first_increment(RVE_FP64)
+    _check_first_increment(w, inp, r)
+    r.close()
+
+
+def test_first_increment_at_256_matches_oracle_on_sampled_voxels():
+    """The 256^3 workload (4096 Voronoi grains, 5 % hard grains) in FP64 at parity
+    tolerances: the 256-point fused z passes and row tangent pass."""
+    from paper_2304_01125_amd import RVE_FP64
+    w, inp, r, st = _first_increment(RVE_FP64, w=workload("voronoi-256-g4096-hard"))
+    _check_first_increment(w, inp, r, seed=12)
+    r.close()
+
+
+def test_widest_divergence_partials_grid():
+    """512 x 512 x 16 (49152 divergence-pass partials, past the CG step's partials before
+    their offset was sized from the grid): a full CG solve at parity tolerances."""
+    from paper_2304_01125_amd import RVE_FP64
+    w = dataclasses.replace(small_polycrystal(n=(512, 512, 16), n_grains=64, seed=13),
+                            amplitude=0.005, ratio=-1, cycles=2, incs_per_cycle=20)
+    w, inp, r, st = _first_increment(RVE_FP64, w=w)
+    _check_first_increment(w, inp, r, seed=13)
+    r.close()
 
 
 def test_mixed_precision_at_full_size_reproduces_fp64_macro_stress():

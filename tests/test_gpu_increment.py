@@ -34,18 +34,27 @@ def run_pair(w, n_inc, precision=0):
     return gpu, ora, out
 
 
+def _rel_or_abs(a, b):
+    return rel_l2(a, b) if np.linalg.norm(b) > 0 else np.abs(a).max()
+
+
 def compare(gpu, ora, tol_field=1e-9, tol_phi=1e-8):
-    f = gpu.fields(("strain", "stress", "damage", "gs", "wp", "eps_p", "rho_ssd", "rho_gnd"))
+    f = gpu.fields(("strain", "stress", "damage", "gs", "wp", "h", "wcrit", "trig", "eps_p",
+                    "rho_ssd", "rho_gnd"))
     o = ora.fields()
     errs = {k: rel_l2(f[k], o[k]) for k in ("strain", "stress", "gs", "wp", "eps_p", "rho_ssd")}
     errs["damage_max"] = np.abs(f["damage"] - o["damage"]).max()
-    errs["rho_gnd"] = rel_l2(f["rho_gnd"], o["rho_gnd"]) if np.linalg.norm(o["rho_gnd"]) > 0 else \
-        np.abs(f["rho_gnd"]).max()
+    for k in ("rho_gnd", "h", "wcrit"):
+        errs[k] = _rel_or_abs(f[k], o[k])
+    # the trigger flag is a decision: identical everywhere (the threshold's margin is far
+    # above the fields' agreement on these workloads)
+    errs["trig_mismatch"] = float(np.count_nonzero(f["trig"] != o["trig"]))
     print("  errors:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     assert errs["strain"] <= tol_field and errs["stress"] <= tol_field
     assert errs["damage_max"] <= tol_phi
-    for k in ("gs", "wp", "eps_p", "rho_ssd", "rho_gnd"):
+    for k in ("gs", "wp", "eps_p", "rho_ssd", "rho_gnd", "h", "wcrit"):
         assert errs[k] <= 1e-8, (k, errs[k])
+    assert errs["trig_mismatch"] == 0
     return errs
 
 

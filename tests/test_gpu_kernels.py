@@ -105,13 +105,26 @@ def test_operator_matches_oracle_and_is_identity_for_homogeneous_tangent():
 
 
 # fused z passes with work-unit counts that are multiples of 8 (XCD-contiguous block
-# order) and not (plain order: 16x12x16, 48x12x48), unfused grids, both precisions
-@pytest.mark.parametrize("n", [(32, 8, 128), (16, 16, 16), (16, 12, 16), (48, 12, 48),
-                               (12, 8, 6), (64, 64, 64)])
+# order) and not (plain order: 16x12x16, 48x12x48), unfused grids, both precisions; every
+# column length of the fused z passes (16, 32, 48, 64, 96, 128, 256) and the row tangent
+# pass at rows of 96 and 256 (256-thread blocks)
+FUSED = [(32, 8, 128), (16, 16, 16), (16, 12, 16), (48, 12, 48), (64, 64, 64), (16, 8, 32),
+         (16, 8, 96), (96, 8, 96), (16, 4, 256), (256, 8, 16)]
+
+
+@pytest.mark.parametrize("n", FUSED + [(12, 8, 6)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_operator_shapes_match_oracle(n, prec):
+    from paper_2304_01125_amd import RveError
     print(f"operator {n} precision {prec}", flush=True)
     w, r = _rve(n, prec)
+    # the grids listed as fused do take the fused z passes (zero launches: a query)
+    try:
+        r.launch_pass(8, 0)
+        fused = True
+    except RveError:
+        fused = False
+    assert fused == (n in FUSED), (n, fused)
     inp = make_inputs(w)
     r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
     rng = np.random.default_rng(0)
