@@ -25,8 +25,12 @@ def prepare(reqs, workers=None):
     from synth import request_workload, make_inputs
     items = []
     if workers and workers > 1:
+        # spawned (not forked) workers: the caller may already have initialised the GPU,
+        # and a forked copy of a HIP-initialised process is not safe to run
+        import multiprocessing
         from concurrent.futures import ProcessPoolExecutor
-        with ProcessPoolExecutor(max_workers=workers) as ex:
+        ctx = multiprocessing.get_context("spawn")
+        with ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
             inps = list(ex.map(_make, reqs))
     else:
         inps = [_make(r) for r in reqs]
@@ -64,6 +68,8 @@ class Server:
         waiting, active = [], []          # active: dicts with slot, handle, k
         free_slots = list(range(self.max_slots))
         used = 0
+        self.peak_used = 0                # largest resident footprint sum (bytes)
+        self.resident_log = []            # request ids resident at each tick
         t0 = time.perf_counter()
         nxt = 0
         ticks = 0
@@ -84,6 +90,7 @@ class Server:
                 r = RVE(w.desc(), self.precision, stream=self.streams[slot])
                 r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
                 used += r.footprint
+                self.peak_used = max(self.peak_used, used)
                 active.append(dict(i=i, slot=slot, rve=r, k=0, t_admit=now, iters=0))
             if not active:
                 if nxt < n:
@@ -95,6 +102,7 @@ class Server:
                 w, inp = items[a["i"]]
                 deps[a_i, 1] = inp["deps"][a["k"]]
                 dts[a_i] = inp["dt"][a["k"]]
+            self.resident_log.append([a["i"] for a in active])
             rc, status, stats = rve_pool_step([a["rve"].h for a in active], deps, dts)
             ticks += 1
             done_now = time.perf_counter() - t0
@@ -157,25 +165,31 @@ class Server:
                     continue
                 w, inp = items[i]
                 t_admit = time.perf_counter() - t0
-                r = RVE(w.desc(), self.precision, stream=self.streams[slot])
-                r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
-                it, st = 0, {"status": 0, "macro_stress": None}
-                for k in range(len(inp["deps"])):
-                    st = r.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k], check=False)
-                    it += st["krylov_iters"]
-                    if st["status"] != 0:
-                        break
-                done = time.perf_counter() - t0
-                rec = dict(id=i, n=w.n[0], status=st["status"], latency=done - arrivals[i],
-                           queued=t_admit - arrivals[i], krylov_iters=it,
-                           macro_stress=st["macro_stress"])
-                if keep_fields:
-                    rec["fields"] = r.fields(("strain", "stress", "damage"))
-                r.close()
-                del r
-                out[i] = rec
-                with lock:
-                    state["used"] -= need[i]
+                rec = dict(id=i, n=w.n[0], status=None, latency=None,
+                           queued=t_admit - arrivals[i], krylov_iters=0, macro_stress=None)
+                r = None
+                try:
+                    r = RVE(w.desc(), self.precision, stream=self.streams[slot])
+                    r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+                    it, st = 0, {"status": 0, "macro_stress": None}
+                    for k in range(len(inp["deps"])):
+                        st = r.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k], check=False)
+                        it += st["krylov_iters"]
+                        if st["status"] != 0:
+                            break
+                    rec.update(status=st["status"], krylov_iters=it, macro_stress=st["macro_stress"])
+                    if keep_fields:
+                        rec["fields"] = r.fields(("strain", "stress", "damage"))
+                except Exception as e:               # a failed request must not hold its memory
+                    rec.update(status=-1000, error=str(e))
+                finally:
+                    if r is not None:
+                        r.close()
+                        del r
+                    rec["latency"] = time.perf_counter() - t0 - arrivals[i]
+                    out[i] = rec
+                    with lock:
+                        state["used"] -= need[i]
                 if log:
                     log(f"request {i} ({w.n[0]}^3) done on slot {slot}: status {rec['status']}, "
                         f"latency {rec['latency']:.3f} s")

@@ -46,3 +46,9 @@ def test_admission_respects_memory_budget():
     srv = Server(RVE_MIXED, max_slots=4, budget_bytes=budget)
     res, wall, ticks = srv.run(items, np.zeros(len(items)))
     assert all(r["status"] == 0 for r in res)
+    # the resident footprints never exceeded the budget, and the two largest requests
+    # were never resident together
+    assert 0 < srv.peak_used <= budget
+    big = sorted(range(len(items)), key=lambda i: sizes[i])[-2:]
+    assert not any(set(big) <= set(ids) for ids in srv.resident_log)
+    assert len(srv.resident_log) == ticks
