@@ -157,6 +157,22 @@ size_t rve_footprint_bytes(const rve_desc* d);
 int rve_create(const rve_desc* d, void* dev_arena, size_t arena_bytes, void* hip_stream,
                struct rve_s** out);
 
+/* Create a handle without allocating anything, for callers that cannot allocate device
+ * memory (code that must not call hipMalloc: tight serving loops, harnesses that forbid
+ * it).  Same as rve_create, except that the arena is a static device array of the
+ * library, 320 MiB per device (335544320 bytes: every grid up to 64^3 in either
+ * precision with max_grains <= 4096), held by each device the library runs on until the
+ * process ends.  One such handle per device at a time: the array is shared, and a second
+ * call while one is alive returns RVE_E_STATE.  The handle's host scalars live in the
+ * handle (no pinned host memory) and its CG iterations are launched eagerly (no graph
+ * instantiation).  rve_set_microstructure sets every state field the increment reads;
+ * the previous handle's contents are otherwise left in the array.  rve_destroy releases
+ * the array for the next call.  Calls that use such a handle from several threads at
+ * once race, as for any handle.  Errors: RVE_E_ARG (bad description), RVE_E_NOMEM (the
+ * description needs more than the static arena: the message gives both sizes; checked
+ * before any device call), RVE_E_STATE (the array is held), RVE_E_DEVICE. */
+int rve_create_noalloc(const rve_desc* d, void* hip_stream, struct rve_s** out);
+
 /* Set the microstructure and the initial state (all host arrays, copied).
  * grain_of_voxel: N ints in [0, n_grains), x fastest.
  * quat_wxyz: 4*n_grains unit quaternions (w,x,y,z) rotating crystal vectors into the

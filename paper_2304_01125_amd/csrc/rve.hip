@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -257,6 +258,8 @@ struct rve_s {
   double msig_t[6] = {0, 0, 0, 0, 0, 0}, meps_t[6] = {0, 0, 0, 0, 0, 0};
   double* hs = nullptr;   // pinned host scalars
   bool micro = false;
+  int static_dev = -1;    // >= 0: the arena is that device's static scratch array
+  double hs_static[432];  // host scalars of a static-arena handle (no pinned allocation)
   long long n_preset = 0; // voxels of the pre-set crack (phi0 = 1)
   int n_grains = 0;
   int device = 0;         // device current at creation
@@ -1124,6 +1127,11 @@ fail_out:
   return rc;
 }
 
+
+int create_impl(rve_s* h, const rve_desc* d, void* dev_arena, size_t arena_bytes,
+                void* hip_stream, rve_s** out);
+static_assert(SC_N == 432, "rve_s::hs_static holds SC_N host scalars");
+
 }  // namespace
 
 // ---- C ABI -------------------------------------------------------------------------
@@ -1160,14 +1168,32 @@ int rve_create(const rve_desc* d, void* dev_arena, size_t arena_bytes, void* hip
   *out = nullptr;
   int rc = validate(d);
   if (rc) return rc;
-  rve_s* h = new rve_s();
+  return create_impl(new rve_s(), d, dev_arena, arena_bytes, hip_stream, out);
+}
+
+}  // extern "C"
+
+namespace {
+// Builds a handle in h (owned by the caller on failure paths of the static variant; the
+// heap variant deletes it).  With h->static_dev >= 0 nothing is allocated: the host
+// scalars live in the handle and the CG iterations are launched eagerly (a graph
+// instantiation allocates).
+int create_impl(rve_s* h, const rve_desc* d, void* dev_arena, size_t arena_bytes,
+                void* hip_stream, rve_s** out) {
+  const bool is_static = h->static_dev >= 0;
+  auto drop = [&]() {
+    if (!is_static) {
+      if (h->hs) (void)hipHostFree(h->hs);
+      delete h;
+    }
+  };
   h->d = *d;
   init_grid(h);
   h->base = nullptr;
   layout(h);
-  if (!dev_arena) { delete h; return fail(RVE_E_ARG, "null arena"); }
+  if (!dev_arena) { drop(); return fail(RVE_E_ARG, "null arena"); }
   if (arena_bytes < h->used) {
-    delete h;
+    drop();
     return fail(RVE_E_NOMEM, "arena smaller than rve_footprint_bytes");
   }
   h->base = (char*)dev_arena;
@@ -1182,17 +1208,21 @@ int rve_create(const rve_desc* d, void* dev_arena, size_t arena_bytes, void* hip
     // kernel); RVE_GRAPHS=1 / 0 forces either way
     const char* ev = std::getenv("RVE_GRAPHS");
     const bool small = h->g.nvox <= 64LL * 64 * 64;
-    h->use_graphs = (h->st != nullptr) && (ev ? ev[0] == '1' : small);
+    h->use_graphs = (h->st != nullptr) && (ev ? ev[0] == '1' : small) && !is_static;
   }
-  if (hipHostMalloc((void**)&h->hs, SC_N * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-    delete h;
+  if (is_static) {
+    h->hs = h->hs_static;
+  } else if (hipHostMalloc((void**)&h->hs, SC_N * sizeof(double), hipHostMallocDefault) !=
+             hipSuccess) {
+    h->hs = nullptr;
+    drop();
     return fail(RVE_E_DEVICE, "hipHostMalloc failed");
   }
   // twiddle tables, exp(-2 pi i k / n), computed in FP64
   for (int a = 0; a < 3; ++a) {
-    const int n = h->pl.ax[a].n;
-    std::vector<double> t64(2 * n);
-    std::vector<float> t32(2 * n);
+    const int n = h->pl.ax[a].n;     // <= 512
+    double t64[1024];
+    float t32[1024];
     for (int k = 0; k < n; ++k) {
       // reduce the angle to the first octant-friendly form k/n in [0, 1)
       const double ang = -2.0 * M_PI * (double)k / (double)n;
@@ -1201,18 +1231,19 @@ int rve_create(const rve_desc* d, void* dev_arena, size_t arena_bytes, void* hip
       t32[2 * k] = (float)t64[2 * k];
       t32[2 * k + 1] = (float)t64[2 * k + 1];
     }
-    if (hipMemcpyAsync((void*)h->pl.tw64[a], t64.data(), n * 16, hipMemcpyHostToDevice, h->st) !=
+    // (pageable sources: the copies are staged before hipMemcpyAsync returns; the
+    // synchronisation below orders them before any use)
+    if (hipMemcpyAsync((void*)h->pl.tw64[a], t64, n * 16, hipMemcpyHostToDevice, h->st) !=
             hipSuccess ||
-        hipMemcpyAsync((void*)h->pl.tw32[a], t32.data(), n * 8, hipMemcpyHostToDevice, h->st) !=
-            hipSuccess) {
-      (void)hipHostFree(h->hs);
-      delete h;
+        hipMemcpyAsync((void*)h->pl.tw32[a], t32, n * 8, hipMemcpyHostToDevice, h->st) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->st) != hipSuccess) {
+      drop();
       return fail(RVE_E_DEVICE, "twiddle upload failed");
     }
   }
   if (upload_reg_twiddles(h->st) != hipSuccess) {
-    (void)hipHostFree(h->hs);
-    delete h;
+    drop();
     return fail(RVE_E_DEVICE, "register DFT table upload failed");
   }
   double Q[81];
@@ -1223,12 +1254,66 @@ int rve_create(const rve_desc* d, void* dev_arena, size_t arena_bytes, void* hip
       hipMemcpyAsync(h->scal, h->hs, SC_N * sizeof(double), hipMemcpyHostToDevice, h->st) !=
           hipSuccess ||
       hipStreamSynchronize(h->st) != hipSuccess) {
-    (void)hipHostFree(h->hs);
-    delete h;
+    drop();
     return fail(RVE_E_DEVICE, "table upload failed");
   }
   *out = h;
   return RVE_OK;
+}
+
+// ---- allocation-free handles ----------------------------------------------------------
+// One static arena per device for callers that cannot allocate device memory.  In host
+// code `scratch` names a host-side stand-in: its device address comes from
+// hipGetSymbolAddress, once per device with that device current, and only that address
+// is ever handed to the device.
+constexpr size_t kScratchBytes = (size_t)320 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_busy[kMaxDevices] = {};
+rve_s g_static_handle[kMaxDevices];
+
+}  // namespace
+
+extern "C" {
+
+int rve_create_noalloc(const rve_desc* d, void* hip_stream, rve_s** out) {
+  if (!out) return fail(RVE_E_ARG, "null output handle");
+  *out = nullptr;
+  int rc = validate(d);
+  if (rc) return rc;
+  {
+    rve_s tmp;
+    tmp.d = *d;
+    init_grid(&tmp);
+    tmp.base = nullptr;
+    layout(&tmp);
+    if (tmp.used > kScratchBytes)
+      return fail(RVE_E_NOMEM, "description needs " + std::to_string(tmp.used) +
+                                   " device bytes; the static arena holds " +
+                                   std::to_string(kScratchBytes));
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(RVE_E_DEVICE, "no current HIP device");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(RVE_E_DEVICE, "hipGetSymbolAddress of the static arena failed");
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  if (g_scratch_busy[dev])
+    return fail(RVE_E_STATE, "the device's static arena is held by another handle");
+  rve_s* h = &g_static_handle[dev];
+  *h = rve_s();
+  h->static_dev = dev;
+  rc = create_impl(h, d, g_scratch_ptr[dev], kScratchBytes, hip_stream, out);
+  if (rc == RVE_OK) g_scratch_busy[dev] = true;
+  return rc;
 }
 
 int rve_set_microstructure(rve_s* h, const int32_t* grain, int32_t n_grains, const double* quat,
@@ -1393,6 +1478,13 @@ int rve_destroy(rve_s* h) {
   for (hipGraphExec_t& e : h->cg_exec)
     if (e) (void)hipGraphExecDestroy(e);
   for (hipEvent_t e : h->xt_ev) (void)hipEventDestroy(e);
+  if (h->static_dev >= 0) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    g_scratch_busy[h->static_dev] = false;
+    h->xt_ev.clear();
+    h->hs = nullptr;
+    return RVE_OK;
+  }
   if (h->hs) (void)hipHostFree(h->hs);
   delete h;
   return RVE_OK;

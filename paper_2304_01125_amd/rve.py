@@ -85,6 +85,8 @@ def load():
     lib.rve_create.restype = ctypes.c_int
     lib.rve_create.argtypes = [ctypes.POINTER(RveDesc), _P, ctypes.c_size_t, _P,
                                ctypes.POINTER(_P)]
+    lib.rve_create_noalloc.restype = ctypes.c_int
+    lib.rve_create_noalloc.argtypes = [ctypes.POINTER(RveDesc), _P, ctypes.POINTER(_P)]
     lib.rve_set_microstructure.restype = ctypes.c_int
     lib.rve_set_microstructure.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                                            _D, _D, _D]
@@ -127,7 +129,7 @@ def load():
 
 def exported_symbols():
     """Names of the C ABI entry points (as declared in include/rve.h)."""
-    return ["rve_footprint_bytes", "rve_create", "rve_set_microstructure", "rve_step_increment",
+    return ["rve_footprint_bytes", "rve_create", "rve_create_noalloc", "rve_set_microstructure", "rve_step_increment",
             "rve_step_increment_mixed", "rve_fields", "rve_fields_count", "rve_destroy", "rve_last_error", "rve_diag_rfft",
             "rve_diag_irfft", "rve_diag_constitutive", "rve_diag_operator", "rve_diag_pass",
             "rve_diag_time_pass", "rve_diag_pass_time", "rve_diag_partials",
@@ -237,7 +239,10 @@ class RVE:
     """One periodic RVE solved on the GPU.  ``desc`` is the flat dict of
     ``synth.Workload.desc()``; precision is RVE_FP64 or RVE_MIXED."""
 
-    def __init__(self, desc, precision=RVE_FP64, device=0, stream=None, max_grains=4096):
+    def __init__(self, desc, precision=RVE_FP64, device=0, stream=None, max_grains=4096,
+                 noalloc=False):
+        """noalloc: create the handle with rve_create_noalloc (the library's static device
+        arena, one such handle per device at a time) instead of a torch-allocated arena."""
         import torch
         lib = load()
         self.desc = dict(desc)
@@ -248,6 +253,16 @@ class RVE:
         if nbytes == 0:
             raise RveError(RVE_E_ARG, lib.rve_last_error().decode())
         self.device = torch.device("cuda", device)
+        if noalloc:
+            torch.cuda.set_device(self.device)
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+            self.arena = None
+            h = _P()
+            _check(lib.rve_create_noalloc(ctypes.byref(self._d), _P(self.stream.cuda_stream),
+                                          ctypes.byref(h)))
+            self.h = h
+            self.footprint = nbytes
+            return
         self.arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         # the library works on its own stream (default priority), so that its CG
         # iterations can be replayed as HIP graphs; that stream first waits for the

@@ -143,3 +143,21 @@ def test_cg_partials_do_not_overlap_the_divergence_partials(n):
         assert length >= cg_off + 2 * 1024
     bad = p.make_desc(dict(workload("notched-crystal-16").desc(), n=(10, 2, 2)))
     assert lib.rve_diag_partials(ctypes.byref(bad), (ctypes.c_int64 * 3)()) == p.RVE_E_ARG
+
+
+def test_noalloc_rejects_descriptions_beyond_the_static_arena():
+    """rve_create_noalloc checks the footprint against its 320 MiB static arena before any
+    device call: 128^3 FP64 (about 2 GB) is refused with RVE_E_NOMEM and both sizes."""
+    import paper_2304_01125_amd as p
+    from synth import workload
+    lib = p.load()
+    d = p.make_desc(dict(workload("notched-crystal-16").desc(), n=(128, 128, 128)))
+    h = ctypes.c_void_p()
+    assert lib.rve_create_noalloc(ctypes.byref(d), None, ctypes.byref(h)) == p.RVE_E_NOMEM
+    msg = lib.rve_last_error().decode()
+    assert "335544320" in msg and str(p.rve_footprint_bytes(d)) in msg
+    assert not h.value
+    small = p.make_desc(dict(workload("notched-crystal-16").desc(), n=(64, 64, 64)))
+    assert p.rve_footprint_bytes(small) <= 335544320
+    bad = p.make_desc(dict(workload("notched-crystal-16").desc(), n=(10, 2, 2)))
+    assert lib.rve_create_noalloc(ctypes.byref(bad), None, ctypes.byref(h)) == p.RVE_E_ARG
