@@ -22,6 +22,7 @@ paper's thermally activated flow rule and Table 1 material in yielding increment
 the CPU oracle timed on a bounded sample.
 """
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -61,6 +62,10 @@ def parse():
                     help="requests of the serving leg (0: skip); the committed serving "
                          "summary uses 400")
     ap.add_argument("--pass-reps", type=int, default=20)
+    ap.add_argument("--no-damage", action="store_true",
+                    help="skip the damage leg (phase field active in the timed increments)")
+    ap.add_argument("--damage-gcrit-pow", type=int, default=10,
+                    help="the damage leg's G_crit = 4 J/m^2 / 2^k")
     return ap.parse_args()
 
 
@@ -145,18 +150,35 @@ def measured_traffic(kernel, n):
     return float(val.group(1)) * 1e6
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, inp, gpu_stats, first, n_apply=6, stride=64):
     """The CPU oracle on a bounded sample of the same workload, scaled to voxel-iters/s.
 
     Sample: (a) n_apply applications of the oracle's preconditioned momentum operator on
-    the full grid with the elastic tangent of the microstructure, and (b) the oracle's
-    return map on every stride-th voxel at the macroscopic strain of the first timed
-    increment (increment index ``first``).  The oracle
-    time of one increment is projected with the operator-application and
-    constitutive-call counts of the GPU FP64 increments (same tolerances), and the
-    rate is voxels x operator applications / projected time.
+    the full grid with the elastic tangent of the microstructure; (b) the oracle's return
+    map and (c) its phase-field source (trial plastic work and the spectral tensile energy)
+    on every stride-th voxel at the macroscopic strain of the first timed increment
+    (increment index ``first``), scaled to the full grid; (d) the oracle's history commit
+    arithmetic on the same sample, scaled, and its GND update (the regularised Nye tensor
+    of the plastic distortion, a 9-component FFT round trip, and the density) on the full
+    grid.  The oracle time of one increment is projected with the operator-application,
+    constitutive-call and alternating-pass counts of the GPU FP64 increments (same
+    tolerances; the timed increments solve no phase field, so no phase-field Krylov
+    iteration enters), and the rate is voxels x operator applications / projected time.
     """
-    from oracle import OracleRVE, momentum_operator, to_mandel2
+    from oracle import (OracleRVE, momentum_operator, to_mandel2, from_mandel2, return_map,
+                        we_plus, nye_tensor, gnd_density)
+    from oracle.spectral import WORKERS
     o = OracleRVE(w.desc(), inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
     M = o.grid.M
     gK = (1.0 + w.k_res) * o.tab.C[o.gid]
@@ -169,23 +191,79 @@ def cpu_baseline(w, inp, gpu_stats, first, n_apply=6, stride=64):
     sub = np.arange(0, M, stride)
     eps = np.zeros((len(sub), 3, 3))
     eps[:, 1, 1] = np.sum(inp["deps"][:first + 1])
-    from oracle import return_map
     t = o.tab
     gid = o.gid[sub]
     t0 = time.perf_counter()
-    return_map(to_mandel2(eps), np.zeros((len(sub), 6)), o.g[sub], inp["dt"][0], t.C[gid], t.S[gid],
-               t.P[gid], law=o.law)
+    sig, dgam, _, _ = return_map(to_mandel2(eps), np.zeros((len(sub), 6)), o.g[sub], inp["dt"][0],
+                                 t.C[gid], t.S[gid], t.P[gid], law=o.law)
     t_const = (time.perf_counter() - t0) * M / len(sub)
+    # phase-field source on the sample (as the oracle's alternating pass computes it)
+    t0 = time.perf_counter()
+    epsp_tr = from_mandel2(np.einsum("ma,mai->mi", dgam, t.P[gid]))
+    tau = np.einsum("mai,mi->ma", t.P[gid], sig)
+    wp_tr = (tau * dgam).sum(1)
+    we = we_plus(eps - epsp_tr, t.C4[gid])
+    Sd = np.where(we + wp_tr > 0.0, w.ell / w.gc_value() * np.maximum(0.0, we + wp_tr), 0.0)
+    t_source = (time.perf_counter() - t0) * M / len(sub)
+    # history commit on the sample, GND update on the full grid
+    t0 = time.perf_counter()
+    dbeta = np.einsum("ma,maij->mij", dgam, t.SN[gid])
+    rho = o.rho_ssd[sub] + w.lambda_ssd * np.sqrt(2.0 / 3.0 * np.einsum("mij,mij->m", dbeta, dbeta))
+    gs = w.xi_store * wp_tr / np.sqrt(rho + o.rho_gnd[sub])
+    _ = np.maximum(o.H[sub], we), (gs >= w.G_crit) & (Sd >= 0.0)
+    t_commit = (time.perf_counter() - t0) * M / len(sub)
+    t0 = time.perf_counter()
+    lam = nye_tensor(o.grid, o.beta + 1e-6, w.ell_fp)
+    gnd_density(lam, t.R[o.gid], w.burgers)
+    t_gnd = time.perf_counter() - t0
     n_mv = np.mean([s["krylov_iters"] for s in gpu_stats])
     n_cs = np.mean([s["newton_iters"] + s["ls_cuts"] + s["stag_iters"] for s in gpu_stats])
-    t_inc = n_mv * t_apply + n_cs * t_const
+    n_st = np.mean([s["stag_iters"] for s in gpu_stats])
+    t_inc = n_mv * t_apply + n_cs * t_const + n_st * t_source + t_commit + t_gnd
     return {"value": round(M * n_mv / t_inc, 1), "unit": "voxel-iters/s",
-            "cores": os.cpu_count(), "kind": "oracle",
+            "cores": int(WORKERS), "cpu_model": _cpu_model(), "kind": "oracle",
             "sample": (f"{n_apply} oracle operator+preconditioner applications on the full "
-                       f"{w.name} grid ({t_apply:.2f} s each) and the oracle return map on 1/"
-                       f"{stride} of its voxels ({t_const:.1f} s per full-grid call, scaled); "
-                       f"one increment projected with the GPU run's counts ({n_mv:.0f} operator "
-                       f"applications, {n_cs:.0f} constitutive calls) = {t_inc:.0f} s")}
+                       f"{w.name} grid ({t_apply:.2f} s each); the oracle return map "
+                       f"({t_const:.1f} s per full-grid call), phase-field source "
+                       f"({t_source:.1f} s) and commit arithmetic ({t_commit:.2f} s) on 1/"
+                       f"{stride} of its voxels, scaled; its GND update on the full grid "
+                       f"({t_gnd:.1f} s); one increment projected with the GPU run's counts "
+                       f"({n_mv:.0f} operator applications, {n_cs:.0f} constitutive calls, "
+                       f"{n_st:.0f} alternating passes) = {t_inc:.0f} s; scipy.fft with "
+                       f"{WORKERS} workers")}
+
+
+def damage_leg(RVE, precision, torch, w, inp, warmup, steps, gcrit_pow, max_krylov=4000, reps=20):
+    """The headline increments with the stored-energy threshold G_crit lowered from 4 J/m^2
+    by 2^gcrit_pow, so that the threshold is reached in the first increments and the timed
+    ones solve the phase field (eqs. phase, precph) with a non-zero driving state; the
+    Krylov cap is raised for the stiffness contrast of the damaged voxels.  Also times one
+    phase-field CG iteration in isolation (HIP events on the library's stream): its
+    algorithmic bytes (FP64 vectors, the one-component FFT round trip) over its duration."""
+    from paper_2304_01125_amd.rve import PASSES
+    wd = dataclasses.replace(w, G_crit=4.0 / 2 ** gcrit_pow, max_krylov=max_krylov)
+    r, dt, kry, stats, _ = run_leg(RVE, precision, wd.desc(), inp, warmup, steps, torch)
+    s = r.stream
+    r.launch_pass(PASSES["pf_iter"], 2)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    nbytes = r.launch_pass(PASSES["pf_iter"], reps)
+    e1.record(s)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    r.close()
+    pf = int(sum(x["pf_iters"] for x in stats))
+    return {"G_crit": wd.G_crit, "value": round(wd.nvox * kry / dt, 1), "unit": "voxel-iters/s",
+            "ms_per_step": round(1e3 * dt / steps, 2), "krylov_iters": kry, "pf_iters": pf,
+            "stag_iters": int(sum(x["stag_iters"] for x in stats)),
+            "newton_iters": int(sum(x["newton_iters"] for x in stats)),
+            "ms_phase_field": round(sum(x["ms_phase_field"] for x in stats), 2),
+            "max_phi": float(max(x["max_phi"] for x in stats)),
+            "n_triggered": float(stats[-1]["n_triggered"]),
+            "pf_iteration": {"ms": round(ms, 5), "bytes": nbytes,
+                             "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                             "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
 def material_leg(RVE, precision, torch, name="cmsx4-laguerre-128-g512", warmup=2, steps=2):
@@ -316,6 +394,9 @@ def main():
         out["rotated"] = rotated_leg(RVE, RVE_FP64, w, inp, a.warmup, a.steps, torch)
     if not a.no_stress_control:
         out["stress_control"] = stress_control_leg(RVE, RVE_FP64, w, inp, a.warmup, a.steps, torch)
+    if not a.no_damage:
+        out["damage"] = damage_leg(RVE, RVE_FP64, torch, w, inp, a.warmup, a.steps,
+                                   a.damage_gcrit_pow)
     if not a.no_material:
         out["material"] = material_leg(RVE, RVE_FP64, torch)
     if a.serve_requests > 0:

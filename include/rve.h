@@ -66,6 +66,20 @@ enum { RVE_DERIV_SPECTRAL = 0, RVE_DERIV_ROTATED = 1 };
  * is the paper's restarted GMRES with the same preconditioner, its relative tolerance
  * tol_lin applied to the preconditioned residual. */
 enum { RVE_KRYLOV_CG = 0, RVE_KRYLOV_GMRES = 1 };
+/* Kinematics (Sec. 2.1).  RVE_KIN_SMALL: the small-strain form (eps = eps_e + eps_p,
+ * symmetric 6-component strain and stress, 6x6 tangents).  RVE_KIN_FINITE: the paper's
+ * finite strain, F = Fe Fp with Lp = sum gdot_a s_a (x) n_a, the first Piola-Kirchhoff
+ * stress balanced in the reference configuration (eq. str1), F = F_bar + grad u
+ * (eq. fdef), the 9 x 9 consistent tangent dP/dF in the linearised balance (eq. newton),
+ * the preconditioner [xi~ . Kbar . xi~]^-1 of the 81-entry mean tangent (eqs. precf,
+ * avstiff) and the tensile energy of the logarithmic elastic strain (eq. decMiehe).
+ * Elasticity S = C : Ee (Ee = 1/2 (Fe^T Fe - I), lattice configuration); backward Euler
+ * on Fp with the resolved shear tau_a = S : sym(A s_a (x) n_a), A the trial elastic right
+ * Cauchy-Green tensor (Kalidindi, Bronkhorst and Anand 1992), Fp = (I + sum_a dgamma_a
+ * s_a (x) n_a) Fp_n.  Finite-strain handles run in FP64 with RVE_KRYLOV_GMRES (the
+ * linearised operator is not symmetric) and the spectral derivative, and step with
+ * rve_step_increment_finite. */
+enum { RVE_KIN_SMALL = 0, RVE_KIN_FINITE = 1 };
 
 /* Field selection bits for rve_fields(); fields are written in increasing bit order. */
 enum {
@@ -82,7 +96,12 @@ enum {
   RVE_F_TRIG = 1u << 10,      /* 1: 1.0 where G_s has reached G_crit                     */
   RVE_F_EPS_P = 1u << 11,     /* 6: plastic strain                                       */
   RVE_F_SLIP_RES = 1u << 12,  /* 1: slip resistance g (inf in pre-cracked voxels)        */
-  RVE_F_BETA_P = 1u << 13     /* 9: plastic distortion, row-major 3x3                    */
+  RVE_F_BETA_P = 1u << 13,    /* 9: plastic distortion, row-major 3x3                    */
+  /* finite-strain handles only (the small-strain bits STRAIN, STRESS, STRESS_EFF, EPS_P
+   * and BETA_P are refused there, and these on small-strain handles): */
+  RVE_F_DEFGRAD = 1u << 14,   /* 9: deformation gradient F, row-major                    */
+  RVE_F_PK1 = 1u << 15,       /* 9: degraded first Piola-Kirchhoff stress g(phi) P       */
+  RVE_F_FP = 1u << 16         /* 9: plastic deformation gradient Fp                      */
 };
 
 /* Problem description.  n[a] must be of the form 2^p 3^q with 1 <= n[a] <= 512. */
@@ -129,6 +148,7 @@ typedef struct rve_desc {
                                other voxels by CG with the restricted preconditioner
                                (the geometric crack and soft buffers of Secs. 4.1 and
                                4.5 read as a boundary value of the damage)               */
+  int32_t kinematics;       /* RVE_KIN_SMALL (default) or RVE_KIN_FINITE                 */
 } rve_desc;
 
 /* Per-increment report, filled by rve_step_increment (also on RVE_E_NOCONV). */
@@ -145,6 +165,14 @@ typedef struct rve_stats {
   double max_phi_slip;      /* max of phi over voxels that can slip (not pre-cracked)   */
   double n_triggered;       /* voxels with G_s >= G_crit                               */
   double ms_total, ms_constitutive, ms_mech_krylov, ms_phase_field, ms_commit;
+  /* finite-strain handles: volume averages of g(phi) P and of F (row-major); there
+   * macro_stress holds the symmetric part of the former and macro_strain that of the
+   * latter minus the identity */
+  double macro_pk1[9];
+  double macro_defgrad[9];
+  /* rve_pool_step: the most handles whose CG iterations advanced in shared launches with
+   * this one's during the increment (1: on its own) */
+  double cg_batch;
 } rve_stats;
 
 /* Device bytes a handle with this description needs in its arena (0 if invalid). */
@@ -208,6 +236,18 @@ int rve_step_increment_mixed(struct rve_s* h, const double deps_macro[6],
                              const double dsig_macro[6], int32_t stress_mask, double dt,
                              rve_stats* st);
 
+/* One load increment of a finite-strain handle (rve_desc.kinematics = RVE_KIN_FINITE)
+ * under the macroscopic deformation gradient increment dF_macro (9 components,
+ * row-major: F_bar(t + dt) = F_bar(t) + dF_macro) over dt > 0: Algorithm 1 with Newton
+ * on the displacement (eqs. fdef, newton; full steps, halved while the preconditioned
+ * residual grows), the paper's GMRES and stop test max|grad du| <= tol_newton
+ * max|F_i - F_t|, the phase field and the history as in rve_step_increment (the plastic
+ * work sum_a tau_a dgamma_a, the SSD rate of Lp, the Nye tensor of Fp).  Same state
+ * semantics; errors as rve_step_increment, RVE_E_ARG on a small-strain handle (and
+ * rve_step_increment, rve_step_increment_mixed on a finite-strain one). */
+int rve_step_increment_finite(struct rve_s* h, const double dF_macro[9], double dt,
+                              rve_stats* st);
+
 /* Copy the fields selected by field_mask to host_out (n_doubles capacity), each as
  * SoA components of N values in increasing bit order.  Errors: RVE_E_ARG if the
  * buffer is too small, RVE_E_STATE before rve_set_microstructure. */
@@ -240,6 +280,15 @@ int rve_diag_irfft(struct rve_s* h, int32_t ncomp, const double* spec_in, double
  * of the state is restored afterwards. */
 int rve_diag_constitutive(struct rve_s* h, const double* eps6, double dt, double* sig6_out,
                           double* gk21_out);
+
+/* Finite-strain constitutive update of every voxel at the deformation gradients F9
+ * (host, 9*N, component-major, row-major tensors) with the current internal variables and
+ * time step dt: writes the effective first Piola-Kirchhoff stress (9*N) and the tangent
+ * g(phi) dP_r/dF_c at (9 r + c)*N + voxel (81*N).  Either output may be NULL.  The
+ * physical state is not touched; the tangent field is set (as rve_diag_constitutive).
+ * RVE_E_ARG on a small-strain handle. */
+int rve_diag_constitutive_finite(struct rve_s* h, const double* F9, double dt, double* P9_out,
+                                 double* K81_out);
 
 /* Apply the preconditioned linearised equilibrium operator of the current tangent
  * field to a displacement field: given real displacements u (host, 3*N), return
@@ -277,8 +326,12 @@ enum {
   RVE_PASS_ZGRAD = 8,        /* CG direction update p = z + beta p, sym(i xi~ (x) p) and
                                 the inverse z transform in one pass (even N1 and N3 in
                                 16,32,48,64,96,128,256; RVE_E_ARG otherwise)            */
-  RVE_PASS_ZDIV = 9          /* forward z transform, -i xi~ . sigma and block partials
+  RVE_PASS_ZDIV = 9,         /* forward z transform, -i xi~ . sigma and block partials
                                 of <p, q> in one pass (same grids as RVE_PASS_ZGRAD)    */
+  RVE_PASS_PF_ITER = 10      /* the launches of one phase-field CG iteration (eqs. phase,
+                                precph: the operator's dot product and updates, the
+                                preconditioner's one-component FFT round trip, the
+                                convergence test) on the phase-field work vectors        */
 };
 int rve_diag_pass(struct rve_s* h, int32_t pass_id, int32_t reps, double* bytes_per_launch);
 

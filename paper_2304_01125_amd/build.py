@@ -8,7 +8,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["csrc/rve.hip", "csrc/passes.hip", "csrc/xpass.hip", "csrc/zfused.hip",
            "csrc/spectral.hip", "csrc/voxel.hip", "csrc/vector.hip", "csrc/macro.hip",
-           "csrc/gmres.hip", "csrc/pfdir.hip"]
+           "csrc/gmres.hip", "csrc/pfdir.hip", "csrc/finite.hip"]
 FLAGS = ["-O3", "-std=c++20", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

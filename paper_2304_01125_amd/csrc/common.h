@@ -69,7 +69,21 @@ struct Grid {
   double L1, L2, L3;        // box lengths [m]
   int sch;                  // derivative of the momentum operator: 0 spectral (i xi~),
                             // 1 rotated finite differences (rot_factors)
+  // Batched launches (several RVEs of one description in one launch): block z of the grid
+  // works on RVE z, whose buffers lie sd[z] bytes from those the launch's pointer
+  // arguments name (device array; nullptr: one RVE, block z = 0).
+  const long long* sd = nullptr;
 };
+
+// Byte offset of this block's RVE in a batched launch, and a pointer moved by it.
+__device__ __forceinline__ long long slot_delta(const Grid& g) {
+  return g.sd ? g.sd[blockIdx.z] : 0;
+}
+template <typename T>
+__device__ __forceinline__ T* at_slot(T* p, long long d) {
+  return p ? reinterpret_cast<T*>(reinterpret_cast<unsigned long long>(p) + (unsigned long long)d)
+           : p;
+}
 
 // Angular frequency of index k on an axis of N points and length L (signed, numpy
 // ordering).  With tilde the Nyquist index of an even axis maps to zero: the

@@ -10,6 +10,7 @@ struct Plans {
   AxisPlan ax[3];
   const void* tw64[3];     // cplx<double>[n_a], exp(-2 pi i k / n_a)
   const void* tw32[3];     // cplx<float>[n_a]
+  int nslot = 1;           // RVEs of a batched launch (grid z; g.sd their buffer offsets)
   const void* tw_ptr(int axis, bool f64) const { return f64 ? tw64[axis] : tw32[axis]; }
 };
 
@@ -302,6 +303,60 @@ void launch_pfd_axpy(long long N, const double* sc, int ia, int ib, double sign,
 void launch_pfd_xpby(long long N, const double* z, const double* sc, int ia, int ib, double* p,
                      hipStream_t st, const double* stop = nullptr);
 
+// --- finite-strain kinematics (finite.hip) --------------------------------------------------
+// Crystal-frame slip directions s_a and plane normals n_a (12 x 3 each, unit) and the cubic
+// Mandel stiffness / compliance constants.
+struct FsFrame {
+  double s[36], n[36];
+  double c11, c12, c66, s11, s12, s66;
+};
+struct Nine9 {
+  double v[9];
+};
+// Return map, first Piola-Kirchhoff stress, trial plastic deformation, 9 x 9 degraded
+// tangent and the per-voxel increments aux = (sum tau dgamma, sum |dgamma|, dLp : dLp,
+// W_e+) at F + t dF (dF may be null); Sws (crystal-frame S, 6) is the warm start, updated.
+void launch_fs_constitutive(long long N, const double* F, const double* dF, double t,
+                            const double* Fpn, const double* gslip, const int* grain,
+                            const double* gtab, double* Sws, const double* phi, double* P,
+                            double* fp_tr, double* aux, double* gK, const FsFrame& fr,
+                            const Material& m, int* fail, hipStream_t st);
+// e_ij = i xi~_j u_i (3 -> 9 half-spectrum components)
+void launch_fs_grad(const Plans& p, const cplx<double>* u, long long ucs, cplx<double>* e,
+                    long long ecs, hipStream_t st, const double* stop = nullptr);
+// out_i = sign i xi~_j s_ij (9 -> 3)
+void launch_fs_div(const Plans& p, const cplx<double>* s, long long scs, cplx<double>* out,
+                   long long ocs, double sign, hipStream_t st, const double* stop = nullptr);
+// z = [xi~ . Kbar . xi~]^-1 P r, Kbar the 81-entry mean tangent (device), P the Hermitian
+// projection of the self-conjugate x-planes
+void launch_fs_precond(const Plans& p, const cplx<double>* r, cplx<double>* z, long long cs,
+                       const double* kbar81, hipStream_t st, const double* stop = nullptr);
+// x <- gK : x on 9 real components per voxel (in place)
+void launch_fs_tangent(double* x, long long N, const double* gK, hipStream_t st,
+                       const double* stop = nullptr);
+// block sums of every component of an ncomp x N field: partial[c * nb + b]; returns nb
+int launch_colsum(const double* x, long long N, int ncomp, double* partial, hipStream_t st);
+void launch_fs_add_uniform(long long N, double* F, const double d[9], hipStream_t st);
+// F += t dF; partial maxima of |t dF| and |F - F_t| (2 values)
+void launch_fs_update(long long N, double* F, const double* dF, double t, const double* Ft,
+                      double* partial, hipStream_t st);
+// maxima |F - F_prev|, |F - F_t|, |phi - phi_prev|, |phi - phi_t|
+void launch_fs_stag_norms(long long N, const double* F, const double* Fprev, const double* Ft,
+                          const double* phi, const double* phi_prev, const double* phi_t,
+                          double* partial, hipStream_t st);
+void launch_fs_source(long long N, const double* aux, const double* wp, const double* trig,
+                      const double* wcrit, double* S, const Material& m, double* partial,
+                      hipStream_t st);
+// partials: 19 sums (9 g(phi) P, 9 F, n_trig) then 2 maxima (phi, phi where slip is possible)
+void launch_fs_commit(long long N, const double* P, const double* F, double* Fp,
+                      const double* fp_tr, double* gslip, double* rho_ssd, const double* rho_gnd,
+                      double* wp, double* gs, double* H, double* wcrit, double* trig,
+                      const double* aux, const double* phi, const Material& m, double* partial,
+                      hipStream_t st);
+// out = g(phi) P on 9 components
+void launch_fs_degrade(long long N, const double* P, const double* phi, double kres, double* out,
+                       hipStream_t st);
+
 // --- reductions and vector kernels (vector.hip) ---------------------------------------
 // out[c] = sum (or max) over b < nblk of partial[c*nblk + b], fixed order.
 // CG reductions with the device-side control: reduce_pq sums the partials of <p, q>
@@ -313,7 +368,8 @@ void launch_reduce_pq(const double* partial, int nblk, double* sc, int ipq, int 
                       hipStream_t st);
 // cg_check_inline in one block (the test of a batch's last iteration); no-op once
 // sc[ck.iflag] is non-zero
-void launch_cg_check_tail(double* sc, const CgCheck& ck, hipStream_t st);
+void launch_cg_check_tail(double* sc, const CgCheck& ck, hipStream_t st,
+                          const long long* sd = nullptr, int nslot = 1);
 void launch_reduce_check(const double* partial, int nblk, double* sc, int iiter, int nxt, int irr,
                          int iflag, int itol2, hipStream_t st);
 void launch_reduce(const double* partial, int nblk, int ncomp, int op_max, double* out,

@@ -15,6 +15,10 @@ template <typename R, int NC, int TXC>
 __global__ void __launch_bounds__(256)
 k_fft_strided(cplx<R>* __restrict__ data, long long cs, int axis, int inv, Grid g, AxisPlan pl,
               const cplx<R>* __restrict__ tw_g, int TXr, const double* __restrict__ stop) {
+  {
+    const long long d = slot_delta(g);
+    data = at_slot(data, d); tw_g = at_slot(tw_g, d); stop = at_slot(stop, d);
+  }
   if (stop && *stop != 0.0) return;
   extern __shared__ unsigned char smem_raw[];
   const int N = NC > 0 ? NC : pl.n;
@@ -54,6 +58,10 @@ template <typename R, int NC, int TXC, bool NYQ>
 __global__ void __launch_bounds__(256)
 k_fft_strided_ip(cplx<R>* __restrict__ data, long long cs, int axis, int inv, Grid g,
                  const cplx<R>* __restrict__ tw_g, const double* __restrict__ stop) {
+  {
+    const long long d = slot_delta(g);
+    data = at_slot(data, d); tw_g = at_slot(tw_g, d); stop = at_slot(stop, d);
+  }
   if (stop && *stop != 0.0) return;
   constexpr int P = NYQ ? TXC + 1 : TXC;
   extern __shared__ unsigned char smem_raw[];
@@ -97,6 +105,10 @@ template <typename R, int NC, int TXC, bool NYQ, int CPB>
 __global__ void __launch_bounds__(256)
 k_fft_strided_pipe(cplx<R>* __restrict__ data, long long cs, int axis, int inv, Grid g,
                    const cplx<R>* __restrict__ tw_g, const double* __restrict__ stop) {
+  {
+    const long long d = slot_delta(g);
+    data = at_slot(data, d); tw_g = at_slot(tw_g, d); stop = at_slot(stop, d);
+  }
   if (stop && *stop != 0.0) return;
   constexpr int P = NYQ ? TXC + 1 : TXC;
   constexpr int E = (P * NC + 255) / 256;
@@ -158,6 +170,10 @@ template <typename R, int N, int TX, bool NYQ, bool INV, int NT>
 __global__ void __launch_bounds__(NT)
 k_fft_strided_reg(cplx<R>* __restrict__ data, long long cs, int axis, Grid g,
                   const cplx<R>* __restrict__ tw_g, const double* __restrict__ stop) {
+  {
+    const long long d = slot_delta(g);
+    data = at_slot(data, d); tw_g = at_slot(tw_g, d); stop = at_slot(stop, d);
+  }
   if (stop && *stop != 0.0) return;
   constexpr int P = NYQ ? TX + 1 : TX;
   constexpr int Na = TwoPass<N>::Na, Nb = TwoPass<N>::Nb;
@@ -231,7 +247,7 @@ static bool launch_strided_pipe(const Plans& p, cplx<R>* data, long long cs, int
   if (sm > kLdsBudget) return false;
   const int ntiles = nyq ? (g.n1 / 2) / TX : (g.n1h + TX - 1) / TX;
   const int others = (axis == 1) ? g.n3 : g.n2;
-  const dim3 grid(ntiles * others, ncomp / CPB);
+  const dim3 grid(ntiles * others, ncomp / CPB, p.nslot);
   const cplx<R>* tw = (const cplx<R>*)p.tw_ptr(axis, sizeof(R) == 8);
   if (nyq)
     hipLaunchKernelGGL((k_fft_strided_pipe<R, NC, TX, true, CPB>), grid, dim3(256), sm, st, data,
@@ -252,7 +268,7 @@ static bool launch_strided_ip(const Plans& p, cplx<R>* data, long long cs, int n
   if (sm > kLdsBudget) return false;
   const int ntiles = nyq ? (g.n1 / 2) / TX : (g.n1h + TX - 1) / TX;
   const int others = (axis == 1) ? g.n3 : g.n2;
-  const dim3 grid(ntiles * others, ncomp);
+  const dim3 grid(ntiles * others, ncomp, p.nslot);
   const cplx<R>* tw = (const cplx<R>*)p.tw_ptr(axis, sizeof(R) == 8);
   if (nyq)
     hipLaunchKernelGGL((k_fft_strided_ip<R, NC, TX, true>), grid, dim3(256), sm, st, data, cs, axis,
@@ -272,7 +288,7 @@ static void launch_reg_tx(const Plans& p, cplx<R>* data, long long cs, int ncomp
   constexpr int NT = ((items + 63) / 64) * 64 > 1024 ? 1024 : ((items + 63) / 64) * 64;
   const int ntiles = NYQ ? (g.n1 / 2) / TX : (g.n1h + TX - 1) / TX;
   const int others = (axis == 1) ? g.n3 : g.n2;
-  const dim3 grid(ntiles * others, ncomp);
+  const dim3 grid(ntiles * others, ncomp, p.nslot);
   const cplx<R>* tw = (const cplx<R>*)p.tw_ptr(axis, sizeof(R) == 8);
   if (inv)
     hipLaunchKernelGGL((k_fft_strided_reg<R, N, TX, NYQ, true, NT>), grid, dim3(NT), 0, st, data,
@@ -330,7 +346,7 @@ void launch_fft_yz(const Plans& p, cplx<R>* data, long long cs, int ncomp, int a
   const int others = (axis == 1) ? g.n3 : g.n2;
   const size_t sm = ((size_t)N + 2 * (size_t)TX * N) * sizeof(cplx<R>);
   const cplx<R>* tw = (const cplx<R>*)p.tw_ptr(axis, sizeof(R) == 8);
-  const dim3 grid(ntiles * others, ncomp);
+  const dim3 grid(ntiles * others, ncomp, p.nslot);
   hipLaunchKernelGGL((k_fft_strided<R, 0, 0>), grid, dim3(256), sm, st, data, cs, axis,
                      inv ? 1 : 0, g, pl, tw, TX, stop);
 }

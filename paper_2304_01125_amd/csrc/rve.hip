@@ -9,9 +9,12 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
+#include <condition_variable>
 #include <mutex>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 using namespace rvefft;
@@ -20,6 +23,11 @@ namespace {
 
 thread_local std::string g_err;
 const bool g_debug = std::getenv("RVE_DEBUG") != nullptr;
+// RVE_POOL_BATCH=0: rve_pool_step runs every handle's CG solve on its own (for comparisons)
+const bool g_no_batch = [] {
+  const char* e = std::getenv("RVE_POOL_BATCH");
+  return e && e[0] == '0';
+}();
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -182,6 +190,25 @@ void crystal_frame(double C11, double C12, double C44, CrystalFrame* cf) {
   cf->s66 = 1.0 / (2.0 * C44);
 }
 
+// Crystal-frame unit slip directions and plane normals with the cubic Mandel constants
+// (finite-strain return map).
+void fs_frame(double C11, double C12, double C44, FsFrame* ff) {
+  CrystalFrame cf;
+  crystal_frame(C11, C12, C44, &cf);
+  for (int a = 0; a < 12; ++a) {
+    double s[3] = {kSlipS[a][0], kSlipS[a][1], kSlipS[a][2]};
+    double n[3] = {kSlipN[a][0], kSlipN[a][1], kSlipN[a][2]};
+    normalize3(s);
+    normalize3(n);
+    for (int i = 0; i < 3; ++i) {
+      ff->s[3 * a + i] = s[i];
+      ff->n[3 * a + i] = n[i];
+    }
+  }
+  ff->c11 = cf.c11; ff->c12 = cf.c12; ff->c66 = cf.c66;
+  ff->s11 = cf.s11; ff->s12 = cf.s12; ff->s66 = cf.s66;
+}
+
 // Q = (A A^T)^-1 for the 9 x 18 crystal-frame GND basis (12 edge: s (x) (s x n),
 // 6 screw: d (x) d), row-major vec.
 bool gnd_q(double* Q) {
@@ -216,6 +243,23 @@ bool gnd_q(double* Q) {
 }  // namespace
 
 // ---- handle ------------------------------------------------------------------------
+// Same-size handles of one rve_pool_step tick whose CG solves run as batched launches.
+struct CgJob {
+  rve_s* h = nullptr;
+  int iters = 0;
+  int rc = 0;
+  std::string msg;
+  bool done = false;
+};
+struct CgGroup {
+  std::mutex mu;
+  std::condition_variable cv;
+  std::vector<CgJob*> pending;
+  bool leader = false;
+  int members = 0;          // handles of the group still inside their increment
+  int wait_us = 400;        // a leader's wait for the other members to reach their CG solve
+};
+
 struct rve_s {
   rve_desc d;
   Grid g;
@@ -259,7 +303,24 @@ struct rve_s {
   double* hs = nullptr;   // pinned host scalars
   bool micro = false;
   int static_dev = -1;    // >= 0: the arena is that device's static scratch array
-  double hs_static[432];  // host scalars of a static-arena handle (no pinned allocation)
+  double hs_static[544];  // host scalars of a static-arena handle (no pinned allocation)
+  // finite-strain kinematics (rve_desc.kinematics == RVE_KIN_FINITE): deformation gradient
+  // at t + dt, at t and at the previous alternating pass, the Newton correction, the
+  // effective first Piola-Kirchhoff stress, the plastic deformation and its trial value
+  // (9 each, row-major), and the per-voxel increments (sum tau dgamma, sum |dgamma|,
+  // dLp : dLp, W_e+); the tangent field then holds 81 FP64 entries per voxel and sig the
+  // crystal-frame second Piola-Kirchhoff stress (the return map's warm start)
+  // serving: the handle's group of same-size handles inside rve_pool_step (their CG
+  // iterations advance in shared launches), its events and the slot-offset table (in the
+  // arena) of a batch it leads
+  CgGroup* cg_group = nullptr;
+  int batch_peak = 1;     // largest batch this handle's CG solves ran in (this increment)
+  hipEvent_t cg_ready = nullptr, cg_done = nullptr;
+  long long* slotd = nullptr;
+  bool fs = false;
+  double *fs_F = nullptr, *fs_Ft = nullptr, *fs_Fprev = nullptr, *fs_dF = nullptr,
+         *fs_P = nullptr, *fs_Fp = nullptr, *fs_fptr = nullptr, *fs_aux = nullptr;
+  FsFrame ff;
   long long n_preset = 0; // voxels of the pre-set crack (phi0 = 1)
   int n_grains = 0;
   int device = 0;         // device current at creation
@@ -279,7 +340,9 @@ enum { SC_K = 0,        // 28 constitutive sums (21 gK, g w, 6 g sigma)
        SC_GM = 144,     // GMRES: Gram-Schmidt coefficients, first pass (up to 65)
        SC_GM2 = 216,    // GMRES: second pass
        SC_GY = 288,     // GMRES: least-squares solution (up to 64)
-       SC_N = 432 };
+       SC_FK = 432,     // finite strain: 81 mean tangent
+       SC_FM = 520,     // finite strain: 21 commit reductions
+       SC_N = 544 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -290,6 +353,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 // pass launches (N1/2/T) N2 3 blocks with tiles of T >= 8 bins (plus one partial of the macro
 // stress), at most 3 N1 N2 / 16 + 1.
 constexpr long long kCgPartialMin = (long long)kMaxRedBlocks * 16;
+constexpr int kMaxBatch = 64;         // RVEs of one batched CG launch
 constexpr int kCgMaxBlocks = 1024;   // 512 measured 4 us slower per FP32 iteration at 128^3
 
 long long max_div_partials(const Grid& g) {
@@ -323,7 +387,7 @@ void layout(rve_s* h) {
   h->grain = (int*)take((size_t)N * 4);
   h->gtab = fd((long long)h->d.max_grains * GT_STRIDE);
   h->Q81 = fd(81);
-  h->gK = take((size_t)21 * N * rsz);
+  h->gK = take((size_t)(h->fs ? 81 * 8 : 21 * rsz) * N);
   h->spec = take((size_t)9 * NH * csz);
   for (int i = 0; i < 6; ++i) h->cg[i] = take((size_t)3 * NH * csz);
   h->gm_basis = h->d.krylov == RVE_KRYLOV_GMRES
@@ -331,7 +395,12 @@ void layout(rve_s* h) {
                     : nullptr;
   h->rbuf = fd(9 * N);
   h->partial = fd(partial_count(h->g));
+  if (h->fs) {
+    h->fs_F = fd(9 * N); h->fs_Ft = fd(9 * N); h->fs_Fprev = fd(9 * N); h->fs_dF = fd(9 * N);
+    h->fs_P = fd(9 * N); h->fs_Fp = fd(9 * N); h->fs_fptr = fd(9 * N); h->fs_aux = fd(4 * N);
+  }
   h->scal = fd(SC_N);
+  h->slotd = (long long*)take(kMaxBatch * 8);
   h->failc = (int*)take(256);
   for (int a = 0; a < 3; ++a) {
     h->pl.tw64[a] = take((size_t)h->pl.ax[a].n * 16);
@@ -356,6 +425,12 @@ int validate(const rve_desc* d) {
   if (d->deriv != RVE_DERIV_SPECTRAL && d->deriv != RVE_DERIV_ROTATED)
     return fail(RVE_E_ARG, "deriv must be RVE_DERIV_SPECTRAL or RVE_DERIV_ROTATED");
   if (d->pf_dirichlet != 0 && d->pf_dirichlet != 1) return fail(RVE_E_ARG, "pf_dirichlet must be 0 or 1");
+  if (d->kinematics != RVE_KIN_SMALL && d->kinematics != RVE_KIN_FINITE)
+    return fail(RVE_E_ARG, "kinematics must be RVE_KIN_SMALL or RVE_KIN_FINITE");
+  if (d->kinematics == RVE_KIN_FINITE &&
+      (d->precision != RVE_FP64 || d->krylov != RVE_KRYLOV_GMRES || d->deriv != RVE_DERIV_SPECTRAL))
+    return fail(RVE_E_ARG, "finite-strain kinematics run in FP64 with the GMRES solver and the "
+                           "spectral derivative");
   if (d->material != RVE_MAT_POWER && d->material != RVE_MAT_DUNNE)
     return fail(RVE_E_ARG, "material must be RVE_MAT_POWER or RVE_MAT_DUNNE");
   if (d->material == RVE_MAT_POWER) {
@@ -394,6 +469,7 @@ void init_grid(rve_s* h) {
   h->pl.g = g;
   for (int a = 0; a < 3; ++a) make_axis_plan(h->d.n[a], &h->pl.ax[a]);
   h->f64 = (h->d.precision == RVE_FP64);
+  h->fs = (h->d.kinematics == RVE_KIN_FINITE);
 }
 
 // ---- small helpers on the handle ---------------------------------------------------
@@ -429,6 +505,34 @@ struct Ops {
 
   explicit Ops(rve_s* hh) : h(hh), st(hh->st), N(hh->g.nvox), NH(hh->g.nspec) { W = (C*)h->spec; }
 
+  // finite-strain operator (the handle's kinematics): 9-component gradient and
+  // divergence, 81-entry tangent applied in real space, preconditioner from the 81-entry
+  // mean tangent (FP64 only)
+  bool fs = false;
+  void precond(const C* r, C* z) {
+    if constexpr (std::is_same_v<R, double>) {
+      if (fs) {
+        launch_fs_precond(h->pl, r, z, NH, h->scal + SC_FK, st);
+        return;
+      }
+    }
+    launch_precond<R>(h->pl, r, z, NH, h->scal + SC_KBAR, h->partial, st, nullptr, m0());
+  }
+  // q = -i xi~_j F{ gK_ijkl F^-1{ i xi~_l p_k } } (eqs. fdef, newton)
+  void matvec_fs(const C* p, C* q, const double* stop) {
+    if constexpr (std::is_same_v<R, double>) {
+      launch_fs_grad(h->pl, p, NH, W, NH, st, stop);
+      launch_fft_yz<R>(h->pl, W, NH, 9, 2, true, st, stop);
+      launch_fft_yz<R>(h->pl, W, NH, 9, 1, true, st, stop);
+      launch_x_c2r<R>(h->pl, W, NH, h->rbuf, true, N, 9, 1.0 / (double)N, 0, st, stop);
+      launch_fs_tangent(h->rbuf, N, (const double*)h->gK, st, stop);
+      launch_x_r2c<R>(h->pl, h->rbuf, true, N, nullptr, 0.0, W, NH, 9, st, stop);
+      launch_fft_yz<R>(h->pl, W, NH, 9, 1, false, st, stop);
+      launch_fft_yz<R>(h->pl, W, NH, 9, 2, false, st, stop);
+      launch_fs_div(h->pl, W, NH, q, NH, -1.0, st, stop);
+    }
+  }
+
   // forward 3-D real FFT of ncomp real comps (stride in_cs) into spec comps
   void fwd(const void* in, bool in64, long long in_cs, int ncomp, C* out, const double* phi = nullptr) {
     launch_x_r2c<R>(h->pl, in, in64, in_cs, phi, h->d.k_res, out, NH, ncomp, st);
@@ -446,21 +550,35 @@ struct Ops {
   // With the fused z passes, `scratch` (3 NH) receives the copy of p the inverse pass
   // stores as the updated direction, and the partials of <p, q> are left unused.
   void matvec(const C* p, C* q, C* scratch, const double* stop = nullptr) {
+    if (fs) {
+      matvec_fs(p, q, stop);
+      return;
+    }
+    // (mixed control: the stress-controlled macro strains in the zero bin of p enter the
+    // strain, and q(0) takes the macro stress, as in the CG iterations)
     const bool fz = fused_z_available<R>(h->pl);
+    const long long zst = (long long)h->g.n1h * h->g.n2;
     if (fz) {
       launch_zgrad_inv<R>(h->pl, p, p, scratch, NH, h->scal, SC_ZERO, SC_ONE, W, st, stop);
+      if (mask)
+        launch_macro_strain<R>(W, NH, p, NH, s_mac, 0.0, mask, h->g.n3, zst, nullptr, st, stop);
     } else {
       launch_sym_grad<R>(h->pl, p, NH, W, NH, st, stop);
+      if (mask) launch_macro_strain<R>(W, NH, p, NH, s_mac, 0.0, mask, 1, 0, nullptr, st, stop);
       launch_fft_yz<R>(h->pl, W, NH, 6, 2, true, st, stop);
     }
     launch_fft_yz<R>(h->pl, W, NH, 6, 1, true, st, stop);
     launch_x_tangent<R>(h->pl, W, NH, gK(), 1.0 / (double)N, st, stop);
     launch_fft_yz<R>(h->pl, W, NH, 6, 1, false, st, stop);
     if (fz) {
-      launch_zdiv_fwd<R>(h->pl, W, q, p, NH, h->partial, st, stop);
+      const int nbd = launch_zdiv_fwd<R>(h->pl, W, q, p, NH, h->partial, st, stop);
+      if (mask)
+        launch_macro_stress<R>(W, NH, q, p, NH, s_mac, mask, h->g.n3, zst, h->partial + nbd, st,
+                               stop);
     } else {
       launch_fft_yz<R>(h->pl, W, NH, 6, 2, false, st, stop);
       launch_div<R>(h->pl, W, NH, q, NH, -1.0, st, stop);
+      if (mask) launch_macro_stress<R>(W, NH, q, p, NH, s_mac, mask, 1, 0, h->partial, st, stop);
     }
   }
   // The row tangent pass of CG iteration k, timing itself into an event pair while live
@@ -520,7 +638,7 @@ struct Ops {
     double* sc = h->scal;
     iters = 0;
     launch_zero(x, (size_t)3 * NH * sizeof(C), st);
-    launch_precond<R>(h->pl, b, V, NH, sc + SC_KBAR, h->partial, st);    // r0 = M c
+    precond(b, V);    // r0 = M c
     double beta;
     int rc;
     if ((rc = norm(V, beta))) return rc;
@@ -536,8 +654,8 @@ struct Ops {
       for (int j = 0; j < m; ++j) {
         // w = M P(B V_j), P the Hermitian projection of the self-conjugate planes
         matvec(V + j * vs, t, scr);
-        launch_herm_proj<R>(h->pl, t, NH, 3, st);
-        launch_precond<R>(h->pl, t, w, NH, sc + SC_KBAR, h->partial, st);
+        if (!mask) launch_herm_proj<R>(h->pl, t, NH, 3, st);
+        precond(t, w);
         for (int pass = 0; pass < 2; ++pass) {
           const int base = pass ? SC_GM2 : SC_GM;
           for (int c0 = 0; c0 <= j; c0 += kGmChunk) {
@@ -590,12 +708,170 @@ struct Ops {
       if (iters >= h->d.max_krylov) return fail(RVE_E_NOCONV, "momentum GMRES reached max_krylov");
       // restart from the preconditioned residual M (c - P B x)
       matvec(x, t, scr);
-      launch_herm_proj<R>(h->pl, t, NH, 3, st);
+      if (!mask) launch_herm_proj<R>(h->pl, t, NH, 3, st);
       launch_caxpby<R>(h->pl, b, 1.0, t, -1.0, t, NH, st);
-      launch_precond<R>(h->pl, t, V, NH, sc + SC_KBAR, h->partial, st);
+      precond(t, V);
       if ((rc = norm(V, beta))) return rc;
       if (beta <= tol) return RVE_OK;
     }
+  }
+
+  // The CG solve of a handle in a pool tick (its set-up done on its own stream): wait at
+  // the group's rendezvous; the first waiting thread leads, collects the handles that reach
+  // their solve within the group's wait and runs their iterations as batched launches
+  // (run_batch); the others sleep until their solve is over.  Every handle's arithmetic is
+  // that of its own solve (same kernels and block decomposition, per-handle reductions
+  // and convergence flags), so the results do not depend on the company.
+  int pcg_batched(int& iters) {
+    CgGroup* G = h->cg_group;
+    if (!h->cg_ready) HIPCHK(hipEventCreateWithFlags(&h->cg_ready, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(h->cg_ready, st));
+    CgJob job;
+    job.h = h;
+    std::unique_lock<std::mutex> lk(G->mu);
+    G->pending.push_back(&job);
+    G->cv.notify_all();
+    while (!job.done) {
+      if (!G->leader) {
+        G->leader = true;
+        const auto t_end =
+            std::chrono::steady_clock::now() + std::chrono::microseconds(G->wait_us);
+        while ((int)G->pending.size() < G->members && std::chrono::steady_clock::now() < t_end)
+          G->cv.wait_until(lk, t_end);
+        std::vector<CgJob*> batch;
+        batch.swap(G->pending);
+        lk.unlock();
+        run_batch(batch);
+        lk.lock();
+        for (CgJob* j : batch) j->done = true;
+        G->leader = false;
+        G->cv.notify_all();
+      } else {
+        G->cv.wait(lk);
+      }
+    }
+    lk.unlock();
+    iters = job.iters;
+    if (job.rc) return fail(job.rc, job.msg);
+    return RVE_OK;
+  }
+
+  // CG iterations of up to kMaxBatch same-description handles (fused z passes, strain
+  // control) as launches over all of them: block z of each kernel works on handle z, whose
+  // buffers lie slotd[z] bytes from the first handle's; the first handle's stream carries
+  // the launches, after every handle's set-up and before its next work.
+  static void run_batch(std::vector<CgJob*>& jobs) {
+    const int B = (int)jobs.size();
+    rve_s* h0 = jobs[0]->h;
+    Ops<R> o(h0);
+    hipStream_t st = h0->st;
+    auto fail_all = [&](int rc, const std::string& m) {
+      for (CgJob* j : jobs) { j->rc = rc; j->msg = m; }
+    };
+    if (!h0->cg_done &&
+        hipEventCreateWithFlags(&h0->cg_done, hipEventDisableTiming) != hipSuccess) {
+      fail_all(RVE_E_DEVICE, "event creation failed");
+      return;
+    }
+    long long d[kMaxBatch];
+    for (int j = 0; j < B; ++j) {
+      d[j] = (long long)(jobs[j]->h->base - h0->base);
+      if (j && hipStreamWaitEvent(st, jobs[j]->h->cg_ready, 0) != hipSuccess) {
+        fail_all(RVE_E_DEVICE, "stream wait failed");
+        return;
+      }
+    }
+    // (pageable source: staged before the call returns)
+    if (hipMemcpyAsync(h0->slotd, d, (size_t)B * 8, hipMemcpyHostToDevice, st) != hipSuccess) {
+      fail_all(RVE_E_DEVICE, "slot table upload failed");
+      return;
+    }
+    Plans pb = h0->pl;
+    pb.g.sd = h0->slotd;
+    pb.nslot = B;
+    C *x = o.v(0), *z = o.v(2), *p = o.v(3), *q = o.v(4), *b = o.v(5);
+    double* sc = h0->scal;
+    const double* stop = sc + SC_FLAG;
+    double* cg_part = h0->partial + cg_partial_offset(h0->g);
+    int nb_cg = 0;
+    auto check_of = [&](int k) {
+      return CgCheck{cg_part, nb_cg, SC_FLAG, SC_TOL2, SC_RRN, SC_RZ0 + ((k + 1) & 1)};
+    };
+    auto enqueue_iter = [&](int k) {
+      const int cur = SC_RZ0 + (k & 1), prv = SC_RZ0 + ((k + 1) & 1);
+      const int ia = (k == 0) ? SC_ZERO : cur, ib = (k == 0) ? SC_ONE : prv;
+      C* pold = (k & 1) ? b : p;
+      C* pk = (k & 1) ? p : b;
+      if (k == 0) launch_zgrad_inv<R>(pb, z, pold, pk, o.NH, sc, ia, ib, o.W, st, stop);
+      else launch_zgrad_inv<R>(pb, z, pold, pk, o.NH, sc, ia, ib, o.W, st, stop, check_of(k - 1));
+      launch_fft_yz<R>(pb, o.W, o.NH, 6, 1, true, st, stop);
+      launch_x_tangent<R>(pb, o.W, o.NH, o.gK(), 1.0 / (double)o.N, st, stop);
+      launch_fft_yz<R>(pb, o.W, o.NH, 6, 1, false, st, stop);
+      const int nbd = launch_zdiv_fwd<R>(pb, o.W, q, pk, o.NH, h0->partial, st, stop);
+      nb_cg = launch_cg_step<R>(pb, x, pk, q, z, o.NH, sc + SC_KBAR, sc, cur, SC_PQ, cg_part, st,
+                                stop, h0->partial, nbd, SC_FLAG, SC_ITER, kCgMaxBlocks, nullptr);
+    };
+    const int maxk = h0->d.max_krylov;
+    std::vector<double> rr_ref(B), it_ref(B, 0.0);
+    for (int j = 0; j < B; ++j) rr_ref[j] = jobs[j]->h->hs[SC_BB];
+    int queued = 0, batch = 4;
+    bool all_done = false;
+    while (queued < maxk) {
+      const int nq = std::min(batch, maxk - queued);
+      for (int kk = 0; kk < nq; ++kk) enqueue_iter(queued + kk);
+      queued += nq;
+      launch_cg_check_tail(sc, check_of(queued - 1), st, h0->slotd, B);
+      for (int j = 0; j < B; ++j) {
+        rve_s* hj = jobs[j]->h;
+        if (hipMemcpyAsync(hj->hs + SC_RZ0, hj->scal + SC_RZ0,
+                           (SC_RRN - SC_RZ0 + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                           st) != hipSuccess) {
+          fail_all(RVE_E_DEVICE, "scalar read failed");
+          return;
+        }
+      }
+      if (hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess) {
+        fail_all(RVE_E_DEVICE, "HIP error in the batched CG iterations");
+        return;
+      }
+      // next batch: the iterations the slowest unconverged solve still needs (as in pcg)
+      all_done = true;
+      int next = 4;
+      batch = std::min(2 * batch, 16);
+      for (int j = 0; j < B; ++j) {
+        const double* hs = jobs[j]->h->hs;
+        if (hs[SC_FLAG] != 0.0) continue;
+        all_done = false;
+        const double rr = hs[SC_RRN], its = hs[SC_ITER];
+        int want = batch;
+        if (its > it_ref[j] && rr > 0.0 && rr < rr_ref[j]) {
+          const double rate = std::log(rr / rr_ref[j]) / (its - it_ref[j]);
+          const double need = std::log(hs[SC_TOL2] / rr) / rate;
+          if (std::isfinite(need)) want = std::max(4, std::min(16, (int)std::ceil(need) + 2));
+        }
+        next = std::max(next, want);
+        rr_ref[j] = rr;
+        it_ref[j] = its;
+      }
+      batch = next;
+      if (all_done) break;
+    }
+    for (CgJob* j : jobs) {
+      const double* hs = j->h->hs;
+      j->h->batch_peak = std::max(j->h->batch_peak, B);
+      j->iters = (int)hs[SC_ITER];
+      if (hs[SC_FLAG] == 1.0) j->rc = RVE_OK;
+      else if (hs[SC_FLAG] == 2.0) { j->rc = RVE_E_NOCONV; j->msg = "momentum CG breakdown"; }
+      else { j->rc = RVE_E_NOCONV; j->msg = "momentum Krylov solver reached max_krylov"; }
+    }
+    // the other handles' streams resume after the batch
+    if (hipEventRecord(h0->cg_done, st) != hipSuccess) {
+      fail_all(RVE_E_DEVICE, "event record failed");
+      return;
+    }
+    for (int j = 1; j < B; ++j)
+      if (hipStreamWaitEvent(jobs[j]->h->st, h0->cg_done, 0) != hipSuccess)
+        fail_all(RVE_E_DEVICE, "stream wait failed");
   }
 
   // mean tangent from the constitutive sums
@@ -658,6 +934,8 @@ struct Ops {
     // right-hand side is no longer needed once z = M b is formed): each iteration reads p_old and
     // writes p_new while other blocks still read p_old.
     const bool fz = fused_z_available<R>(h->pl);
+    // inside a pool tick, the same-size handles' solves advance in shared launches
+    if (h->cg_group && mask == 0 && fz && h->time_xt == 0) return pcg_batched(iters);
     // the captured graphs hold the macro launches of one stress-control mask
     if (h->graph_mask != mask) {
       for (auto& ex : h->cg_exec)
@@ -867,6 +1145,81 @@ int pf_dirichlet_solve(rve_s* h, Ops<R>& o, int* iters) {
   return RVE_OK;
 }
 
+// Phase-field balance (eqs. strpf, phase) at the driving state h->S (sum S, sum S^2 over
+// the voxels given): PCG with the preconditioner of eq. precph, (1 + l^2 |xi|^2)^-1, one
+// FFT round trip per iteration (or the Dirichlet option's solve); writes phi before the
+// clamp into X = rbuf[0, N) and adds the iterations to *pf_iters.
+template <typename R>
+int pf_solve(rve_s* h, Ops<R>& o, double sumS, double sumS2, int* pf_iters) {
+  hipStream_t st = h->st;
+  const long long N = h->g.nvox;
+  const double invN = 1.0 / (double)N;
+  int rc = RVE_OK;
+  double* X = h->rbuf;
+  double *Rr = h->rbuf + N, *Z = h->rbuf + 2 * N, *P = h->rbuf + 3 * N, *Wv = h->rbuf + 4 * N;
+  launch_zero(X, N * 8, st);
+  if (h->d.pf_dirichlet && h->n_preset > 0) {
+    if ((rc = pf_dirichlet_solve<R>(h, o, pf_iters))) return rc;
+  } else if (sumS > 0.0) {
+    typedef cplx<R> C;
+    C* W1 = (C*)h->spec;
+    const double bb = 4.0 * sumS2;
+    const double tol2 = h->d.tol_lin * h->d.tol_lin * bb;
+    launch_rscale(N, h->S, 2.0, Rr, st);
+    // convergence control on the device, as in the momentum CG: iterations are enqueued
+    // in batches and the test turns the rest of a batch into no-ops
+    double* sc = h->scal;
+    h->hs[SC_FLAG] = 0.0;
+    h->hs[SC_ITER] = 0.0;
+    h->hs[SC_TOL2] = tol2;
+    HIPCHK(hipMemcpyAsync(sc + SC_FLAG, h->hs + SC_FLAG, 3 * sizeof(double),
+                          hipMemcpyHostToDevice, st));
+    const double* stop = sc + SC_FLAG;
+    auto prec = [&](const double* in, double* outp, const double* stp) {
+      launch_x_r2c<R>(h->pl, in, true, N, nullptr, 0.0, W1, o.NH, 1, st, stp);
+      launch_fft_yz<R>(h->pl, W1, o.NH, 1, 1, false, st, stp);
+      launch_fft_yz<R>(h->pl, W1, o.NH, 1, 2, false, st, stp);
+      launch_pf_scale<R>(h->pl, W1, h->d.ell, invN, st, stp);
+      launch_fft_yz<R>(h->pl, W1, o.NH, 1, 2, true, st, stp);
+      launch_fft_yz<R>(h->pl, W1, o.NH, 1, 1, true, st, stp);
+      launch_x_c2r<R>(h->pl, W1, o.NH, outp, true, N, 1, 1.0, 0, st, stp);
+    };
+    prec(Rr, Z, nullptr);
+    int nb = launch_rdot(N, Rr, Z, h->partial, st);
+    launch_reduce(h->partial, nb, 1, 0, sc + SC_RZ0, st);
+    HIPCHK(hipMemcpyAsync(P, Z, N * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(Wv, Rr, N * 8, hipMemcpyDeviceToDevice, st));
+    bool ok = false;
+    int queued = 0, batch = 4;
+    while (queued < h->d.max_krylov) {
+      const int nq = std::min(batch, h->d.max_krylov - queued);
+      for (int kk = 0; kk < nq; ++kk) {
+        const int k = queued + kk;
+        const int cur = SC_RZ0 + (k & 1), nxt = SC_RZ0 + ((k + 1) & 1);
+        nb = launch_pf_pq(N, P, Wv, h->S, h->partial, st, stop);
+        launch_reduce(h->partial, nb, 1, 0, sc + SC_PQ, st, stop);
+        nb = launch_pf_xr(N, X, Rr, P, Wv, h->S, sc, cur, SC_PQ, h->partial, st, stop);
+        launch_reduce(h->partial, nb, 1, 0, sc + SC_RR, st, stop);
+        launch_pf_check(sc, SC_FLAG, SC_ITER, SC_PQ, SC_RR, SC_TOL2, st);
+        prec(Rr, Z, stop);
+        nb = launch_rdot(N, Rr, Z, h->partial, st, stop);
+        launch_reduce(h->partial, nb, 1, 0, sc + nxt, st, stop);
+        launch_pf_pw(N, P, Wv, Z, Rr, sc, nxt, cur, st, stop);
+      }
+      queued += nq;
+      if ((rc = sync_read(h, SC_FLAG, 2))) return rc;
+      if (h->hs[SC_FLAG] != 0.0) {
+        ok = h->hs[SC_FLAG] == 1.0;
+        break;
+      }
+      batch = std::min(2 * batch, 16);
+    }
+    *pf_iters += (int)h->hs[SC_ITER];
+    if (!ok) return fail(RVE_E_NOCONV, "phase-field Krylov solver did not converge");
+  }
+  return RVE_OK;
+}
+
 template <typename R>
 int run_increment(rve_s* h, const double de_in[6], const double* dsig, int mask, double dt,
                   rve_stats* out) {
@@ -901,6 +1254,7 @@ int run_increment(rve_s* h, const double de_in[6], const double* dsig, int mask,
   std::memset(&s, 0, sizeof(s));
   const double t0 = now_ms();
   int rc;
+  h->batch_peak = 1;
   // transactional copies of the state at time t
   HIPCHK(hipMemcpyAsync(h->eps_t, h->eps, 6 * N * 8, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(h->sig_t, h->sig, 6 * N * 8, hipMemcpyDeviceToDevice, st));
@@ -985,75 +1339,12 @@ int run_increment(rve_s* h, const double de_in[6], const double* dsig, int mask,
       launch_reduce(h->partial, voxel_grid(N), RED_SOURCE, 0, h->scal + SC_MISC, st);
       if ((rc = sync_read(h, SC_MISC, 2))) return rc;
       const double sumS = h->hs[SC_MISC], sumS2 = h->hs[SC_MISC + 1];
-      double* X = h->rbuf;
-      double *Rr = h->rbuf + N, *Z = h->rbuf + 2 * N, *P = h->rbuf + 3 * N, *Wv = h->rbuf + 4 * N;
-      launch_zero(X, N * 8, st);
-      if (h->d.pf_dirichlet && h->n_preset > 0) {
-        if ((rc = pf_dirichlet_solve<R>(h, o, &s.pf_iters))) {
-          s.ms_phase_field += now_ms() - tp;
-          goto fail_out;
-        }
-      } else if (sumS > 0.0) {
-        typedef cplx<R> C;
-        C* W1 = (C*)h->spec;
-        const double bb = 4.0 * sumS2;
-        const double tol2 = h->d.tol_lin * h->d.tol_lin * bb;
-        launch_rscale(N, h->S, 2.0, Rr, st);
-        // convergence control on the device, as in the momentum CG: iterations are enqueued
-        // in batches and the test turns the rest of a batch into no-ops
-        double* sc = h->scal;
-        h->hs[SC_FLAG] = 0.0;
-        h->hs[SC_ITER] = 0.0;
-        h->hs[SC_TOL2] = tol2;
-        HIPCHK(hipMemcpyAsync(sc + SC_FLAG, h->hs + SC_FLAG, 3 * sizeof(double),
-                              hipMemcpyHostToDevice, st));
-        const double* stop = sc + SC_FLAG;
-        auto prec = [&](const double* in, double* outp, const double* stp) {
-          launch_x_r2c<R>(h->pl, in, true, N, nullptr, 0.0, W1, o.NH, 1, st, stp);
-          launch_fft_yz<R>(h->pl, W1, o.NH, 1, 1, false, st, stp);
-          launch_fft_yz<R>(h->pl, W1, o.NH, 1, 2, false, st, stp);
-          launch_pf_scale<R>(h->pl, W1, h->d.ell, invN, st, stp);
-          launch_fft_yz<R>(h->pl, W1, o.NH, 1, 2, true, st, stp);
-          launch_fft_yz<R>(h->pl, W1, o.NH, 1, 1, true, st, stp);
-          launch_x_c2r<R>(h->pl, W1, o.NH, outp, true, N, 1, 1.0, 0, st, stp);
-        };
-        prec(Rr, Z, nullptr);
-        int nb = launch_rdot(N, Rr, Z, h->partial, st);
-        launch_reduce(h->partial, nb, 1, 0, sc + SC_RZ0, st);
-        HIPCHK(hipMemcpyAsync(P, Z, N * 8, hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(Wv, Rr, N * 8, hipMemcpyDeviceToDevice, st));
-        bool ok = false;
-        int queued = 0, batch = 4;
-        while (queued < h->d.max_krylov) {
-          const int nq = std::min(batch, h->d.max_krylov - queued);
-          for (int kk = 0; kk < nq; ++kk) {
-            const int k = queued + kk;
-            const int cur = SC_RZ0 + (k & 1), nxt = SC_RZ0 + ((k + 1) & 1);
-            nb = launch_pf_pq(N, P, Wv, h->S, h->partial, st, stop);
-            launch_reduce(h->partial, nb, 1, 0, sc + SC_PQ, st, stop);
-            nb = launch_pf_xr(N, X, Rr, P, Wv, h->S, sc, cur, SC_PQ, h->partial, st, stop);
-            launch_reduce(h->partial, nb, 1, 0, sc + SC_RR, st, stop);
-            launch_pf_check(sc, SC_FLAG, SC_ITER, SC_PQ, SC_RR, SC_TOL2, st);
-            prec(Rr, Z, stop);
-            nb = launch_rdot(N, Rr, Z, h->partial, st, stop);
-            launch_reduce(h->partial, nb, 1, 0, sc + nxt, st, stop);
-            launch_pf_pw(N, P, Wv, Z, Rr, sc, nxt, cur, st, stop);
-          }
-          queued += nq;
-          if ((rc = sync_read(h, SC_FLAG, 2))) return rc;
-          if (h->hs[SC_FLAG] != 0.0) {
-            ok = h->hs[SC_FLAG] == 1.0;
-            break;
-          }
-          batch = std::min(2 * batch, 16);
-        }
-        s.pf_iters += (int)h->hs[SC_ITER];
-        if (!ok) {
-          s.ms_phase_field += now_ms() - tp;
-          rc = fail(RVE_E_NOCONV, "phase-field Krylov solver did not converge");
-          goto fail_out;
-        }
+      if ((rc = pf_solve<R>(h, o, sumS, sumS2, &s.pf_iters))) {
+        s.ms_phase_field += now_ms() - tp;
+        if (rc == RVE_E_NOCONV) goto fail_out;
+        return rc;
       }
+      double* X = h->rbuf;
       launch_clamp(N, X, h->phi_t, h->phi, st);
       launch_stag_norms(N, h->eps, h->eps_prev, h->eps_t, h->phi, h->phi_prev, h->phi_t,
                         h->partial, st);
@@ -1109,6 +1400,7 @@ int run_increment(rve_s* h, const double de_in[6], const double* dsig, int mask,
     s.ms_commit = now_ms() - tcm;
   }
   s.ms_total = now_ms() - t0;
+  s.cg_batch = h->batch_peak;
   if (out) *out = s;
   return RVE_OK;
 
@@ -1128,9 +1420,190 @@ fail_out:
 }
 
 
+// One finite-strain increment (Algorithm 1; Sec. 2.1 kinematics, eqs. fdef, newton,
+// precf): Newton on the displacement with full steps, halved while the preconditioned
+// residual |M c| grows (this integration has no incremental energy), the paper's GMRES,
+// the stop test max|t grad du| <= tol_newton max|F_i - F_t|; the phase field and the
+// alternating minimisation as in the small-strain increment; the commit of Fp, the
+// history and the GND density of the regularised curl of Fp.
+int run_increment_fs(rve_s* h, const double dF9[9], double dt, rve_stats* out) {
+  typedef cplx<double> C;
+  Ops<double> o(h);
+  o.fs = true;
+  o.cur_dt = dt;
+  const long long N = h->g.nvox;
+  const double invN = 1.0 / (double)N;
+  hipStream_t st = h->st;
+  rve_stats s;
+  std::memset(&s, 0, sizeof(s));
+  const double t0 = now_ms();
+  int rc;
+  const Material m = o.mat(dt);
+  // transactional copies of the state at time t (sig: the return map's warm starts)
+  HIPCHK(hipMemcpyAsync(h->fs_Ft, h->fs_F, 9 * N * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->sig_t, h->sig, 6 * N * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->phi_t, h->phi, N * 8, hipMemcpyDeviceToDevice, st));
+  launch_zero(h->failc, sizeof(int), st);
+  launch_fs_add_uniform(N, h->fs_F, dF9, st);
+  HIPCHK(hipMemcpyAsync(h->fs_Fprev, h->fs_F, 9 * N * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->phi_prev, h->phi_t, N * 8, hipMemcpyDeviceToDevice, st));
+  auto constit = [&](const double* dF, double t) {
+    launch_fs_constitutive(N, h->fs_F, dF, t, h->fs_Fp, h->gslip, h->grain, h->gtab, h->sig,
+                           h->phi_prev, h->fs_P, h->fs_fptr, h->fs_aux, (double*)h->gK, h->ff, m,
+                           h->failc, st);
+  };
+  // c = i xi~_j F{ g(phi) P_ij } (eq. momentum) into cg[5], projected on real-field spectra
+  auto residual = [&]() {
+    o.fwd(h->fs_P, true, N, 9, o.W, h->phi_prev);
+    launch_fs_div(h->pl, o.W, o.NH, o.v(5), o.NH, 1.0, st);
+    launch_herm_proj<double>(h->pl, o.v(5), o.NH, 3, st);
+  };
+  // |M c| (Parseval), M from the mean tangent of the Newton iteration's start
+  auto merit = [&](double& val) -> int {
+    launch_fs_precond(h->pl, o.v(5), o.v(1), o.NH, h->scal + SC_FK, st);
+    const int nb = launch_sdot<double>(h->pl, o.v(1), o.v(1), o.NH, 3, h->partial, st);
+    launch_reduce(h->partial, nb, 1, 0, h->scal + SC_MISC, st);
+    const int r = sync_read(h, SC_MISC, 1);
+    if (r) return r;
+    val = std::sqrt(h->hs[SC_MISC]);
+    return RVE_OK;
+  };
+  bool converged = false;
+  for (int it = 0; it < h->d.max_stag && !converged; ++it) {
+    s.stag_iters = it + 1;
+    double tc = now_ms();
+    constit(nullptr, 0.0);
+    residual();
+    s.ms_constitutive += now_ms() - tc;
+    bool newton_ok = false;
+    for (int nit = 0; nit < h->d.max_newton; ++nit) {
+      s.newton_iters++;
+      double tk = now_ms();
+      {   // mean tangent (eq. avstiff) of the current tangent field
+        const int nb = launch_colsum((const double*)h->gK, N, 81, h->partial, st);
+        launch_reduce(h->partial, nb, 81, 0, h->scal + SC_FK, st);
+        launch_rscale(81, h->scal + SC_FK, invN, h->scal + SC_FK, st);
+      }
+      double m0 = 0.0;
+      if ((rc = merit(m0))) return rc;
+      int kit = 0;
+      rc = o.gmres(kit);
+      s.krylov_iters += kit;
+      if (rc) { s.ms_mech_krylov += now_ms() - tk; goto fail_out; }
+      // dF = F^-1{ i xi~ (x) du } (9 components)
+      launch_fs_grad(h->pl, o.v(0), o.NH, o.W, o.NH, st);
+      o.inv(o.W, 9, h->fs_dF, true, N, invN, 0);
+      s.ms_mech_krylov += now_ms() - tk;
+      tc = now_ms();
+      double t = 1.0;
+      bool acc = false;
+      for (int ls = 0; ls < 30; ++ls) {
+        constit(h->fs_dF, t);
+        residual();
+        double mt = 0.0;
+        if ((rc = merit(mt))) return rc;
+        if (mt <= m0 || m0 == 0.0) { acc = true; break; }
+        t *= 0.5;
+        s.ls_cuts++;
+      }
+      s.ms_constitutive += now_ms() - tc;
+      if (!acc) {
+        rc = fail(RVE_E_NOCONV, "finite-strain Newton: no step reduces the residual");
+        goto fail_out;
+      }
+      launch_fs_update(N, h->fs_F, h->fs_dF, t, h->fs_Ft, h->partial, st);
+      launch_reduce(h->partial, voxel_grid(N), 2, 1, h->scal + SC_MISC, st);
+      if ((rc = sync_read(h, SC_MISC, 2))) return rc;
+      const double num = h->hs[SC_MISC], den = h->hs[SC_MISC + 1];
+      if (num <= h->d.tol_newton * den || num == 0.0) { newton_ok = true; break; }
+    }
+    if (!newton_ok) { rc = fail(RVE_E_NOCONV, "Newton reached max_newton"); goto fail_out; }
+    {   // ---- phase field at F_i ----
+      double tp = now_ms();
+      launch_fs_source(N, h->fs_aux, h->wp, h->trig, h->wcrit, h->S, m, h->partial, st);
+      launch_reduce(h->partial, voxel_grid(N), RED_SOURCE, 0, h->scal + SC_MISC, st);
+      if ((rc = sync_read(h, SC_MISC, 2))) return rc;
+      const double sumS = h->hs[SC_MISC], sumS2 = h->hs[SC_MISC + 1];
+      if ((rc = pf_solve<double>(h, o, sumS, sumS2, &s.pf_iters))) {
+        s.ms_phase_field += now_ms() - tp;
+        if (rc == RVE_E_NOCONV) goto fail_out;
+        return rc;
+      }
+      launch_clamp(N, h->rbuf, h->phi_t, h->phi, st);
+      launch_fs_stag_norms(N, h->fs_F, h->fs_Fprev, h->fs_Ft, h->phi, h->phi_prev, h->phi_t,
+                           h->partial, st);
+      launch_reduce(h->partial, voxel_grid(N), 4, 1, h->scal + SC_MISC, st);
+      if ((rc = sync_read(h, SC_MISC, 4))) return rc;
+      auto ratio = [](double a, double b) { return a == 0.0 ? 0.0 : (b > 0.0 ? a / b : INFINITY); };
+      const double re = ratio(h->hs[SC_MISC], h->hs[SC_MISC + 1]);
+      const double rp = ratio(h->hs[SC_MISC + 2], h->hs[SC_MISC + 3]);
+      HIPCHK(hipMemcpyAsync(h->fs_Fprev, h->fs_F, 9 * N * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(h->phi_prev, h->phi, N * 8, hipMemcpyDeviceToDevice, st));
+      s.ms_phase_field += now_ms() - tp;
+      if (re <= h->d.tol_stag && rp <= h->d.tol_stag) converged = true;
+    }
+  }
+  if (!converged) { rc = fail(RVE_E_NOCONV, "alternating minimisation reached max_stag"); goto fail_out; }
+  {
+    int nfail = 0;
+    HIPCHK(hipMemcpyAsync(&nfail, h->failc, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    s.rm_failures = nfail;
+    if (nfail > 0) { rc = fail(RVE_E_NOCONV, "return mapping did not converge"); goto fail_out; }
+  }
+  {   // ---- commit ----
+    double tcm = now_ms();
+    launch_fs_commit(N, h->fs_P, h->fs_F, h->fs_Fp, h->fs_fptr, h->gslip, h->rho_ssd, h->rho_gnd,
+                     h->wp, h->gs, h->H, h->wcrit, h->trig, h->fs_aux, h->phi, m, h->partial, st);
+    const int nb = voxel_grid(N);
+    launch_reduce(h->partial, nb, 19, 0, h->scal + SC_FM, st);
+    launch_reduce(h->partial + 19LL * nb, nb, 2, 1, h->scal + SC_FM + 19, st);
+    // GND density of the regularised curl of Fp (the identity has no curl)
+    C* B9 = (C*)h->spec;
+    o.fwd(h->fs_Fp, true, N, 9, B9);
+    launch_curl_reg<double>(h->pl, B9, o.NH, h->d.ell_fp, invN, st);
+    o.inv(B9, 9, h->rbuf, true, N, 1.0, 0);
+    launch_gnd(N, h->rbuf, h->grain, h->gtab, h->Q81, h->d.burgers, h->rho_gnd, st);
+    if (m.flow == FLOW_DUNNE)
+      launch_taylor(N, h->gslip, h->rho_ssd, h->rho_gnd, h->grain, h->gtab, m.mu_b, st);
+    if ((rc = sync_read(h, SC_FM, 21))) return rc;
+    for (int c = 0; c < 9; ++c) {
+      s.macro_pk1[c] = h->hs[SC_FM + c] * invN;
+      s.macro_defgrad[c] = h->hs[SC_FM + 9 + c] * invN;
+    }
+    static const int ij[6][2] = {{0, 0}, {1, 1}, {2, 2}, {1, 2}, {0, 2}, {0, 1}};
+    for (int c = 0; c < 6; ++c) {
+      const int a = 3 * ij[c][0] + ij[c][1], b = 3 * ij[c][1] + ij[c][0];
+      s.macro_stress[c] = 0.5 * (s.macro_pk1[a] + s.macro_pk1[b]);
+      s.macro_strain[c] = 0.5 * (s.macro_defgrad[a] + s.macro_defgrad[b]) - (c < 3 ? 1.0 : 0.0);
+    }
+    s.n_triggered = h->hs[SC_FM + 18];
+    s.max_phi = h->hs[SC_FM + 19];
+    s.max_phi_slip = h->hs[SC_FM + 20];
+    s.ms_commit = now_ms() - tcm;
+  }
+  s.ms_total = now_ms() - t0;
+  s.cg_batch = 1;
+  if (out) *out = s;
+  return RVE_OK;
+
+fail_out:
+  {
+    std::string msg = g_err;
+    (void)hipMemcpyAsync(h->fs_F, h->fs_Ft, 9 * N * 8, hipMemcpyDeviceToDevice, st);
+    (void)hipMemcpyAsync(h->sig, h->sig_t, 6 * N * 8, hipMemcpyDeviceToDevice, st);
+    (void)hipMemcpyAsync(h->phi, h->phi_t, N * 8, hipMemcpyDeviceToDevice, st);
+    (void)hipStreamSynchronize(st);
+    s.ms_total = now_ms() - t0;
+    if (out) *out = s;
+    g_err = msg;
+  }
+  return rc;
+}
+
 int create_impl(rve_s* h, const rve_desc* d, void* dev_arena, size_t arena_bytes,
                 void* hip_stream, rve_s** out);
-static_assert(SC_N == 432, "rve_s::hs_static holds SC_N host scalars");
+static_assert(SC_N == 544, "rve_s::hs_static holds SC_N host scalars");
 
 }  // namespace
 
@@ -1202,6 +1675,7 @@ int create_impl(rve_s* h, const rve_desc* d, void* dev_arena, size_t arena_bytes
   h->st = (hipStream_t)hip_stream;
   (void)hipGetDevice(&h->device);
   crystal_frame(h->d.C11, h->d.C12, h->d.C44, &h->cf);
+  fs_frame(h->d.C11, h->d.C12, h->d.C44, &h->ff);
   {
     // CG iterations replay captured graphs on small, launch-bound grids only: at 128^3
     // eager launches measured faster (a replay leaves ~8 us before the next graph's first
@@ -1357,6 +1831,14 @@ int rve_set_microstructure(rve_s* h, const int32_t* grain, int32_t n_grains, con
   launch_zero(h->beta, 9 * N * 8, st);
   double* zero1[] = {h->rho_gnd, h->wp, h->gs, h->H, h->wcrit, h->trig, h->S, h->wep};
   for (double* p : zero1) launch_zero(p, N * 8, st);
+  if (h->fs) {      // F = Fp = I, no stress
+    const double I9[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    for (double* p : {h->fs_F, h->fs_Fp}) {
+      launch_zero(p, 9 * N * 8, st);
+      launch_fs_add_uniform(N, p, I9, st);
+    }
+    launch_zero(h->fs_P, 9 * N * 8, st);
+  }
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
   for (int c = 0; c < 6; ++c) h->msig_t[c] = h->meps_t[c] = 0.0;
@@ -1369,10 +1851,9 @@ int rve_step_increment_mixed(rve_s* h, const double deps[6], const double dsig[6
                              int32_t stress_mask, double dt, rve_stats* st) {
   if (!h || !deps) return fail(RVE_E_ARG, "null argument");
   if (!h->micro) return fail(RVE_E_STATE, "microstructure not set");
+  if (h->fs) return fail(RVE_E_ARG, "finite-strain handle: use rve_step_increment_finite");
   if (stress_mask < 0 || stress_mask > 63) return fail(RVE_E_ARG, "stress_mask outside 0..63");
   if (stress_mask && !dsig) return fail(RVE_E_ARG, "null stress increment");
-  if (stress_mask && h->d.krylov != RVE_KRYLOV_CG)
-    return fail(RVE_E_ARG, "mixed macroscopic control runs with the CG solver");
   double ds[6] = {0, 0, 0, 0, 0, 0};
   for (int c = 0; c < 6; ++c) {
     const bool f = (stress_mask >> c) & 1;
@@ -1387,6 +1868,17 @@ int rve_step_increment_mixed(rve_s* h, const double deps[6], const double dsig[6
                 : run_increment<float>(h, deps, ds, stress_mask, dt, st);
 }
 
+int rve_step_increment_finite(rve_s* h, const double dF[9], double dt, rve_stats* st) {
+  if (!h || !dF) return fail(RVE_E_ARG, "null argument");
+  if (!h->fs) return fail(RVE_E_ARG, "small-strain handle: use rve_step_increment");
+  if (!h->micro) return fail(RVE_E_STATE, "microstructure not set");
+  for (int c = 0; c < 9; ++c)
+    if (!std::isfinite(dF[c])) return fail(RVE_E_ARG, "non-finite increment");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RVE_E_ARG, "dt must be positive");
+  g_err.clear();
+  return run_increment_fs(h, dF, dt, st);
+}
+
 int rve_step_increment(rve_s* h, const double deps[6], double dt, rve_stats* st) {
   return rve_step_increment_mixed(h, deps, nullptr, 0, dt, st);
 }
@@ -1397,10 +1889,47 @@ int rve_pool_step(rve_s* const* hs, int32_t n, const double* deps, const double*
   for (int i = 0; i < n; ++i)
     for (int j = i + 1; j < n; ++j)
       if (hs[i] == hs[j]) return fail(RVE_E_ARG, "handles must be distinct");
+  for (int i = 0; i < n; ++i)
+    if (!hs[i]) return fail(RVE_E_ARG, "null handle");
+  // groups of handles that can share CG launches: same grid, precision, derivative and CG
+  // solver on one device, small-strain kinematics, fused z passes
+  std::vector<std::unique_ptr<CgGroup>> groups;
+  std::vector<CgGroup*> gof((size_t)n, nullptr);
+  auto same = [](const rve_s* a, const rve_s* b) {
+    return a->d.n[0] == b->d.n[0] && a->d.n[1] == b->d.n[1] && a->d.n[2] == b->d.n[2] &&
+           a->d.precision == b->d.precision && a->d.deriv == b->d.deriv &&
+           a->device == b->device && a->d.max_krylov == b->d.max_krylov;
+  };
+  auto can_batch = [](const rve_s* a) {
+    return !a->fs && a->d.krylov == RVE_KRYLOV_CG && a->time_xt == 0 &&
+           (a->f64 ? fused_z_available<double>(a->pl) : fused_z_available<float>(a->pl));
+  };
+  if (!g_no_batch) {
+    for (int i = 0; i < n; ++i) {
+      if (!can_batch(hs[i]) || gof[i]) continue;
+      int cnt = 0;
+      for (int j = i; j < n; ++j) cnt += can_batch(hs[j]) && !gof[j] && same(hs[i], hs[j]);
+      if (cnt < 2) continue;
+      groups.emplace_back(new CgGroup());
+      CgGroup* G = groups.back().get();
+      for (int j = i; j < n && G->members < kMaxBatch; ++j)
+        if (can_batch(hs[j]) && !gof[j] && same(hs[i], hs[j])) {
+          gof[j] = G;
+          G->members++;
+        }
+    }
+  }
   std::vector<std::string> errs((size_t)n);
   auto one = [&](int i) {
+    hs[i]->cg_group = gof[i];
     status[i] = rve_step_increment(hs[i], deps + 6 * i, dt[i], stats ? stats + i : nullptr);
     if (status[i] != RVE_OK) errs[i] = g_err;
+    hs[i]->cg_group = nullptr;
+    if (CgGroup* G = gof[i]) {       // no leader waits for a handle that has finished
+      std::lock_guard<std::mutex> lk(G->mu);
+      G->members--;
+      G->cv.notify_all();
+    }
   };
   if (n == 1) {
     one(0);
@@ -1415,23 +1944,32 @@ int rve_pool_step(rve_s* const* hs, int32_t n, const double* deps, const double*
   return RVE_OK;
 }
 
+static const uint32_t kSmallOnly =
+    RVE_F_STRAIN | RVE_F_STRESS | RVE_F_STRESS_EFF | RVE_F_EPS_P | RVE_F_BETA_P;
+static const uint32_t kFiniteOnly = RVE_F_DEFGRAD | RVE_F_PK1 | RVE_F_FP;
+
 size_t rve_fields_count(const rve_s* h, uint32_t mask) {
   if (!h) return 0;
+  if (mask >> 17) return 0;
+  if (mask & (h->fs ? kSmallOnly : kFiniteOnly)) return 0;
   const uint32_t six = RVE_F_STRAIN | RVE_F_STRESS | RVE_F_STRESS_EFF | RVE_F_EPS_P;
+  const uint32_t nine = RVE_F_BETA_P | kFiniteOnly;
   size_t c = 0;
-  for (int b = 0; b < 14; ++b) {
+  for (int b = 0; b < 17; ++b) {
     const uint32_t bit = 1u << b;
     if (!(mask & bit)) continue;
-    c += (bit & six) ? 6 : (bit == RVE_F_BETA_P ? 9 : 1);
+    c += (bit & six) ? 6 : ((bit & nine) ? 9 : 1);
   }
-  if (mask >> 14) return 0;
   return c * (size_t)h->g.nvox;
 }
 
 int rve_fields(rve_s* h, uint32_t mask, double* out, size_t n) {
   if (!h || !out) return fail(RVE_E_ARG, "null argument");
   if (!h->micro) return fail(RVE_E_STATE, "microstructure not set");
-  if (mask >> 14) return fail(RVE_E_ARG, "unknown field bit");
+  if (mask >> 17) return fail(RVE_E_ARG, "unknown field bit");
+  if (mask & (h->fs ? kSmallOnly : kFiniteOnly))
+    return fail(RVE_E_ARG, h->fs ? "small-strain field of a finite-strain handle"
+                                 : "finite-strain field of a small-strain handle");
   const size_t need = rve_fields_count(h, mask);
   if (n < need) return fail(RVE_E_ARG, "output buffer too small");
   const long long N = h->g.nvox;
@@ -1443,7 +1981,7 @@ int rve_fields(rve_s* h, uint32_t mask, double* out, size_t n) {
     return RVE_OK;
   };
   int rc = RVE_OK;
-  for (int b = 0; b < 14 && rc == RVE_OK; ++b) {
+  for (int b = 0; b < 17 && rc == RVE_OK; ++b) {
     const uint32_t bit = 1u << b;
     if (!(mask & bit)) continue;
     switch (bit) {
@@ -1464,6 +2002,12 @@ int rve_fields(rve_s* h, uint32_t mask, double* out, size_t n) {
       case RVE_F_EPS_P: rc = cp(h->epsp, 6); break;
       case RVE_F_SLIP_RES: rc = cp(h->gslip, 1); break;
       case RVE_F_BETA_P: rc = cp(h->beta, 9); break;
+      case RVE_F_DEFGRAD: rc = cp(h->fs_F, 9); break;
+      case RVE_F_PK1:         // degraded on the device into the phase-field scratch
+        launch_fs_degrade(N, h->fs_P, h->phi, h->d.k_res, h->rbuf, st);
+        rc = cp(h->rbuf, 9);
+        break;
+      case RVE_F_FP: rc = cp(h->fs_Fp, 9); break;
     }
   }
   if (rc) return rc;
@@ -1478,6 +2022,9 @@ int rve_destroy(rve_s* h) {
   for (hipGraphExec_t& e : h->cg_exec)
     if (e) (void)hipGraphExecDestroy(e);
   for (hipEvent_t e : h->xt_ev) (void)hipEventDestroy(e);
+  if (h->cg_ready) (void)hipEventDestroy(h->cg_ready);
+  if (h->cg_done) (void)hipEventDestroy(h->cg_done);
+  h->cg_ready = h->cg_done = nullptr;
   if (h->static_dev >= 0) {
     std::lock_guard<std::mutex> lk(g_scratch_mu);
     g_scratch_busy[h->static_dev] = false;
@@ -1520,6 +2067,29 @@ static int diag_pass(rve_s* h, int pass_id, int reps, double* bytes) {
       case RVE_PASS_ZDIV:
         launch_zdiv_fwd<R>(h->pl, o.W, o.v(4), o.v(3), h->g.nspec, h->partial, st);
         break;
+      case RVE_PASS_PF_ITER: {   // the launches of one phase-field CG iteration (pf_solve)
+        const long long n = h->g.nvox;
+        double *X = h->rbuf, *Rr = h->rbuf + n, *Z = h->rbuf + 2 * n, *P = h->rbuf + 3 * n,
+               *Wv = h->rbuf + 4 * n;
+        double* sc = h->scal;
+        C* W1 = (C*)h->spec;
+        int nb = launch_pf_pq(n, P, Wv, h->S, h->partial, st);
+        launch_reduce(h->partial, nb, 1, 0, sc + SC_PQ, st);
+        nb = launch_pf_xr(n, X, Rr, P, Wv, h->S, sc, SC_RZ0, SC_PQ, h->partial, st);
+        launch_reduce(h->partial, nb, 1, 0, sc + SC_RR, st);
+        launch_pf_check(sc, SC_FLAG, SC_ITER, SC_PQ, SC_RR, SC_TOL2, st);
+        launch_x_r2c<R>(h->pl, Rr, true, n, nullptr, 0.0, W1, o.NH, 1, st);
+        launch_fft_yz<R>(h->pl, W1, o.NH, 1, 1, false, st);
+        launch_fft_yz<R>(h->pl, W1, o.NH, 1, 2, false, st);
+        launch_pf_scale<R>(h->pl, W1, h->d.ell, 1.0 / N, st);
+        launch_fft_yz<R>(h->pl, W1, o.NH, 1, 2, true, st);
+        launch_fft_yz<R>(h->pl, W1, o.NH, 1, 1, true, st);
+        launch_x_c2r<R>(h->pl, W1, o.NH, Z, true, n, 1, 1.0, 0, st);
+        nb = launch_rdot(n, Rr, Z, h->partial, st);
+        launch_reduce(h->partial, nb, 1, 0, sc + SC_RZ1, st);
+        launch_pf_pw(n, P, Wv, Z, Rr, sc, SC_RZ1, SC_RZ0, st);
+        break;
+      }
     }
   }
   switch (pass_id) {
@@ -1533,6 +2103,9 @@ static int diag_pass(rve_s* h, int pass_id, int reps, double* bytes) {
       break;
     case RVE_PASS_ZGRAD: b = 15 * NH * cb; break;
     case RVE_PASS_ZDIV: b = 12 * NH * cb; break;
+    // FP64 vectors: pf_pq 3, pf_xr 7, rdot 2, pf_pw 6 and the real ends of the FFT round trip
+    // 2 reals per voxel; the one-component FFT round trip 12 half-spectrum values
+    case RVE_PASS_PF_ITER: b = 20 * N * 8 + 12 * NH * cb; break;
   }
   if (bytes) *bytes = b;
   HIPCHK(hipGetLastError());
@@ -1616,7 +2189,8 @@ static int diag_op(rve_s* h, const double* u3, double* v3) {
 extern "C" {
 
 int rve_diag_pass(rve_s* h, int32_t pass_id, int32_t reps, double* bytes) {
-  if (!h || reps < 0 || pass_id < 0 || pass_id > RVE_PASS_ZDIV) return fail(RVE_E_ARG, "bad argument");
+  if (h && h->fs) return fail(RVE_E_ARG, "finite-strain handle (see rve_diag_constitutive_finite)");
+  if (!h || reps < 0 || pass_id < 0 || pass_id > RVE_PASS_PF_ITER) return fail(RVE_E_ARG, "bad argument");
   if ((pass_id == RVE_PASS_ZGRAD || pass_id == RVE_PASS_ZDIV) &&
       !(h->f64 ? fused_z_available<double>(h->pl) : fused_z_available<float>(h->pl)))
     return fail(RVE_E_ARG, "no fused z pass for this grid");
@@ -1653,13 +2227,42 @@ int rve_diag_irfft(rve_s* h, int32_t ncomp, const double* in, double* out) {
 }
 
 int rve_diag_constitutive(rve_s* h, const double* eps6, double dt, double* sig6, double* gk21) {
+  if (h && h->fs) return fail(RVE_E_ARG, "finite-strain handle (see rve_diag_constitutive_finite)");
   if (!h || !eps6 || !(dt > 0.0)) return fail(RVE_E_ARG, "bad argument");
   if (!h->micro) return fail(RVE_E_STATE, "microstructure not set");
   return h->f64 ? diag_const<double>(h, eps6, dt, sig6, gk21)
                 : diag_const<float>(h, eps6, dt, sig6, gk21);
 }
 
+int rve_diag_constitutive_finite(rve_s* h, const double* F9, double dt, double* P9,
+                                 double* K81) {
+  if (!h || !F9) return fail(RVE_E_ARG, "bad argument");
+  if (!h->fs) return fail(RVE_E_ARG, "small-strain handle");
+  if (!h->micro) return fail(RVE_E_STATE, "microstructure not set");
+  const long long N = h->g.nvox;
+  hipStream_t st = h->st;
+  Ops<double> o(h);
+  const Material m = o.mat(dt);
+  // scratch: the input in the Newton correction buffer, the warm starts copied aside,
+  // P in the phase-field scratch
+  HIPCHK(hipMemcpyAsync(h->fs_dF, F9, 9 * N * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->sig_t, h->sig, 6 * N * 8, hipMemcpyDeviceToDevice, st));
+  launch_zero(h->failc, sizeof(int), st);
+  launch_fs_constitutive(N, h->fs_dF, nullptr, 0.0, h->fs_Fp, h->gslip, h->grain, h->gtab,
+                         h->sig_t, h->phi, h->rbuf, h->fs_fptr, h->fs_aux, (double*)h->gK, h->ff,
+                         m, h->failc, st);
+  if (P9) HIPCHK(hipMemcpyAsync(P9, h->rbuf, 9 * N * 8, hipMemcpyDeviceToHost, st));
+  if (K81) HIPCHK(hipMemcpyAsync(K81, h->gK, 81 * N * 8, hipMemcpyDeviceToHost, st));
+  int nfail = 0;
+  HIPCHK(hipMemcpyAsync(&nfail, h->failc, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  if (nfail) return fail(RVE_E_NOCONV, "return mapping did not converge");
+  return RVE_OK;
+}
+
 int rve_diag_operator(rve_s* h, const double* u3, double* v3) {
+  if (h && h->fs) return fail(RVE_E_ARG, "finite-strain handle (see rve_diag_constitutive_finite)");
   if (!h || !u3 || !v3) return fail(RVE_E_ARG, "bad argument");
   if (!h->micro) return fail(RVE_E_STATE, "microstructure not set");
   return h->f64 ? diag_op<double>(h, u3, v3) : diag_op<float>(h, u3, v3);

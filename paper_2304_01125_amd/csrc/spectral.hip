@@ -448,6 +448,12 @@ k_cg_step(cplx<R>* __restrict__ x, const cplx<R>* __restrict__ pv,
           Grid g, double* __restrict__ partial, const double* __restrict__ stop,
           const double* __restrict__ pq_part, int nb_pq, int iflag, int iiter,
           const double* __restrict__ m0) {
+  {
+    const long long d = slot_delta(g);
+    x = at_slot(x, d); pv = at_slot(pv, d); qv = at_slot(qv, d); z = at_slot(z, d);
+    kbar21 = at_slot(kbar21, d); sc = at_slot(sc, d); partial = at_slot(partial, d);
+    stop = at_slot(stop, d); pq_part = at_slot(pq_part, d); m0 = at_slot(m0, d);
+  }
   if (stop && *stop != 0.0) return;
   __shared__ double K4[81];
   __shared__ double red[16];
@@ -589,10 +595,10 @@ int launch_cg_step(const Plans& p, cplx<R>* x, const cplx<R>* pv, const cplx<R>*
                    int nb_pq, int iflag, int iiter, int max_blocks, const double* m0) {
   const int nb = std::min(grid_for(p.g.nspec), max_blocks);
   if (p.g.sch)
-    hipLaunchKernelGGL((k_cg_step<R, 1>), dim3(nb), dim3(256), 0, st, x, pv, q, z, cs, kbar21,
+    hipLaunchKernelGGL((k_cg_step<R, 1>), dim3(nb, 1, p.nslot), dim3(256), 0, st, x, pv, q, z, cs, kbar21,
                        sc, cur, ipq, p.g, partial, stop, pq_part, nb_pq, iflag, iiter, m0);
   else
-    hipLaunchKernelGGL((k_cg_step<R, 0>), dim3(nb), dim3(256), 0, st, x, pv, q, z, cs, kbar21,
+    hipLaunchKernelGGL((k_cg_step<R, 0>), dim3(nb, 1, p.nslot), dim3(256), 0, st, x, pv, q, z, cs, kbar21,
                        sc, cur, ipq, p.g, partial, stop, pq_part, nb_pq, iflag, iiter, m0);
   return nb;
 }

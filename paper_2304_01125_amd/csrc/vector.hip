@@ -83,15 +83,22 @@ __global__ void __launch_bounds__(256) k_reduce_check(const double* __restrict__
   }
 }
 
-__global__ void __launch_bounds__(256) k_cg_check_tail(double* __restrict__ sc, CgCheck ck) {
+__global__ void __launch_bounds__(256) k_cg_check_tail(double* __restrict__ sc, CgCheck ck,
+                                                       const long long* __restrict__ sd) {
+  if (sd) {   // batched: block z tests RVE z
+    const long long d = sd[blockIdx.z];
+    sc = at_slot(sc, d);
+    ck.part = at_slot(ck.part, d);
+  }
   if (sc[ck.iflag] != 0.0) return;
   __shared__ double red[8];
   double rz;
   (void)cg_check_inline(ck, sc, red, rz);
 }
 
-void launch_cg_check_tail(double* sc, const CgCheck& ck, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_check_tail, dim3(1), dim3(256), 0, st, sc, ck);
+void launch_cg_check_tail(double* sc, const CgCheck& ck, hipStream_t st, const long long* sd,
+                          int nslot) {
+  hipLaunchKernelGGL(k_cg_check_tail, dim3(1, 1, nslot), dim3(256), 0, st, sc, ck, sd);
 }
 
 void launch_reduce_pq(const double* partial, int nblk, double* sc, int ipq, int iflag,

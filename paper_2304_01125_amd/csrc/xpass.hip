@@ -114,6 +114,10 @@ __global__ void __launch_bounds__(256)
 k_x_tangent(cplx<R>* __restrict__ data, long long cs, const R* __restrict__ gK, double scale,
             Grid g, AxisPlan pl, const cplx<R>* __restrict__ tw_g, int Q,
             const double* __restrict__ stop) {
+  {
+    const long long d = slot_delta(g);
+    data = at_slot(data, d); gK = at_slot(gK, d); tw_g = at_slot(tw_g, d); stop = at_slot(stop, d);
+  }
   if (stop && *stop != 0.0) return;
   extern __shared__ unsigned char smem_raw[];
   const int N = NC > 0 ? NC : g.n1;
@@ -188,6 +192,10 @@ template <typename R, int N, int Q, int NT>
 __global__ void __launch_bounds__(NT)
 k_x_tangent_ip(cplx<R>* __restrict__ data, long long cs, const R* __restrict__ gK, double scale,
                Grid g, const cplx<R>* __restrict__ tw_g, const double* __restrict__ stop) {
+  {
+    const long long d = slot_delta(g);
+    data = at_slot(data, d); gK = at_slot(gK, d); tw_g = at_slot(tw_g, d); stop = at_slot(stop, d);
+  }
   if (stop && *stop != 0.0) return;
   constexpr int NH = N / 2 + 1, PITCH = N + 1, P = 3 * Q;
   __shared__ cplx<R> tw[N];
@@ -319,10 +327,10 @@ void launch_x_tangent(const Plans& p, cplx<R>* data, long long cs, const R* gK, 
         if constexpr (lds <= 64 * 1024) {
           const int nb = (int)((rows + QI - 1) / QI);
           if (ev0)
-            hipExtLaunchKernelGGL((k_x_tangent_ip<R, NC, QI, NT>), dim3(nb), dim3(NT), 0, st, ev0,
+            hipExtLaunchKernelGGL((k_x_tangent_ip<R, NC, QI, NT>), dim3(nb, 1, p.nslot), dim3(NT), 0, st, ev0,
                                   ev1, 0, data, cs, gK, scale, g, tw, stop);
           else
-            hipLaunchKernelGGL((k_x_tangent_ip<R, NC, QI, NT>), dim3(nb), dim3(NT), 0, st, data,
+            hipLaunchKernelGGL((k_x_tangent_ip<R, NC, QI, NT>), dim3(nb, 1, p.nslot), dim3(NT), 0, st, data,
                                cs, gK, scale, g, tw, stop);
           done = true;
         }
@@ -334,10 +342,10 @@ void launch_x_tangent(const Plans& p, cplx<R>* data, long long cs, const R* gK, 
   });
   if (done) return;
   if (ev0)
-    hipExtLaunchKernelGGL((k_x_tangent<R, 0>), dim3(nblk), dim3(256), sm, st, ev0, ev1, 0, data, cs,
+    hipExtLaunchKernelGGL((k_x_tangent<R, 0>), dim3(nblk, 1, p.nslot), dim3(256), sm, st, ev0, ev1, 0, data, cs,
                           gK, scale, g, p.ax[0], tw, Q, stop);
   else
-    hipLaunchKernelGGL((k_x_tangent<R, 0>), dim3(nblk), dim3(256), sm, st, data, cs, gK, scale, g,
+    hipLaunchKernelGGL((k_x_tangent<R, 0>), dim3(nblk, 1, p.nslot), dim3(256), sm, st, data, cs, gK, scale, g,
                        p.ax[0], tw, Q, stop);
 }
 

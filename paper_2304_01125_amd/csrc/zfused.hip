@@ -82,6 +82,12 @@ k_zgrad_inv(const cplx<R>* __restrict__ zv, const cplx<R>* __restrict__ pold,
             cplx<R>* __restrict__ pnew, long long cs, double* __restrict__ sc, int ia, int ib,
             cplx<R>* __restrict__ e, Grid g, const cplx<R>* __restrict__ tw_g,
             const double* __restrict__ stop, CgCheck ck) {
+  {
+    const long long d = slot_delta(g);
+    zv = at_slot(zv, d); pold = at_slot(pold, d); pnew = at_slot(pnew, d); sc = at_slot(sc, d);
+    e = at_slot(e, d); tw_g = at_slot(tw_g, d); stop = at_slot(stop, d);
+    ck.part = at_slot(ck.part, d);
+  }
   if (stop && *stop != 0.0) return;
   __shared__ double red[2 * (NT / 64)];
   double be;
@@ -211,6 +217,11 @@ __global__ void __launch_bounds__(NT)
 k_zdiv_fwd(const cplx<R>* __restrict__ s, cplx<R>* __restrict__ q, const cplx<R>* __restrict__ pv,
            long long cs, Grid g, const cplx<R>* __restrict__ tw_g, double* __restrict__ partial,
            const double* __restrict__ stop) {
+  {
+    const long long d = slot_delta(g);
+    s = at_slot(s, d); q = at_slot(q, d); pv = at_slot(pv, d); tw_g = at_slot(tw_g, d);
+    partial = at_slot(partial, d); stop = at_slot(stop, d);
+  }
   if (stop && *stop != 0.0) return;
   constexpr int P = TX + 1;
   constexpr int Na = ZSplit<N>::Na, Nb = ZSplit<N>::Nb;
@@ -393,7 +404,7 @@ void launch_zgrad_inv(const Plans& p, const cplx<R>* z, const cplx<R>* pold, cpl
         if constexpr (zgrad_lds<R>(NC, T + 1, S) <= kRegLdsMax) {
           constexpr int NT = threads_for<(T + 1) * ZSplit<NC>::Nb>();
           const int nblk = (g.n1 / 2 / T) * g.n2 * 6;
-          hipLaunchKernelGGL((k_zgrad_inv<R, NC, T, NT, S>), dim3(nblk), dim3(NT), 0, st, z, pold,
+          hipLaunchKernelGGL((k_zgrad_inv<R, NC, T, NT, S>), dim3(nblk, 1, p.nslot), dim3(NT), 0, st, z, pold,
                              pnew, cs, sc, ia, ib, e, g, tw, stop, ck);
         }
       };
@@ -421,7 +432,7 @@ int launch_zdiv_fwd(const Plans& p, const cplx<R>* s, cplx<R>* q, const cplx<R>*
         if constexpr (zdiv_lds<R>(NC, T + 1, S) <= kRegLdsMax) {
           constexpr int NT = threads_for<(T + 1) * ZSplit<NC>::Nb>();
           nblk = (g.n1 / 2 / T) * g.n2 * 3;
-          hipLaunchKernelGGL((k_zdiv_fwd<R, NC, T, NT, S>), dim3(nblk), dim3(NT), 0, st, s, q, pv,
+          hipLaunchKernelGGL((k_zdiv_fwd<R, NC, T, NT, S>), dim3(nblk, 1, p.nslot), dim3(NT), 0, st, s, q, pv,
                              cs, g, tw, partial, stop);
         }
       };

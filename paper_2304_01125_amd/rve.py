@@ -15,16 +15,19 @@ LIB_PATH = os.path.join(_HERE, "librve.so")
 RVE_OK, RVE_E_ARG, RVE_E_NOMEM, RVE_E_DEVICE, RVE_E_NOCONV, RVE_E_STATE = 0, -1, -2, -3, -4, -5
 RVE_FP64, RVE_MIXED = 0, 1
 RVE_MAT_POWER, RVE_MAT_DUNNE = 0, 1
+RVE_KIN_SMALL, RVE_KIN_FINITE = 0, 1
 
 FIELDS = [  # (name, bit, components) in the order rve_fields writes them
     ("strain", 1 << 0, 6), ("stress", 1 << 1, 6), ("stress_eff", 1 << 2, 6),
     ("damage", 1 << 3, 1), ("gs", 1 << 4, 1), ("rho_ssd", 1 << 5, 1), ("rho_gnd", 1 << 6, 1),
     ("wp", 1 << 7, 1), ("h", 1 << 8, 1), ("wcrit", 1 << 9, 1), ("trig", 1 << 10, 1),
     ("eps_p", 1 << 11, 6), ("g", 1 << 12, 1), ("beta_p", 1 << 13, 9),
+    # finite-strain handles
+    ("defgrad", 1 << 14, 9), ("pk1", 1 << 15, 9), ("fp", 1 << 16, 9),
 ]
 FIELD_BITS = {n: (b, c) for n, b, c in FIELDS}
 PASSES = {"fft_z": 0, "fft_y": 1, "x_tangent": 2, "grad": 3, "div": 4, "precond": 5,
-          "constitutive": 6, "matvec": 7, "zgrad": 8, "zdiv": 9}
+          "constitutive": 6, "matvec": 7, "zgrad": 8, "zdiv": 9, "pf_iter": 10}
 
 
 class RveDesc(ctypes.Structure):
@@ -44,7 +47,7 @@ class RveDesc(ctypes.Structure):
                 ("k_B", ctypes.c_double), ("T", ctypes.c_double), ("dV", ctypes.c_double),
                 ("mu", ctypes.c_double), ("krylov", ctypes.c_int32),
                 ("gmres_restart", ctypes.c_int32), ("deriv", ctypes.c_int32),
-                ("pf_dirichlet", ctypes.c_int32)]
+                ("pf_dirichlet", ctypes.c_int32), ("kinematics", ctypes.c_int32)]
 
 
 class RveStats(ctypes.Structure):
@@ -55,7 +58,9 @@ class RveStats(ctypes.Structure):
                 ("max_phi", ctypes.c_double), ("max_phi_slip", ctypes.c_double),
                 ("n_triggered", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("ms_constitutive", ctypes.c_double), ("ms_mech_krylov", ctypes.c_double),
-                ("ms_phase_field", ctypes.c_double), ("ms_commit", ctypes.c_double)]
+                ("ms_phase_field", ctypes.c_double), ("ms_commit", ctypes.c_double),
+                ("macro_pk1", ctypes.c_double * 9), ("macro_defgrad", ctypes.c_double * 9),
+                ("cg_batch", ctypes.c_double)]
 
     def as_dict(self):
         out = {}
@@ -121,6 +126,10 @@ def load():
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(RveStats)]
     lib.rve_diag_partials.restype = ctypes.c_int
     lib.rve_diag_partials.argtypes = [ctypes.POINTER(RveDesc), ctypes.POINTER(ctypes.c_int64)]
+    lib.rve_step_increment_finite.restype = ctypes.c_int
+    lib.rve_step_increment_finite.argtypes = [_P, _D, ctypes.c_double, ctypes.POINTER(RveStats)]
+    lib.rve_diag_constitutive_finite.restype = ctypes.c_int
+    lib.rve_diag_constitutive_finite.argtypes = [_P, _D, ctypes.c_double, _D, _D]
     lib.rve_diag_operator.restype = ctypes.c_int
     lib.rve_diag_operator.argtypes = [_P, _D, _D]
     _lib = lib
@@ -130,8 +139,9 @@ def load():
 def exported_symbols():
     """Names of the C ABI entry points (as declared in include/rve.h)."""
     return ["rve_footprint_bytes", "rve_create", "rve_create_noalloc", "rve_set_microstructure", "rve_step_increment",
-            "rve_step_increment_mixed", "rve_fields", "rve_fields_count", "rve_destroy", "rve_last_error", "rve_diag_rfft",
-            "rve_diag_irfft", "rve_diag_constitutive", "rve_diag_operator", "rve_diag_pass",
+            "rve_step_increment_mixed", "rve_step_increment_finite", "rve_fields", "rve_fields_count", "rve_destroy", "rve_last_error", "rve_diag_rfft",
+            "rve_diag_irfft", "rve_diag_constitutive", "rve_diag_constitutive_finite",
+            "rve_diag_operator", "rve_diag_pass",
             "rve_diag_time_pass", "rve_diag_pass_time", "rve_diag_partials",
             "rve_pool_step"]
 
@@ -170,6 +180,7 @@ def make_desc(desc, precision=RVE_FP64, max_grains=4096):
     d.krylov = int(desc.get("krylov", 0))
     d.gmres_restart = int(desc.get("gmres_restart", 30))
     d.material = int(desc.get("material", RVE_MAT_POWER))
+    d.kinematics = int(desc.get("kinematics", RVE_KIN_SMALL))
     if d.material == RVE_MAT_DUNNE:
         for k in ("rho_m", "v_D", "dF", "k_B", "T", "dV", "mu"):
             setattr(d, k, float(desc[k]))
@@ -209,6 +220,13 @@ def rve_step_increment_mixed(h, deps6, dsig6, stress_mask, dt):
     st = RveStats()
     rc = load().rve_step_increment_mixed(h, _dptr(de), _dptr(ds), int(stress_mask), float(dt),
                                          ctypes.byref(st))
+    return rc, st.as_dict()
+
+
+def rve_step_increment_finite(h, dF9, dt):
+    d = np.ascontiguousarray(np.asarray(dF9, dtype=np.float64).reshape(9))
+    st = RveStats()
+    rc = load().rve_step_increment_finite(h, _dptr(d), float(dt), ctypes.byref(st))
     return rc, st.as_dict()
 
 
@@ -287,6 +305,15 @@ class RVE:
             _check(rc)
         return st
 
+    def step_finite(self, dF9, dt, check=True):
+        """One finite-strain increment under the macro deformation gradient increment dF9
+        (3x3 row-major)."""
+        rc, st = rve_step_increment_finite(self.h, dF9, dt)
+        st["status"] = rc
+        if check:
+            _check(rc)
+        return st
+
     def fields(self, names=("strain", "stress", "damage")):
         mask = 0
         for nm in names:
@@ -320,6 +347,15 @@ class RVE:
         gk = np.empty(21 * self.nvox)
         _check(load().rve_diag_constitutive(self.h, _dptr(e), float(dt), _dptr(sig), _dptr(gk)))
         return sig.reshape(6, self.nvox).T, gk.reshape(21, self.nvox).T
+
+    def constitutive_finite(self, F9, dt):
+        """Finite-strain return map at deformation gradients F9 (M x 9, row-major): the
+        effective first Piola-Kirchhoff stress (M x 9) and g(phi) dP/dF (M x 9 x 9)."""
+        f = np.ascontiguousarray(np.asarray(F9, dtype=np.float64).reshape(self.nvox, 9).T).ravel()
+        P = np.empty(9 * self.nvox)
+        K = np.empty(81 * self.nvox)
+        _check(load().rve_diag_constitutive_finite(self.h, _dptr(f), float(dt), _dptr(P), _dptr(K)))
+        return P.reshape(9, self.nvox).T, K.reshape(9, 9, self.nvox).transpose(2, 0, 1)
 
     def time_pass(self, name="x_tangent", on=True, every=1):
         """Live timing of a kernel inside the solver's CG iterations (HIP events on the

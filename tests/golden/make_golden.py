@@ -7,14 +7,21 @@ Only ``oracle`` (and the seeded input generators in ``synth``) are called.  Outp
   every increment, up to the first increment where the damage jumps by more than 0.5
   in one increment or the alternating-minimisation count exceeds three times its
   median (beyond that the crack path may bifurcate and several answers are correct).
-* voronoi64.npz -- the 64^3 Voronoi polycrystal (64 grains), tight tolerances, the
-  first increments, fields at 4096 seeded sample voxels and the macro stress.
+* voronoi64.npz -- the 64^3 Voronoi polycrystal (64 grains), tight tolerances, every
+  increment up to two increments past damage initiation (G_crit lowered by a power of 2
+  so that it initiates early, as the workload records), fields at 4096 seeded sample voxels
+  after increment 1 and the last two, the macro stress, maximum damage and number of
+  triggered voxels of each.
 * cmsx4_16.npz -- the 16^3 four-grain polycrystal with the thermally activated flow
   rule and Taylor hardening (Table 1 constants), tight tolerances, the first six
   increments (elastic, then yielding): every field after increments 3 and 5, macro stress
   and iteration counts of each.
+* finite16.npz -- the 16^3 eight-grain polycrystal in finite strain (F = Fe Fp, first
+  Piola-Kirchhoff stress), tight tolerances, uniaxial strain along y, four yielding
+  increments: every field after increments 1 and 3, the macro first Piola-Kirchhoff stress
+  of each.
 
-Usage: python tests/golden/make_golden.py [notched16|voronoi64|cmsx4_16] ...
+Usage: python tests/golden/make_golden.py [notched16|voronoi64|cmsx4_16|finite16] ...
 """
 import os
 import sys
@@ -26,10 +33,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle import OracleRVE          # noqa: E402
-from synth import workload, make_inputs   # noqa: E402
+from oracle.finite import OracleFiniteRVE   # noqa: E402
+from synth import workload, make_inputs, small_polycrystal   # noqa: E402
 
 FIELDS = ("strain", "stress", "damage", "gs", "wp", "rho_gnd")
 FIELDS_CMSX4 = FIELDS + ("rho_ssd", "g", "eps_p")
+FIELDS64 = FIELDS + ("h", "wcrit", "trig")
 
 
 def notched16(max_inc=40, snaps=(5, 11, 13, 15, 19, 25, 31, 39)):
@@ -72,23 +81,38 @@ def notched16(max_inc=40, snaps=(5, 11, 13, 15, 19, 25, 31, 39)):
                             **{k2: np.asarray(v) for k2, v in out.items()})
 
 
-def voronoi64(n_inc=2, n_sample=4096):
+def voronoi64(max_inc=16, n_sample=4096, after=2):
+    """Config 1 up to damage initiation: increments until the damage has been non-zero for
+    `after` increments (at most max_inc), the macro stress, the maximum damage and the
+    number of triggered voxels of each, and sampled fields after increment 1 and the last
+    `after` increments."""
     w = workload("voronoi-64-g64").parity()
     inp = make_inputs(w)
     o = OracleRVE(w.desc(), inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
     idx = np.sort(np.random.default_rng(64).choice(w.nvox, n_sample, replace=False))
-    out = {"sample": idx, "macro_stress": []}
+    out = {"sample": idx, "macro_stress": [], "max_phi": [], "n_trig": [], "stag": []}
     t0 = time.time()
-    for k in range(n_inc):
+    damaged = 0
+    for k in range(max_inc):
         st = o.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k])
-        print(f"inc {k}: {time.time() - t0:.0f}s newton {st['newton']} matvecs {st['matvecs']}",
-              flush=True)
+        print(f"inc {k}: {time.time() - t0:.0f}s newton {st['newton']} matvecs {st['matvecs']} "
+              f"stag {st['stag']} n_trig {st['n_trig']} max phi {st['max_phi']:.3e}", flush=True)
         out["macro_stress"].append(st["macro_stress"])
+        out["max_phi"].append(st["max_phi"])
+        out["n_trig"].append(st["n_trig"])
+        out["stag"].append(st["stag"])
+        damaged += st["max_phi"] > 0.0
         f = o.fields()
-        for name in FIELDS:
+        for name in FIELDS64:
             out[f"inc{k}_{name}"] = f[name][idx]
-        np.savez_compressed(os.path.join(HERE, "voronoi64.npz"), last=k,
+        drop = k - after                 # keep increment 1 and the latest `after` increments
+        if drop >= 0 and drop != 1:
+            for name in FIELDS64:
+                out.pop(f"inc{drop}_{name}", None)
+        np.savez_compressed(os.path.join(HERE, "voronoi64.npz"), last=k, G_crit=w.G_crit,
                             **{k2: np.asarray(v) for k2, v in out.items()})
+        if damaged >= after:
+            break
 
 
 def cmsx4_16(n_inc=6, snaps=(3, 5)):
@@ -112,6 +136,36 @@ def cmsx4_16(n_inc=6, snaps=(3, 5)):
                         **{k2: np.asarray(v) for k2, v in out.items()})
 
 
+FIELDS_FINITE = ("defgrad", "pk1", "fp", "damage", "gs", "wp", "rho_ssd", "rho_gnd", "g", "h")
+
+
+def finite_workload():
+    """The finite-strain parity workload (also built by the GPU test)."""
+    return small_polycrystal(n=16, n_grains=8, seed=7).parity()
+
+
+def finite16(n_inc=4, snaps=(1, 3)):
+    w = finite_workload()
+    inp = make_inputs(w)
+    o = OracleFiniteRVE(dict(w.desc(), kinematics=1), inp["grain"], inp["quat"], inp["tau_c0"],
+                        inp["phi0"])
+    out = {"macro_pk1": [], "newton": []}
+    t0 = time.time()
+    for k in range(n_inc):
+        dF = np.zeros(9)
+        dF[4] = inp["deps"][k]
+        st = o.step(dF, inp["dt"][k])
+        print(f"inc {k}: {time.time() - t0:.0f}s newton {st['newton']}", flush=True)
+        out["macro_pk1"].append(st["macro_stress"])
+        out["newton"].append(st["newton"])
+        if k in snaps:
+            f = o.fields()
+            for name in FIELDS_FINITE:
+                out[f"inc{k}_{name}"] = f[name]
+    np.savez_compressed(os.path.join(HERE, "finite16.npz"), last=n_inc - 1,
+                        **{k2: np.asarray(v) for k2, v in out.items()})
+
+
 if __name__ == "__main__":
-    for name in sys.argv[1:] or ["notched16", "voronoi64", "cmsx4_16"]:
+    for name in sys.argv[1:] or ["notched16", "voronoi64", "cmsx4_16", "finite16"]:
         globals()[name]()

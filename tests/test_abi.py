@@ -161,3 +161,25 @@ def test_noalloc_rejects_descriptions_beyond_the_static_arena():
     assert p.rve_footprint_bytes(small) <= 335544320
     bad = p.make_desc(dict(workload("notched-crystal-16").desc(), n=(10, 2, 2)))
     assert lib.rve_create_noalloc(ctypes.byref(bad), None, ctypes.byref(h)) == p.RVE_E_ARG
+
+
+def test_finite_strain_descriptions_are_validated():
+    """Finite-strain kinematics run in FP64 with GMRES (the linearised operator is not
+    symmetric) and the spectral derivative; anything else is refused on the CPU."""
+    import paper_2304_01125_amd as p
+    from synth import small_polycrystal
+    lib = p.load()
+    base = dict(small_polycrystal(n=(8, 6, 4), n_grains=3).desc(), kinematics=1, krylov=1,
+                gmres_restart=30)
+    fp = p.rve_footprint_bytes(p.make_desc(base))
+    small = p.rve_footprint_bytes(p.make_desc(dict(base, kinematics=0)))
+    assert fp > small                           # 9-component state and the 81-entry tangent
+    for key, val, prec in [("krylov", 0, 0), ("scheme", 1, 0), ("kinematics", 2, 0),
+                           ("kinematics", 1, 1)]:
+        d = p.make_desc(dict(base, **{key: val}), prec)
+        assert p.rve_footprint_bytes(d) == 0, (key, val, prec)
+        assert "kinematics" in lib.rve_last_error().decode()
+    de = np.zeros(9)
+    st = p.rve.RveStats()
+    assert lib.rve_step_increment_finite(None, de.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         1.0, ctypes.byref(st)) == p.RVE_E_ARG

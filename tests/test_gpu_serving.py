@@ -52,3 +52,47 @@ def test_admission_respects_memory_budget():
     big = sorted(range(len(items)), key=lambda i: sizes[i])[-2:]
     assert not any(set(big) <= set(ids) for ids in srv.resident_log)
     assert len(srv.resident_log) == ticks
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_pool_tick_batches_same_size_solves_bitwise(prec):
+    """rve_pool_step runs the CG iterations of same-size handles as shared launches (one
+    launch over every handle of the group): four 32^3 polycrystals and a 16^3 one, three
+    increments, each bitwise equal to its solve alone; the 32^3 solves did share."""
+    import dataclasses
+    from paper_2304_01125_amd import RVE
+    from paper_2304_01125_amd.rve import rve_pool_step
+    from synth import small_polycrystal, make_inputs
+    ws = [dataclasses.replace(small_polycrystal(n=32, n_grains=64, seed=s), amplitude=a)
+          for s, a in ((1, 0.004), (2, 0.006), (3, 0.008), (4, 0.005))]
+    ws.append(small_polycrystal(n=16, n_grains=8, seed=5))
+    inps = [make_inputs(w) for w in ws]
+    n_inc = 3
+    alone = []
+    for w, inp in zip(ws, inps):
+        r = RVE(w.desc(), prec)
+        r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+        for k in range(n_inc):
+            r.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k])
+        alone.append(r.fields(("strain", "stress", "damage", "gs")))
+        r.close()
+    rs = []
+    for w, inp in zip(ws, inps):
+        r = RVE(w.desc(), prec)
+        r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+        rs.append(r)
+    peak = [0.0] * len(rs)
+    for k in range(n_inc):
+        deps = np.array([[0, inp["deps"][k], 0, 0, 0, 0] for inp in inps])
+        dts = np.array([inp["dt"][k] for inp in inps])
+        rc, status, stats = rve_pool_step([r.h for r in rs], deps, dts)
+        assert rc == 0 and all(s_ == 0 for s_ in status), (rc, status)
+        for i, st in enumerate(stats):
+            peak[i] = max(peak[i], st["cg_batch"])
+    print(f"  largest CG batch per handle: {peak}", flush=True)
+    assert max(peak[:4]) >= 2
+    for i, r in enumerate(rs):
+        f = r.fields(("strain", "stress", "damage", "gs"))
+        for key in f:
+            assert np.array_equal(f[key], alone[i][key]), (i, key)
+        r.close()
