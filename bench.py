@@ -66,6 +66,9 @@ def parse():
                     help="skip the damage leg (phase field active in the timed increments)")
     ap.add_argument("--damage-gcrit-pow", type=int, default=10,
                     help="the damage leg's G_crit = 4 J/m^2 / 2^k")
+    ap.add_argument("--damage-gc", type=float, default=100.0,
+                    help="the damage leg's fracture toughness G_c in J/m^2 (growth stays "
+                         "stable over the timed increments at 100; at 20 it is not)")
     return ap.parse_args()
 
 
@@ -233,15 +236,18 @@ def cpu_baseline(w, inp, gpu_stats, first, n_apply=6, stride=64):
                        f"{WORKERS} workers")}
 
 
-def damage_leg(RVE, precision, torch, w, inp, warmup, steps, gcrit_pow, max_krylov=4000, reps=20):
+def damage_leg(RVE, precision, torch, w, inp, warmup, steps, gcrit_pow, gc, max_krylov=4000,
+               reps=20):
     """The headline increments with the stored-energy threshold G_crit lowered from 4 J/m^2
     by 2^gcrit_pow, so that the threshold is reached in the first increments and the timed
-    ones solve the phase field (eqs. phase, precph) with a non-zero driving state; the
-    Krylov cap is raised for the stiffness contrast of the damaged voxels.  Also times one
+    ones solve the phase field (eqs. phase, precph) with a non-zero driving state, and the
+    toughness G_c raised to gc so that the damage grows stably instead of localising into
+    a through crack within one increment; the Krylov cap is raised for the stiffness
+    contrast of the damaged voxels.  Also times one
     phase-field CG iteration in isolation (HIP events on the library's stream): its
     algorithmic bytes (FP64 vectors, the one-component FFT round trip) over its duration."""
     from paper_2304_01125_amd.rve import PASSES
-    wd = dataclasses.replace(w, G_crit=4.0 / 2 ** gcrit_pow, max_krylov=max_krylov)
+    wd = dataclasses.replace(w, G_crit=4.0 / 2 ** gcrit_pow, Gc=gc, max_krylov=max_krylov)
     r, dt, kry, stats, _ = run_leg(RVE, precision, wd.desc(), inp, warmup, steps, torch)
     s = r.stream
     r.launch_pass(PASSES["pf_iter"], 2)
@@ -254,7 +260,7 @@ def damage_leg(RVE, precision, torch, w, inp, warmup, steps, gcrit_pow, max_kryl
     ms = e0.elapsed_time(e1) / reps
     r.close()
     pf = int(sum(x["pf_iters"] for x in stats))
-    return {"G_crit": wd.G_crit, "value": round(wd.nvox * kry / dt, 1), "unit": "voxel-iters/s",
+    return {"G_crit": wd.G_crit, "Gc": wd.Gc, "value": round(wd.nvox * kry / dt, 1), "unit": "voxel-iters/s",
             "ms_per_step": round(1e3 * dt / steps, 2), "krylov_iters": kry, "pf_iters": pf,
             "stag_iters": int(sum(x["stag_iters"] for x in stats)),
             "newton_iters": int(sum(x["newton_iters"] for x in stats)),
@@ -331,6 +337,12 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    serve_items = None
+    if a.serve_requests > 0:     # the serving requests' inputs, before any GPU work
+        from paper_2304_01125_amd.serve import prepare
+        from synth import serving_requests
+        serve_items = prepare(serving_requests(a.serve_requests, 4)[2],
+                              min(16, os.cpu_count() or 1))
     import torch
     from paper_2304_01125_amd import RVE, RVE_FP64, RVE_MIXED
     from synth import workload, make_inputs
@@ -396,14 +408,13 @@ def main():
         out["stress_control"] = stress_control_leg(RVE, RVE_FP64, w, inp, a.warmup, a.steps, torch)
     if not a.no_damage:
         out["damage"] = damage_leg(RVE, RVE_FP64, torch, w, inp, a.warmup, a.steps,
-                                   a.damage_gcrit_pow)
+                                   a.damage_gcrit_pow, a.damage_gc)
     if not a.no_material:
         out["material"] = material_leg(RVE, RVE_FP64, torch)
     if a.serve_requests > 0:
         from paper_2304_01125_amd.serve import serve_benchmark
-        out["serving"] = serve_benchmark(a.serve_requests, 8, 4, min(16, os.cpu_count() or 1),
-                                         log=lambda m: print("# " + m, file=sys.stderr,
-                                                             flush=True))
+        out["serving"] = serve_benchmark(a.serve_requests, 8, 4, log=lambda m: print(
+            "# " + m, file=sys.stderr, flush=True), items=serve_items)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, inp, st64, a.warmup)
     print(json.dumps(out), flush=True)

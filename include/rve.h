@@ -149,6 +149,26 @@ typedef struct rve_desc {
                                (the geometric crack and soft buffers of Secs. 4.1 and
                                4.5 read as a boundary value of the damage)               */
   int32_t kinematics;       /* RVE_KIN_SMALL (default) or RVE_KIN_FINITE                 */
+  int32_t gnd_coupling;     /* 0 (default): the Taylor strength of an increment is that of
+                               the densities committed at the end of the previous one
+                               (GND lagged one increment).  1 (RVE_MAT_DUNNE, small
+                               strain): it is that of the increment's own end, tau_c0 + mu
+                               b sqrt(rho_SSD,n+1 + rho_GND,n+1), both densities from the
+                               increment's slip (the GND density from the regularised Nye
+                               tensor of beta_n + d beta: non-local); the alternating
+                               minimisation resolves it, passing until also the strength's
+                               relative change max|g_i - g_i-1| / max|g_i - g_n| <=
+                               tol_stag; G_s then uses rho_GND,n+1                        */
+  int32_t plane_stress;     /* 0 (default) or 1: pointwise plane stress of a plate one voxel
+                               thick (Secs. 4.1-4.3; n[2] = 1, small strain).  The
+                               out-of-plane stress (zz, yz, xz) vanishes at every voxel,
+                               the out-of-plane strain is a local unknown (not a
+                               displacement gradient), each Newton step eliminates it by
+                               static condensation of the linearised point, and the
+                               in-plane strain stays compatible.  The steps then take no
+                               out-of-plane macro control: deps[2..4] must be 0 and the
+                               stress mask may name xx, yy, xy only (RVE_E_ARG otherwise);
+                               macro_strain reports the mean out-of-plane strain      */
 } rve_desc;
 
 /* Per-increment report, filled by rve_step_increment (also on RVE_E_NOCONV). */

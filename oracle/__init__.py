@@ -19,6 +19,9 @@ small-strain specialisation (symmetric strain/stress, 6x6 tangents):
 * the AT2 phase-field balance with the stored-energy driving force
   (eqs. strpf, crit, decMiehe, zeta, phase) with the preconditioner of
   eq. precph (read as (1 + l^2 |xi|^2)^-1);
+* pointwise plane stress of plates one voxel thick (Sec. 4.1-4.3): the out-of-plane
+  stress held at zero at every voxel by a local solve, the in-plane balance on the
+  condensed tangent;
 * the non-linear alternating minimisation of one time increment (Algorithm 1),
   the history commit (SSD density, plastic work, stored energy density G_s,
   W_crit) and the regularised Nye-tensor GND density (eqs. nye1, the Fourier
@@ -35,6 +38,7 @@ from .constitutive import (GrainTables, return_map, slip_increments, PowerLaw, D
                            flow_law)
 from .spectral import Grid
 from .mechanics import solve_mechanics, momentum_operator
+from .planestress import solve_mechanics_plane, local_plane_stress, condensed_tangent
 from .phasefield import split_positive, we_plus, solve_phase_field, solve_phase_field_dirichlet
 from .history import nye_tensor, gnd_density
 from .increment import OracleRVE
@@ -42,6 +46,6 @@ from .increment import OracleRVE
 __all__ = ["quat_to_rot", "cubic_stiffness", "rotate4", "fcc_slip_systems", "screw_directions",
            "to_mandel2", "from_mandel2", "to_mandel4", "from_mandel4", "gnd_matrix",
            "GrainTables", "return_map", "slip_increments", "PowerLaw", "DunneLaw", "flow_law", "Grid", "solve_mechanics",
-           "momentum_operator",
+           "momentum_operator", "solve_mechanics_plane", "local_plane_stress", "condensed_tangent",
            "split_positive", "we_plus", "solve_phase_field", "solve_phase_field_dirichlet", "nye_tensor", "gnd_density",
            "OracleRVE"]

@@ -25,6 +25,19 @@ Readings: phi is also capped at 1; the driving state uses the threshold and the
 trigger flag of the start of the increment; rho_GND enters G_s one increment
 late; the Taylor strength of an increment is that of the densities committed at
 the end of the previous one (g frozen over the step, as for the power law).
+
+Option ``gnd_coupling`` (thermally activated flow with Taylor hardening): the strength
+of the increment is that of its own end, g_{n+1} = tau_c0 + mu b sqrt(rho_SSD,n+1 +
+rho_GND,n+1), with both densities from the increment's slip (the SSD rate and the
+regularised Nye tensor of the plastic distortion beta_n + d beta, non-local), resolved
+by the alternating minimisation: each pass solves the momentum balance at the current
+strength, recomputes the end-of-increment densities and the strength from its slip,
+and the loop also requires max|g_i - g_{i-1}| / max|g_i - g_n| <= tol (0/0 read as 0);
+G_s then uses rho_GND,n+1.
+
+Option ``plane_stress`` (plates one voxel thick, N3 = 1; Sec. 4.1-4.3): the out-of-plane
+stress vanishes at every voxel and the out-of-plane strain is a local unknown
+(planestress.py); macro control then names in-plane components only.
 """
 import numpy as np
 
@@ -32,6 +45,7 @@ from .constitutive import GrainTables, return_map, flow_law
 from .crystal import to_mandel2, from_mandel2
 from .spectral import Grid
 from .mechanics import solve_mechanics
+from .planestress import solve_mechanics_plane
 from .phasefield import we_plus, solve_phase_field, solve_phase_field_dirichlet
 from .history import nye_tensor, gnd_density
 
@@ -77,6 +91,10 @@ class OracleRVE:
         self.beta = np.zeros((M, 3, 3))
         self.law = flow_law(d)
         self.taylor = int(d.get("material", 0)) == 1
+        self.coupled = self.taylor and bool(d.get("gnd_coupling", 0))
+        self.plane = bool(d.get("plane_stress", 0))
+        if self.plane and self.grid.n[2] != 1:
+            raise ValueError("plane stress needs a grid one voxel thick (N3 = 1)")
         self.tau0 = tau[self.gid].astype(np.float64)
         self.phi = np.zeros(M) if phi0 is None else np.asarray(phi0, dtype=float).copy()
         self.rho_ssd = np.full(M, d["rho0"])
@@ -125,6 +143,8 @@ class OracleRVE:
         stats = {}
         free = [c for c in range(6) if (stress_mask >> c) & 1]
         de6 = np.array(deps6, dtype=float)
+        if self.plane and (any(c in (2, 3, 4) for c in free) or np.any(de6[2:5] != 0.0)):
+            raise ValueError("in plane stress the out-of-plane components are not controlled")
         de6[free] = 0.0
         dE = from_tensor6(de6)[0]
         target = self.macro_sig.copy()
@@ -136,11 +156,14 @@ class OracleRVE:
         eps_prev = eps_t + dE[None]
         phi_prev = phi_t.copy()
         constit = lambda e: self.constit(e, dt)
+        g_n = self.g.copy()
+        slipping = np.isfinite(g_n)
+        rho_gnd_new = self.rho_gnd
+        mech = solve_mechanics_plane if self.plane else solve_mechanics
         for it in range(d["max_stag"]):
-            eps_i, sig, dgam = solve_mechanics(grid, eps_prev, eps_t, self.degradation(phi_prev),
-                                               constit, d["tol_newton"], d["tol_lin"],
-                                               d["max_newton"], d["max_krylov"], stats,
-                                               free=free, sig_target=tgtM)
+            eps_i, sig, dgam = mech(grid, eps_prev, eps_t, self.degradation(phi_prev), constit,
+                                    d["tol_newton"], d["tol_lin"], d["max_newton"],
+                                    d["max_krylov"], stats, free=free, sig_target=tgtM)
             epsp_tr = self.epsp + from_mandel2(np.einsum("ma,mai->mi", dgam, t.P[gid]))
             tau = np.einsum("mai,mi->ma", t.P[gid], sig)
             wp_tr = self.Wp + (tau * dgam).sum(1)
@@ -158,9 +181,22 @@ class OracleRVE:
             r_e = _ratio(np.abs(tensor6(eps_i - eps_prev)).max(),
                          np.abs(tensor6(eps_i - eps_t)).max())
             r_p = _ratio(np.abs(phi_i - phi_prev).max(), np.abs(phi_i - phi_t).max())
+            r_g = 0.0
+            if self.coupled:
+                # end-of-increment densities from this pass's slip, and the strength
+                dbeta_i = np.einsum("ma,maij->mij", dgam, t.SN[gid])
+                rho_ssd_new = self.rho_ssd + d["lambda_ssd"] * np.sqrt(
+                    2.0 / 3.0 * np.einsum("mij,mij->m", dbeta_i, dbeta_i))
+                lam_i = nye_tensor(grid, self.beta + dbeta_i, d["ell_fp"])
+                rho_gnd_new = gnd_density(lam_i, t.R[gid], d["burgers"])
+                g_new = np.where(slipping, self.tau0 + d["mu"] * d["burgers"] *
+                                 np.sqrt(rho_ssd_new + rho_gnd_new), np.inf)
+                r_g = _ratio(np.abs(g_new - self.g)[slipping].max(initial=0.0),
+                             np.abs(g_new - g_n)[slipping].max(initial=0.0))
+                self.g = g_new
             eps_prev, phi_prev = eps_i, phi_i
             stats["stag"] = it + 1
-            if r_e <= d["tol_stag"] and r_p <= d["tol_stag"]:
+            if r_e <= d["tol_stag"] and r_p <= d["tol_stag"] and r_g <= d["tol_stag"]:
                 break
         else:
             raise RuntimeError("alternating minimisation did not converge")
@@ -175,6 +211,8 @@ class OracleRVE:
             self.g = self.g + d["h_lin"] * np.abs(dgam).sum(1)
         self.rho_ssd = self.rho_ssd + d["lambda_ssd"] * np.sqrt(
             2.0 / 3.0 * np.einsum("mij,mij->m", dbeta, dbeta))
+        if self.coupled:
+            self.rho_gnd = rho_gnd_new          # G_s with the end-of-increment GND density
         dw = (tau * dgam).sum(1)
         self.Wp = self.Wp + dw
         self.Gs = self.Gs + d["xi_store"] * dw / np.sqrt(self.rho_ssd + self.rho_gnd)

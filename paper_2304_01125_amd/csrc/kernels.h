@@ -258,11 +258,26 @@ void launch_constitutive(long long N, const double* eps, const double* deps, dou
                          const double* epsp, const double* gslip, const int* grain,
                          const double* gtab, double* sig, const double* phi, R* gK, double* gw,
                          const CrystalFrame& cf, const Material& m, double* partial, int* fail,
-                         hipStream_t st);
+                         hipStream_t st, double* ps_sig = nullptr, double* ps_rec = nullptr);
+// plane stress: d e_O = -B d e_P - r on the Newton correction, from the per-voxel B and r
+// that the constitutive launch's condensation left in rec (12 N)
+void launch_plane_recover(long long N, double* deps, const double* rec, hipStream_t st);
 void launch_source(long long N, const double* eps, const double* sig, const double* epsp,
                    const double* gslip, const int* grain, const double* gtab, const double* wp,
                    const double* trig, const double* wcrit, double* S, double* wep,
                    const Material& m, double* partial, hipStream_t st);
+// GND-coupled hardening (option): end-of-increment plastic distortion (9) and SSD density
+// of the slip at the converged stress and the current strength
+void launch_trial_hardening(long long N, const double* sig, const double* gslip,
+                            const double* beta, const double* rho_ssd, const int* grain,
+                            const double* gtab, const Material& m, double* beta_tr,
+                            double* rho_ssd_tr, hipStream_t st);
+// g_next = tau_c0 + mu b sqrt(rho_SSD + rho_GND) of those densities; partial maxima of
+// |g_next - g| and |g_next - g_n| (2 values) over the voxels that can slip
+void launch_taylor_next(long long N, const double* gslip, const double* g_n,
+                        const double* rho_ssd_tr, const double* rho_gnd_tr, const int* grain,
+                        const double* gtab, double mu_b, double* g_next, double* partial,
+                        hipStream_t st);
 // Taylor hardening g = tau_c0 + mu b sqrt(rho_SSD + rho_GND) of the voxels that can slip
 void launch_taylor(long long N, double* gslip, const double* rho_ssd, const double* rho_gnd,
                    const int* grain, const double* gtab, double mu_b, hipStream_t st);

@@ -23,11 +23,12 @@ namespace {
 
 thread_local std::string g_err;
 const bool g_debug = std::getenv("RVE_DEBUG") != nullptr;
-// RVE_POOL_BATCH=0: rve_pool_step runs every handle's CG solve on its own (for comparisons)
-const bool g_no_batch = [] {
+// RVE_POOL_BATCH=0 (read at every rve_pool_step): every handle's CG solve runs on its own
+// (for comparisons)
+bool pool_batching_off() {
   const char* e = std::getenv("RVE_POOL_BATCH");
   return e && e[0] == '0';
-}();
+}
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -317,6 +318,12 @@ struct rve_s {
   int batch_peak = 1;     // largest batch this handle's CG solves ran in (this increment)
   hipEvent_t cg_ready = nullptr, cg_done = nullptr;
   long long* slotd = nullptr;
+  // GND-coupled hardening option: the strength at t_n, the next pass's strength and the
+  // end-of-increment SSD and GND densities of the current pass
+  double *g_n = nullptr, *g_next = nullptr, *rho_ssd_tr = nullptr, *rho_gnd_tr = nullptr;
+  // plane-stress option: the condensed effective stress of the in-plane balance (6 N) and
+  // the per-voxel recovery of the out-of-plane strain correction, B and r (12 N)
+  double *ps_sig = nullptr, *ps_rec = nullptr;
   bool fs = false;
   double *fs_F = nullptr, *fs_Ft = nullptr, *fs_Fprev = nullptr, *fs_dF = nullptr,
          *fs_P = nullptr, *fs_Fp = nullptr, *fs_fptr = nullptr, *fs_aux = nullptr;
@@ -350,14 +357,15 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 // cg_partial_offset() (at most 2 x kCgMaxBlocks: every block of the next inverse z pass sums
 // them).  The CG step's blocks write their partials while other blocks of the same launch
 // still sum the divergence pass's, so the two ranges must not overlap: the fused divergence
-// pass launches (N1/2/T) N2 3 blocks with tiles of T >= 8 bins (plus one partial of the macro
-// stress), at most 3 N1 N2 / 16 + 1.
+// pass launches ((N1/2/T) N2 + ceil(N2/T)) 3 blocks with tiles of T >= 8 bins (the second
+// term: the Nyquist-column units), plus one partial of the macro stress, at most
+// 3 (N1 N2 / 16 + ceil(N2 / 8)) + 1.
 constexpr long long kCgPartialMin = (long long)kMaxRedBlocks * 16;
 constexpr int kMaxBatch = 64;         // RVEs of one batched CG launch
 constexpr int kCgMaxBlocks = 1024;   // 512 measured 4 us slower per FP32 iteration at 128^3
 
 long long max_div_partials(const Grid& g) {
-  const long long fused = 3LL * g.n1 * g.n2 / 16 + 1;
+  const long long fused = 3LL * ((long long)g.n1 * g.n2 / 16 + (g.n2 + 7) / 8) + 1;
   return fused > kMaxRedBlocks + 1 ? fused : kMaxRedBlocks + 1;
 }
 long long cg_partial_offset(const Grid& g) {
@@ -395,6 +403,12 @@ void layout(rve_s* h) {
                     : nullptr;
   h->rbuf = fd(9 * N);
   h->partial = fd(partial_count(h->g));
+  if (h->d.gnd_coupling) {
+    h->g_n = fd(N); h->g_next = fd(N); h->rho_ssd_tr = fd(N); h->rho_gnd_tr = fd(N);
+  }
+  if (h->d.plane_stress) {
+    h->ps_sig = fd(6 * N); h->ps_rec = fd(12 * N);
+  }
   if (h->fs) {
     h->fs_F = fd(9 * N); h->fs_Ft = fd(9 * N); h->fs_Fprev = fd(9 * N); h->fs_dF = fd(9 * N);
     h->fs_P = fd(9 * N); h->fs_Fp = fd(9 * N); h->fs_fptr = fd(9 * N); h->fs_aux = fd(4 * N);
@@ -425,6 +439,16 @@ int validate(const rve_desc* d) {
   if (d->deriv != RVE_DERIV_SPECTRAL && d->deriv != RVE_DERIV_ROTATED)
     return fail(RVE_E_ARG, "deriv must be RVE_DERIV_SPECTRAL or RVE_DERIV_ROTATED");
   if (d->pf_dirichlet != 0 && d->pf_dirichlet != 1) return fail(RVE_E_ARG, "pf_dirichlet must be 0 or 1");
+  if (d->gnd_coupling != 0 && d->gnd_coupling != 1)
+    return fail(RVE_E_ARG, "gnd_coupling must be 0 or 1");
+  if (d->gnd_coupling && (d->material != RVE_MAT_DUNNE || d->kinematics != RVE_KIN_SMALL))
+    return fail(RVE_E_ARG, "gnd_coupling needs the Taylor hardening of RVE_MAT_DUNNE and "
+                           "small-strain kinematics");
+  if (d->plane_stress != 0 && d->plane_stress != 1)
+    return fail(RVE_E_ARG, "plane_stress must be 0 or 1");
+  if (d->plane_stress && (d->n[2] != 1 || d->kinematics != RVE_KIN_SMALL))
+    return fail(RVE_E_ARG, "plane_stress needs a grid one voxel thick (n[2] = 1) and "
+                           "small-strain kinematics");
   if (d->kinematics != RVE_KIN_SMALL && d->kinematics != RVE_KIN_FINITE)
     return fail(RVE_E_ARG, "kinematics must be RVE_KIN_SMALL or RVE_KIN_FINITE");
   if (d->kinematics == RVE_KIN_FINITE &&
@@ -881,7 +905,8 @@ struct Ops {
     Material m = mat(0.0);
     m.dt = cur_dt;
     launch_constitutive<R>(N, h->eps, deps, t, h->epsp, h->gslip, h->grain, h->gtab, h->sig, phi,
-                           gK(), h->gw, h->cf, m, h->partial, h->failc, st);
+                           gK(), h->gw, h->cf, m, h->partial, h->failc, st, h->ps_sig,
+                           h->ps_rec);
     launch_reduce(h->partial, voxel_grid(N), RED_CONST, 0, h->scal + SC_K, st);
     return RVE_OK;
   }
@@ -1255,7 +1280,9 @@ int run_increment(rve_s* h, const double de_in[6], const double* dsig, int mask,
   const double t0 = now_ms();
   int rc;
   h->batch_peak = 1;
+  const bool coupled = h->d.gnd_coupling != 0;
   // transactional copies of the state at time t
+  if (coupled) HIPCHK(hipMemcpyAsync(h->g_n, h->gslip, N * 8, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(h->eps_t, h->eps, 6 * N * 8, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(h->sig_t, h->sig, 6 * N * 8, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(h->phi_t, h->phi, N * 8, hipMemcpyDeviceToDevice, st));
@@ -1280,8 +1307,8 @@ int run_increment(rve_s* h, const double de_in[6], const double* dsig, int mask,
       double tk = now_ms();
       o.kbar();
       if (mask) launch_macro_prec(h->scal + SC_KBAR, o.s_mac * o.s_mac, mask, h->scal + SC_M0, st);
-      // c = i xi~ . F{ g sigma }
-      o.fwd(h->sig, true, N, 6, o.W, h->phi_prev);
+      // c = i xi~ . F{ g sigma } (plane stress: the condensed stress)
+      o.fwd(h->ps_sig ? h->ps_sig : h->sig, true, N, 6, o.W, h->phi_prev);
       launch_div<R>(h->pl, o.W, o.NH, o.v(5), o.NH, 1.0, st);
       launch_herm_proj<R>(h->pl, o.v(5), o.NH, 3, st);
       // zero bin: -s (sum g sigma - N sigma*) on the stress-controlled components
@@ -1296,6 +1323,7 @@ int run_increment(rve_s* h, const double de_in[6], const double* dsig, int mask,
         launch_macro_strain<R>(o.W, o.NH, o.v(0), o.NH, o.s_mac, o.s_mac * invN, mask, 1, 0,
                                h->scal + SC_DE, st);
       o.inv(o.W, 6, h->deps, true, N, invN, 0);
+      if (h->ps_rec) launch_plane_recover(N, h->deps, h->ps_rec, st);
       launch_slope(N, h->sig, h->deps, h->phi_prev, h->d.k_res, h->partial, st);
       launch_reduce(h->partial, voxel_grid(N), 1, 0, h->scal + SC_MISC, st);
       if ((rc = sync_read(h, SC_MISC, 1))) return rc;
@@ -1356,7 +1384,28 @@ int run_increment(rve_s* h, const double de_in[6], const double* dsig, int mask,
       HIPCHK(hipMemcpyAsync(h->eps_prev, h->eps, 6 * N * 8, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync(h->phi_prev, h->phi, N * 8, hipMemcpyDeviceToDevice, st));
       s.ms_phase_field += now_ms() - tp;
-      if (re <= h->d.tol_stag && rp <= h->d.tol_stag) converged = true;
+      double rg = 0.0;
+      if (coupled) {
+        // the end-of-increment densities of this pass's slip (the Nye tensor of the trial
+        // plastic distortion, non-local) and the Taylor strength of the next pass
+        Material mc = o.mat(dt);
+        launch_trial_hardening(N, h->sig, h->gslip, h->beta, h->rho_ssd, h->grain, h->gtab, mc,
+                               h->rbuf, h->rho_ssd_tr, st);
+        typedef cplx<R> C;
+        C* B9 = (C*)h->spec;
+        o.fwd(h->rbuf, true, N, 9, B9);
+        launch_curl_reg<R>(h->pl, B9, o.NH, h->d.ell_fp, invN, st);
+        o.inv(B9, 9, h->rbuf, true, N, 1.0, 0);
+        launch_gnd(N, h->rbuf, h->grain, h->gtab, h->Q81, h->d.burgers, h->rho_gnd_tr, st);
+        launch_taylor_next(N, h->gslip, h->g_n, h->rho_ssd_tr, h->rho_gnd_tr, h->grain, h->gtab,
+                           mc.mu_b, h->g_next, h->partial, st);
+        launch_reduce(h->partial, voxel_grid(N), 2, 1, h->scal + SC_MISC, st);
+        if ((rc = sync_read(h, SC_MISC, 2))) return rc;
+        rg = ratio(h->hs[SC_MISC], h->hs[SC_MISC + 1]);
+      }
+      if (re <= h->d.tol_stag && rp <= h->d.tol_stag && rg <= h->d.tol_stag) converged = true;
+      else if (coupled)   // the next pass solves the momentum balance at the new strength
+        HIPCHK(hipMemcpyAsync(h->gslip, h->g_next, N * 8, hipMemcpyDeviceToDevice, st));
     }
   }
   if (!converged) { rc = fail(RVE_E_NOCONV, "alternating minimisation reached max_stag"); goto fail_out; }
@@ -1371,6 +1420,8 @@ int run_increment(rve_s* h, const double de_in[6], const double* dsig, int mask,
     // ---- commit ----
     double tcm = now_ms();
     Material m = o.mat(dt);
+    if (coupled)      // G_s with the end-of-increment GND density
+      HIPCHK(hipMemcpyAsync(h->rho_gnd, h->rho_gnd_tr, N * 8, hipMemcpyDeviceToDevice, st));
     launch_commit(N, h->sig, h->gslip, h->epsp, h->beta, h->rho_ssd, h->rho_gnd, h->wp, h->gs, h->H,
                   h->wcrit, h->trig, h->wep, h->phi, h->eps, h->grain, h->gtab, m, h->partial, st);
     const int nb = voxel_grid(N);
@@ -1408,6 +1459,7 @@ fail_out:
   // roll back to time t
   {
     std::string msg = g_err;
+    if (coupled) (void)hipMemcpyAsync(h->gslip, h->g_n, N * 8, hipMemcpyDeviceToDevice, st);
     (void)hipMemcpyAsync(h->eps, h->eps_t, 6 * N * 8, hipMemcpyDeviceToDevice, st);
     (void)hipMemcpyAsync(h->sig, h->sig_t, 6 * N * 8, hipMemcpyDeviceToDevice, st);
     (void)hipMemcpyAsync(h->phi, h->phi_t, N * 8, hipMemcpyDeviceToDevice, st);
@@ -1854,6 +1906,10 @@ int rve_step_increment_mixed(rve_s* h, const double deps[6], const double dsig[6
   if (h->fs) return fail(RVE_E_ARG, "finite-strain handle: use rve_step_increment_finite");
   if (stress_mask < 0 || stress_mask > 63) return fail(RVE_E_ARG, "stress_mask outside 0..63");
   if (stress_mask && !dsig) return fail(RVE_E_ARG, "null stress increment");
+  if (h->d.plane_stress && ((stress_mask & 0b011100) || deps[2] != 0.0 || deps[3] != 0.0 ||
+                            deps[4] != 0.0))
+    return fail(RVE_E_ARG, "plane stress: the out-of-plane components (zz, yz, xz) are "
+                           "stress free at every voxel and take no macro control");
   double ds[6] = {0, 0, 0, 0, 0, 0};
   for (int c = 0; c < 6; ++c) {
     const bool f = (stress_mask >> c) & 1;
@@ -1904,7 +1960,7 @@ int rve_pool_step(rve_s* const* hs, int32_t n, const double* deps, const double*
     return !a->fs && a->d.krylov == RVE_KRYLOV_CG && a->time_xt == 0 &&
            (a->f64 ? fused_z_available<double>(a->pl) : fused_z_available<float>(a->pl));
   };
-  if (!g_no_batch) {
+  if (!pool_batching_off()) {
     for (int i = 0; i < n; ++i) {
       if (!can_batch(hs[i]) || gof[i]) continue;
       int cnt = 0;

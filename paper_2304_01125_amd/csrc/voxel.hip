@@ -343,6 +343,130 @@ k_constitutive(long long N, const double* __restrict__ eps, const double* __rest
   }
 }
 
+// ---------------------------------------------------------------------------
+// Pointwise plane stress of plates one voxel thick (Sec. 4.1-4.3): the out-of-plane
+// stress (Mandel O = zz, yz, xz = 2, 3, 4) vanishes at every voxel and the out-of-plane
+// strain is a local unknown.  Each Newton step eliminates it by static condensation of
+// the linearised point:
+//   d e_O = -B d e_P - r,   B = K_OO^-1 K_OP,   r = K_OO^-1 sigma_O,
+// so that the in-plane balance sees the tangent K_PP - K_PO B (the stiffness of the
+// constrained point) and the stress sigma_P - B^T sigma_O (P = xx, yy, xy = 0, 1, 5).
+// This pass rewrites gK in place: the PP block condensed, the PO block zero and the OO
+// block kept (so the displacement u_z, whose equation then decouples with a zero right
+// side, stays zero in the Krylov solve); it writes the condensed effective stress (tensor
+// components, out-of-plane ones zero) and, per voxel, B (9, row-major over O x P) and r
+// (3, Mandel, undegraded) for the recovery of d e_O.
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_plane_condense(long long N, R* __restrict__ gK, const double* __restrict__ sig,
+                 const double* __restrict__ phi, double kres, double* __restrict__ sig_c,
+                 double* __restrict__ rec, int* __restrict__ fail) {
+  constexpr int Pi[3] = {0, 1, 5}, Oi[3] = {2, 3, 4};
+  const double s2 = 1.41421356237309504880, is2 = 0.70710678118654752440;
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x) {
+    double K[21];
+#pragma unroll
+    for (int c = 0; c < 21; ++c) K[c] = (double)gK[c * N + v];
+    double sm[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sm[c] = (c < 3 ? 1.0 : s2) * sig[c * N + v];
+    const double q = 1.0 - phi[v];
+    const double gphi = q * q + kres;
+    // inverse of the SPD 3x3 block K_OO by cofactors
+    const double a00 = K[pk(2, 2)], a01 = K[pk(2, 3)], a02 = K[pk(2, 4)];
+    const double a11 = K[pk(3, 3)], a12 = K[pk(3, 4)], a22 = K[pk(4, 4)];
+    const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22,
+                 c02 = a01 * a12 - a02 * a11, c11 = a00 * a22 - a02 * a02,
+                 c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
+    const double det = a00 * c00 + a01 * c01 + a02 * c02;
+    if (!(det > 0.0) || !isfinite(det)) {
+      atomicAdd(fail, 1);
+      continue;
+    }
+    const double id = 1.0 / det;
+    const double Ai[3][3] = {{c00 * id, c01 * id, c02 * id},
+                             {c01 * id, c11 * id, c12 * id},
+                             {c02 * id, c12 * id, c22 * id}};
+    double B[3][3], r[3], so[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) so[a] = sm[Oi[a]];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double t = 0.0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) t += Ai[a][b] * K[pk(Oi[b], Pi[j])];
+        B[a][j] = t;
+      }
+      double t = 0.0;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) t += Ai[a][b] * so[b];
+      r[a] = gphi * t;          // gK = g K: K_OO^-1 sigma_O = g (gK_OO)^-1 sigma_O
+    }
+    double Kc[3][3], sc[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double t = K[pk(Pi[i], Pi[j])];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) t -= K[pk(Pi[i], Oi[a])] * B[a][j];
+        Kc[i][j] = t;
+      }
+      double t = sm[Pi[i]];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) t -= B[a][i] * so[a];
+      sc[i] = t;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+      for (int j = i; j < 3; ++j) gK[pk(Pi[i], Pi[j]) * N + v] = (R)(0.5 * (Kc[i][j] + Kc[j][i]));
+#pragma unroll
+      for (int a = 0; a < 3; ++a) gK[pk(Pi[i], Oi[a]) * N + v] = (R)0.0;
+    }
+    sig_c[0 * N + v] = sc[0];
+    sig_c[1 * N + v] = sc[1];
+    sig_c[5 * N + v] = is2 * sc[2];
+    sig_c[2 * N + v] = 0.0;
+    sig_c[3 * N + v] = 0.0;
+    sig_c[4 * N + v] = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) rec[(3 * a + j) * N + v] = B[a][j];
+      rec[(9 + a) * N + v] = r[a];
+    }
+  }
+}
+
+// d e_O = -B d e_P - r on the Newton correction (tensor components)
+__global__ void __launch_bounds__(256) k_plane_recover(long long N, double* __restrict__ deps,
+                                                       const double* __restrict__ rec) {
+  const double s2 = 1.41421356237309504880, is2 = 0.70710678118654752440;
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x) {
+    const double dp[3] = {deps[0 * N + v], deps[1 * N + v], s2 * deps[5 * N + v]};
+    double dO[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double t = -rec[(9 + a) * N + v];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) t -= rec[(3 * a + j) * N + v] * dp[j];
+      dO[a] = t;
+    }
+    deps[2 * N + v] = dO[0];
+    deps[3 * N + v] = is2 * dO[1];
+    deps[4 * N + v] = is2 * dO[2];
+  }
+}
+
+void launch_plane_recover(long long N, double* deps, const double* rec, hipStream_t st) {
+  hipLaunchKernelGGL(k_plane_recover, dim3(voxel_grid(N)), dim3(256), 0, st, N, deps, rec);
+}
+
 // Block partials of the constitutive sums: sum gK (21), sum g w, sum g(phi) sigma (6).
 template <typename R>
 __global__ void __launch_bounds__(256)
@@ -372,7 +496,7 @@ void launch_constitutive(long long N, const double* eps, const double* deps, dou
                          const double* epsp, const double* gslip, const int* grain,
                          const double* gtab, double* sig, const double* phi, R* gK, double* gw,
                          const CrystalFrame& cf, const Material& m, double* partial, int* fail,
-                         hipStream_t st) {
+                         hipStream_t st, double* ps_sig, double* ps_rec) {
   const long long nb = (N + 255) / 256;
   if (m.flow == FLOW_DUNNE)
     hipLaunchKernelGGL((k_constitutive<R, FLOW_DUNNE>), dim3((int)(nb < 1 ? 1 : nb)), dim3(256), 0,
@@ -380,6 +504,9 @@ void launch_constitutive(long long N, const double* eps, const double* deps, dou
   else
     hipLaunchKernelGGL((k_constitutive<R, FLOW_POWER>), dim3((int)(nb < 1 ? 1 : nb)), dim3(256), 0,
                        st, N, eps, deps, t, epsp, gslip, grain, gtab, sig, phi, gK, gw, cf, m, fail);
+  if (ps_sig)
+    hipLaunchKernelGGL((k_plane_condense<R>), dim3(voxel_grid(N)), dim3(256), 0, st, N, gK, sig,
+                       phi, m.kres, ps_sig, ps_rec, fail);
   hipLaunchKernelGGL((k_const_sums<R>), dim3(voxel_grid(N)), dim3(256), 0, st, N, gK, gw, sig,
                      phi, m.kres, partial);
 }
@@ -387,12 +514,12 @@ template void launch_constitutive<double>(long long, const double*, const double
                                           const double*, const double*, const int*, const double*,
                                           double*, const double*, double*, double*,
                                           const CrystalFrame&, const Material&, double*, int*,
-                                          hipStream_t);
+                                          hipStream_t, double*, double*);
 template void launch_constitutive<float>(long long, const double*, const double*, double,
                                          const double*, const double*, const int*, const double*,
                                          double*, const double*, float*, double*,
                                          const CrystalFrame&, const Material&, double*, int*,
-                                         hipStream_t);
+                                         hipStream_t, double*, double*);
 
 // ---------------------------------------------------------------------------
 
@@ -564,6 +691,76 @@ void launch_commit(long long N, const double* sig, double* gslip, double* epsp, 
   hipLaunchKernelGGL(k_commit, dim3(voxel_grid(N)), dim3(256), 0, st, N, sig, gslip, epsp, beta,
                      rho_ssd, rho_gnd, wp, gs, H, wcrit, trig, wep, phi, eps, grain, gtab, m,
                      partial);
+}
+
+// GND-coupled hardening (option): the end-of-increment plastic distortion beta + d beta
+// (into beta_tr, 9 components) and SSD density of the slip at the converged stress and the
+// current strength, as the commit would form them.
+__global__ void __launch_bounds__(256) k_trial_hardening(
+    long long N, const double* __restrict__ sig, const double* __restrict__ gslip,
+    const double* __restrict__ beta, const double* __restrict__ rho_ssd,
+    const int* __restrict__ grain, const double* __restrict__ gtab, Material m,
+    double* __restrict__ beta_tr, double* __restrict__ rho_ssd_tr) {
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x) {
+    const double* gt = gtab + (long long)grain[v] * GT_STRIDE;
+    double st[6], sm[6];
+    load6(sig, N, v, st);
+    to_mandel(st, sm);
+    double tau[12], dg[12];
+    slip(gt + GT_P, sm, gslip[v], m, tau, dg);
+    double db2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      double d = 0.0;
+#pragma unroll
+      for (int a = 0; a < 12; ++a) d += dg[a] * gt[GT_SN + a * 9 + i];
+      beta_tr[i * N + v] = beta[i * N + v] + d;
+      db2 += d * d;
+    }
+    rho_ssd_tr[v] = rho_ssd[v] + m.lambda_ssd * sqrt(2.0 / 3.0 * db2);
+  }
+}
+
+// The Taylor strength of the end-of-increment densities, g_next = tau_c0 + mu b sqrt(
+// rho_SSD + rho_GND) (voxels that cannot slip keep g = inf), and the partial maxima of
+// |g_next - g| and |g_next - g_n| over the voxels that can slip.
+__global__ void __launch_bounds__(256) k_taylor_next(
+    long long N, const double* __restrict__ gslip, const double* __restrict__ g_n,
+    const double* __restrict__ rho_ssd_tr, const double* __restrict__ rho_gnd_tr,
+    const int* __restrict__ grain, const double* __restrict__ gtab, double mu_b,
+    double* __restrict__ g_next, double* __restrict__ partial) {
+  double mx[2] = {0.0, 0.0};
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x) {
+    const double g = gslip[v];
+    if (!isfinite(g)) {
+      g_next[v] = g;
+      continue;
+    }
+    const double tau0 = gtab[(long long)grain[v] * GT_STRIDE + GT_TAU0];
+    const double gn = tau0 + mu_b * sqrt(rho_ssd_tr[v] + rho_gnd_tr[v]);
+    g_next[v] = gn;
+    mx[0] = fmax(mx[0], fabs(gn - g));
+    mx[1] = fmax(mx[1], fabs(gn - g_n[v]));
+  }
+  block_partials<2, true>(mx, partial);
+}
+
+void launch_trial_hardening(long long N, const double* sig, const double* gslip,
+                            const double* beta, const double* rho_ssd, const int* grain,
+                            const double* gtab, const Material& m, double* beta_tr,
+                            double* rho_ssd_tr, hipStream_t st) {
+  hipLaunchKernelGGL(k_trial_hardening, dim3(voxel_grid(N)), dim3(256), 0, st, N, sig, gslip, beta,
+                     rho_ssd, grain, gtab, m, beta_tr, rho_ssd_tr);
+}
+
+void launch_taylor_next(long long N, const double* gslip, const double* g_n,
+                        const double* rho_ssd_tr, const double* rho_gnd_tr, const int* grain,
+                        const double* gtab, double mu_b, double* g_next, double* partial,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_taylor_next, dim3(voxel_grid(N)), dim3(256), 0, st, N, gslip, g_n,
+                     rho_ssd_tr, rho_gnd_tr, grain, gtab, mu_b, g_next, partial);
 }
 
 // Taylor hardening (Sec. 2.1): g = tau_c0 + mu b sqrt(rho_SSD + rho_GND) from the

@@ -47,7 +47,8 @@ class RveDesc(ctypes.Structure):
                 ("k_B", ctypes.c_double), ("T", ctypes.c_double), ("dV", ctypes.c_double),
                 ("mu", ctypes.c_double), ("krylov", ctypes.c_int32),
                 ("gmres_restart", ctypes.c_int32), ("deriv", ctypes.c_int32),
-                ("pf_dirichlet", ctypes.c_int32), ("kinematics", ctypes.c_int32)]
+                ("pf_dirichlet", ctypes.c_int32), ("kinematics", ctypes.c_int32),
+                ("gnd_coupling", ctypes.c_int32), ("plane_stress", ctypes.c_int32)]
 
 
 class RveStats(ctypes.Structure):
@@ -181,6 +182,8 @@ def make_desc(desc, precision=RVE_FP64, max_grains=4096):
     d.gmres_restart = int(desc.get("gmres_restart", 30))
     d.material = int(desc.get("material", RVE_MAT_POWER))
     d.kinematics = int(desc.get("kinematics", RVE_KIN_SMALL))
+    d.gnd_coupling = int(desc.get("gnd_coupling", 0))
+    d.plane_stress = int(desc.get("plane_stress", 0))
     if d.material == RVE_MAT_DUNNE:
         for k in ("rho_m", "v_D", "dF", "k_B", "T", "dV", "mu"):
             setattr(d, k, float(desc[k]))

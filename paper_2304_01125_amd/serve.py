@@ -238,13 +238,17 @@ def summary(recs, wall):
             "wall_s": round(wall, 2)}
 
 
-def serve_benchmark(n_req=400, slots=8, seed=4, workers=8, log=None):
-    """Serial plain-FP64 baseline, then the mixed-precision server on a Poisson stream at
-    rate factor x the serial capacity.  Returns a JSON-able dict."""
+def serve_benchmark(n_req=400, slots=8, seed=4, workers=8, log=None, items=None, low_rate=0.5):
+    """Serial plain-FP64 baseline, then the mixed-precision server (tick mode: one
+    rve_pool_step per tick, the CG iterations of same-size requests in shared launches) on
+    the Poisson stream at rate factor x the serial capacity, then the same server at
+    `low_rate` x its own measured throughput (latency without a growing queue).  Returns a
+    JSON-able dict.  `items`: the prepared requests (else prepared here)."""
     from synth import serving_requests
     from . import RVE_FP64, RVE_MIXED
     factor, gaps, reqs = serving_requests(n_req, seed)
-    items = prepare(reqs, workers)
+    if items is None:
+        items = prepare(reqs, workers)
     if log:
         log(f"prepared {len(items)} requests")
     serial, wall_s = run_serial(items, RVE_FP64, log=log)
@@ -252,12 +256,20 @@ def serve_benchmark(n_req=400, slots=8, seed=4, workers=8, log=None):
     lam = factor * cap
     arrivals = np.cumsum(gaps) / lam
     srv = Server(RVE_MIXED, max_slots=slots)
-    res, wall = srv.run_async(items, arrivals, log=log)
+    res, wall, ticks = srv.run(items, arrivals, log=log)
     ok = sum(1 for r in res if r["status"] == 0)
     ok_s = sum(1 for r in serial if r["status"] == 0)
-    return {"requests": n_req, "slots": slots, "rate_factor": round(factor, 3),
-            "arrival_rate_per_s": round(lam, 3), "completed": ok, "completed_serial": ok_s,
-            "server_mixed": summary(res, wall), "serial_fp64": summary(serial, wall_s)}
+    out = {"requests": n_req, "slots": slots, "rate_factor": round(factor, 3),
+           "arrival_rate_per_s": round(lam, 3), "completed": ok, "completed_serial": ok_s,
+           "server_mixed": summary(res, wall), "serial_fp64": summary(serial, wall_s),
+           "ticks": ticks}
+    # below capacity: arrivals at low_rate x the server's throughput under the stream above
+    thr = len(res) / wall
+    lam_low = low_rate * thr
+    res2, wall2, _ = srv.run(items, np.cumsum(gaps) / lam_low, log=log)
+    out["server_mixed_below_capacity"] = dict(summary(res2, wall2),
+                                             arrival_rate_per_s=round(lam_low, 3))
+    return out
 
 
 def main():

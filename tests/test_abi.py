@@ -127,9 +127,10 @@ def test_material_derivative_and_mixed_control_arguments_are_validated():
                                (512, 384, 128), (384, 512, 256), (512, 512, 512), (2, 2, 2)])
 def test_cg_partials_do_not_overlap_the_divergence_partials(n):
     """The CG step writes its block partials while other blocks of the same launch still sum
-    the fused divergence pass's (one per block of (N1/2/T) N2 3 blocks, T >= 8, plus one of
-    the macro stress): the two ranges of the reduction buffer must be disjoint on every grid
-    (512 x 512 x 16 launches 49152 divergence blocks)."""
+    the fused divergence pass's (one per block of ((N1/2/T) N2 + ceil(N2/T)) 3 blocks, T >= 8,
+    the second term the Nyquist-column units, plus one of the macro stress): the two ranges of
+    the reduction buffer must be disjoint on every grid (512 x 512 x 16 launches 49344
+    divergence blocks)."""
     import paper_2304_01125_amd as p
     from synth import workload
     lib = p.load()
@@ -138,7 +139,7 @@ def test_cg_partials_do_not_overlap_the_divergence_partials(n):
         out = (ctypes.c_int64 * 3)()
         assert lib.rve_diag_partials(ctypes.byref(d), out) == p.RVE_OK
         max_div, cg_off, length = out
-        assert max_div >= 3 * (n[0] // 16) * n[1] + 1
+        assert max_div >= 3 * ((n[0] // 16) * n[1] + (n[1] + 7) // 8) + 1
         assert cg_off >= max_div
         assert length >= cg_off + 2 * 1024
     bad = p.make_desc(dict(workload("notched-crystal-16").desc(), n=(10, 2, 2)))
@@ -183,3 +184,32 @@ def test_finite_strain_descriptions_are_validated():
     st = p.rve.RveStats()
     assert lib.rve_step_increment_finite(None, de.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                          1.0, ctypes.byref(st)) == p.RVE_E_ARG
+
+
+def test_gnd_coupling_is_validated():
+    import paper_2304_01125_amd as p
+    from synth import small_polycrystal, cmsx4
+    lib = p.load()
+    dunne = small_polycrystal(n=(8, 6, 4), n_grains=3, **cmsx4()).desc()
+    assert p.rve_footprint_bytes(p.make_desc(dict(dunne, gnd_coupling=1))) > \
+        p.rve_footprint_bytes(p.make_desc(dunne))
+    for bad in (dict(dunne, gnd_coupling=2),
+                dict(small_polycrystal(n=(8, 6, 4), n_grains=3).desc(), gnd_coupling=1),
+                dict(dunne, gnd_coupling=1, kinematics=1, krylov=1)):
+        assert p.rve_footprint_bytes(p.make_desc(bad)) == 0
+        assert "gnd_coupling" in lib.rve_last_error().decode()
+
+
+def test_plane_stress_is_validated():
+    import paper_2304_01125_amd as p
+    from synth import small_polycrystal
+    lib = p.load()
+    plate = small_polycrystal(n=(8, 6, 1), n_grains=3).desc()
+    N = 8 * 6
+    assert p.rve_footprint_bytes(p.make_desc(dict(plate, plane_stress=1))) >= \
+        p.rve_footprint_bytes(p.make_desc(plate)) + 18 * 8 * N
+    for bad in (dict(plate, plane_stress=2),
+                dict(small_polycrystal(n=(8, 6, 2), n_grains=3).desc(), plane_stress=1),
+                dict(plate, plane_stress=1, kinematics=1, krylov=1)):
+        assert p.rve_footprint_bytes(p.make_desc(bad)) == 0
+        assert "plane_stress" in lib.rve_last_error().decode()
