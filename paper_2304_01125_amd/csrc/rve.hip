@@ -25,6 +25,18 @@ thread_local std::string g_err;
 const bool g_debug = std::getenv("RVE_DEBUG") != nullptr;
 // RVE_POOL_BATCH=0 (read at every rve_pool_step): every handle's CG solve runs on its own
 // (for comparisons)
+// Where the convergence test of a CG iteration runs: in its own single-block kernel before
+// the next inverse z pass (default), or inside every block of that pass (RVE_CG_CHECK=inline,
+// where each block first sums the step's partials: at one resident block per CU that
+// latency is exposed once per block)
+bool cg_check_inline_mode() {
+  static const bool v = [] {
+    const char* e = std::getenv("RVE_CG_CHECK");
+    return e && std::strcmp(e, "inline") == 0;
+  }();
+  return v;
+}
+
 bool pool_batching_off() {
   const char* e = std::getenv("RVE_POOL_BATCH");
   return e && e[0] == '0';
@@ -357,15 +369,14 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 // cg_partial_offset() (at most 2 x kCgMaxBlocks: every block of the next inverse z pass sums
 // them).  The CG step's blocks write their partials while other blocks of the same launch
 // still sum the divergence pass's, so the two ranges must not overlap: the fused divergence
-// pass launches ((N1/2/T) N2 + ceil(N2/T)) 3 blocks with tiles of T >= 8 bins (the second
-// term: the Nyquist-column units), plus one partial of the macro stress, at most
-// 3 (N1 N2 / 16 + ceil(N2 / 8)) + 1.
+// pass launches (N1/2/T) N2 3 blocks with tiles of T >= 8 bins (plus one partial of the macro
+// stress), at most 3 N1 N2 / 16 + 1.
 constexpr long long kCgPartialMin = (long long)kMaxRedBlocks * 16;
 constexpr int kMaxBatch = 64;         // RVEs of one batched CG launch
 constexpr int kCgMaxBlocks = 1024;   // 512 measured 4 us slower per FP32 iteration at 128^3
 
 long long max_div_partials(const Grid& g) {
-  const long long fused = 3LL * ((long long)g.n1 * g.n2 / 16 + (g.n2 + 7) / 8) + 1;
+  const long long fused = 3LL * g.n1 * g.n2 / 16 + 1;
   return fused > kMaxRedBlocks + 1 ? fused : kMaxRedBlocks + 1;
 }
 long long cg_partial_offset(const Grid& g) {
@@ -826,8 +837,14 @@ struct Ops {
       const int ia = (k == 0) ? SC_ZERO : cur, ib = (k == 0) ? SC_ONE : prv;
       C* pold = (k & 1) ? b : p;
       C* pk = (k & 1) ? p : b;
-      if (k == 0) launch_zgrad_inv<R>(pb, z, pold, pk, o.NH, sc, ia, ib, o.W, st, stop);
-      else launch_zgrad_inv<R>(pb, z, pold, pk, o.NH, sc, ia, ib, o.W, st, stop, check_of(k - 1));
+      if (k == 0) {
+        launch_zgrad_inv<R>(pb, z, pold, pk, o.NH, sc, ia, ib, o.W, st, stop);
+      } else if (cg_check_inline_mode()) {
+        launch_zgrad_inv<R>(pb, z, pold, pk, o.NH, sc, ia, ib, o.W, st, stop, check_of(k - 1));
+      } else {
+        launch_cg_check_tail(sc, check_of(k - 1), st, h0->slotd, B);
+        launch_zgrad_inv<R>(pb, z, pold, pk, o.NH, sc, ia, ib, o.W, st, stop);
+      }
       launch_fft_yz<R>(pb, o.W, o.NH, 6, 1, true, st, stop);
       launch_x_tangent<R>(pb, o.W, o.NH, o.gK(), 1.0 / (double)o.N, st, stop);
       launch_fft_yz<R>(pb, o.W, o.NH, 6, 1, false, st, stop);
@@ -984,8 +1001,14 @@ struct Ops {
       if (fz) {
         C* pold = (k & 1) ? b : p;
         C* pk = (k & 1) ? p : b;
-        if (k == 0) launch_zgrad_inv<R>(h->pl, z, pold, pk, NH, sc, ia, ib, W, st, stop);
-        else launch_zgrad_inv<R>(h->pl, z, pold, pk, NH, sc, ia, ib, W, st, stop, check_of(k - 1));
+        if (k == 0) {
+          launch_zgrad_inv<R>(h->pl, z, pold, pk, NH, sc, ia, ib, W, st, stop);
+        } else if (cg_check_inline_mode()) {
+          launch_zgrad_inv<R>(h->pl, z, pold, pk, NH, sc, ia, ib, W, st, stop, check_of(k - 1));
+        } else {      // the test writes <r, z> into sc[ia] and the flag the pass stops on
+          launch_cg_check_tail(sc, check_of(k - 1), st);
+          launch_zgrad_inv<R>(h->pl, z, pold, pk, NH, sc, ia, ib, W, st, stop);
+        }
         if (mask)   // macro strain along the (0, 0) z column (z already inverse transformed)
           launch_macro_strain<R>(W, NH, pk, NH, s_mac, 0.0, mask, h->g.n3, zst, nullptr, st, stop);
         launch_fft_yz<R>(h->pl, W, NH, 6, 1, true, st, stop);
@@ -1947,14 +1970,19 @@ int rve_pool_step(rve_s* const* hs, int32_t n, const double* deps, const double*
       if (hs[i] == hs[j]) return fail(RVE_E_ARG, "handles must be distinct");
   for (int i = 0; i < n; ++i)
     if (!hs[i]) return fail(RVE_E_ARG, "null handle");
-  // groups of handles that can share CG launches: same grid, precision, derivative and CG
-  // solver on one device, small-strain kinematics, fused z passes
+  // groups of handles that can share CG launches: same grid, voxel size, precision,
+  // derivative and CG solver on one device, small-strain kinematics, fused z passes, and the
+  // same arena layout (the batched launches find every handle's buffers at the leader's
+  // offsets, so every option that places buffers must agree)
   std::vector<std::unique_ptr<CgGroup>> groups;
   std::vector<CgGroup*> gof((size_t)n, nullptr);
   auto same = [](const rve_s* a, const rve_s* b) {
     return a->d.n[0] == b->d.n[0] && a->d.n[1] == b->d.n[1] && a->d.n[2] == b->d.n[2] &&
-           a->d.precision == b->d.precision && a->d.deriv == b->d.deriv &&
-           a->device == b->device && a->d.max_krylov == b->d.max_krylov;
+           a->d.h == b->d.h && a->d.precision == b->d.precision && a->d.deriv == b->d.deriv &&
+           a->device == b->device && a->d.max_krylov == b->d.max_krylov &&
+           a->d.max_grains == b->d.max_grains && a->d.gnd_coupling == b->d.gnd_coupling &&
+           a->d.plane_stress == b->d.plane_stress && a->d.krylov == b->d.krylov &&
+           a->used == b->used;
   };
   auto can_batch = [](const rve_s* a) {
     return !a->fs && a->d.krylov == RVE_KRYLOV_CG && a->time_xt == 0 &&

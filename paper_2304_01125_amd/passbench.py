@@ -1,6 +1,6 @@
 """Launch one operator building block repeatedly (for profilers and counters).
 
-    python -m paper_2304_01125_amd.passbench --pass x_tangent --n 128 --reps 20 [--mixed]
+    python -m paper_2304_01125_amd.passbench --pass x_tangent[,zgrad,...] --n 128 --reps 20 [--mixed]
     python -m paper_2304_01125_amd.passbench --copy-mib 512 --reps 20
 
 The first form builds a handle on an N^3 grid of the 512-grain Laguerre workload's
@@ -21,6 +21,9 @@ def main():
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--mixed", action="store_true")
     ap.add_argument("--copy-mib", type=float, default=0.0)
+    ap.add_argument("--grains", type=int, default=0,
+                    help="grains of the microstructure (default N^3/4096; the pass timings do "
+                         "not depend on it, its generation time does)")
     a = ap.parse_args()
     import numpy as np
     import torch
@@ -45,23 +48,24 @@ def main():
     from synth import workload, make_inputs
     import dataclasses
     w = dataclasses.replace(workload("laguerre-128-g512"), n=(a.n, a.n, a.n),
-                            n_grains=max(1, a.n ** 3 // 4096))
+                            n_grains=a.grains or max(1, a.n ** 3 // 4096))
     inp = make_inputs(w)
     r = RVE(w.desc(), RVE_MIXED if a.mixed else RVE_FP64)
     r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
     r.launch_pass(PASSES["constitutive"], 1)     # populate the tangent field
-    pid = PASSES[a.pass_name]
-    r.launch_pass(pid, 2)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(r.stream)
-    nbytes = r.launch_pass(pid, a.reps)
-    e1.record(r.stream)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / a.reps
-    print(json.dumps({"pass": a.pass_name, "n": a.n, "mixed": a.mixed, "reps": a.reps,
-                      "ms": ms, "bytes_per_launch": nbytes,
-                      "GB/s": nbytes / (ms * 1e-3) / 1e9}))
+    for name in a.pass_name.split(","):
+        pid = PASSES[name]
+        r.launch_pass(pid, 2)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(r.stream)
+        nbytes = r.launch_pass(pid, a.reps)
+        e1.record(r.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / a.reps
+        print(json.dumps({"pass": name, "n": a.n, "mixed": a.mixed, "reps": a.reps,
+                          "ms": ms, "bytes_per_launch": nbytes,
+                          "GB/s": nbytes / (ms * 1e-3) / 1e9}), flush=True)
     r.close()
 
 

@@ -127,10 +127,9 @@ def test_material_derivative_and_mixed_control_arguments_are_validated():
                                (512, 384, 128), (384, 512, 256), (512, 512, 512), (2, 2, 2)])
 def test_cg_partials_do_not_overlap_the_divergence_partials(n):
     """The CG step writes its block partials while other blocks of the same launch still sum
-    the fused divergence pass's (one per block of ((N1/2/T) N2 + ceil(N2/T)) 3 blocks, T >= 8,
-    the second term the Nyquist-column units, plus one of the macro stress): the two ranges of
-    the reduction buffer must be disjoint on every grid (512 x 512 x 16 launches 49344
-    divergence blocks)."""
+    the fused divergence pass's (one per block of (N1/2/T) N2 3 blocks, T >= 8, plus one of
+    the macro stress): the two ranges of the reduction buffer must be disjoint on every grid
+    (512 x 512 x 16 launches 49152 divergence blocks)."""
     import paper_2304_01125_amd as p
     from synth import workload
     lib = p.load()
@@ -139,7 +138,7 @@ def test_cg_partials_do_not_overlap_the_divergence_partials(n):
         out = (ctypes.c_int64 * 3)()
         assert lib.rve_diag_partials(ctypes.byref(d), out) == p.RVE_OK
         max_div, cg_off, length = out
-        assert max_div >= 3 * ((n[0] // 16) * n[1] + (n[1] + 7) // 8) + 1
+        assert max_div >= 3 * (n[0] // 16) * n[1] + 1
         assert cg_off >= max_div
         assert length >= cg_off + 2 * 1024
     bad = p.make_desc(dict(workload("notched-crystal-16").desc(), n=(10, 2, 2)))
