@@ -179,9 +179,11 @@ WORKLOADS = {
     "notched-crystal-16": Workload(name="notched-crystal-16", n=(16, 16, 16), n_grains=1,
                                    seed=0, amplitude=0.005, ratio=-1, cycles=2,
                                    incs_per_cycle=20, notch=True, G_crit=0.25),
-    # plain FP64 polycrystal
+    # plain FP64 polycrystal; damage initiates from the stored energy (G_crit lowered from
+    # 4 by powers of 2, to 4 / 2^7 J/m^2, so that it starts within the first cycle)
     "voronoi-64-g64": Workload(name="voronoi-64-g64", n=(64, 64, 64), n_grains=64, seed=1,
-                               amplitude=0.006, ratio=0, cycles=3, incs_per_cycle=20),
+                               amplitude=0.006, ratio=0, cycles=3, incs_per_cycle=20,
+                               G_crit=4.0 / 2 ** 7),
     # headline: 128^3, 512 log-normal Laguerre grains, fully reversed
     "laguerre-128-g512": Workload(name="laguerre-128-g512", n=(128, 128, 128), n_grains=512,
                                   seed=2, amplitude=0.005, ratio=-1, cycles=2,

@@ -81,11 +81,13 @@ def notched16(max_inc=40, snaps=(5, 11, 13, 15, 19, 25, 31, 39)):
                             **{k2: np.asarray(v) for k2, v in out.items()})
 
 
-def voronoi64(max_inc=16, n_sample=4096, after=2):
+def voronoi64(max_inc=16, n_sample=4096, keep=2, stop_after=1):
     """Config 1 up to damage initiation: increments until the damage has been non-zero for
-    `after` increments (at most max_inc), the macro stress, the maximum damage and the
+    `stop_after` increments (at most max_inc), the macro stress, the maximum damage and the
     number of triggered voxels of each, and sampled fields after increment 1 and the last
-    `after` increments."""
+    `keep` increments.  (The first damaging increment needs about 50 alternating passes at
+    the parity tolerances, about two hours of this oracle on 8 cores; the next one, where
+    the damage runs to 1, about 100.)"""
     w = workload("voronoi-64-g64").parity()
     inp = make_inputs(w)
     o = OracleRVE(w.desc(), inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
@@ -105,13 +107,13 @@ def voronoi64(max_inc=16, n_sample=4096, after=2):
         f = o.fields()
         for name in FIELDS64:
             out[f"inc{k}_{name}"] = f[name][idx]
-        drop = k - after                 # keep increment 1 and the latest `after` increments
+        drop = k - keep                  # keep increment 1 and the latest `keep` increments
         if drop >= 0 and drop != 1:
             for name in FIELDS64:
                 out.pop(f"inc{drop}_{name}", None)
         np.savez_compressed(os.path.join(HERE, "voronoi64.npz"), last=k, G_crit=w.G_crit,
                             **{k2: np.asarray(v) for k2, v in out.items()})
-        if damaged >= after:
+        if damaged >= stop_after:
             break
 
 
@@ -164,6 +166,33 @@ def finite16(n_inc=4, snaps=(1, 3)):
                 out[f"inc{k}_{name}"] = f[name]
     np.savez_compressed(os.path.join(HERE, "finite16.npz"), last=n_inc - 1,
                         **{k2: np.asarray(v) for k2, v in out.items()})
+
+
+def laguerre128(n_inc=5, n_sample=4096):
+    """The benchmark workload (128^3, 512 Laguerre grains) at the paper's production
+    tolerances: macro stress, Newton and alternating counts of its first n_inc increments and
+    sampled strain and stress after the first, the reference the GPU's FP64 and mixed
+    precision increments are compared with at full size (about 20 minutes per increment of
+    this oracle on 8 cores)."""
+    w = workload("laguerre-128-g512")
+    inp = make_inputs(w)
+    o = OracleRVE(w.desc(), inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+    idx = np.sort(np.random.default_rng(128).choice(w.nvox, n_sample, replace=False))
+    out = {"sample": idx, "macro_stress": [], "newton": [], "stag": []}
+    t0 = time.time()
+    for k in range(n_inc):
+        st = o.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k])
+        print(f"inc {k}: {time.time() - t0:.0f}s newton {st['newton']} matvecs {st['matvecs']} "
+              f"stag {st['stag']}", flush=True)
+        out["macro_stress"].append(st["macro_stress"])
+        out["newton"].append(st["newton"])
+        out["stag"].append(st["stag"])
+        if k == 0:
+            f = o.fields()
+            for name in ("strain", "stress"):
+                out[f"inc0_{name}"] = f[name][idx]
+        np.savez_compressed(os.path.join(HERE, "laguerre128.npz"), last=k,
+                            **{k2: np.asarray(v) for k2, v in out.items()})
 
 
 if __name__ == "__main__":

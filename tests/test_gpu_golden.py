@@ -53,17 +53,37 @@ def test_notched_crystal_16_matches_stored_oracle():
 
 
 def test_voronoi_64_sampled_voxels_match_stored_oracle():
+    """Config 1 up to damage initiation: the macro stress, the number of triggered voxels
+    and the maximum damage of every increment, and the sampled fields after increment 1
+    and the last two increments (the first voxel triggered, then damage active: about 50
+    alternating passes), against the stored oracle run."""
     from paper_2304_01125_amd import RVE
     ref = np.load(os.path.join(GOLDEN, "voronoi64.npz"))
     idx = ref["sample"]
     w = workload("voronoi-64-g64").parity()
+    assert w.G_crit == float(ref["G_crit"])
     inp = make_inputs(w)
     r = RVE(w.desc())
     r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
-    for k in range(int(ref["last"]) + 1):
+    last = int(ref["last"])
+    for k in range(last + 1):
         st = r.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k])
-        print(f"  inc {k}: newton {st['newton_iters']} krylov {st['krylov_iters']}", flush=True)
+        print(f"  inc {k}: newton {st['newton_iters']} krylov {st['krylov_iters']} stag "
+              f"{st['stag_iters']} triggered {st['n_triggered']:.0f} max phi "
+              f"{st['max_phi']:.3e} (oracle {ref['n_trig'][k]}, {ref['max_phi'][k]:.3e})",
+              flush=True)
         ms = np.array(st["macro_stress"])
         assert np.abs(ms - ref["macro_stress"][k]).max() <= 1e-9 * np.abs(ref["macro_stress"][k]).max()
-        _check(r.fields(("strain", "stress", "damage", "gs", "wp")), ref, f"inc{k}", idx=idx)
+        assert st["n_triggered"] == ref["n_trig"][k]
+        assert abs(st["max_phi"] - ref["max_phi"][k]) <= 1e-8
+        if f"inc{k}_strain" in ref.files:
+            f = r.fields(("strain", "stress", "damage", "gs", "wp", "h", "wcrit", "trig"))
+            _check(f, ref, f"inc{k}", idx=idx)
+            for name in ("h", "wcrit"):
+                a, b = f[name][idx], ref[f"inc{k}_{name}"]
+                e = rel_l2(a, b) if np.linalg.norm(b) > 0 else np.abs(a).max()
+                assert e <= 1e-8, (name, e)
+            assert np.array_equal(f["trig"][idx], ref[f"inc{k}_trig"])
+    # damage initiated from the stored energy within the stored increments
+    assert ref["max_phi"][last] > 0.0 and ref["n_trig"][last] > 0
     r.close()
