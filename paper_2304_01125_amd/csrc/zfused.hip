@@ -365,11 +365,13 @@ template <typename R, int N>
 static int fused_tile(const Grid& g, bool div) {
   if (g.n1 % 2 != 0 || g.n3 != N) return 0;
   const int half = g.n1 / 2;
-  // the widest tile that fits for the gradient pass (32 bins measured faster than 16); the
-  // divergence pass holds two LDS arrays and runs more blocks per CU at 8 bins (128^3: 47
-  // against 60 us FP64 at 16 bins, 26 against 34 us FP32 at 32)
-  const int cap = div ? 8 : 32;
-  for (int TX : {32, 16, 8}) {
+  // the widest tile that fits for the gradient pass (32 bins measured faster than 16; in
+  // FP32 64-bin tiles, whose row segments are as long in bytes as the FP64 pass's 32-bin
+  // ones: 31.1 against 32.4 us at 128^3); the divergence pass holds two LDS arrays and runs
+  // more blocks per CU at 8 bins (128^3: 47 against 60 us FP64 at 16 bins, 26 against 34 us
+  // FP32 at 32)
+  const int cap = div ? 8 : (sizeof(R) == 4 ? 64 : 32);
+  for (int TX : {64, 32, 16, 8}) {
     if (TX > cap) continue;
     const size_t lds = div ? zdiv_lds<R>(N, TX + 1, g.sch) : zgrad_lds<R>(N, TX + 1, g.sch);
     if (half % TX == 0 && lds <= kRegLdsMax) return TX;
@@ -412,7 +414,8 @@ void launch_zgrad_inv(const Plans& p, const cplx<R>* z, const cplx<R>* pold, cpl
         if (g.sch) go.template operator()<T, 1>();
         else go.template operator()<T, 0>();
       };
-      if (TX == 32) go2.template operator()<32>();
+      if (TX == 64) go2.template operator()<64>();
+      else if (TX == 32) go2.template operator()<32>();
       else if (TX == 16) go2.template operator()<16>();
       else if (TX == 8) go2.template operator()<8>();
     }

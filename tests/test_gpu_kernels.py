@@ -107,12 +107,14 @@ def test_operator_matches_oracle_and_is_identity_for_homogeneous_tangent():
 # fused z passes with work-unit counts that are multiples of 8 (XCD-contiguous block
 # order) and not (plain order: 16x12x16, 48x12x48), unfused grids, both precisions; every
 # column length of the fused z passes (16, 32, 48, 64, 96, 128, 256) and the row tangent
-# pass at rows of 96 and 256 (256-thread blocks)
+# pass at rows of 96, 128 and 256 (256-thread blocks); 64-bin tiles of the FP32 inverse z
+# pass (rows of 128 and 256)
 FUSED = [(32, 8, 128), (16, 16, 16), (16, 12, 16), (48, 12, 48), (64, 64, 64), (16, 8, 32),
-         (16, 8, 96), (96, 8, 96), (16, 4, 256), (256, 8, 16)]
+         (16, 8, 96), (96, 8, 96), (16, 4, 256), (256, 8, 16), (128, 6, 16)]
+# (128, 9, 3): the unfused path on rows of 128
 
 
-@pytest.mark.parametrize("n", FUSED + [(12, 8, 6)])
+@pytest.mark.parametrize("n", FUSED + [(12, 8, 6), (128, 9, 3)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_operator_shapes_match_oracle(n, prec):
     from paper_2304_01125_amd import RveError
