@@ -199,6 +199,31 @@ __device__ __forceinline__ void load_kbar4(double* K4, const double* __restrict_
   }
 }
 
+// The acoustic tensor A_ik = sum_jl t_j K_ijkl t_l as 6 x 6 coefficients on the products
+// tau = (t0 t0, t1 t1, t2 t2, t1 t2, t0 t2, t0 t1): A_p = sum_m C[p][m] tau_m for the pairs
+// p = (i, k) in 00 01 02 11 12 22, with C = K_ijkl for j = l and K_ijkl + K_ilkj for
+// m = (j, l), j < l.  36 uniform values (LDS), 36 FMA per bin.
+__device__ __forceinline__ double kbar_entry(const double* __restrict__ kbar21, int i, int j,
+                                             int k, int l) {
+  const int a = mandel_index(i, j), b = mandel_index(k, l);
+  const int lo = min(a, b), hi = max(a, b);
+  const int idx = lo * 6 - lo * (lo - 1) / 2 + (hi - lo);
+  const double wa = (a < 3) ? 1.0 : 1.41421356237309504880;
+  const double wb = (b < 3) ? 1.0 : 1.41421356237309504880;
+  return kbar21[idx] / (wa * wb);
+}
+__device__ __forceinline__ void load_acoustic36(double* C, const double* __restrict__ kbar21) {
+  if (threadIdx.x < 36) {
+    constexpr int pi[6] = {0, 0, 0, 1, 1, 2}, pk[6] = {0, 1, 2, 1, 2, 2};
+    constexpr int mj[6] = {0, 1, 2, 1, 0, 0}, ml[6] = {0, 1, 2, 2, 2, 1};
+    const int p = threadIdx.x / 6, m = threadIdx.x % 6;
+    const int i = pi[p], k = pk[p], j = mj[m], l = ml[m];
+    double c = kbar_entry(kbar21, i, j, k, l);
+    if (j != l) c += kbar_entry(kbar21, i, l, k, j);
+    C[threadIdx.x] = c;
+  }
+}
+
 // Zero bin under mixed macroscopic control: zo = m0 ri on the bin's six reals
 // (Mandel macro components xx, yy, zz, yz, xz, xy held as x: (xx, xy), y: (yy, yz),
 // z: (zz, xz)).
@@ -235,28 +260,29 @@ __device__ __forceinline__ void apply_F0(const double* __restrict__ f, const cpl
   ro[2] = cplx<double>{rm[2], rm[4]};
 }
 
-// zo = [t . K . t]^-1 ri (zero where t = 0), t = xi~ of the bin; with As set, the acoustic
-// tensor t . K . t itself (upper triangle: 00 01 02 11 12 22; zero where t = 0).
+// zo = [t . K . t]^-1 ri (zero where t = 0), t = xi~ of the bin, the acoustic tensor from
+// the 36 coefficients of load_acoustic36; with As set, the acoustic tensor t . K . t itself
+// (upper triangle: 00 01 02 11 12 22; zero where t = 0).
 template <typename R>
-__device__ __forceinline__ void apply_M(const double t[3], const double* K4, const cplx<R> ri[3],
-                                        cplx<R> zo[3], double* As = nullptr) {
+__device__ __forceinline__ void apply_M6(const double t[3], const double* C, const cplx<R> ri[3],
+                                         cplx<R> zo[3], double* As = nullptr) {
   zo[0] = zo[1] = zo[2] = cplx<R>{0, 0};
   if (As)
     for (int i = 0; i < 6; ++i) As[i] = 0.0;
   if (t[0] == 0.0 && t[1] == 0.0 && t[2] == 0.0) return;
-  double A[3][3];
-  for (int i = 0; i < 3; ++i)
-    for (int k = i; k < 3; ++k) {
-      double s = 0.0;
-      for (int j = 0; j < 3; ++j)
-        for (int l = 0; l < 3; ++l) s += t[j] * K4[((i * 3 + j) * 3 + k) * 3 + l] * t[l];
-      A[i][k] = s;
-      A[k][i] = s;
-    }
-  if (As) {
-    As[0] = A[0][0]; As[1] = A[0][1]; As[2] = A[0][2];
-    As[3] = A[1][1]; As[4] = A[1][2]; As[5] = A[2][2];
+  const double tau[6] = {t[0] * t[0], t[1] * t[1], t[2] * t[2], t[1] * t[2], t[0] * t[2],
+                         t[0] * t[1]};
+  double a6[6];
+#pragma unroll
+  for (int p = 0; p < 6; ++p) {
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) s += C[p * 6 + m] * tau[m];
+    a6[p] = s;
   }
+  if (As)
+    for (int i = 0; i < 6; ++i) As[i] = a6[i];
+  const double A[3][3] = {{a6[0], a6[1], a6[2]}, {a6[1], a6[3], a6[4]}, {a6[2], a6[4], a6[5]}};
   const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
   const double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
   const double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
@@ -470,7 +496,8 @@ k_cg_step(cplx<R>* __restrict__ x, const cplx<R>* __restrict__ pv,
   } else {
     pq = sc[ipq];
   }
-  load_kbar4(K4, kbar21);
+  if constexpr (SCH == 0) load_acoustic36(K4, kbar21);
+  else load_kbar4(K4, kbar21);
   __syncthreads();
   const double al = sc[cur] / pq;
   const bool even = (g.n1 % 2 == 0);
@@ -534,7 +561,7 @@ k_cg_step(cplx<R>* __restrict__ x, const cplx<R>* __restrict__ pv,
       apply_F0(m0 + 36, zn, rd);
     } else if constexpr (SCH == 0) {
       double As[6];
-      apply_M(t, K4b, hq, mq, As);
+      apply_M6(t, K4b, hq, mq, As);
       z_update();
       const double A[3][3] = {{As[0], As[1], As[2]}, {As[1], As[3], As[4]},
                               {As[2], As[4], As[5]}};
@@ -629,7 +656,9 @@ __global__ void __launch_bounds__(256) k_precond(const cplx<R>* __restrict__ r, 
                           const double* __restrict__ stop, const double* __restrict__ m0) {
   if (stop && *stop != 0.0) return;
   __shared__ double K4[81];
+  __shared__ double C36[36];
   __shared__ double red[1024 / 64];
+  load_acoustic36(C36, kbar21);
   if (threadIdx.x < 81) {
     const int i = threadIdx.x / 27, j = (threadIdx.x / 9) % 3, k = (threadIdx.x / 3) % 3,
               l = threadIdx.x % 3;
@@ -668,7 +697,7 @@ __global__ void __launch_bounds__(256) k_precond(const cplx<R>* __restrict__ r, 
       kvec(g, q.kx, q.ky, q.kz, kk);
       apply_Mk(kk, K4b, ri, zo);
     } else {
-      apply_M(t, K4b, ri, zo);
+      apply_M6(t, C36 + koff, ri, zo);
     }
     z[b] = zo[0];
     z[cs + b] = zo[1];
