@@ -238,11 +238,14 @@ def summary(recs, wall):
             "wall_s": round(wall, 2)}
 
 
-def serve_benchmark(n_req=400, slots=8, seed=4, workers=8, log=None, items=None, low_rate=0.5):
-    """Serial plain-FP64 baseline, then the mixed-precision server (tick mode: one
-    rve_pool_step per tick, the CG iterations of same-size requests in shared launches) on
-    the Poisson stream at rate factor x the serial capacity, then the same server at
-    `low_rate` x its own measured throughput (latency without a growing queue).  Returns a
+def serve_benchmark(n_req=400, slots=8, seed=4, workers=8, log=None, items=None, low_rate=0.5,
+                    modes=("async", "tick")):
+    """Serial plain-FP64 baseline, then the mixed-precision server in each of `modes` on the
+    Poisson stream at rate factor x the serial capacity, and at `low_rate` x its own measured
+    throughput (latency without a growing queue).  Mode "async": each slot runs its request's
+    increments back to back on its own stream and host thread; "tick": one rve_pool_step per
+    tick, the CG iterations of same-size requests in shared launches.  The first mode fills
+    `server_mixed` and `server_mixed_below_capacity`, every mode `<mode>`.  Returns a
     JSON-able dict.  `items`: the prepared requests (else prepared here)."""
     from synth import serving_requests
     from . import RVE_FP64, RVE_MIXED
@@ -256,19 +259,33 @@ def serve_benchmark(n_req=400, slots=8, seed=4, workers=8, log=None, items=None,
     lam = factor * cap
     arrivals = np.cumsum(gaps) / lam
     srv = Server(RVE_MIXED, max_slots=slots)
-    res, wall, ticks = srv.run(items, arrivals, log=log)
-    ok = sum(1 for r in res if r["status"] == 0)
     ok_s = sum(1 for r in serial if r["status"] == 0)
     out = {"requests": n_req, "slots": slots, "rate_factor": round(factor, 3),
-           "arrival_rate_per_s": round(lam, 3), "completed": ok, "completed_serial": ok_s,
-           "server_mixed": summary(res, wall), "serial_fp64": summary(serial, wall_s),
-           "ticks": ticks}
-    # below capacity: arrivals at low_rate x the server's throughput under the stream above
-    thr = len(res) / wall
-    lam_low = low_rate * thr
-    res2, wall2, _ = srv.run(items, np.cumsum(gaps) / lam_low, log=log)
-    out["server_mixed_below_capacity"] = dict(summary(res2, wall2),
-                                             arrival_rate_per_s=round(lam_low, 3))
+           "arrival_rate_per_s": round(lam, 3), "completed_serial": ok_s,
+           "serial_fp64": summary(serial, wall_s)}
+    for i, mode in enumerate(modes):
+        def serve(arr):
+            if mode == "async":
+                res, wall = srv.run_async(items, arr, log=log)
+                return res, wall, None
+            return srv.run(items, arr, log=log)
+
+        res, wall, ticks = serve(arrivals)
+        m = {"completed": sum(1 for r in res if r["status"] == 0),
+             "server_mixed": summary(res, wall)}
+        if ticks is not None:
+            m["ticks"] = ticks
+        # below capacity: arrivals at low_rate x this server's throughput under the stream
+        lam_low = low_rate * len(res) / wall
+        res2, wall2, _ = serve(np.cumsum(gaps) / lam_low)
+        m["server_mixed_below_capacity"] = dict(summary(res2, wall2),
+                                               arrival_rate_per_s=round(lam_low, 3))
+        out[mode] = m
+        if i == 0:
+            out["mode"] = mode
+            out["completed"] = m["completed"]
+            out["server_mixed"] = m["server_mixed"]
+            out["server_mixed_below_capacity"] = m["server_mixed_below_capacity"]
     return out
 
 
@@ -279,9 +296,11 @@ def main():
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--json", default=None)
+    ap.add_argument("--mode", choices=["tick", "async", "both"], default="both")
     a = ap.parse_args()
+    modes = ("async", "tick") if a.mode == "both" else (a.mode,)
     res = serve_benchmark(a.requests, a.slots, a.seed, a.workers,
-                          log=lambda m: print(m, file=sys.stderr, flush=True))
+                          log=lambda m: print(m, file=sys.stderr, flush=True), modes=modes)
     print(json.dumps(res), flush=True)
     if a.json:
         with open(a.json, "w") as f:
