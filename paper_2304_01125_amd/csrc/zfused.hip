@@ -344,7 +344,6 @@ k_zdiv_fwd(const cplx<R>* __restrict__ s, cplx<R>* __restrict__ q, const cplx<R>
   block_partial_sum(acc, partial, red);
 }
 
-// LDS bytes of the fused z kernels
 // LDS bytes of the fused z kernels (the rotated scheme adds its factor tables, 3 P + 2 N
 // complex)
 template <typename R>
@@ -359,22 +358,42 @@ constexpr size_t zdiv_lds(int N, int P, int sch) {
          16 * sizeof(double);
 }
 
-// Largest x tile (32, 16 or 8 bins plus the Nyquist column) whose LDS fits; 0 if the
-// grid has no fused z pass (odd n1, or n3 without a register DFT).
+// LDS ceiling of one fused z block: the whole 160 KB of a gfx950 CU (the 256-point
+// columns take one block per CU; the shorter columns stay within kRegLdsMax by their caps)
+constexpr size_t kZLdsMax = 160 * 1024;
+
+// Widest x tile (64, 32, 16 or 8 bins plus the Nyquist column) allowed for a column length
+// and precision.  Up to 128-point columns: the widest tile that fits for the gradient pass
+// (32 bins measured faster than 16; in FP32 64-bin tiles, whose row segments are as long in
+// bytes as the FP64 pass's 32-bin ones: 31.1 against 32.4 us at 128^3); the divergence pass
+// holds two LDS arrays and runs more blocks per CU at 8 bins (128^3: 47 against 60 us FP64
+// at 16 bins, 26 against 34 us FP32 at 32).  256-point columns are bound by the locality
+// of their accesses, not by occupancy: the z planes of a 256^2 half spectrum lie 528 KB
+// apart (FP64), and a block moves one short row segment per plane and operand across all
+// 256 planes (the address translations hit; the requests wait on their data).  Longer
+// segments help: one block per CU with 32-bin tiles (FP64 gradient pass) takes 781 against
+// 1135 us, 16-bin divergence tiles 608 against 669 us; in FP32 64- and 32-bin tiles 476
+// against 633 and 345 against 390 us (a second resident block, at 16 bins with fewer
+// registers, gained 1 %).  At 128 points the same widening is slower.
+template <typename R>
+constexpr int z_tile_cap(int N, bool div) {
+  if (N == 256) return div ? (sizeof(R) == 4 ? 32 : 16) : (sizeof(R) == 4 ? 64 : 32);
+  return div ? 8 : (sizeof(R) == 4 ? 64 : 32);
+}
+template <typename R>
+constexpr size_t z_lds_max(int N) { return N == 256 ? kZLdsMax : kRegLdsMax; }
+
+// Largest x tile within the cap whose LDS fits; 0 if the grid has no fused z pass (odd
+// n1, or n3 without a register DFT).
 template <typename R, int N>
 static int fused_tile(const Grid& g, bool div) {
   if (g.n1 % 2 != 0 || g.n3 != N) return 0;
   const int half = g.n1 / 2;
-  // the widest tile that fits for the gradient pass (32 bins measured faster than 16; in
-  // FP32 64-bin tiles, whose row segments are as long in bytes as the FP64 pass's 32-bin
-  // ones: 31.1 against 32.4 us at 128^3); the divergence pass holds two LDS arrays and runs
-  // more blocks per CU at 8 bins (128^3: 47 against 60 us FP64 at 16 bins, 26 against 34 us
-  // FP32 at 32)
-  const int cap = div ? 8 : (sizeof(R) == 4 ? 64 : 32);
+  const int cap = z_tile_cap<R>(N, div);
   for (int TX : {64, 32, 16, 8}) {
     if (TX > cap) continue;
     const size_t lds = div ? zdiv_lds<R>(N, TX + 1, g.sch) : zgrad_lds<R>(N, TX + 1, g.sch);
-    if (half % TX == 0 && lds <= kRegLdsMax) return TX;
+    if (half % TX == 0 && lds <= z_lds_max<R>(N)) return TX;
   }
   return 0;
 }
@@ -403,7 +422,8 @@ void launch_zgrad_inv(const Plans& p, const cplx<R>* z, const cplx<R>* pold, cpl
     if constexpr (NC > 0) {
       const int TX = fused_tile<R, NC>(g, false);
       auto go = [&]<int T, int S>() {
-        if constexpr (zgrad_lds<R>(NC, T + 1, S) <= kRegLdsMax) {
+        if constexpr (T <= z_tile_cap<R>(NC, false) &&
+                      zgrad_lds<R>(NC, T + 1, S) <= z_lds_max<R>(NC)) {
           constexpr int NT = threads_for<(T + 1) * ZSplit<NC>::Nb>();
           const int nblk = (g.n1 / 2 / T) * g.n2 * 6;
           hipLaunchKernelGGL((k_zgrad_inv<R, NC, T, NT, S>), dim3(nblk, 1, p.nslot), dim3(NT), 0, st, z, pold,
@@ -432,7 +452,8 @@ int launch_zdiv_fwd(const Plans& p, const cplx<R>* s, cplx<R>* q, const cplx<R>*
     if constexpr (NC > 0) {
       const int TX = fused_tile<R, NC>(g, true);
       auto go = [&]<int T, int S>() {
-        if constexpr (zdiv_lds<R>(NC, T + 1, S) <= kRegLdsMax) {
+        if constexpr (T <= z_tile_cap<R>(NC, true) &&
+                      zdiv_lds<R>(NC, T + 1, S) <= z_lds_max<R>(NC)) {
           constexpr int NT = threads_for<(T + 1) * ZSplit<NC>::Nb>();
           nblk = (g.n1 / 2 / T) * g.n2 * 3;
           hipLaunchKernelGGL((k_zdiv_fwd<R, NC, T, NT, S>), dim3(nblk, 1, p.nslot), dim3(NT), 0, st, s, q, pv,

@@ -108,9 +108,10 @@ def test_operator_matches_oracle_and_is_identity_for_homogeneous_tangent():
 # order) and not (plain order: 16x12x16, 48x12x48), unfused grids, both precisions; every
 # column length of the fused z passes (16, 32, 48, 64, 96, 128, 256) and the row tangent
 # pass at rows of 96, 128 and 256 (256-thread blocks); 64-bin tiles of the FP32 inverse z
-# pass (rows of 128 and 256)
+# pass (rows of 128 and 256); the wide tiles of 256-point columns (one block per CU: 32- and
+# 16-bin FP64, 64- and 32-bin FP32 tiles) on rows of 128
 FUSED = [(32, 8, 128), (16, 16, 16), (16, 12, 16), (48, 12, 48), (64, 64, 64), (16, 8, 32),
-         (16, 8, 96), (96, 8, 96), (16, 4, 256), (256, 8, 16), (128, 6, 16)]
+         (16, 8, 96), (96, 8, 96), (16, 4, 256), (256, 8, 16), (128, 6, 16), (128, 2, 256)]
 # (128, 9, 3): the unfused path on rows of 128
 
 

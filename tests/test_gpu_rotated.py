@@ -15,7 +15,8 @@ from test_gpu_increment import compare
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("n", [(32, 8, 128), (16, 16, 16), (12, 8, 6), (18, 64, 64)])
+@pytest.mark.parametrize("n", [(32, 8, 128), (16, 16, 16), (12, 8, 6), (18, 64, 64),
+                               (128, 2, 256)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_operator_matches_oracle(n, prec):
     from paper_2304_01125_amd import RVE
