@@ -97,6 +97,18 @@ __device__ __forceinline__ void slip_law(const Flow& f, double t, double& dg, do
   }
 }
 
+// The power law's slip_law together with the system's potential share (slip_pot), both
+// from the one power |x|^(n-1).
+__device__ __forceinline__ void slip_law_pot_power(const Flow& f, double t, double& dg,
+                                                   double& ddg, double& pot) {
+  const double x = t * f.ig;
+  const double ax = fabs(x);
+  const double pw = pow_e(ax, f.c1 - 1.0, f.nm1);
+  dg = f.c0 * copysign(ax * pw, x);
+  ddg = f.c0 * f.c1 * f.ig * pw;
+  pot = fabs(t) * ax * pw;
+}
+
 // One system's share of the dissipation potential, without the factor pot_scale:
 // |t| |t/g|^n (power law), sinh(beta <|t| - g> / 2)^2 = (cosh(beta <|t| - g>) - 1) / 2
 // (thermally activated; no cancellation near the threshold).
@@ -134,7 +146,9 @@ __device__ __forceinline__ void cubic_mul(double a, double b, double c, const do
   y[5] = c * x[5];
 }
 
-// In-place upper Cholesky J = U^T U on the packed triangle; false if not SPD.
+// In-place upper Cholesky J = U^T U on the packed triangle; false if not SPD.  The
+// diagonal is stored inverted (1 / U_ii): the solves and the inverse then multiply where
+// they would divide, and the serial chains of the triangular solves carry no divisions.
 __device__ __forceinline__ bool chol6p(double J[21]) {
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
@@ -142,9 +156,8 @@ __device__ __forceinline__ bool chol6p(double J[21]) {
 #pragma unroll
     for (int k = 0; k < i; ++k) s -= J[pk(k, i)] * J[pk(k, i)];
     if (!(s > 0.0)) return false;
-    const double d = sqrt(s);
-    J[pk(i, i)] = d;
-    const double id = 1.0 / d;
+    const double id = rsqrt(s);
+    J[pk(i, i)] = id;
 #pragma unroll
     for (int j = i + 1; j < 6; ++j) {
       double t = J[pk(i, j)];
@@ -156,7 +169,7 @@ __device__ __forceinline__ bool chol6p(double J[21]) {
   return true;
 }
 
-// Solve U^T U x = b with the packed upper factor U.
+// Solve U^T U x = b with the packed upper factor U of chol6p (inverted diagonal).
 __device__ __forceinline__ void chol6p_solve(const double U[21], const double b[6], double x[6]) {
   double y[6];
 #pragma unroll
@@ -164,29 +177,29 @@ __device__ __forceinline__ void chol6p_solve(const double U[21], const double b[
     double s = b[i];
 #pragma unroll
     for (int k = 0; k < i; ++k) s -= U[pk(k, i)] * y[k];
-    y[i] = s / U[pk(i, i)];
+    y[i] = s * U[pk(i, i)];
   }
 #pragma unroll
   for (int i = 5; i >= 0; --i) {
     double s = y[i];
 #pragma unroll
     for (int k = i + 1; k < 6; ++k) s -= U[pk(i, k)] * x[k];
-    x[i] = s / U[pk(i, i)];
+    x[i] = s * U[pk(i, i)];
   }
 }
 
-// K = J^-1 = U^-1 U^-T (packed 21) from the packed upper factor U.
+// K = J^-1 = U^-1 U^-T (packed 21) from the packed upper factor U of chol6p.
 __device__ __forceinline__ void chol6p_inverse(const double U[21], double K[21]) {
   double W[21];            // W = U^-1, upper triangular, packed
 #pragma unroll
   for (int j = 5; j >= 0; --j) {
-    W[pk(j, j)] = 1.0 / U[pk(j, j)];
+    W[pk(j, j)] = U[pk(j, j)];
 #pragma unroll
     for (int i = j - 1; i >= 0; --i) {
       double s = 0.0;
 #pragma unroll
       for (int k = i + 1; k <= j; ++k) s += U[pk(i, k)] * W[pk(k, j)];
-      W[pk(i, j)] = -s / U[pk(i, i)];
+      W[pk(i, j)] = -s * U[pk(i, i)];
     }
   }
 #pragma unroll

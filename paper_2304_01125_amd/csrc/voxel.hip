@@ -67,15 +67,22 @@ __device__ __forceinline__ double potential(const CrystalFrame& cf, const double
 }
 
 // Residual R = S (sig - sig_tr) + sum dgamma P and packed Jacobian J (21), accumulated
-// slip system by slip system.
+// slip system by slip system; with phi, also Phi(sig) (the power law's from the same
+// resolved stresses and powers, the same arithmetic as potential()).
 template <int F>
 __device__ __forceinline__ void resjac(const CrystalFrame& cf, const double sig[6],
                                        const double str[6], const Flow& f, double Rv[6],
-                                       double J[21]) {
+                                       double J[21], double* phi = nullptr) {
   double d[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) d[i] = sig[i] - str[i];
   cubic_mul(cf.s11, cf.s12, cf.s66, d, Rv);
+  constexpr bool POW = F == FLOW_POWER;
+  double el = 0.0, pl = 0.0;
+  if (POW && phi) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) el += d[i] * Rv[i];
+  }
 #pragma unroll
   for (int i = 0; i < 6; ++i)
 #pragma unroll
@@ -87,7 +94,13 @@ __device__ __forceinline__ void resjac(const CrystalFrame& cf, const double sig[
 #pragma unroll
     for (int b = 0; b < 6; ++b) t += cf.P[a * 6 + b] * sig[b];
     double dg, ddg;
-    slip_law<F>(f, t, dg, ddg);
+    if constexpr (POW) {
+      double pot;
+      slip_law_pot_power(f, t, dg, ddg, pot);
+      if (phi) pl += pot;
+    } else {
+      slip_law<F>(f, t, dg, ddg);
+    }
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
       Rv[i] += dg * cf.P[a * 6 + i];
@@ -96,6 +109,7 @@ __device__ __forceinline__ void resjac(const CrystalFrame& cf, const double sig[
       for (int j = i; j < 6; ++j) J[pk(i, j)] += di * cf.P[a * 6 + j];
     }
   }
+  if (phi) *phi = POW ? 0.5 * el + pot_scale<F>(f) * pl : potential<F>(cf, sig, str, f);
 }
 
 // Solve the return map with Newton steps and a backtracking line search on Phi.  sig
@@ -135,13 +149,12 @@ __device__ int return_map(const CrystalFrame& cf, const double str[6], const Flo
   int it;
   bool conv = false;
   for (it = 0; it < 400; ++it) {
-    double Rv[6], J[21], d[6], mR[6];
-    resjac<F>(cf, sig, str, f, Rv, J);
+    double Rv[6], J[21], d[6], mR[6], phi0;
+    resjac<F>(cf, sig, str, f, Rv, J, &phi0);
     if (!chol6p(J)) return -1;
 #pragma unroll
     for (int i = 0; i < 6; ++i) mR[i] = -Rv[i];
     chol6p_solve(J, mR, d);
-    const double phi0 = potential<F>(cf, sig, str, f);
     double slope = 0.0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) slope += Rv[i] * d[i];
@@ -277,8 +290,8 @@ k_constitutive(long long N, const double* __restrict__ eps, const double* __rest
     const int its = return_map<F>(cf, str, f, sig);
     if (its < 0) atomicAdd(fail, 1);
     // tangent at the root, crystal frame
-    double Rv[6], J[21];
-    resjac<F>(cf, sig, str, f, Rv, J);
+    double Rv[6], J[21], phi_root;
+    resjac<F>(cf, sig, str, f, Rv, J, &phi_root);
     double K[21];
     if (chol6p(J)) chol6p_inverse(J, K);
     else {
@@ -295,7 +308,7 @@ k_constitutive(long long N, const double* __restrict__ eps, const double* __rest
       double el = 0.0;
 #pragma unroll
       for (int i = 0; i < 6; ++i) el += str[i] * Ss[i];
-      comp(gw, N, 0, b8) = gphi * (0.5 * el - potential<F>(cf, sig, str, f));
+      comp(gw, N, 0, b8) = gphi * (0.5 * el - phi_root);
     }
     // back to the sample frame: sigma = Rm sig Rm^T; gK = g(phi) Q K Q^T with Q the
     // Mandel form of the rotation, Q_IJ = (w_I / w_J) (R_ik R_jl + [k != l] R_il R_jk)
