@@ -1349,22 +1349,27 @@ int run_increment(rve_s* h, const double de_in[6], const double* dsig, int mask,
       if (h->ps_rec) launch_plane_recover(N, h->deps, h->ps_rec, st);
       launch_slope(N, h->sig, h->deps, h->phi_prev, h->d.k_res, h->partial, st);
       launch_reduce(h->partial, voxel_grid(N), 1, 0, h->scal + SC_MISC, st);
-      if ((rc = sync_read(h, SC_MISC, 1))) return rc;
+      s.ms_mech_krylov += now_ms() - tk;
+      // backtracking on the incremental energy; its first trial (t = 1) is evaluated
+      // whatever the slope, so it is enqueued before the host reads the slope, and one
+      // round trip returns the slope, the trial's sums (and the macro strain increment)
+      tc = now_ms();
+      o.constitutive(h->deps, 1.0, h->phi_prev);
+      static_assert(SC_K == 0 && SC_MISC > SC_K + 28 && SC_DE > SC_MISC, "scalar slot order");
+      if ((rc = sync_read(h, SC_K, (mask ? SC_DE + 6 : SC_MISC + 1) - SC_K))) return rc;
       double slope = h->hs[SC_MISC] * invN;
       double dE[6] = {0, 0, 0, 0, 0, 0};
       if (mask) {
-        if ((rc = sync_read(h, SC_DE, 6))) return rc;
         for (int c = 0; c < 6; ++c) dE[c] = h->hs[SC_DE + c];
         slope += ext(dE, 0.0, nullptr);          // - sigma*_F . dE_F
       }
-      s.ms_mech_krylov += now_ms() - tk;
-      // backtracking on the incremental energy
-      tc = now_ms();
       double t = 1.0, Pit = 0.0;
       bool acc = false;
       for (int ls = 0; ls < 40; ++ls) {
-        o.constitutive(h->deps, t, h->phi_prev);
-        if ((rc = sync_read(h, SC_K, 28))) return rc;
+        if (ls > 0) {
+          o.constitutive(h->deps, t, h->phi_prev);
+          if ((rc = sync_read(h, SC_K, 28))) return rc;
+        }
         Pit = h->hs[SC_K + 21] * invN + ext(Ecur, t, dE);
         if (Pit - Pi <= 1e-4 * t * slope + 1e-13 * std::fabs(Pi)) { acc = true; break; }
         t *= 0.5;

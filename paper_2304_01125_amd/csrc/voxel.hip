@@ -260,13 +260,10 @@ k_constitutive(long long N, const double* __restrict__ eps, const double* __rest
   const unsigned v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v < N) {
     const unsigned b8 = v * 8u, bR = v * (unsigned)sizeof(R);
-    // grain rotation crystal -> sample (9 values, kept through the return map)
-    double Rm[9];
-    {
-      const double* gR = gtab + (long long)comp(grain, N, 0, v * 4u) * GT_STRIDE + GT_R;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) Rm[i] = gR[i];
-    }
+    // grain rotation crystal -> sample: read before the return map and again after it
+    // (the second read through an offset the compiler cannot see through, so that the
+    // nine values are not held in registers across the Newton iteration)
+    const double* gR = gtab + (long long)comp(grain, N, 0, v * 4u) * GT_STRIDE + GT_R;
     double e[6], ep[6], s0[6], de[6], ec[6], str[6], sig[6];
     load6o(eps, N, b8, e);
     if (deps) {
@@ -279,16 +276,25 @@ k_constitutive(long long N, const double* __restrict__ eps, const double* __rest
 #pragma unroll
     for (int c = 0; c < 6; ++c) e[c] -= ep[c];
     {
-      double tc[6];
-      to_crystal(Rm, e, tc);
+      double Rm0[9], tc[6];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Rm0[i] = gR[i];
+      to_crystal(Rm0, e, tc);
       to_mandel(tc, ec);
-      to_crystal(Rm, s0, tc);
+      to_crystal(Rm0, s0, tc);
       to_mandel(tc, sig);
     }
     cubic_mul(cf.c11, cf.c12, cf.c66, ec, str);
     const Flow f = make_flow(m, comp(gslip, N, 0, b8));
     const int its = return_map<F>(cf, str, f, sig);
     if (its < 0) atomicAdd(fail, 1);
+    double Rm[9];
+    {
+      int roff = 0;
+      asm volatile("" : "+v"(roff));
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Rm[i] = gR[i + roff];
+    }
     // tangent at the root, crystal frame
     double Rv[6], J[21], phi_root;
     resjac<F>(cf, sig, str, f, Rv, J, &phi_root);
