@@ -18,8 +18,10 @@ increments; the other passes timed in isolation), the FP64 rate of the same incr
 paper's GMRES(30) in place of CG, with the rotated-scheme discrete derivative and under uniaxial stress (mixed macroscopic control),
 a short serving run (a 40-request seeded stream of 32^3-96^3 solves: mixed-precision
 server against serial FP64 solves, solves/s and p50/p99 latency), the FP64 rate of the same grid with the
-paper's thermally activated flow rule and Table 1 material in yielding increments, and
-the CPU oracle timed on a bounded sample.
+paper's thermally activated flow rule and Table 1 material in yielding increments (also
+with the GND-coupled Taylor strength), the headline increments with finite-strain
+kinematics, a 256 x 256 x 1 plate in pointwise plane stress, and the CPU oracle timed on a
+bounded sample.
 """
 import argparse
 import dataclasses
@@ -67,6 +69,12 @@ def parse():
     ap.add_argument("--pass-reps", type=int, default=20)
     ap.add_argument("--no-damage", action="store_true",
                     help="skip the damage leg (phase field active in the timed increments)")
+    ap.add_argument("--no-finite", action="store_true",
+                    help="skip the finite-strain leg (headline grid and load, GMRES(30))")
+    ap.add_argument("--no-gnd", action="store_true",
+                    help="skip the GND-coupled hardening leg (Table 1 material)")
+    ap.add_argument("--no-plate", action="store_true",
+                    help="skip the plane-stress plate leg (256 x 256 x 1)")
     ap.add_argument("--damage-gcrit-pow", type=int, default=10,
                     help="the damage leg's G_crit = 4 J/m^2 / 2^k")
     ap.add_argument("--damage-gc", type=float, default=100.0,
@@ -335,6 +343,84 @@ def rotated_leg(RVE, precision, w, inp, warmup, steps, torch):
             "newton_iters": int(sum(x["newton_iters"] for x in stats))}
 
 
+def _timed(step, warmup, steps, torch):
+    """Warm-up increments, then `steps` timed ones; returns (seconds, Krylov iterations,
+    per-increment stats)."""
+    for k in range(warmup):
+        step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [step(k) for k in range(warmup, warmup + steps)]
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, int(sum(x["krylov_iters"] for x in stats)), stats
+
+
+def finite_leg(RVE, precision, w, inp, warmup, steps, torch, m=30):
+    """The headline grid and load with finite-strain kinematics (F = Fe Fp, first
+    Piola-Kirchhoff stress, the 9-component momentum operator; GMRES(m), the solver these
+    kinematics run with); the macro deformation gradient's yy entry follows the load."""
+    r = RVE(dict(w.desc(), kinematics=1, krylov=1, gmres_restart=m), precision)
+    r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+
+    def step(k):
+        dF = np.zeros(9)
+        dF[4] = inp["deps"][k]
+        return r.step_finite(dF, inp["dt"][k])
+    dt, kry, stats = _timed(step, warmup, steps, torch)
+    r.close()
+    return {"kinematics": f"finite strain, GMRES({m})", "value": round(w.nvox * kry / dt, 1),
+            "unit": "voxel-iters/s (9-component operator)",
+            "ms_per_step": round(1e3 * dt / steps, 2), "krylov_iters": kry,
+            "newton_iters": int(sum(x["newton_iters"] for x in stats))}
+
+
+def gnd_leg(RVE, precision, torch, name="cmsx4-laguerre-128-g512", warmup=2, steps=1):
+    """The Table 1 material's yielding increments with the Taylor strength coupled to the
+    GND density inside the increment (Nye tensor of the trial plastic distortion, resolved
+    by the alternating minimisation)."""
+    from synth import workload, make_inputs
+    w = workload(name)
+    inp = make_inputs(w)
+    r = RVE(dict(w.desc(), gnd_coupling=1), precision)
+    r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+    dt, kry, stats = _timed(lambda k: r.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k]),
+                            warmup, steps, torch)
+    r.close()
+    return {"workload": name, "hardening": "Taylor, GND-coupled within the increment",
+            "value": round(w.nvox * kry / dt, 1), "unit": "voxel-iters/s",
+            "ms_per_step": round(1e3 * dt / steps, 2), "increments": f"{warmup}..{warmup + steps - 1}",
+            "krylov_iters": kry, "newton_iters": int(sum(x["newton_iters"] for x in stats)),
+            "stag_iters": int(sum(x["stag_iters"] for x in stats))}
+
+
+def plate_leg(RVE, precision, torch, warmup=1, steps=4):
+    """A plate of 256 x 256 x 1 voxels (the paper's plate grids) with 64 Voronoi grains in
+    pointwise plane stress under uniaxial load: yy strain controlled, the in-plane xx and
+    xy macro stresses held at zero."""
+    from synth import small_polycrystal, make_inputs
+    w = small_polycrystal(n=(256, 256, 1), n_grains=64, seed=7, amplitude=0.006)
+    inp = make_inputs(w)
+    r = RVE(dict(w.desc(), plane_stress=1), precision)
+    r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+    dt, kry, stats = _timed(lambda k: r.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k],
+                                             dsig6=np.zeros(6), stress_mask=0b100001),
+                            warmup, steps, torch)
+    r.close()
+    return {"grid": list(w.n), "grains": w.n_grains,
+            "control": "plane stress, uniaxial (yy strain; xx, xy macro stress 0)",
+            "value": round(w.nvox * kry / dt, 1), "unit": "voxel-iters/s",
+            "ms_per_step": round(1e3 * dt / steps, 2), "krylov_iters": kry,
+            "newton_iters": int(sum(x["newton_iters"] for x in stats))}
+
+
+def _guarded(fn, *args, **kw):
+    """A widened leg's failure is reported in its own entry; it does not end the run."""
+    try:
+        return fn(*args, **kw)
+    except Exception as e:           # noqa: BLE001 - recorded, not raised
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -414,6 +500,13 @@ def main():
                                    a.damage_gcrit_pow, a.damage_gc)
     if not a.no_material:
         out["material"] = material_leg(RVE, RVE_FP64, torch)
+    if not a.no_finite:
+        out["finite_strain"] = _guarded(finite_leg, RVE, RVE_FP64, w, inp, a.warmup, a.steps,
+                                        torch)
+    if not a.no_gnd:
+        out["gnd_coupled"] = _guarded(gnd_leg, RVE, RVE_FP64, torch)
+    if not a.no_plate:
+        out["plane_stress"] = _guarded(plate_leg, RVE, RVE_FP64, torch)
     if a.serve_requests > 0:
         from paper_2304_01125_amd.serve import serve_benchmark
         out["serving"] = serve_benchmark(a.serve_requests, a.serve_slots, 4, log=lambda m: print(

@@ -31,9 +31,12 @@ of the increment is that of its own end, g_{n+1} = tau_c0 + mu b sqrt(rho_SSD,n+
 rho_GND,n+1), with both densities from the increment's slip (the SSD rate and the
 regularised Nye tensor of the plastic distortion beta_n + d beta, non-local), resolved
 by the alternating minimisation: each pass solves the momentum balance at the current
-strength, recomputes the end-of-increment densities and the strength from its slip,
-and the loop also requires max|g_i - g_{i-1}| / max|g_i - g_n| <= tol (0/0 read as 0);
-G_s then uses rho_GND,n+1.
+strength, recomputes the end-of-increment densities and the strength T(g) from its slip,
+and the loop also requires max|T(g_i) - g_i| / max|T(g_i) - g_n| <= tol (0/0 read as 0);
+G_s then uses rho_GND,n+1.  The next pass's strength is g_i + omega_i (T(g_i) - g_i)
+with Aitken's delta-squared factor (Irons and Tuck; omega_0 = 1/2), since the plain
+update g_(i+1) = T(g_i) (option gnd_relax = 0) can stall in yielding polycrystals; both
+have the same fixed point.
 
 Option ``plane_stress`` (plates one voxel thick, N3 = 1; Sec. 4.1-4.3): the out-of-plane
 stress vanishes at every voxel and the out-of-plane strain is a local unknown
@@ -92,6 +95,8 @@ class OracleRVE:
         self.law = flow_law(d)
         self.taylor = int(d.get("material", 0)) == 1
         self.coupled = self.taylor and bool(d.get("gnd_coupling", 0))
+        self.relax = self.coupled and int(d.get("gnd_relax", 1)) == 1
+        self.relax_omega0 = 0.5
         self.plane = bool(d.get("plane_stress", 0))
         if self.plane and self.grid.n[2] != 1:
             raise ValueError("plane stress needs a grid one voxel thick (N3 = 1)")
@@ -159,6 +164,7 @@ class OracleRVE:
         g_n = self.g.copy()
         slipping = np.isfinite(g_n)
         rho_gnd_new = self.rho_gnd
+        omega, res_prev = self.relax_omega0, None
         mech = solve_mechanics_plane if self.plane else solve_mechanics
         for it in range(d["max_stag"]):
             eps_i, sig, dgam = mech(grid, eps_prev, eps_t, self.degradation(phi_prev), constit,
@@ -193,7 +199,20 @@ class OracleRVE:
                                  np.sqrt(rho_ssd_new + rho_gnd_new), np.inf)
                 r_g = _ratio(np.abs(g_new - self.g)[slipping].max(initial=0.0),
                              np.abs(g_new - g_n)[slipping].max(initial=0.0))
-                self.g = g_new
+                if self.relax:
+                    # Aitken's delta-squared relaxation of the fixed point g = T(g)
+                    # (Irons and Tuck): residual r_i = T(g_i) - g_i over the slipping
+                    # voxels, omega_i = -omega_(i-1) r_(i-1).(r_i - r_(i-1)) / |r_i - r_(i-1)|^2
+                    res = np.where(slipping, g_new - self.g, 0.0)
+                    if it > 0:
+                        dr = res - res_prev
+                        den = float((dr * dr).sum())
+                        if den > 0.0:
+                            omega = -omega * float((res_prev * dr).sum()) / den
+                    res_prev = res
+                    self.g = np.where(slipping, self.g + omega * res, np.inf)
+                else:
+                    self.g = g_new
             eps_prev, phi_prev = eps_i, phi_i
             stats["stag"] = it + 1
             if r_e <= d["tol_stag"] and r_p <= d["tol_stag"] and r_g <= d["tol_stag"]:

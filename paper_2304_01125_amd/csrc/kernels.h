@@ -278,6 +278,14 @@ void launch_taylor_next(long long N, const double* gslip, const double* g_n,
                         const double* rho_ssd_tr, const double* rho_gnd_tr, const int* grain,
                         const double* gtab, double mu_b, double* g_next, double* partial,
                         hipStream_t st);
+// Aitken's delta-squared relaxation of the coupled strength's fixed point g = T(g) (Irons
+// and Tuck), over the voxels that can slip, with r = g_next - g the pass's residual:
+// partial sums of r_prev . (r - r_prev) and |r - r_prev|^2 (2 values; r_prev read as 0 on
+// the first pass), then g <- g + omega r and r_prev <- r
+void launch_aitken_dots(long long N, const double* gslip, const double* g_next,
+                        const double* r_prev, int first, double* partial, hipStream_t st);
+void launch_aitken_relax(long long N, double* gslip, const double* g_next, double* r_prev,
+                         double omega, hipStream_t st);
 // Taylor hardening g = tau_c0 + mu b sqrt(rho_SSD + rho_GND) of the voxels that can slip
 void launch_taylor(long long N, double* gslip, const double* rho_ssd, const double* rho_gnd,
                    const int* grain, const double* gtab, double mu_b, hipStream_t st);

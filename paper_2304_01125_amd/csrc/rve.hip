@@ -332,7 +332,8 @@ struct rve_s {
   long long* slotd = nullptr;
   // GND-coupled hardening option: the strength at t_n, the next pass's strength and the
   // end-of-increment SSD and GND densities of the current pass
-  double *g_n = nullptr, *g_next = nullptr, *rho_ssd_tr = nullptr, *rho_gnd_tr = nullptr;
+  double *g_n = nullptr, *g_next = nullptr, *rho_ssd_tr = nullptr, *rho_gnd_tr = nullptr,
+         *g_res = nullptr;
   // plane-stress option: the condensed effective stress of the in-plane balance (6 N) and
   // the per-voxel recovery of the out-of-plane strain correction, B and r (12 N)
   double *ps_sig = nullptr, *ps_rec = nullptr;
@@ -416,6 +417,7 @@ void layout(rve_s* h) {
   h->partial = fd(partial_count(h->g));
   if (h->d.gnd_coupling) {
     h->g_n = fd(N); h->g_next = fd(N); h->rho_ssd_tr = fd(N); h->rho_gnd_tr = fd(N);
+    h->g_res = fd(N);
   }
   if (h->d.plane_stress) {
     h->ps_sig = fd(6 * N); h->ps_rec = fd(12 * N);
@@ -1316,6 +1318,7 @@ int run_increment(rve_s* h, const double de_in[6], const double* dsig, int mask,
   HIPCHK(hipMemcpyAsync(h->phi_prev, h->phi_t, N * 8, hipMemcpyDeviceToDevice, st));
 
   bool converged = false;
+  double omega = 0.5;        // relaxation of the coupled strength (Aitken; first pass 1/2)
   for (int it = 0; it < h->d.max_stag && !converged; ++it) {
     s.stag_iters = it + 1;
     // ---- momentum balance at phi_prev (Newton + PCG, line search on the energy) ----
@@ -1427,13 +1430,22 @@ int run_increment(rve_s* h, const double de_in[6], const double* dsig, int mask,
         launch_gnd(N, h->rbuf, h->grain, h->gtab, h->Q81, h->d.burgers, h->rho_gnd_tr, st);
         launch_taylor_next(N, h->gslip, h->g_n, h->rho_ssd_tr, h->rho_gnd_tr, h->grain, h->gtab,
                            mc.mu_b, h->g_next, h->partial, st);
-        launch_reduce(h->partial, voxel_grid(N), 2, 1, h->scal + SC_MISC, st);
-        if ((rc = sync_read(h, SC_MISC, 2))) return rc;
+        const int nbv = voxel_grid(N);
+        launch_reduce(h->partial, nbv, 2, 1, h->scal + SC_MISC, st);
+        launch_aitken_dots(N, h->gslip, h->g_next, h->g_res, it == 0, h->partial + 2LL * nbv, st);
+        launch_reduce(h->partial + 2LL * nbv, nbv, 2, 0, h->scal + SC_MISC + 2, st);
+        if ((rc = sync_read(h, SC_MISC, 4))) return rc;
         rg = ratio(h->hs[SC_MISC], h->hs[SC_MISC + 1]);
+        // Aitken's update of the relaxation factor from the last two residuals
+        const double num_w = h->hs[SC_MISC + 2], den_w = h->hs[SC_MISC + 3];
+        if (it > 0 && den_w > 0.0) omega = -omega * num_w / den_w;
       }
+      if (g_debug)
+        std::fprintf(stderr, "  stag pass %d: strain %.3e damage %.3e strength %.3e\n", it, re, rp,
+                     rg);
       if (re <= h->d.tol_stag && rp <= h->d.tol_stag && rg <= h->d.tol_stag) converged = true;
-      else if (coupled)   // the next pass solves the momentum balance at the new strength
-        HIPCHK(hipMemcpyAsync(h->gslip, h->g_next, N * 8, hipMemcpyDeviceToDevice, st));
+      else if (coupled)   // the next pass solves the momentum balance at the relaxed strength
+        launch_aitken_relax(N, h->gslip, h->g_next, h->g_res, omega, st);
     }
   }
   if (!converged) { rc = fail(RVE_E_NOCONV, "alternating minimisation reached max_stag"); goto fail_out; }

@@ -782,6 +782,51 @@ void launch_taylor_next(long long N, const double* gslip, const double* g_n,
                      rho_ssd_tr, rho_gnd_tr, grain, gtab, mu_b, g_next, partial);
 }
 
+// Aitken relaxation of the coupled strength (see launch_aitken_dots in kernels.h).
+__global__ void __launch_bounds__(256) k_aitken_dots(
+    long long N, const double* __restrict__ gslip, const double* __restrict__ g_next,
+    const double* __restrict__ r_prev, int first, double* __restrict__ partial) {
+  double s[2] = {0.0, 0.0};
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x) {
+    const double g = gslip[v];
+    if (!isfinite(g)) continue;
+    const double r = g_next[v] - g;
+    const double rp = first ? 0.0 : r_prev[v];
+    const double dr = r - rp;
+    s[0] += rp * dr;
+    s[1] += dr * dr;
+  }
+  block_partials<2, false>(s, partial);
+}
+
+__global__ void __launch_bounds__(256) k_aitken_relax(
+    long long N, double* __restrict__ gslip, const double* __restrict__ g_next,
+    double* __restrict__ r_prev, double omega) {
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x) {
+    const double g = gslip[v];
+    if (!isfinite(g)) {
+      r_prev[v] = 0.0;
+      continue;
+    }
+    const double r = g_next[v] - g;
+    gslip[v] = g + omega * r;
+    r_prev[v] = r;
+  }
+}
+
+void launch_aitken_dots(long long N, const double* gslip, const double* g_next,
+                        const double* r_prev, int first, double* partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_aitken_dots, dim3(voxel_grid(N)), dim3(256), 0, st, N, gslip, g_next,
+                     r_prev, first, partial);
+}
+void launch_aitken_relax(long long N, double* gslip, const double* g_next, double* r_prev,
+                         double omega, hipStream_t st) {
+  hipLaunchKernelGGL(k_aitken_relax, dim3(voxel_grid(N)), dim3(256), 0, st, N, gslip, g_next,
+                     r_prev, omega);
+}
+
 // Taylor hardening (Sec. 2.1): g = tau_c0 + mu b sqrt(rho_SSD + rho_GND) from the
 // committed densities; voxels that cannot slip (g = inf) keep their strength.
 __global__ void __launch_bounds__(256) k_taylor(long long N, double* __restrict__ gslip,

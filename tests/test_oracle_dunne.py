@@ -262,3 +262,29 @@ def test_gnd_coupled_polycrystal_is_a_fixed_point():
         assert np.abs(oc.rho_gnd - rg).max() <= 1e-9 * max(rg.max(), 1.0)
     assert oc.rho_gnd.max() > 1e-3 * oc.rho_ssd.max()
     assert np.abs(oc.g - ol.g).max() > 1e-6 * oc.g.max()
+
+
+def test_gnd_coupled_relaxation_reaches_the_plain_iterations_fixed_point():
+    """The coupled strength is resolved with Aitken's delta-squared relaxation of the
+    fixed point g = T(g) (Irons and Tuck); the fixed point does not depend on how it is
+    reached: where the plain alternating iteration converges, the relaxed one reaches the
+    same strength, stress and strain, in no more passes."""
+    w = small_polycrystal(n=(8, 8, 8), n_grains=3, seed=5, cycles=1, incs_per_cycle=20,
+                          **cmsx4()).parity()
+    inp = make_inputs(w)
+    base = dict(w.desc(), gnd_coupling=1, tol_stag=1e-9)
+    orx = OracleRVE(base, inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+    opl = OracleRVE(dict(base, gnd_relax=0), inp["grain"], inp["quat"], inp["tau_c0"],
+                    inp["phi0"])
+    assert orx.relax and not opl.relax
+    passes = [0, 0]
+    for k in range(4):
+        de = np.array([0.0, inp["deps"][k], 0, 0, 0, 0])
+        sr = orx.step(de, inp["dt"][k])
+        sp = opl.step(de, inp["dt"][k])
+        passes[0] += sr["stag"]
+        passes[1] += sp["stag"]
+        assert np.abs(orx.g - opl.g).max() <= 1e-7 * np.abs(opl.g - opl.tau0).max(), k
+        assert np.abs(orx.sig - opl.sig).max() <= 1e-7 * np.abs(opl.sig).max(), k
+        assert np.abs(orx.eps - opl.eps).max() <= 1e-7 * np.abs(opl.eps).max(), k
+    assert passes[0] <= passes[1], passes
