@@ -397,8 +397,8 @@ def plate_leg(RVE, precision, torch, warmup=1, steps=4):
     """A plate of 256 x 256 x 1 voxels (the paper's plate grids) with 64 Voronoi grains in
     pointwise plane stress under uniaxial load: yy strain controlled, the in-plane xx and
     xy macro stresses held at zero."""
-    from synth import small_polycrystal, make_inputs
-    w = small_polycrystal(n=(256, 256, 1), n_grains=64, seed=7, amplitude=0.006)
+    from synth import workload, make_inputs
+    w = workload("plate-256-g64")
     inp = make_inputs(w)
     r = RVE(dict(w.desc(), plane_stress=1), precision)
     r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
@@ -406,7 +406,7 @@ def plate_leg(RVE, precision, torch, warmup=1, steps=4):
                                              dsig6=np.zeros(6), stress_mask=0b100001),
                             warmup, steps, torch)
     r.close()
-    return {"grid": list(w.n), "grains": w.n_grains,
+    return {"workload": w.name, "grid": list(w.n), "grains": w.n_grains,
             "control": "plane stress, uniaxial (yy strain; xx, xy macro stress 0)",
             "value": round(w.nvox * kry / dt, 1), "unit": "voxel-iters/s",
             "ms_per_step": round(1e3 * dt / steps, 2), "krylov_iters": kry,

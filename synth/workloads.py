@@ -192,6 +192,10 @@ WORKLOADS = {
     "voronoi-256-g4096-hard": Workload(name="voronoi-256-g4096-hard", n=(256, 256, 256),
                                        n_grains=4096, seed=3, amplitude=0.007, ratio=0,
                                        cycles=2, incs_per_cycle=16, hard_fraction=0.05),
+    # a plate one voxel thick (the paper's plate grids, Secs. 4.1-4.3), 64 Voronoi grains,
+    # for pointwise plane stress under uniaxial load
+    "plate-256-g64": Workload(name="plate-256-g64", n=(256, 256, 1), n_grains=64, seed=7,
+                              amplitude=0.006, ratio=0, cycles=3, incs_per_cycle=20),
     # thermally activated flow with Taylor hardening (Table 1): 16^3 Voronoi, 4 grains
     # (the oracle takes about a minute for the first six increments at tight tolerances)
     "cmsx4-voronoi-16-g4": Workload(name="cmsx4-voronoi-16-g4", n=(16, 16, 16), n_grains=4,

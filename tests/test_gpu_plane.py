@@ -104,3 +104,49 @@ def test_out_of_plane_macro_control_is_refused():
     st = gpu.step([0, 1e-4, 0, 0, 0, 0], 1.0, dsig6=np.zeros(6), stress_mask=UNIAXIAL_PLATE)
     assert abs(st["macro_strain"][1] - 1e-4) <= 1e-15
     gpu.close()
+
+
+def test_paper_plate_matches_stored_oracle_at_production_tolerances():
+    """The paper's plate grid (256 x 256 x 1, 64 grains; Secs. 4.1-4.3) in pointwise plane
+    stress under uniaxial load at the production tolerances, FP64 and mixed precision,
+    against the stored oracle run (tests/golden/make_golden.py plate256): the macro stress
+    and strain of every stored increment (FP64 1e-5, mixed 1e-4), sampled strain and stress
+    after the first and the last, and zero out-of-plane stress.  The Newton counts differ
+    (printed): the oracle solves the plane-stress condition inside every constitutive
+    evaluation, the GPU condenses it in each Newton step, and both stop at the same
+    solution."""
+    import os
+    from paper_2304_01125_amd import RVE, RVE_FP64, RVE_MIXED
+    from synth import workload
+    ref = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                               "plate256.npz"))
+    last = int(ref["last"])
+    w = workload("plate-256-g64")
+    inp = make_inputs(w)
+    idx = ref["sample"]
+    for prec, bar in ((RVE_FP64, 1e-5), (RVE_MIXED, 1e-4)):
+        gpu = RVE(dict(w.desc(), plane_stress=1), prec)
+        gpu.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+        for k in range(last + 1):
+            st = gpu.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k], dsig6=np.zeros(6),
+                          stress_mask=UNIAXIAL_PLATE)
+            ms, me = ref["macro_stress"][k], ref["macro_strain"][k]
+            es = np.abs(np.array(st["macro_stress"]) - ms).max() / np.abs(ms).max()
+            ee = np.abs(np.array(st["macro_strain"]) - me).max() / np.abs(me).max()
+            print(f"  precision {prec} inc {k}: newton {st['newton_iters']} (oracle "
+                  f"{int(ref['newton'][k])}) macro stress {es:.2e} strain {ee:.2e}", flush=True)
+            assert es <= bar and ee <= bar, (prec, k, es, ee)
+            if f"inc{k}_stress" in ref.files:
+                f = gpu.fields(("strain", "stress"))
+                for name in ("strain", "stress"):
+                    a, b = f[name][idx], ref[f"inc{k}_{name}"]
+                    fe = np.linalg.norm(a - b) / np.linalg.norm(b)
+                    print(f"    inc {k} {name} at {len(idx)} sampled voxels: {fe:.2e}", flush=True)
+                    assert fe <= bar, (prec, k, name, fe)
+        # the last Newton step condenses the linearised point; at the production stop
+        # test (steps of 5e-3 of the increment) it leaves a second-order out-of-plane
+        # residual (observed 2.7e-8 FP64), where the parity runs above reach 1e-10
+        oop = _out_of_plane(gpu)
+        print(f"    out-of-plane stress {oop:.2e} of the largest component", flush=True)
+        assert oop <= 1e-6
+        gpu.close()
