@@ -223,30 +223,6 @@ def plate256(n_inc=6, n_sample=4096):
                         **{k2: np.asarray(v) for k2, v in out.items()})
 
 
-def voronoi256(n_inc=1, n_sample=4096):
-    """The 256^3 workload (4096 Voronoi grains, 5 % hard) at the production tolerances:
-    macro stress and Newton count of its first increment and sampled strain and stress
-    after it (about an hour of this oracle on 8 cores, ~20 GB of host memory)."""
-    w = workload("voronoi-256-g4096-hard")
-    inp = make_inputs(w)
-    o = OracleRVE(w.desc(), inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
-    idx = np.sort(np.random.default_rng(2560).choice(w.nvox, n_sample, replace=False))
-    out = {"sample": idx, "macro_stress": [], "newton": [], "stag": []}
-    t0 = time.time()
-    for k in range(n_inc):
-        st = o.step([0, inp["deps"][k], 0, 0, 0, 0], inp["dt"][k])
-        print(f"inc {k}: {time.time() - t0:.0f}s newton {st['newton']} matvecs {st['matvecs']} "
-              f"stag {st['stag']}", flush=True)
-        out["macro_stress"].append(st["macro_stress"])
-        out["newton"].append(st["newton"])
-        out["stag"].append(st["stag"])
-        f = o.fields()
-        for name in ("strain", "stress"):
-            out[f"inc{k}_{name}"] = f[name][idx]
-        np.savez_compressed(os.path.join(HERE, "voronoi256.npz"), last=k,
-                            **{k2: np.asarray(v) for k2, v in out.items()})
-
-
 if __name__ == "__main__":
     for name in sys.argv[1:] or ["notched16", "voronoi64", "cmsx4_16", "finite16"]:
         globals()[name]()
