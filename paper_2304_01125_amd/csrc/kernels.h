@@ -253,12 +253,15 @@ enum { RED_CONST = 28,  // 21 sum gK, 1 sum g*w, 6 sum g*sigma
 
 int voxel_grid(long long n);
 
+// Returns the number of block partials written (RED_CONST components, component-major) for
+// launch_reduce: one per 256-voxel block of the return map, whose kernel forms them, or, with
+// plane stress (the sums follow the condensation), those of a separate pass.
 template <typename R>
-void launch_constitutive(long long N, const double* eps, const double* deps, double t,
-                         const double* epsp, const double* gslip, const int* grain,
-                         const double* gtab, double* sig, const double* phi, R* gK, double* gw,
-                         const CrystalFrame& cf, const Material& m, double* partial, int* fail,
-                         hipStream_t st, double* ps_sig = nullptr, double* ps_rec = nullptr);
+int launch_constitutive(long long N, const double* eps, const double* deps, double t,
+                        const double* epsp, const double* gslip, const int* grain,
+                        const double* gtab, double* sig, const double* phi, R* gK, double* gw,
+                        const CrystalFrame& cf, const Material& m, double* partial, int* fail,
+                        hipStream_t st, double* ps_sig = nullptr, double* ps_rec = nullptr);
 // plane stress: d e_O = -B d e_P - r on the Newton correction, from the per-voxel B and r
 // that the constitutive launch's condensation left in rec (12 N)
 void launch_plane_recover(long long N, double* deps, const double* rec, hipStream_t st);

@@ -384,7 +384,12 @@ long long cg_partial_offset(const Grid& g) {
   const long long need = (max_div_partials(g) + 63) / 64 * 64;
   return need > kCgPartialMin ? need : kCgPartialMin;
 }
-long long partial_count(const Grid& g) { return cg_partial_offset(g) + kMaxRedBlocks * 16; }
+// (also the return map's per-block constitutive sums: RED_CONST per 256-voxel block)
+long long partial_count(const Grid& g) {
+  const long long base = cg_partial_offset(g) + kMaxRedBlocks * 16;
+  const long long sums = (long long)RED_CONST * ((g.nvox + 255) / 256);
+  return base > sums ? base : sums;
+}
 
 
 
@@ -923,10 +928,10 @@ struct Ops {
   int constitutive(const double* deps, double t, const double* phi) {
     Material m = mat(0.0);
     m.dt = cur_dt;
-    launch_constitutive<R>(N, h->eps, deps, t, h->epsp, h->gslip, h->grain, h->gtab, h->sig, phi,
-                           gK(), h->gw, h->cf, m, h->partial, h->failc, st, h->ps_sig,
-                           h->ps_rec);
-    launch_reduce(h->partial, voxel_grid(N), RED_CONST, 0, h->scal + SC_K, st);
+    const int nb = launch_constitutive<R>(N, h->eps, deps, t, h->epsp, h->gslip, h->grain,
+                                          h->gtab, h->sig, phi, gK(), h->gw, h->cf, m,
+                                          h->partial, h->failc, st, h->ps_sig, h->ps_rec);
+    launch_reduce(h->partial, nb, RED_CONST, 0, h->scal + SC_K, st);
     return RVE_OK;
   }
   double cur_dt = 0.0;

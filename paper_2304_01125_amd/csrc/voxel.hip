@@ -255,9 +255,14 @@ k_constitutive(long long N, const double* __restrict__ eps, const double* __rest
                double t, const double* __restrict__ epsp, const double* __restrict__ gslip,
                const int* __restrict__ grain, const double* __restrict__ gtab,
                double* __restrict__ sig_io, const double* __restrict__ phi, R* __restrict__ gK,
-               double* __restrict__ gw, CrystalFrame cf, Material m, int* __restrict__ fail) {
+               double* __restrict__ gw, CrystalFrame cf, Material m, int* __restrict__ fail,
+               double* __restrict__ sums) {
   // one voxel per thread (N < 2^29, so byte offsets fit 32 bits)
   const unsigned v = blockIdx.x * blockDim.x + threadIdx.x;
+  // with sums: the block partials of the constitutive sums (sum gK as stored, sum g w,
+  // sum g(phi) sigma; the layout of k_const_sums), formed from the values as they are
+  // written instead of a second pass over the fields
+  double acc[RED_CONST];
   if (v < N) {
     const unsigned b8 = v * 8u, bR = v * (unsigned)sizeof(R);
     // grain rotation crystal -> sample: read before the return map and again after it
@@ -314,7 +319,9 @@ k_constitutive(long long N, const double* __restrict__ eps, const double* __rest
       double el = 0.0;
 #pragma unroll
       for (int i = 0; i < 6; ++i) el += str[i] * Ss[i];
-      comp(gw, N, 0, b8) = gphi * (0.5 * el - phi_root);
+      const double wv = gphi * (0.5 * el - phi_root);
+      comp(gw, N, 0, b8) = wv;
+      acc[21] = wv;
     }
     // back to the sample frame: sigma = Rm sig Rm^T; gK = g(phi) Q K Q^T with Q the
     // Mandel form of the rotation, Q_IJ = (w_I / w_J) (R_ik R_jl + [k != l] R_il R_jk)
@@ -324,7 +331,10 @@ k_constitutive(long long N, const double* __restrict__ eps, const double* __rest
       from_mandel(sig, tc);
       to_sample(Rm, tc, st);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) comp(sig_io, N, c, b8) = st[c];
+      for (int c = 0; c < 6; ++c) {
+        comp(sig_io, N, c, b8) = st[c];
+        acc[22 + c] = gphi * st[c];
+      }
     }
     double Q[36];
     {
@@ -356,10 +366,16 @@ k_constitutive(long long N, const double* __restrict__ eps, const double* __rest
         double a = 0.0;
 #pragma unroll
         for (int l = 0; l < 6; ++l) a += u[l] * Q[j * 6 + l];
-        comp(gK, N, pk(i, j), bR) = (R)(gphi * a);
+        const R kv = (R)(gphi * a);
+        comp(gK, N, pk(i, j), bR) = kv;
+        acc[pk(i, j)] = (double)kv;
       }
     }
+  } else {
+#pragma unroll
+    for (int c = 0; c < RED_CONST; ++c) acc[c] = 0.0;
   }
+  if (sums) block_partials<RED_CONST, false>(acc, sums);
 }
 
 // ---------------------------------------------------------------------------
@@ -511,30 +527,34 @@ k_const_sums(long long N, const R* __restrict__ gK, const double* __restrict__ g
 }
 
 template <typename R>
-void launch_constitutive(long long N, const double* eps, const double* deps, double t,
-                         const double* epsp, const double* gslip, const int* grain,
-                         const double* gtab, double* sig, const double* phi, R* gK, double* gw,
-                         const CrystalFrame& cf, const Material& m, double* partial, int* fail,
-                         hipStream_t st, double* ps_sig, double* ps_rec) {
-  const long long nb = (N + 255) / 256;
+int launch_constitutive(long long N, const double* eps, const double* deps, double t,
+                        const double* epsp, const double* gslip, const int* grain,
+                        const double* gtab, double* sig, const double* phi, R* gK, double* gw,
+                        const CrystalFrame& cf, const Material& m, double* partial, int* fail,
+                        hipStream_t st, double* ps_sig, double* ps_rec) {
+  const int nb = (int)((N + 255) / 256);
+  // plane stress condenses the tangent after the return map: its sums take a pass of
+  // their own after the condensation
+  double* fused = ps_sig ? nullptr : partial;
   if (m.flow == FLOW_DUNNE)
-    hipLaunchKernelGGL((k_constitutive<R, FLOW_DUNNE>), dim3((int)(nb < 1 ? 1 : nb)), dim3(256), 0,
-                       st, N, eps, deps, t, epsp, gslip, grain, gtab, sig, phi, gK, gw, cf, m, fail);
+    hipLaunchKernelGGL((k_constitutive<R, FLOW_DUNNE>), dim3(nb < 1 ? 1 : nb), dim3(256), 0, st, N,
+                       eps, deps, t, epsp, gslip, grain, gtab, sig, phi, gK, gw, cf, m, fail, fused);
   else
-    hipLaunchKernelGGL((k_constitutive<R, FLOW_POWER>), dim3((int)(nb < 1 ? 1 : nb)), dim3(256), 0,
-                       st, N, eps, deps, t, epsp, gslip, grain, gtab, sig, phi, gK, gw, cf, m, fail);
-  if (ps_sig)
-    hipLaunchKernelGGL((k_plane_condense<R>), dim3(voxel_grid(N)), dim3(256), 0, st, N, gK, sig,
-                       phi, m.kres, ps_sig, ps_rec, fail);
+    hipLaunchKernelGGL((k_constitutive<R, FLOW_POWER>), dim3(nb < 1 ? 1 : nb), dim3(256), 0, st, N,
+                       eps, deps, t, epsp, gslip, grain, gtab, sig, phi, gK, gw, cf, m, fail, fused);
+  if (fused) return nb < 1 ? 1 : nb;
+  hipLaunchKernelGGL((k_plane_condense<R>), dim3(voxel_grid(N)), dim3(256), 0, st, N, gK, sig,
+                     phi, m.kres, ps_sig, ps_rec, fail);
   hipLaunchKernelGGL((k_const_sums<R>), dim3(voxel_grid(N)), dim3(256), 0, st, N, gK, gw, sig,
                      phi, m.kres, partial);
+  return voxel_grid(N);
 }
-template void launch_constitutive<double>(long long, const double*, const double*, double,
+template int launch_constitutive<double>(long long, const double*, const double*, double,
                                           const double*, const double*, const int*, const double*,
                                           double*, const double*, double*, double*,
                                           const CrystalFrame&, const Material&, double*, int*,
                                           hipStream_t, double*, double*);
-template void launch_constitutive<float>(long long, const double*, const double*, double,
+template int launch_constitutive<float>(long long, const double*, const double*, double,
                                          const double*, const double*, const int*, const double*,
                                          double*, const double*, float*, double*,
                                          const CrystalFrame&, const Material&, double*, int*,

@@ -141,6 +141,8 @@ def test_cg_partials_do_not_overlap_the_divergence_partials(n):
         assert max_div >= 3 * (n[0] // 16) * n[1] + 1
         assert cg_off >= max_div
         assert length >= cg_off + 2 * 1024
+        # the return map's block partials of the 28 constitutive sums, one per 256 voxels
+        assert length >= 28 * ((n[0] * n[1] * n[2] + 255) // 256)
     bad = p.make_desc(dict(workload("notched-crystal-16").desc(), n=(10, 2, 2)))
     assert lib.rve_diag_partials(ctypes.byref(bad), (ctypes.c_int64 * 3)()) == p.RVE_E_ARG
 
