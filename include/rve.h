@@ -381,6 +381,28 @@ int rve_diag_pass_time(struct rve_s* h, int64_t* launches, double* total_ms);
 int rve_pool_step(struct rve_s* const* handles, int32_t n, const double* deps, const double* dt,
                   int32_t* status, rve_stats* stats);
 
+/* Serving pool: many handles in one device arena owned by the caller (kept alive until
+ * rve_pool_destroy), for servers that admit and retire solves continuously without a
+ * device allocation per request.  A handle created in the pool takes its footprint
+ * (rve_footprint_bytes, rounded up to 256 bytes) from the first free range of the arena
+ * that holds it, and rve_destroy returns the range; neighbouring free ranges merge.
+ * Admission by memory is the create call: RVE_E_NOMEM when no free range fits (the
+ * message gives the size and the largest free range).  Pool calls are thread-safe; the
+ * handles are used as any handle (one thread at a time each) and may be stepped together
+ * with rve_pool_step. */
+struct rve_pool_s;
+/* dev_arena of arena_bytes bytes (aligned up to 256 bytes here).  Errors: RVE_E_ARG (null
+ * arena or output, or less than 256 usable bytes). */
+int rve_pool_create(void* dev_arena, size_t arena_bytes, struct rve_pool_s** out);
+/* As rve_create, with the arena range taken from the pool.  Errors: those of rve_create,
+ * RVE_E_NOMEM (no free range fits). */
+int rve_create_in_pool(struct rve_pool_s* pool, const rve_desc* d, void* hip_stream,
+                       struct rve_s** out);
+/* Free bytes of the pool, and in *largest_range (if not NULL) its largest free range. */
+size_t rve_pool_free_bytes(struct rve_pool_s* pool, size_t* largest_range);
+/* Releases the pool (not the arena).  Errors: RVE_E_STATE while handles of it are alive. */
+int rve_pool_destroy(struct rve_pool_s* pool);
+
 typedef struct rve_s* rve_t;
 
 #ifdef __cplusplus

@@ -9,7 +9,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <new>
 #include <condition_variable>
 #include <mutex>
 #include <string>
@@ -316,6 +318,8 @@ struct rve_s {
   double* hs = nullptr;   // pinned host scalars
   bool micro = false;
   int static_dev = -1;    // >= 0: the arena is that device's static scratch array
+  struct rve_pool_s* pool = nullptr;   // the serving pool whose arena holds this one's
+  size_t pool_off = 0, pool_len = 0;
   double hs_static[544];  // host scalars of a static-arena handle (no pinned allocation)
   // finite-strain kinematics (rve_desc.kinematics == RVE_KIN_FINITE): deformation gradient
   // at t + dt, at t and at the previous alternating pass, the Newton correction, the
@@ -2122,6 +2126,12 @@ int rve_fields(rve_s* h, uint32_t mask, double* out, size_t n) {
   return RVE_OK;
 }
 
+}  // extern "C"
+namespace {
+void pool_release(rve_pool_s* p, size_t off, size_t len);
+}
+extern "C" {
+
 int rve_destroy(rve_s* h) {
   if (!h) return RVE_OK;
   if (h->st) (void)hipStreamSynchronize(h->st);
@@ -2140,7 +2150,10 @@ int rve_destroy(rve_s* h) {
     return RVE_OK;
   }
   if (h->hs) (void)hipHostFree(h->hs);
+  rve_pool_s* pool = h->pool;
+  const size_t off = h->pool_off, len = h->pool_len;
   delete h;
+  if (pool) pool_release(pool, off, len);
   return RVE_OK;
 }
 
@@ -2392,3 +2405,117 @@ bool make_axis_plan(int n, AxisPlan* out) {
   return m == 1;
 }
 }  // namespace rvefft
+
+// ---- serving pool: one caller-owned device arena shared by many handles -------------
+// First fit over the free ranges of the arena (256-byte granules); a handle created in the
+// pool takes its footprint from it and gives it back at rve_destroy, where neighbouring
+// free ranges merge again.
+struct rve_pool_s {
+  char* base = nullptr;
+  size_t bytes = 0;
+  std::mutex mu;
+  std::map<size_t, size_t> free_;   // offset -> length of each free range
+  int live = 0;
+};
+
+namespace {
+void pool_release(rve_pool_s* p, size_t off, size_t len) {
+  std::lock_guard<std::mutex> lk(p->mu);
+  auto next = p->free_.lower_bound(off);
+  if (next != p->free_.end() && off + len == next->first) {
+    len += next->second;
+    next = p->free_.erase(next);
+  }
+  if (next != p->free_.begin()) {
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      prev->second += len;
+      --p->live;
+      return;
+    }
+  }
+  p->free_[off] = len;
+  --p->live;
+}
+}  // namespace
+
+extern "C" {
+
+int rve_pool_create(void* dev_arena, size_t arena_bytes, rve_pool_s** out) {
+  if (!out) return fail(RVE_E_ARG, "null output");
+  *out = nullptr;
+  if (!dev_arena) return fail(RVE_E_ARG, "null arena");
+  const uintptr_t b = (uintptr_t)dev_arena, a = (b + 255) & ~(uintptr_t)255;
+  if (arena_bytes < (a - b) + 256) return fail(RVE_E_ARG, "arena smaller than one granule");
+  const size_t len = (arena_bytes - (a - b)) & ~(size_t)255;
+  rve_pool_s* p = new (std::nothrow) rve_pool_s;
+  if (!p) return fail(RVE_E_NOMEM, "host allocation failed");
+  p->base = (char*)a;
+  p->bytes = len;
+  p->free_[0] = len;
+  *out = p;
+  return RVE_OK;
+}
+
+int rve_create_in_pool(rve_pool_s* pool, const rve_desc* d, void* hip_stream, rve_s** out) {
+  if (!pool || !out) return fail(RVE_E_ARG, "null pool or output");
+  *out = nullptr;
+  const int rc0 = validate(d);
+  if (rc0) return rc0;
+  const size_t need = align_up(rve_footprint_bytes(d));
+  size_t off = 0;
+  bool found = false;
+  size_t largest = 0;
+  {
+    std::lock_guard<std::mutex> lk(pool->mu);
+    for (auto it = pool->free_.begin(); it != pool->free_.end(); ++it) {
+      largest = std::max(largest, it->second);
+      if (it->second >= need) {
+        off = it->first;
+        const size_t rest = it->second - need;
+        pool->free_.erase(it);
+        if (rest) pool->free_[off + need] = rest;
+        found = true;
+        ++pool->live;
+        break;
+      }
+    }
+  }
+  if (!found)
+    return fail(RVE_E_NOMEM, "no free range of " + std::to_string(need) +
+                                 " bytes in the pool (largest " + std::to_string(largest) + ")");
+  const int rc = rve_create(d, pool->base + off, need, hip_stream, out);
+  if (rc) {
+    pool_release(pool, off, need);
+    return rc;
+  }
+  (*out)->pool = pool;
+  (*out)->pool_off = off;
+  (*out)->pool_len = need;
+  return RVE_OK;
+}
+
+size_t rve_pool_free_bytes(rve_pool_s* pool, size_t* largest_range) {
+  if (largest_range) *largest_range = 0;
+  if (!pool) return 0;
+  std::lock_guard<std::mutex> lk(pool->mu);
+  size_t tot = 0;
+  for (const auto& r : pool->free_) {
+    tot += r.second;
+    if (largest_range) *largest_range = std::max(*largest_range, r.second);
+  }
+  return tot;
+}
+
+int rve_pool_destroy(rve_pool_s* pool) {
+  if (!pool) return RVE_OK;
+  {
+    std::lock_guard<std::mutex> lk(pool->mu);
+    if (pool->live)
+      return fail(RVE_E_STATE, std::to_string(pool->live) + " handles of the pool are alive");
+  }
+  delete pool;
+  return RVE_OK;
+}
+
+}  // extern "C"

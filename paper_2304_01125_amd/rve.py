@@ -125,6 +125,14 @@ def load():
     lib.rve_pool_step.restype = ctypes.c_int
     lib.rve_pool_step.argtypes = [ctypes.POINTER(_P), ctypes.c_int32, _D, _D,
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(RveStats)]
+    lib.rve_pool_create.restype = ctypes.c_int
+    lib.rve_pool_create.argtypes = [_P, ctypes.c_size_t, ctypes.POINTER(_P)]
+    lib.rve_create_in_pool.restype = ctypes.c_int
+    lib.rve_create_in_pool.argtypes = [_P, ctypes.POINTER(RveDesc), _P, ctypes.POINTER(_P)]
+    lib.rve_pool_free_bytes.restype = ctypes.c_size_t
+    lib.rve_pool_free_bytes.argtypes = [_P, ctypes.POINTER(ctypes.c_size_t)]
+    lib.rve_pool_destroy.restype = ctypes.c_int
+    lib.rve_pool_destroy.argtypes = [_P]
     lib.rve_diag_partials.restype = ctypes.c_int
     lib.rve_diag_partials.argtypes = [ctypes.POINTER(RveDesc), ctypes.POINTER(ctypes.c_int64)]
     lib.rve_step_increment_finite.restype = ctypes.c_int
@@ -144,7 +152,8 @@ def exported_symbols():
             "rve_diag_irfft", "rve_diag_constitutive", "rve_diag_constitutive_finite",
             "rve_diag_operator", "rve_diag_pass",
             "rve_diag_time_pass", "rve_diag_pass_time", "rve_diag_partials",
-            "rve_pool_step"]
+            "rve_pool_step", "rve_pool_create", "rve_create_in_pool", "rve_pool_free_bytes",
+            "rve_pool_destroy"]
 
 
 class RveError(RuntimeError):
@@ -256,14 +265,42 @@ def rve_pool_step(handles, deps, dt):
     return rc, list(status), [s.as_dict() for s in stats]
 
 
+class RvePool:
+    """A serving pool (rve_pool_create): one torch-allocated device arena of budget_bytes
+    from which RVE(..., pool=...) handles take their footprint and to which they return it
+    at close()."""
+
+    def __init__(self, budget_bytes, device=0):
+        import torch
+        lib = load()
+        self.device = torch.device("cuda", device)
+        self.arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        self.h = _P()
+        _check(lib.rve_pool_create(_P(self.arena.data_ptr()), int(budget_bytes),
+                                   ctypes.byref(self.h)))
+
+    def free_bytes(self):
+        """(total free bytes, largest free range)"""
+        largest = ctypes.c_size_t(0)
+        tot = load().rve_pool_free_bytes(self.h, ctypes.byref(largest))
+        return int(tot), int(largest.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(load().rve_pool_destroy(self.h))
+            self.h = None
+
+
 class RVE:
     """One periodic RVE solved on the GPU.  ``desc`` is the flat dict of
     ``synth.Workload.desc()``; precision is RVE_FP64 or RVE_MIXED."""
 
     def __init__(self, desc, precision=RVE_FP64, device=0, stream=None, max_grains=4096,
-                 noalloc=False):
+                 noalloc=False, pool=None):
         """noalloc: create the handle with rve_create_noalloc (the library's static device
-        arena, one such handle per device at a time) instead of a torch-allocated arena."""
+        arena, one such handle per device at a time) instead of a torch-allocated arena;
+        pool: an RvePool whose arena holds the handle (rve_create_in_pool)."""
         import torch
         lib = load()
         self.desc = dict(desc)
@@ -281,6 +318,17 @@ class RVE:
             h = _P()
             _check(lib.rve_create_noalloc(ctypes.byref(self._d), _P(self.stream.cuda_stream),
                                           ctypes.byref(h)))
+            self.h = h
+            self.footprint = nbytes
+            return
+        if pool is not None:
+            torch.cuda.set_device(self.device)
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+            self.arena = None
+            self.pool = pool            # the pool's arena outlives the handle
+            h = _P()
+            _check(lib.rve_create_in_pool(pool.h, ctypes.byref(self._d),
+                                          _P(self.stream.cuda_stream), ctypes.byref(h)))
             self.h = h
             self.footprint = nbytes
             return

@@ -4,7 +4,10 @@ Requests (a microstructure, a grid size and a load history each) arrive over tim
 The server keeps up to `max_slots` solves resident in HBM, admits a waiting request as
 soon as a slot is free and its arena footprint fits the memory budget, and advances
 all resident solves by one load increment per tick with ``rve_pool_step`` (one HIP
-stream per slot, so their kernels overlap on the device).  A request that finishes its
+stream per slot, so their kernels overlap on the device).  With ``use_pool`` the budget is
+one device arena held by the library (``rve_pool_create``): a request is admitted when
+``rve_create_in_pool`` finds a free range for its footprint, and its range returns to the
+pool when its handle is destroyed.  A request that finishes its
 last increment releases its slot and memory at once; newcomers join at the next tick,
 without waiting for the others to finish.  Reported: solves/s, p50/p99 latency
 (arrival to completion) and the same for serial solves.
@@ -45,9 +48,9 @@ def _make(req):
 
 
 class Server:
-    def __init__(self, precision, max_slots=8, budget_bytes=32 << 30, device=0):
+    def __init__(self, precision, max_slots=8, budget_bytes=32 << 30, device=0, use_pool=False):
         import torch
-        from . import load
+        from . import load, RvePool
         load()
         self.torch = torch
         self.precision = precision
@@ -55,11 +58,32 @@ class Server:
         self.budget = budget_bytes
         self.device = torch.device("cuda", device)
         self.streams = [torch.cuda.Stream(self.device) for _ in range(max_slots)]
+        self.pool = RvePool(budget_bytes, device) if use_pool else None
+        self.pool_total = self.pool.free_bytes()[0] if use_pool else 0
+
+    def close(self):
+        if self.pool is not None:
+            self.pool.close()
+            self.pool = None
+
+    def _admit(self, w, slot):
+        """A handle for workload w on the slot's stream, or None when the pool has no free
+        range for it yet; raises RveError(RVE_E_NOMEM) for a request larger than the whole
+        pool, which no release can admit."""
+        from .rve import RVE, RveError, RVE_E_NOMEM
+        if self.pool is None:
+            return RVE(w.desc(), self.precision, stream=self.streams[slot])
+        try:
+            return RVE(w.desc(), self.precision, stream=self.streams[slot], pool=self.pool)
+        except RveError as e:
+            if e.code == RVE_E_NOMEM and self.pool.free_bytes()[0] < self.pool_total:
+                return None
+            raise
 
     def run(self, items, arrivals, keep_fields=False, log=None):
         """items: [(workload, inputs)], arrivals: seconds after start (non-decreasing).
         Returns per-request dicts (latency, status, ...) and the wall time."""
-        from .rve import RVE, rve_pool_step
+        from .rve import RveError, rve_pool_step
         from . import make_desc, rve_footprint_bytes
         torch = self.torch
         n = len(items)
@@ -83,11 +107,20 @@ class Server:
                 i = waiting[0]
                 w, inp = items[i]
                 need = rve_footprint_bytes(make_desc(w.desc(), self.precision))
-                if used + need > self.budget and active:
+                if self.pool is None and used + need > self.budget and active:
+                    break
+                slot = free_slots[0]
+                try:
+                    r = self._admit(w, slot)
+                except RveError as e:           # larger than the whole pool
+                    waiting.pop(0)
+                    out[i] = dict(id=i, n=w.n[0], status=e.code, latency=now - arrivals[i],
+                                  queued=0.0, krylov_iters=0, macro_stress=None, error=str(e))
+                    continue
+                if r is None:
                     break
                 waiting.pop(0)
-                slot = free_slots.pop(0)
-                r = RVE(w.desc(), self.precision, stream=self.streams[slot])
+                free_slots.pop(0)
                 r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
                 used += r.footprint
                 self.peak_used = max(self.peak_used, used)
@@ -136,7 +169,6 @@ class Server:
         request that fits the memory budget, runs its increments on the slot's stream,
         releases its memory and takes the next one; slots never wait for each other."""
         import threading
-        from .rve import RVE
         n = len(items)
         order = list(np.argsort(arrivals, kind="stable"))
         out = [None] * n
@@ -155,11 +187,22 @@ class Server:
                         return
                     i = order[state["next"]]
                     wait = arrivals[i] - (time.perf_counter() - t0)
-                    if wait > 0 or state["used"] + need[i] > self.budget:
+                    r = err = None
+                    if wait > 0 or (self.pool is None and state["used"] + need[i] > self.budget):
                         i = None
                     else:
-                        state["next"] += 1
-                        state["used"] += need[i]
+                        if self.pool is not None:
+                            # created under the lock, so requests take pool ranges in
+                            # arrival order
+                            try:
+                                r = self._admit(items[i][0], slot)
+                            except Exception as e:
+                                err = e
+                            if r is None and err is None:
+                                i = None
+                        if i is not None:
+                            state["next"] += 1
+                            state["used"] += need[i]
                 if i is None:
                     time.sleep(0.002)
                     continue
@@ -167,9 +210,11 @@ class Server:
                 t_admit = time.perf_counter() - t0
                 rec = dict(id=i, n=w.n[0], status=None, latency=None,
                            queued=t_admit - arrivals[i], krylov_iters=0, macro_stress=None)
-                r = None
                 try:
-                    r = RVE(w.desc(), self.precision, stream=self.streams[slot])
+                    if err is not None:
+                        raise err
+                    if r is None:
+                        r = self._admit(w, slot)
                     r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
                     it, st = 0, {"status": 0, "macro_stress": None}
                     for k in range(len(inp["deps"])):

@@ -214,3 +214,19 @@ def test_plane_stress_is_validated():
                 dict(plate, plane_stress=1, kinematics=1, krylov=1)):
         assert p.rve_footprint_bytes(p.make_desc(bad)) == 0
         assert "plane_stress" in lib.rve_last_error().decode()
+
+
+def test_pool_create_validates_its_arena():
+    """rve_pool_create refuses a null arena or one with no 256-byte granule, before any
+    device call; pool calls on a null pool are harmless or refused."""
+    import paper_2304_01125_amd as p
+    lib = p.load()
+    h = ctypes.c_void_p()
+    assert lib.rve_pool_create(None, 1 << 20, ctypes.byref(h)) == p.RVE_E_ARG
+    assert lib.rve_pool_create(ctypes.c_void_p(4096), 100, ctypes.byref(h)) == p.RVE_E_ARG
+    assert "granule" in lib.rve_last_error().decode()
+    assert lib.rve_pool_destroy(None) == p.RVE_OK
+    assert lib.rve_pool_free_bytes(None, None) == 0
+    d = p.make_desc(__import__("synth").workload("notched-crystal-16").desc())
+    out = ctypes.c_void_p()
+    assert lib.rve_create_in_pool(None, ctypes.byref(d), None, ctypes.byref(out)) == p.RVE_E_ARG

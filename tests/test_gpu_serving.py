@@ -37,13 +37,21 @@ def test_each_result_alone_equals_result_in_the_mix(slots):
             assert np.array_equal(a["fields"][k], b["fields"][k]), (a["id"], k)
 
 
-def test_admission_respects_memory_budget():
+@pytest.mark.parametrize("use_pool", [False, True])
+def test_admission_respects_memory_budget(use_pool):
+    """Both servers finish every request under a budget that never holds the two largest;
+    with use_pool the budget is one library arena (rve_create_in_pool admission), whose
+    ranges are all free again at the end."""
     from paper_2304_01125_amd import RVE_MIXED, make_desc, rve_footprint_bytes
     from paper_2304_01125_amd.serve import Server
     gaps, items = _items(4, seed=6)
     sizes = [rve_footprint_bytes(make_desc(w.desc(), RVE_MIXED)) for w, _ in items]
     budget = max(sizes) + min(sizes) - 1          # never two of the largest at once
-    srv = Server(RVE_MIXED, max_slots=4, budget_bytes=budget)
+    srv = Server(RVE_MIXED, max_slots=4, budget_bytes=budget, use_pool=use_pool)
+    if use_pool:
+        res, wall = srv.run_async(items, np.zeros(len(items)))
+        assert all(r["status"] == 0 for r in res), [r["status"] for r in res]
+        assert srv.pool.free_bytes() == (srv.pool_total, srv.pool_total)
     res, wall, ticks = srv.run(items, np.zeros(len(items)))
     assert all(r["status"] == 0 for r in res)
     # the resident footprints never exceeded the budget, and the two largest requests
@@ -52,6 +60,7 @@ def test_admission_respects_memory_budget():
     big = sorted(range(len(items)), key=lambda i: sizes[i])[-2:]
     assert not any(set(big) <= set(ids) for ids in srv.resident_log)
     assert len(srv.resident_log) == ticks
+    srv.close()
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -96,3 +105,47 @@ def test_pool_tick_batches_same_size_solves_bitwise(prec):
         for key in f:
             assert np.array_equal(f[key], alone[i][key]), (i, key)
         r.close()
+
+
+def test_pool_admits_by_footprint_and_reuses_released_ranges():
+    """rve_create_in_pool: handles take their footprint from the pool's arena until no free
+    range fits (RVE_E_NOMEM), a destroyed handle's range is taken again, the pool refuses
+    destruction while handles live, and pool handles stepped together with rve_pool_step
+    give bitwise the results of a handle in an arena of its own."""
+    from paper_2304_01125_amd import (RVE, RvePool, RveError, RVE_MIXED, RVE_E_NOMEM,
+                                      RVE_E_STATE, make_desc, rve_footprint_bytes, rve_pool_step)
+    from synth import small_polycrystal, make_inputs
+    print("pool of 32^3 mixed-precision handles", flush=True)
+    w = small_polycrystal(n=(32, 32, 32), n_grains=8, seed=4)
+    inp = make_inputs(w)
+    fp = (rve_footprint_bytes(make_desc(w.desc(), RVE_MIXED)) + 255) // 256 * 256
+    pool = RvePool(5 * fp // 2)
+    assert pool.free_bytes()[0] >= 2 * fp
+    a = RVE(w.desc(), RVE_MIXED, pool=pool)
+    b = RVE(w.desc(), RVE_MIXED, pool=pool)
+    with pytest.raises(RveError) as e:
+        RVE(w.desc(), RVE_MIXED, pool=pool)
+    assert e.value.code == RVE_E_NOMEM
+    with pytest.raises(RveError) as e:
+        pool.close()
+    assert e.value.code == RVE_E_STATE
+    a.close()
+    c = RVE(w.desc(), RVE_MIXED, pool=pool)        # the released range is taken again
+    ref = RVE(w.desc(), RVE_MIXED)
+    for r in (b, c, ref):
+        r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+    for k in range(3):
+        de = [0, inp["deps"][k], 0, 0, 0, 0]
+        rc, status, _ = rve_pool_step([b.h, c.h], [de, de], [inp["dt"][k]] * 2)
+        assert rc == 0 and status == [0, 0]
+        ref.step(de, inp["dt"][k])
+    fr = ref.fields(("strain", "stress"))
+    for r in (b, c):
+        f = r.fields(("strain", "stress"))
+        for name in ("strain", "stress"):
+            assert np.array_equal(f[name], fr[name]), name
+    for r in (b, c, ref):
+        r.close()
+    tot, largest = pool.free_bytes()
+    assert tot == largest and tot >= 2 * fp          # the free ranges merged again
+    pool.close()
