@@ -60,6 +60,7 @@ class Server:
         self.streams = [torch.cuda.Stream(self.device) for _ in range(max_slots)]
         self.pool = RvePool(budget_bytes, device) if use_pool else None
         self.pool_total = self.pool.free_bytes()[0] if use_pool else 0
+        self.peak_used = 0                # largest resident footprint sum (bytes)
 
     def close(self):
         if self.pool is not None:
@@ -74,7 +75,11 @@ class Server:
         if self.pool is None:
             return RVE(w.desc(), self.precision, stream=self.streams[slot])
         try:
-            return RVE(w.desc(), self.precision, stream=self.streams[slot], pool=self.pool)
+            r = RVE(w.desc(), self.precision, stream=self.streams[slot], pool=self.pool)
+            # resident bytes from the pool itself: a handle returns its range at close(),
+            # before the server's own count of resident bytes drops
+            self.peak_used = max(self.peak_used, self.pool_total - self.pool.free_bytes()[0])
+            return r
         except RveError as e:
             if e.code == RVE_E_NOMEM and self.pool.free_bytes()[0] < self.pool_total:
                 return None
@@ -123,7 +128,8 @@ class Server:
                 free_slots.pop(0)
                 r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
                 used += r.footprint
-                self.peak_used = max(self.peak_used, used)
+                if self.pool is None:
+                    self.peak_used = max(self.peak_used, used)
                 active.append(dict(i=i, slot=slot, rve=r, k=0, t_admit=now, iters=0))
             if not active:
                 if nxt < n:
@@ -174,6 +180,7 @@ class Server:
         out = [None] * n
         lock = threading.Lock()
         state = {"next": 0, "used": 0}
+        self.peak_used = 0
         from . import make_desc, rve_footprint_bytes
         need = [rve_footprint_bytes(make_desc(w.desc(), self.precision)) for w, _ in items]
         t0 = time.perf_counter()
@@ -203,6 +210,8 @@ class Server:
                         if i is not None:
                             state["next"] += 1
                             state["used"] += need[i]
+                            if self.pool is None:
+                                self.peak_used = max(self.peak_used, state["used"])
                 if i is None:
                     time.sleep(0.002)
                     continue
@@ -284,14 +293,17 @@ def summary(recs, wall):
 
 
 def serve_benchmark(n_req=400, slots=8, seed=4, workers=8, log=None, items=None, low_rate=0.5,
-                    modes=("async", "tick")):
+                    modes=("async", "tick"), use_pool=False, capacity=None, budget_bytes=32 << 30):
     """Serial plain-FP64 baseline, then the mixed-precision server in each of `modes` on the
     Poisson stream at rate factor x the serial capacity, and at `low_rate` x its own measured
     throughput (latency without a growing queue).  Mode "async": each slot runs its request's
     increments back to back on its own stream and host thread; "tick": one rve_pool_step per
     tick, the CG iterations of same-size requests in shared launches.  The first mode fills
     `server_mixed` and `server_mixed_below_capacity`, every mode `<mode>`.  Returns a
-    JSON-able dict.  `items`: the prepared requests (else prepared here)."""
+    JSON-able dict.  `items`: the prepared requests (else prepared here); `use_pool`: admission
+    by first fit in one library-held arena (rve_create_in_pool) instead of the budget sum;
+    `capacity`: the serial solves/s that sets the arrival rate, given instead of measured
+    (the serial run is skipped); low_rate <= 0 skips the below-capacity runs."""
     from synth import serving_requests
     from . import RVE_FP64, RVE_MIXED
     factor, gaps, reqs = serving_requests(n_req, seed)
@@ -299,15 +311,23 @@ def serve_benchmark(n_req=400, slots=8, seed=4, workers=8, log=None, items=None,
         items = prepare(reqs, workers)
     if log:
         log(f"prepared {len(items)} requests")
-    serial, wall_s = run_serial(items, RVE_FP64, log=log)
-    cap = len(serial) / wall_s
+    if capacity is None:
+        serial, wall_s = run_serial(items, RVE_FP64, log=log)
+        cap = len(serial) / wall_s
+    else:
+        serial, cap = None, float(capacity)
     lam = factor * cap
     arrivals = np.cumsum(gaps) / lam
-    srv = Server(RVE_MIXED, max_slots=slots)
-    ok_s = sum(1 for r in serial if r["status"] == 0)
+    srv = Server(RVE_MIXED, max_slots=slots, budget_bytes=budget_bytes, use_pool=use_pool)
     out = {"requests": n_req, "slots": slots, "rate_factor": round(factor, 3),
-           "arrival_rate_per_s": round(lam, 3), "completed_serial": ok_s,
-           "serial_fp64": summary(serial, wall_s)}
+           "arrival_rate_per_s": round(lam, 3),
+           "admission": "pool (first fit)" if use_pool else "budget sum",
+           "budget_gib": round(budget_bytes / 2 ** 30, 3)}
+    if serial is not None:
+        out["completed_serial"] = sum(1 for r in serial if r["status"] == 0)
+        out["serial_fp64"] = summary(serial, wall_s)
+    else:
+        out["serial_capacity_given"] = cap
     for i, mode in enumerate(modes):
         def serve(arr):
             if mode == "async":
@@ -317,20 +337,24 @@ def serve_benchmark(n_req=400, slots=8, seed=4, workers=8, log=None, items=None,
 
         res, wall, ticks = serve(arrivals)
         m = {"completed": sum(1 for r in res if r["status"] == 0),
-             "server_mixed": summary(res, wall)}
+             "server_mixed": summary(res, wall),
+             "peak_resident_gib": round(srv.peak_used / 2 ** 30, 3)}
         if ticks is not None:
             m["ticks"] = ticks
         # below capacity: arrivals at low_rate x this server's throughput under the stream
-        lam_low = low_rate * len(res) / wall
-        res2, wall2, _ = serve(np.cumsum(gaps) / lam_low)
-        m["server_mixed_below_capacity"] = dict(summary(res2, wall2),
-                                               arrival_rate_per_s=round(lam_low, 3))
+        if low_rate > 0:
+            lam_low = low_rate * len(res) / wall
+            res2, wall2, _ = serve(np.cumsum(gaps) / lam_low)
+            m["server_mixed_below_capacity"] = dict(summary(res2, wall2),
+                                                   arrival_rate_per_s=round(lam_low, 3))
         out[mode] = m
         if i == 0:
             out["mode"] = mode
             out["completed"] = m["completed"]
             out["server_mixed"] = m["server_mixed"]
-            out["server_mixed_below_capacity"] = m["server_mixed_below_capacity"]
+            if low_rate > 0:
+                out["server_mixed_below_capacity"] = m["server_mixed_below_capacity"]
+    srv.close()
     return out
 
 
@@ -342,10 +366,19 @@ def main():
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--json", default=None)
     ap.add_argument("--mode", choices=["tick", "async", "both"], default="both")
+    ap.add_argument("--pool", action="store_true",
+                    help="admit by first fit in one library-held arena (rve_create_in_pool)")
+    ap.add_argument("--budget-gib", type=float, default=32.0)
+    ap.add_argument("--capacity", type=float, default=None,
+                    help="serial solves/s that sets the arrival rate (skips the serial run)")
+    ap.add_argument("--low-rate", type=float, default=0.5,
+                    help="below-capacity arrival rate / server throughput (0: skip)")
     a = ap.parse_args()
     modes = ("async", "tick") if a.mode == "both" else (a.mode,)
     res = serve_benchmark(a.requests, a.slots, a.seed, a.workers,
-                          log=lambda m: print(m, file=sys.stderr, flush=True), modes=modes)
+                          log=lambda m: print(m, file=sys.stderr, flush=True), modes=modes,
+                          use_pool=a.pool, capacity=a.capacity, low_rate=a.low_rate,
+                          budget_bytes=int(a.budget_gib * 2 ** 30))
     print(json.dumps(res), flush=True)
     if a.json:
         with open(a.json, "w") as f:

@@ -51,6 +51,7 @@ def test_admission_respects_memory_budget(use_pool):
     if use_pool:
         res, wall = srv.run_async(items, np.zeros(len(items)))
         assert all(r["status"] == 0 for r in res), [r["status"] for r in res]
+        assert 0 < srv.peak_used <= srv.pool_total <= budget
         assert srv.pool.free_bytes() == (srv.pool_total, srv.pool_total)
     res, wall, ticks = srv.run(items, np.zeros(len(items)))
     assert all(r["status"] == 0 for r in res)
