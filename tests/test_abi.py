@@ -230,3 +230,21 @@ def test_pool_create_validates_its_arena():
     d = p.make_desc(__import__("synth").workload("notched-crystal-16").desc())
     out = ctypes.c_void_p()
     assert lib.rve_create_in_pool(None, ctypes.byref(d), None, ctypes.byref(out)) == p.RVE_E_ARG
+    # a pool over an address range the host never dereferences: base rounded up to 256 B,
+    # length down to whole granules; a handle larger than the pool, or an invalid
+    # description, is refused before any device call, and the empty pool is destroyed
+    assert lib.rve_pool_create(ctypes.c_void_p(4096 + 8), 1 << 20, ctypes.byref(h)) == p.RVE_OK
+    largest = ctypes.c_size_t(0)
+    total = lib.rve_pool_free_bytes(h, ctypes.byref(largest))
+    assert total == largest.value == (1 << 20) - 256
+    need = p.rve_footprint_bytes(d)
+    assert need > total
+    assert lib.rve_create_in_pool(h, ctypes.byref(d), None, ctypes.byref(out)) == p.RVE_E_NOMEM
+    msg = lib.rve_last_error().decode()
+    assert str((need + 255) // 256 * 256) in msg and str(total) in msg, msg
+    assert not out.value
+    bad = p.make_desc(__import__("synth").workload("notched-crystal-16").desc())
+    bad.n[0] = 0
+    assert lib.rve_create_in_pool(h, ctypes.byref(bad), None, ctypes.byref(out)) == p.RVE_E_ARG
+    assert lib.rve_pool_free_bytes(h, None) == total       # nothing was taken
+    assert lib.rve_pool_destroy(h) == p.RVE_OK
