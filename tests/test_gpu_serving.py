@@ -150,3 +150,45 @@ def test_pool_admits_by_footprint_and_reuses_released_ranges():
     tot, largest = pool.free_bytes()
     assert tot == largest and tot >= 2 * fp          # the free ranges merged again
     pool.close()
+
+
+def test_pool_first_fit_with_mixed_sizes():
+    """Handles of three sizes in one pool: the free bytes drop by each handle's footprint
+    rounded up to 256 B, a small handle takes the gap a larger one left (first fit, lowest
+    offset), releases that are not adjacent stay separate ranges, and the last release
+    merges everything back into one range.  The handle in the gap then solves an increment
+    bitwise like a handle in its own arena."""
+    from paper_2304_01125_amd import RVE, RvePool, RVE_FP64, make_desc, rve_footprint_bytes
+    from synth import small_polycrystal, make_inputs
+    print("pool with 8^3, 16^3 and 24^3 handles", flush=True)
+    ws = {n: small_polycrystal(n=(n, n, n), n_grains=4, seed=n) for n in (8, 16, 24)}
+    fp = {n: (rve_footprint_bytes(make_desc(w.desc(), RVE_FP64)) + 255) // 256 * 256
+          for n, w in ws.items()}
+    assert fp[8] < fp[16] < fp[24]
+    pool = RvePool(fp[16] + fp[24] + fp[16] + 4096)
+    total = pool.free_bytes()[0]
+    a = RVE(ws[16].desc(), RVE_FP64, pool=pool)         # [a | b | c | rest]
+    b = RVE(ws[24].desc(), RVE_FP64, pool=pool)
+    c = RVE(ws[16].desc(), RVE_FP64, pool=pool)
+    used = fp[16] + fp[24] + fp[16]
+    assert pool.free_bytes() == (total - used, total - used)
+    b.close()                                          # gap of fp[24] between a and c
+    assert pool.free_bytes() == (total - used + fp[24], fp[24])
+    d = RVE(ws[8].desc(), RVE_FP64, pool=pool)          # first fit: into the gap
+    assert pool.free_bytes() == (total - used + fp[24] - fp[8], fp[24] - fp[8])
+    inp = make_inputs(ws[8])
+    ref = RVE(ws[8].desc(), RVE_FP64)
+    for r in (d, ref):
+        r.set_microstructure(inp["grain"], inp["quat"], inp["tau_c0"], inp["phi0"])
+        r.step([0, inp["deps"][0], 0, 0, 0, 0], inp["dt"][0])
+    fd, fr = d.fields(("strain", "stress")), ref.fields(("strain", "stress"))
+    for k in ("strain", "stress"):
+        assert np.array_equal(fd[k], fr[k]), k
+    ref.close()
+    a.close()                                          # [free | d | gap | c | rest]
+    tot, largest = pool.free_bytes()
+    assert tot == total - fp[16] - fp[8] and largest == max(fp[16], fp[24] - fp[8], total - used)
+    c.close()
+    d.close()
+    assert pool.free_bytes() == (total, total)
+    pool.close()
