@@ -12,7 +12,8 @@ last increment releases its slot and memory at once; newcomers join at the next 
 without waiting for the others to finish.  Reported: solves/s, p50/p99 latency
 (arrival to completion) and the same for serial solves.
 
-    python -m paper_2304_01125_amd.serve --requests 400 [--slots 8] [--json out.json]
+    python -m paper_2304_01125_amd.serve --requests 400 [--slots 8] [--mode async|tick|both]
+        [--pool] [--budget-gib 32] [--capacity SOLVES_PER_S] [--low-rate 0.5] [--json out.json]
 """
 import argparse
 import json
